@@ -1,0 +1,132 @@
+"""Seeded synthetic inputs shaped like the paper's test problems.
+
+This module only states problems: grids, parameters, boundary choices and
+seeded porosity fields.  It holds none of the lattice Boltzmann arithmetic, so
+both the FP64 oracle and the GPU library can consume what it produces without
+sharing any of the method's code.
+
+A problem is a plain ``dict`` with these keys (lattice units, spacing 1):
+
+  nr, nz                 grid: rows along r (index j), columns along z (index k)
+  r0                     radius of row j = 0 (rows sit at r0 + j)
+  L                      characteristic length of Eq. (9)
+  side_rmin, side_rmax   "wall" | "axis" (r_min only) | "periodic"
+  side_z                 "wall" | "periodic"
+  therm_rmin, therm_rmax, therm_z   "fixed" | "adiabatic"
+  T_rmin, T_rmax, T_zmin, T_zmax    wall temperatures of fixed walls
+  T_ref, T_init, delta_T reference temperature T_0 of Eq. (7), initial
+                         temperature, temperature difference (0: T_rmin - T_rmax)
+  phi, Da, F_phi         porosity (reference porosity with a field), Darcy
+                         number, Forchheimer coefficient (negative: Ergun, Eq. 8)
+  Ra, Pr, J, lam, Ma     Eq. (9) groups and the Mach number of Eq. (39)
+  tau_nu                 > 0 overrides Eq. (39)
+  accel_r, accel_z       external acceleration a of Eq. (7)
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+ERGUN = -1.0  # F_phi < 0 selects the Ergun relation of Eq. (8)
+
+
+def pipe(nr: int = 64, nz: int = 8, phi: float = 0.6, Da: float = 1e-2, Re: float = 10.0,
+         tau_nu: float = 0.8, Pr: float = 1.0, F_phi: float = ERGUN, T_wall: float = 1.0,
+         T_init: float = 0.0) -> dict:
+    """Porous-pipe flow driven by an axial body force, periodic in z.
+
+    Rows are cell-centred about the axis (r0 = 1/2); the wall row nr-1 sits at
+    R = nr - 1/2, which is also the length scale L (the paper's pipe problem
+    uses L = r_i).  The axial acceleration is chosen so that the mean velocity
+    of the Brinkman-extended Darcy solution (Forchheimer term off) gives the
+    requested Re = U R / nu.
+    """
+    from scipy.special import i0, i1
+
+    R = nr - 0.5
+    nu = (tau_nu - 0.5) / 3.0  # J = 1
+    K = Da * R * R
+    k = math.sqrt(phi / K)
+    U = Re * nu / R
+    mean_factor = 1.0 - 2.0 * float(i1(k * R)) / (k * R * float(i0(k * R)))
+    accel = U * nu / (K * mean_factor)
+    return dict(nr=nr, nz=nz, r0=0.5, L=R, side_rmin="axis", side_rmax="wall",
+                side_z="periodic", therm_rmin="adiabatic", therm_rmax="fixed",
+                therm_z="adiabatic", T_rmin=0.0, T_rmax=T_wall, T_zmin=0.0, T_zmax=0.0,
+                T_ref=0.0, T_init=T_init, delta_T=T_wall - T_init, phi=phi, Da=Da,
+                F_phi=F_phi, Ra=0.0, Pr=Pr, J=1.0, lam=1.0, Ma=0.1, tau_nu=tau_nu,
+                accel_r=0.0, accel_z=accel)
+
+
+def annulus(nr: int = 256, nz: int = 256, Rstar: float = 2.0, phi: float = 0.6,
+            Da: float = 1e-4, Ra: float = 1e5, Pr: float = 1.0, F_phi: float = ERGUN,
+            T_i: float = 1.0, T_o: float = 0.0, J: float = 1.0, lam: float = 1.0,
+            Ma: float = 0.1) -> dict:
+    """Natural convection between coaxial cylinders (Fig. 3 problem).
+
+    Wall nodes lie on the walls: L = r_o - r_i = nr - 1, H = nz - 1,
+    r_i = L / (R* - 1).  Hot inner wall, cold outer wall, adiabatic ends,
+    T_0 = (T_i + T_o) / 2, interior starting at T_o and at rest.
+    """
+    L = nr - 1.0
+    ri = L / (Rstar - 1.0)
+    return dict(nr=nr, nz=nz, r0=ri, L=L, side_rmin="wall", side_rmax="wall",
+                side_z="wall", therm_rmin="fixed", therm_rmax="fixed", therm_z="adiabatic",
+                T_rmin=T_i, T_rmax=T_o, T_zmin=0.0, T_zmax=0.0, T_ref=0.5 * (T_i + T_o),
+                T_init=T_o, delta_T=T_i - T_o, phi=phi, Da=Da, F_phi=F_phi, Ra=Ra, Pr=Pr,
+                J=J, lam=lam, Ma=Ma, tau_nu=0.0, accel_r=0.0, accel_z=0.0)
+
+
+def table2(Ra: float, nr: int = 100, nz: int = 200) -> dict:
+    """Annulus without porous medium as in Sec. 4.2 / Table 2 (phi = 1, Da = 1e8)."""
+    return annulus(nr=nr, nz=nz, Rstar=2.0, phi=1.0, Da=1e8, Ra=Ra, Pr=0.7, F_phi=0.0)
+
+
+def porosity_grf(nz: int, nr: int, seed: int = 1409, sigma: float = 8.0, mean: float = 0.6,
+                 std: float = 0.15, lo: float = 0.3, hi: float = 0.95) -> np.ndarray:
+    """Seeded Gaussian random porosity field, [nz, nr] float64.
+
+    White N(0,1) noise from numpy's PCG64 with the given seed, a Gaussian
+    filter of ``sigma`` cells (reflecting edges), standardised to zero mean and
+    unit variance, then phi = clip(mean + std * xi, lo, hi).
+    """
+    from scipy.ndimage import gaussian_filter
+
+    rng = np.random.default_rng(seed)
+    xi = rng.standard_normal((nz, nr), dtype=np.float64)
+    xi = gaussian_filter(xi, sigma=sigma, mode="reflect")
+    xi = (xi - xi.mean()) / xi.std()
+    return np.clip(mean + std * xi, lo, hi)
+
+
+def variable_porosity_annulus(n: int = 8192, Ra: float = 1e6, Da: float = 1e-3,
+                              seed: int = 1409):
+    """The throughput problem: an n x n annulus (R* = 2, Pr = 1) with a seeded
+    porosity field of mean 0.6 (also the reference porosity for K), Ergun
+    Forchheimer coefficient from the local porosity.  Returns (problem, phi)."""
+    cfg = annulus(nr=n, nz=n, Rstar=2.0, phi=0.6, Da=Da, Ra=Ra, Pr=1.0, F_phi=ERGUN)
+    return cfg, porosity_grf(n, n, seed=seed)
+
+
+def sweep(n_inst: int = 1024, seed: int = 1409, sizes=None) -> list:
+    """Batched parameter sweep of annuli with uneven grids and parameters.
+
+    Nr, Nz uniform on {32, 64, ..., 512}; Ra log-uniform on [1e3, 1e6];
+    Da log-uniform on [1e-6, 1e-2]; phi uniform on [0.3, 0.95]; R* log-uniform
+    on [1.2, 10]; Pr from {0.71, 1, 7}; Ergun Forchheimer coefficient.
+    """
+    rng = np.random.default_rng(seed)
+    sizes = np.arange(32, 513, 32) if sizes is None else np.asarray(sizes)
+    out = []
+    for _ in range(n_inst):
+        nr = int(rng.choice(sizes))
+        nz = int(rng.choice(sizes))
+        Ra = 10.0 ** rng.uniform(3.0, 6.0)
+        Da = 10.0 ** rng.uniform(-6.0, -2.0)
+        phi = float(rng.uniform(0.3, 0.95))
+        Rstar = math.exp(rng.uniform(math.log(1.2), math.log(10.0)))
+        Pr = float(rng.choice([0.71, 1.0, 7.0]))
+        out.append(annulus(nr=nr, nz=nz, Rstar=Rstar, phi=phi, Da=Da, Ra=Ra, Pr=Pr,
+                           F_phi=ERGUN))
+    return out
