@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Throughput of the fused D2Q9-MRT + D2Q5 step on one MI355X.
+
+Workload: the 8192 x 8192 annulus of the throughput problem (R* = 2,
+Ra = 1e6, Da = 1e-3, Pr = 1, seeded Gaussian random porosity field, Ergun
+Forchheimer coefficient), cold start, residual and wall-Nusselt check every
+100 steps.  One bench step = one time step of the whole lattice (all of the
+fused update, plus the check every 100 steps).  Inputs are resident in HBM
+before the timed region starts.
+
+Prints one JSON line: MLUPS (million node updates per second, one node = both
+lattices), the HBM roofline of the step kernel (algorithmic bytes per launch
+over its average duration from HIP events on the library's stream) and the
+FP64 CPU oracle timed on a bounded sample of the same problem.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS (fused D2Q9+D2Q5) & % HBM roofline; time-to-steady warm vs cold start"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic_8192.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1409_5929_amd", "csrc", f)
+                  for f in ("lbm_axi.hip", "lbm_axi_dev.h", "lbm_axi_desc.h")]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage: str):
+    """HBM bytes per step-kernel launch from committed rocprofv3 counter runs,
+    if they were taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = t.get(storage)
+    if not e or t.get("source_sha") != kernel_source_sha():
+        return None
+    return e["bytes_per_launch"]
+
+
+def cpu_baseline(cfg, phi, seconds: float):
+    """The FP64 oracle on a 1024 x 1024 corner of the same problem (inner
+    wall, bottom wall), stepped until `seconds` of work are done."""
+    import oracle
+
+    oracle.build(force=False)
+    w = 1024
+    c = dict(cfg)
+    c.update(nr=w, nz=w, side_rmax="wall", therm_rmax="adiabatic")
+    o = oracle.Oracle(c, phi_field=phi[:w, :w])
+    o.step(1)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        o.step(1)
+        n += 1
+        dt = time.perf_counter() - t0
+        if dt >= seconds and n >= 2:
+            break
+    o.close()
+    return dict(value=w * w * n / dt / 1e6, unit="MLUPS", cores=oracle.threads(), kind="oracle",
+                sample=f"{w}x{w} corner window of the {cfg['nr']}x{cfg['nz']} problem "
+                       f"(same physics and porosity field), {n} steps in {dt:.1f} s, FP64")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--size", type=int, default=8192)
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16"])
+    ap.add_argument("--check-interval", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 2 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md); rerun with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import lbm_inputs as li
+    from paper_1409_5929_amd import Lattice
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    n = args.size
+    log(f"porosity field {n}x{n} (seed 1409)")
+    cfg, _ = li.variable_porosity_annulus(n=n)
+    phi = li.porosity_grf(n, n, seed=1409)
+    log("create lattice")
+    stream = torch.cuda.Stream()  # the library launches on this stream; events are recorded on it
+    lat = Lattice(cfg, phi=phi.astype(np.float32), storage=args.storage,
+                  check_interval=args.check_interval, stream=stream.cuda_stream)
+    log(f"warmup {args.warmup} steps")
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+
+    if args.copy_calibration:
+        src = torch.empty(2 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    log(f"timed {args.steps} steps")
+    lat.set_timing(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    lat.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    kern_ms, launches = lat.kernel_time()
+    lat.set_timing(False)
+    res = lat.residual()
+    info = lat.info()
+    lat.close()
+
+    esz = 4 if args.storage == "fp32" else 2
+    fluid = (n - 2) * (n - 2)
+    bytes_node = 28 * esz + 4  # 14 populations read + 14 written, porosity read
+    # launches that also write u_z, u_r, T for the residual (two per check interval)
+    macro_launches = 0
+    t0 = args.warmup
+    for t in range(t0, t0 + args.steps):
+        if args.check_interval > 0 and ((t + 1) % args.check_interval == 0 or
+                                        (t > 0 and t % args.check_interval == 0)):
+            macro_launches += 1
+    alg_bytes = launches * fluid * bytes_node + macro_launches * 12 * n * n
+    avg_ms = kern_ms / max(launches, 1)
+    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.storage)
+    mlups = n * n * args.steps / (total_ms * 1e-3) / 1e6
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(total_ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"annulus {n}x{n} (R*=2, Ra=1e6, Da=1e-3, Pr=1, seeded porosity field "
+                        f"mean 0.6 sd 0.15 sigma 8 clipped [0.3,0.95], Ergun F_phi), cold start, "
+                        f"check every {args.check_interval} steps",
+            "nr": n, "nz": n, "storage": args.storage, "check_interval": args.check_interval,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "k_step (fused collide-stream, even and odd AA variants)",
+            "bytes_per_node": bytes_node,
+            "avg_launch_ms": round(avg_ms, 5),
+            "launches": launches,
+        },
+        "residual": float(res["res"][0]),
+        "nu_i": float(res["nu_i"][0]),
+        "t": int(info["t"]),
+    }
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline (oracle, ~{args.cpu_seconds:.0f} s)")
+        out["cpu_baseline"] = cpu_baseline(cfg, phi, args.cpu_seconds)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * lbm_axi -- axisymmetric MRT lattice Boltzmann for thermal flow in porous
+ * media on AMD Instinct MI355X (gfx950).
+ *
+ * The library advances the model of Liu, He and Li (arXiv:1409.5929): the
+ * r-weighted D2Q9 multiple-relaxation-time lattice for the flow (Sec. 3.1,
+ * Eqs. 13-32) coupled to the D2Q5 lattice for the temperature (Sec. 3.2,
+ * Eqs. 33-38), with the porous-medium body force of Eqs. (6)-(8) and the
+ * relaxation times of Eq. (39).  One call of lbm_axi_step performs, per node
+ * and time step, the fused update: macroscopic values (Eqs. 26-30, 38),
+ * moment-space collision (Eqs. 16-25), back-transform and streaming (Eq. 22),
+ * temperature collision and streaming (Eqs. 33-37).
+ *
+ * Conventions for every entry point:
+ *   - Return value: LBM_AXI_OK (0) or a negative lbm_axi_error code; nothing
+ *     aborts.  lbm_axi_last_error() gives a message for the calling thread.
+ *   - Ownership: the caller owns every pointer it passes; inputs are copied
+ *     before the call returns (device memory belongs to the handle).
+ *   - Public 2-D arrays are C-ordered [nz][nr], r fastest, no padding.
+ *   - A handle is not thread-safe; all its work runs on one HIP stream.
+ *
+ * Points the paper leaves open are settled as follows (the same readings the
+ * test oracle takes; the paper's section is named for each):
+ *   - Lattice: row j at radius r0 + j, column k at z = k, unit spacing
+ *     (Sec. 4).  Wall nodes lie on the walls (rows 0, nr-1; columns 0, nz-1).
+ *   - Walls: non-equilibrium extrapolation (Sec. 4): a wall node takes the
+ *     equilibrium of (density of its fluid neighbour, zero velocity, wall
+ *     temperature) plus the neighbour's non-equilibrium part, unscaled, and
+ *     collides with those values.  The neighbour is the normal one, the
+ *     diagonal one at corners.  Adiabatic walls copy the neighbour's
+ *     temperature; at a corner a fixed-temperature radial wall wins.
+ *   - Axis (LBM_SIDE_AXIS at r_min, r0 must be 1/2): a mirror row at r = -1/2
+ *     with f_i(-r) = -f_i*(r) for the r-weighted populations (i* reverses
+ *     e_r) and g_i(-r) = g_i*(r).
+ *   - Source moments: with src_printed = 0 the axisymmetric correction a_r of
+ *     Eq. (25) enters the second-order moments of Eq. (24) without the 1/phi
+ *     factor that the porous-medium force F carries; src_printed = 1 divides
+ *     all of F~ by phi exactly as Eq. (24) is printed (equal when phi = 1).
+ *   - Start: f = f^eq - S~/2 at rho = 1 (the change of variables before
+ *     Eq. 15), g = g^eq (Eq. 35).
+ *   - Buoyancy (Eq. 7) along +z with g*beta*dT = (Ma c_s)^2 / L when Ra > 0.
+ *   - Variable porosity: K(x) from Eq. (8) with the particle diameter fixed by
+ *     K(phi) = Da L^2 at the reference porosity p.phi; F_phi < 0 selects the
+ *     Ergun coefficient of Eq. (8) from the local porosity.
+ */
+#ifndef LBM_AXI_H
+#define LBM_AXI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_axi lbm_axi;
+
+enum lbm_axi_error {
+  LBM_AXI_OK = 0,
+  LBM_AXI_EINVAL = -1,       /* invalid argument or parameter */
+  LBM_AXI_ENOMEM = -2,       /* device or host allocation failed */
+  LBM_AXI_EDEVICE = -3,      /* a HIP call failed (message names it) */
+  LBM_AXI_EUNSUPPORTED = -4  /* a parameter value the model does not define */
+};
+
+enum lbm_axi_side {
+  LBM_SIDE_WALL = 0,     /* no-slip wall, nodes on the wall */
+  LBM_SIDE_AXIS = 1,     /* axis of symmetry; r_min only */
+  LBM_SIDE_PERIODIC = 2  /* periodic; along r only for tests (both r sides) */
+};
+
+enum lbm_axi_thermal { LBM_T_FIXED = 0, LBM_T_ADIABATIC = 1 };
+
+/* Storage of the populations.  Arithmetic is FP32 in every case. */
+enum lbm_axi_storage {
+  LBM_STORE_FP32 = 0,
+  LBM_STORE_FP16 = 1, /* shifted: deviation from the rest state, scaled by 2^storage_shift */
+  LBM_STORE_BF16 = 2
+};
+
+/* Per-instance run state reported by lbm_axi_residual. */
+enum lbm_axi_run_state {
+  LBM_RUNNING = 0,
+  LBM_CONVERGED = 1, /* residual <= tol, or exactly 0 */
+  LBM_DIVERGED = 2,  /* residual NaN or infinite */
+  LBM_STALLED = 3    /* max_steps reached */
+};
+
+/*
+ * Problem statement of one instance.  Lattice units: dt = dr = dz = 1.
+ * lbm_axi_default_params fills the paper's defaults (Sec. 4): J = lambda = 1,
+ * Ma = 0.1, s_e = s_eps = 1.1, s_q = 1.2, s_j = 1, sigma = 1.
+ */
+typedef struct lbm_axi_params {
+  int32_t nr, nz;              /* grid: rows along r, columns along z (>= 3 each with walls) */
+  int32_t side_rmin, side_rmax, side_z;      /* lbm_axi_side */
+  int32_t therm_rmin, therm_rmax, therm_z;   /* lbm_axi_thermal */
+  int32_t storage;             /* lbm_axi_storage */
+  int32_t storage_shift;       /* power-of-two scale of shifted storage (FP16: default 10) */
+  int32_t check_interval;      /* residual / Nusselt check every N steps (>= 2; 0 = never) */
+  int32_t src_printed;         /* 1: Eq. (24) exactly as printed (see above) */
+  double r0;                   /* radius of row 0 (> 0; 1/2 with an axis) */
+  double L;                    /* characteristic length of Eq. (9) */
+  double phi;                  /* porosity; reference porosity when a field is given */
+  double Da;                   /* Darcy number K / L^2 (Eq. 9) */
+  double F_phi;                /* Forchheimer coefficient of Eq. (6); < 0: Ergun, Eq. (8) */
+  double Ra, Pr, J, lambda;    /* Eq. (9) groups; Ra > 0 turns buoyancy on */
+  double sigma;                /* heat-capacity ratio: only 1 is defined (Eq. 4) */
+  double Ma;                   /* Mach number of Eq. (39) */
+  double tau_nu;               /* > 0 overrides tau_nu of Eq. (39) */
+  double accel_r, accel_z;     /* external acceleration a of Eq. (7) */
+  double s_e, s_eps, s_q, s_j; /* relaxation rates of Eq. (23); s_nu = 1 / tau_nu */
+  double T_rmin, T_rmax, T_zmin, T_zmax; /* temperatures of fixed-temperature walls */
+  double T_ref;                /* reference temperature T_0 of Eq. (7) */
+  double T_init;               /* initial temperature where no field is given */
+  double delta_T;              /* temperature difference of Ra and Nu; 0: T_rmin - T_rmax */
+  double tol;                  /* convergence threshold on the residual (0: only an exact 0) */
+  int64_t max_steps;           /* stall after this many steps (0: never) */
+} lbm_axi_params;
+
+/* Fill *p with the paper's default rates and ratios; grid and physics zero. */
+void lbm_axi_default_params(lbm_axi_params* p);
+
+/*
+ * Create n_inst independent instances (p points to n_inst parameter blocks)
+ * and set them to the start state.  phi_field: NULL, or n_inst host pointers,
+ * each NULL (uniform p.phi) or [nz][nr] floats with 0 < phi < 1.  init_uzurT:
+ * NULL, or n_inst host pointers, each NULL (rest, T_init) or [3][nz][nr]
+ * floats (u_z, u_r, T).  hip_stream: the hipStream_t to run on (NULL: the
+ * library creates one).  On failure *out is NULL and device memory is freed.
+ * Every instance must use the same check_interval.
+ */
+int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* phi_field,
+                   const float* const* init_uzurT, void* hip_stream, lbm_axi** out);
+
+/*
+ * Advance every running instance by nsteps time steps (asynchronous on the
+ * handle's stream).  Every check_interval steps the residual and the wall
+ * Nusselt numbers are computed on the device and the run state updated;
+ * instances that stop are skipped from then on.
+ */
+int lbm_axi_step(lbm_axi* h, int32_t nsteps);
+
+/*
+ * Macroscopic fields of instance inst at its current time (pre-collision):
+ * u_z, u_r, p = rho c_s^2 / phi and T (Eqs. 26-28, 38 and the text after
+ * Eq. 30), and the node classes (bit 0 r_min wall, 1 r_max wall, 2 z_min
+ * wall, 3 z_max wall, 4 row next to the axis).  Each pointer may be NULL.
+ * Wall nodes report u = 0, their wall temperature and the density of the
+ * neighbour they are built from.  dst_is_device: 1 if the pointers are device
+ * memory (written on the handle's stream, not waited for), 0 for host memory
+ * (the call waits).
+ */
+int lbm_axi_macros(lbm_axi* h, int32_t inst, float* uz, float* ur, float* p, float* T,
+                   uint8_t* mask, int32_t dst_is_device);
+
+/*
+ * Latest check of every instance (waits for the stream).  Each pointer may be
+ * NULL; arrays have n_inst entries.  The paper defines no convergence
+ * criterion; res = max(R_u, R_T) with R_u = rms over the fluid nodes of
+ * |u^n - u^{n-1}| divided by the characteristic velocity Ma c_s (text before
+ * Eq. 39) and R_T = rms of T^n - T^{n-1} divided by dT (FP64 sums).  nu_i,
+ * nu_o = Eq. (42) on the r_min and r_max walls (second-order one-sided dT/dr,
+ * trapezoid rule, H = nz - 1).  status = lbm_axi_run_state.  Before the
+ * first check res = +inf.
+ */
+int lbm_axi_residual(lbm_axi* h, double* res, double* nu_i, double* nu_o, int32_t* status);
+
+/*
+ * Details of instance inst (waits for the stream): out[0] = its time step,
+ * out[1] = step of the latest check, out[2] = run state, out[3] = bytes of
+ * device memory the handle holds.  out has 4 entries.
+ */
+int lbm_axi_info(lbm_axi* h, int32_t inst, int64_t* out);
+
+/*
+ * Kernel timing: with on = 1 every later step-kernel launch is bracketed by
+ * HIP events on the handle's stream; lbm_axi_kernel_time returns the summed
+ * milliseconds and the number of launches since timing was switched on
+ * (waits for the stream).  on = 0 stops timing.
+ */
+int lbm_axi_set_timing(lbm_axi* h, int32_t on);
+int lbm_axi_kernel_time(lbm_axi* h, double* total_ms, int64_t* launches);
+
+/* Wait for the handle's stream. */
+int lbm_axi_sync(lbm_axi* h);
+
+/* Free everything the handle holds.  NULL is allowed. */
+void lbm_axi_destroy(lbm_axi* h);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* lbm_axi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_AXI_H */

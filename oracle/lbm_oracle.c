@@ -577,25 +577,30 @@ void orc_macros(const orc_state* s, double* uz, double* ur, double* p, double* T
 }
 
 /*
- * Steady-state residual between times t-1 and t over fluid nodes (the paper
- * gives no criterion): out[0] = ||u^t - u^{t-1}|| / ||u^t||,
- * out[1] = ||T^t - T^{t-1}|| / ||T^t||, out[2] = max of both; 0/0 counts as 0.
- * Returns -1 before the first step.
+ * Steady-state residual between times t-1 and t over the N fluid nodes (the
+ * paper gives no criterion): the root-mean-square change per step of the
+ * velocity and of the temperature, scaled by the characteristic velocity
+ * U = Ma c_s (text before Eq. 39) and by the temperature difference dT:
+ * out[0] = sqrt(sum |u^t - u^{t-1}|^2 / N) / U, out[1] = the same for T / dT,
+ * out[2] = max of both.  Returns -1 before the first step.
  */
 int orc_residual(const orc_state* s, double* out) {
   if (!s->have_prev) return -1;
-  double du = 0, uu = 0, dT = 0, TT = 0;
+  double du = 0, dT = 0;
+  long nf = 0;
   for (int idx = 0; idx < s->n; ++idx) {
     if (is_boundary(s->mask[idx])) continue;
     double a = s->ur[idx] - s->pur[idx], b = s->uz[idx] - s->puz[idx];
     du += a * a + b * b;
-    uu += s->ur[idx] * s->ur[idx] + s->uz[idx] * s->uz[idx];
     double c = s->T[idx] - s->pT[idx];
     dT += c * c;
-    TT += s->T[idx] * s->T[idx];
+    nf += 1;
   }
-  out[0] = du == 0.0 ? 0.0 : sqrt(du / uu);
-  out[1] = dT == 0.0 ? 0.0 : sqrt(dT / TT);
+  double U = s->p.Ma > 0.0 ? s->p.Ma * sqrt(CS2) : 1.0;
+  double Tc = s->p.delta_T != 0.0 ? fabs(s->p.delta_T) : fabs(s->p.T_rmin - s->p.T_rmax);
+  if (Tc == 0.0) Tc = 1.0;
+  out[0] = nf ? sqrt(du / nf) / U : 0.0;
+  out[1] = nf ? sqrt(dT / nf) / Tc : 0.0;
   out[2] = out[0] > out[1] ? out[0] : out[1];
   return 0;
 }

@@ -1,0 +1,736 @@
+// lbm_axi: C-ABI library of the axisymmetric MRT lattice Boltzmann model for
+// thermal flow in porous media (Liu, He, Li, arXiv:1409.5929) on gfx950.
+//
+// Kernels
+//   k_step     fused D2Q9-MRT + D2Q5 collide-stream, AA pattern, in place
+//              (lbm_axi_dev.h); optionally writes u_z, u_r, T for the check
+//   k_resid    FP64 partial sums of the residual and of the Eq. (42) wall
+//              integrals (wave shuffles, then LDS across the block's waves)
+//   k_final    per-instance reduction of the partials, run-state update
+//   k_init     start state
+//   k_step<MODE_FIELDS>  macroscopic fields of one instance (no population writes)
+//
+// Launch geometry: blocks of 64 x 4 threads; lanes run along r (coalesced
+// rows), the 4 waves take interleaved z rows, and each thread walks KZ rows
+// so that its per-radius constants are computed once.  Tiles of all
+// instances form one list; block b takes tile (b % 8) * ceil(T / 8) + b / 8,
+// so that each of the 8 XCDs (blocks are dealt to XCDs round-robin) sweeps a
+// contiguous band of rows and neighbouring tiles share its L2.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm_axi.h"
+#include "lbm_axi_desc.h"
+#include "lbm_axi_dev.h"
+
+using namespace lbmaxi;
+
+namespace {
+
+constexpr int BX = 64;   // lanes along r
+constexpr int BY = 4;    // waves per block, interleaved along z
+constexpr int RB = 256;  // threads of the reduction kernels
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(LBM_AXI_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));  \
+  } while (0)
+
+struct DevResult {
+  double res, res_u, res_T, nu_i, nu_o, u_rms;
+  long long t_check, t_stop;
+};
+
+struct ResTile {
+  int inst, k0, k1, pad;
+};
+
+}  // namespace
+
+struct lbm_axi {
+  int n_inst = 0;
+  int storage = 0;
+  int check = 0;
+  int kz = 4;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<lbm_axi_params> prm;
+  std::vector<InstDev> hdesc;
+  InstDev* ddesc = nullptr;
+  std::vector<void*> allocs;
+  int4* dtiles = nullptr;       // XCD-ordered tiles of all instances
+  int ntiles_launch = 0;
+  int4* dtiles_plain = nullptr; // tiles in instance order
+  std::vector<int> tile_first, tile_count;
+  ResTile* drt = nullptr;
+  int nrt = 0;
+  double* dpart = nullptr;      // [nrt][6]
+  double* dtol = nullptr;       // per-instance tolerance
+  double* dnus = nullptr;       // per instance: r_w / (H dT) of both walls, 1 / (Ma c_s), 1 / dT
+  long long* dmx = nullptr;     // per-instance max_steps
+  int* dstatus = nullptr;
+  DevResult* dres = nullptr;
+  int* dfirst = nullptr;        // per-instance first reduction tile and count
+  long long t = 0;              // global time level
+  int prev_slot = 0;            // check buffer holding the step before a check
+  size_t bytes = 0;
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  double timed_ms = 0.0;
+  long long timed_launches = 0;
+};
+
+// ---- kernels ------------------------------------------------------------------
+
+template <typename S, bool ODD, int MODE>
+__global__ __launch_bounds__(BX* BY) void k_step(const InstDev* __restrict__ descs,
+                                                 const int4* __restrict__ tiles,
+                                                 const int* __restrict__ status, int kz,
+                                                 int mac_slot, FieldOut fo) {
+  const int4 tl = tiles[blockIdx.x];
+  if (tl.x < 0) return;
+  if (MODE != MODE_FIELDS && status[tl.x] != RUN) return;
+  const InstDev D = descs[tl.x];
+  const int j = tl.y + (int)threadIdx.x;
+  if (j >= D.nr) return;
+  if ((D.side_rmin == SIDE_WALL && j == 0) || (D.side_rmax == SIDE_WALL && j == D.nr - 1)) return;
+  const RowC R = make_row(D, j);
+  const bool zwall = D.side_z == SIDE_WALL;
+  for (int i = 0; i < kz; ++i) {
+    const int k = tl.z + (int)threadIdx.y + BY * i;
+    if (k >= D.nz) break;
+    if (zwall && (k == 0 || k == D.nz - 1)) continue;
+    node_update<S, ODD, MODE>(D, R, j, k, mac_slot, fo);
+  }
+}
+
+template <typename S>
+__global__ __launch_bounds__(BX* BY) void k_init(const InstDev* __restrict__ descs,
+                                                 const int4* __restrict__ tiles, int kz,
+                                                 const float* __restrict__ init, int inst) {
+  const int4 tl = tiles[blockIdx.x];
+  if (tl.x != inst) return;
+  const InstDev D = descs[inst];
+  const int j = tl.y + (int)threadIdx.x;
+  if (j >= D.nr) return;
+  const int64_t n = (int64_t)D.nr * D.nz;
+  for (int i = 0; i < kz; ++i) {
+    const int k = tl.z + (int)threadIdx.y + BY * i;
+    if (k >= D.nz) break;
+    const int64_t o = (int64_t)k * D.nr + j;
+    init_node<S>(D, j, k, init[o], init[n + o], init[2 * n + o]);
+  }
+}
+
+// Start state without an init field: rest, uniform T_init.
+template <typename S>
+__global__ __launch_bounds__(BX* BY) void k_init_uniform(const InstDev* __restrict__ descs,
+                                                         const int4* __restrict__ tiles, int kz,
+                                                         float T_init, int inst) {
+  const int4 tl = tiles[blockIdx.x];
+  if (tl.x != inst) return;
+  const InstDev D = descs[inst];
+  const int j = tl.y + (int)threadIdx.x;
+  if (j >= D.nr) return;
+  for (int i = 0; i < kz; ++i) {
+    const int k = tl.z + (int)threadIdx.y + BY * i;
+    if (k >= D.nz) break;
+    init_node<S>(D, j, k, 0.0f, 0.0f, T_init);
+  }
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// FP64 partial sums over fluid nodes of the rows [k0, k1) of one instance:
+// |du|^2, node count, dT^2, |u|^2, and the Eq. (42) integrands on both walls.
+__global__ __launch_bounds__(RB) void k_resid(const InstDev* __restrict__ descs,
+                                              const ResTile* __restrict__ rts, int cur,
+                                              double* __restrict__ part) {
+  const ResTile rt = rts[blockIdx.x];
+  const InstDev D = descs[rt.inst];
+  const float* cu = D.mac[cur];
+  const float* pv = D.mac[1 - cur];
+  const int64_t pl = D.plane;
+  double a[6] = {0, 0, 0, 0, 0, 0};
+  for (int k = rt.k0; k < rt.k1; ++k) {
+    const double ck = (k == 0 || k == D.nz - 1) ? 0.5 : 1.0;
+    for (int j = threadIdx.x; j < D.nr; j += RB) {
+      const int64_t o = (int64_t)k * D.stride + j;
+      if (!is_boundary(D, j, k)) {
+        const double uz = cu[o], ur = cu[pl + o], T = cu[2 * pl + o];
+        const double duz = uz - (double)pv[o], dur = ur - (double)pv[pl + o];
+        const double dT = T - (double)pv[2 * pl + o];
+        (void)T;
+        a[0] += duz * duz + dur * dur;
+        a[1] += 1.0;
+        a[2] += dT * dT;
+        a[3] += uz * uz + ur * ur;
+      }
+      if (j == 0 && D.nr >= 3) {
+        const double g = (-3.0 * cu[2 * pl + o] + 4.0 * cu[2 * pl + o + 1] - cu[2 * pl + o + 2]) * 0.5;
+        a[4] += ck * g;
+      }
+      if (j == D.nr - 1 && D.nr >= 3) {
+        const double g = (3.0 * cu[2 * pl + o] - 4.0 * cu[2 * pl + o - 1] + cu[2 * pl + o - 2]) * 0.5;
+        a[5] += ck * g;
+      }
+    }
+  }
+  __shared__ double sh[RB / 64][6];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int q = 0; q < 6; ++q) {
+    const double v = wave_sum(a[q]);
+    if (lane == 0) sh[w][q] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double v = 0.0;
+    for (int i = 0; i < RB / 64; ++i) v += sh[i][threadIdx.x];
+    part[(int64_t)blockIdx.x * 6 + threadIdx.x] = v;
+  }
+}
+
+// Per instance: sum its partials in order, form the residual (root-mean-
+// square change per step of u and T over the fluid nodes, scaled by Ma c_s
+// and dT) and the Nusselt numbers, update the run state.
+__global__ void k_final(const InstDev* __restrict__ descs, const int* __restrict__ first,
+                        const double* __restrict__ part, int n_inst, long long t,
+                        const double* __restrict__ tol, const long long* __restrict__ max_steps,
+                        const double* __restrict__ nu_scale, int* __restrict__ status,
+                        DevResult* __restrict__ out) {
+  const int inst = blockIdx.x * blockDim.x + threadIdx.x;
+  if (inst >= n_inst) return;
+  double a[6] = {0, 0, 0, 0, 0, 0};
+  const int b0 = first[2 * inst], nb = first[2 * inst + 1];
+  for (int b = b0; b < b0 + nb; ++b)
+    for (int q = 0; q < 6; ++q) a[q] += part[(int64_t)b * 6 + q];
+  const double nf = a[1] > 0.0 ? a[1] : 1.0;
+  const double ru = sqrt(a[0] / nf) * nu_scale[4 * inst + 2];
+  const double rT = sqrt(a[2] / nf) * nu_scale[4 * inst + 3];
+  double res = ru > rT ? ru : rT;
+  if (ru != ru || rT != rT) res = ru + rT;  // NaN propagates
+  DevResult r = out[inst];
+  r.res = res;
+  r.res_u = ru;
+  r.res_T = rT;
+  r.nu_i = -nu_scale[4 * inst] * a[4];
+  r.nu_o = -nu_scale[4 * inst + 1] * a[5];
+  r.u_rms = sqrt(a[3] / nf);
+  r.t_check = t;
+  int s = status[inst];
+  if (s == RUN) {
+    if (!isfinite(res)) s = DIVERGED;
+    else if (res <= tol[inst]) s = CONVERGED;
+    else if (max_steps[inst] > 0 && t + 1 >= max_steps[inst]) s = STALLED;
+    if (s != RUN) {
+      r.t_stop = t + 1;
+      status[inst] = s;
+    }
+  }
+  out[inst] = r;
+}
+
+// ---- host side ------------------------------------------------------------------
+
+namespace {
+
+int validate(const lbm_axi_params& p, int i) {
+  const std::string pre = "instance " + std::to_string(i) + ": ";
+  if (p.side_rmin < 0 || p.side_rmin > 2 || p.side_rmax < 0 || p.side_rmax > 2 || p.side_z < 0 ||
+      p.side_z > 2)
+    return fail(LBM_AXI_EINVAL, pre + "side code out of range");
+  if (p.side_z == SIDE_AXIS) return fail(LBM_AXI_EINVAL, pre + "the z sides cannot be an axis");
+  if (p.side_rmax == SIDE_AXIS) return fail(LBM_AXI_EINVAL, pre + "the axis can only be at r_min");
+  if ((p.side_rmin == SIDE_PERIODIC) != (p.side_rmax == SIDE_PERIODIC))
+    return fail(LBM_AXI_EINVAL, pre + "radial periodicity needs both r sides periodic");
+  if (p.side_rmin == SIDE_AXIS && p.r0 != 0.5)
+    return fail(LBM_AXI_EINVAL, pre + "an axis needs r0 = 1/2 (cell-centred rows)");
+  if (p.side_rmin == SIDE_AXIS && p.side_z == SIDE_WALL)
+    return fail(LBM_AXI_EUNSUPPORTED, pre + "axis together with axial walls is not supported");
+  if (p.nr < 3 || p.nz < 1 || (p.side_z == SIDE_WALL && p.nz < 3))
+    return fail(LBM_AXI_EINVAL, pre + "grid too small (nr >= 3, nz >= 3 with axial walls)");
+  if ((int64_t)p.nr * p.nz > (int64_t)1 << 31)
+    return fail(LBM_AXI_EINVAL, pre + "grid larger than 2^31 nodes");
+  if (!(p.r0 > 0.0)) return fail(LBM_AXI_EINVAL, pre + "r0 must be positive");
+  if (!(p.phi > 0.0 && p.phi <= 1.0)) return fail(LBM_AXI_EINVAL, pre + "phi must lie in (0, 1]");
+  if (!(p.Da > 0.0) || !(p.L > 0.0)) return fail(LBM_AXI_EINVAL, pre + "Da and L must be positive");
+  if (!(p.J > 0.0) || !(p.Pr > 0.0) || !(p.lambda > 0.0))
+    return fail(LBM_AXI_EINVAL, pre + "J, Pr and lambda must be positive");
+  if (p.sigma != 1.0)
+    return fail(LBM_AXI_EUNSUPPORTED, pre + "only a heat-capacity ratio of 1 is defined (Eq. 4)");
+  if (p.storage < 0 || p.storage > 2) return fail(LBM_AXI_EINVAL, pre + "storage code out of range");
+  if (p.check_interval == 1 || p.check_interval < 0)
+    return fail(LBM_AXI_EINVAL, pre + "check_interval must be 0 or >= 2");
+  if (!(p.tau_nu > 0.0) && !(p.Ra > 0.0))
+    return fail(LBM_AXI_EINVAL, pre + "give tau_nu or a positive Ra (Eq. 39)");
+  return LBM_AXI_OK;
+}
+
+void* dalloc(lbm_axi* h, size_t bytes, hipError_t* err) {
+  void* p = nullptr;
+  *err = hipMalloc(&p, bytes);
+  if (*err != hipSuccess) return nullptr;
+  h->allocs.push_back(p);
+  h->bytes += bytes;
+  return p;
+}
+
+template <typename S>
+int launch_step(lbm_axi* h, bool odd, int mode, int slot) {
+  const dim3 blk(BX, BY);
+  const FieldOut fo{nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (!odd) {
+    if (mode == MODE_STEP)
+      k_step<S, false, MODE_STEP><<<h->ntiles_launch, blk, 0, h->stream>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo);
+    else
+      k_step<S, false, MODE_STEP_MACRO><<<h->ntiles_launch, blk, 0, h->stream>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo);
+  } else {
+    if (mode == MODE_STEP)
+      k_step<S, true, MODE_STEP><<<h->ntiles_launch, blk, 0, h->stream>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo);
+    else
+      k_step<S, true, MODE_STEP_MACRO><<<h->ntiles_launch, blk, 0, h->stream>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo);
+  }
+  HIPCHK(hipGetLastError());
+  return LBM_AXI_OK;
+}
+
+template <typename S>
+int launch_fields(lbm_axi* h, int inst, bool odd, const FieldOut& fo) {
+  const dim3 blk(BX, BY);
+  const int4* tl = h->dtiles_plain + h->tile_first[inst];
+  if (!odd)
+    k_step<S, false, MODE_FIELDS><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->dstatus, h->kz, 0, fo);
+  else
+    k_step<S, true, MODE_FIELDS><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->dstatus, h->kz, 0, fo);
+  HIPCHK(hipGetLastError());
+  return LBM_AXI_OK;
+}
+
+template <typename S>
+int launch_init(lbm_axi* h, int inst, const float* dinit, float T_init) {
+  const dim3 blk(BX, BY);
+  const int4* tl = h->dtiles_plain + h->tile_first[inst];
+  if (dinit)
+    k_init<S><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->kz, dinit, inst);
+  else
+    k_init_uniform<S><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->kz, T_init, inst);
+  HIPCHK(hipGetLastError());
+  return LBM_AXI_OK;
+}
+
+int dispatch_step(lbm_axi* h, bool odd, int mode, int slot) {
+  switch (h->storage) {
+    case LBM_STORE_FP32: return launch_step<float>(h, odd, mode, slot);
+    case LBM_STORE_FP16: return launch_step<__half>(h, odd, mode, slot);
+    default: return launch_step<__hip_bfloat16>(h, odd, mode, slot);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void lbm_axi_default_params(lbm_axi_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->side_rmin = p->side_rmax = p->side_z = LBM_SIDE_WALL;
+  p->therm_rmin = p->therm_rmax = LBM_T_FIXED;
+  p->therm_z = LBM_T_ADIABATIC;
+  p->storage = LBM_STORE_FP32;
+  p->storage_shift = 0;
+  p->check_interval = 100;
+  p->r0 = 1.0;
+  p->L = 1.0;
+  p->phi = 1.0;
+  p->Da = 1e8;
+  p->J = p->lambda = p->sigma = 1.0;
+  p->Pr = 1.0;
+  p->Ma = 0.1;
+  p->s_e = p->s_eps = 1.1;
+  p->s_q = 1.2;
+  p->s_j = 1.0;
+}
+
+const char* lbm_axi_last_error(void) { return g_err.c_str(); }
+
+void lbm_axi_destroy(lbm_axi* h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  for (auto& e : h->ev) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  for (void* p : h->allocs) (void)hipFree(p);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+}
+
+int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* phi_field,
+                   const float* const* init_uzurT, void* hip_stream, lbm_axi** out) {
+  if (out) *out = nullptr;
+  if (!p || !out || n_inst < 1) return fail(LBM_AXI_EINVAL, "null argument or n_inst < 1");
+  for (int i = 0; i < n_inst; ++i) {
+    int rc = validate(p[i], i);
+    if (rc) return rc;
+    if (p[i].storage != p[0].storage)
+      return fail(LBM_AXI_EINVAL, "all instances must use the same storage");
+    if (p[i].check_interval != p[0].check_interval)
+      return fail(LBM_AXI_EINVAL, "all instances must use the same check_interval");
+    if (phi_field && phi_field[i]) {
+      if (!(p[i].phi > 0.0 && p[i].phi < 1.0))
+        return fail(LBM_AXI_EINVAL, "a porosity field needs a reference porosity in (0, 1)");
+      const int64_t n = (int64_t)p[i].nr * p[i].nz;
+      for (int64_t c = 0; c < n; ++c)
+        if (!(phi_field[i][c] > 0.0f && phi_field[i][c] < 1.0f))
+          return fail(LBM_AXI_EINVAL, "porosity field values must lie in (0, 1)");
+    }
+  }
+  lbm_axi* h = new lbm_axi();
+  h->n_inst = n_inst;
+  h->storage = p[0].storage;
+  h->check = p[0].check_interval;
+  h->prm.assign(p, p + n_inst);
+  auto bail = [&](int rc) {
+    lbm_axi_destroy(h);
+    return rc;
+  };
+#define HIPBAIL(call)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return bail(fail(LBM_AXI_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_))); \
+  } while (0)
+  if (hip_stream) {
+    h->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess)
+      return bail(fail(LBM_AXI_EDEVICE, "hipStreamCreate failed"));
+    h->own_stream = true;
+  }
+  const size_t esz = h->storage == LBM_STORE_FP32 ? 4 : 2;
+  hipError_t err = hipSuccess;
+  h->hdesc.resize(n_inst);
+  std::vector<int4> tiles;
+  const int tile_h = BY * h->kz;
+  for (int i = 0; i < n_inst; ++i) {
+    const lbm_axi_params& q = p[i];
+    InstDev& D = h->hdesc[i];
+    const bool field = phi_field && phi_field[i];
+    {
+      std::string msg;
+      const int rc = describe(q, field, D, msg);
+      if (rc) return bail(fail(rc, msg));
+    }
+    D.pop = dalloc(h, (size_t)14 * D.plane * esz, &err);
+    if (!D.pop) return bail(fail(LBM_AXI_ENOMEM, std::string("population array: ") + hipGetErrorString(err)));
+    if (field) {
+      float* dphi = (float*)dalloc(h, (size_t)D.plane * 4, &err);
+      if (!dphi) return bail(fail(LBM_AXI_ENOMEM, "porosity field"));
+      std::vector<float> pad((size_t)D.plane, q.phi);
+      for (int k = 0; k < q.nz; ++k)
+        std::memcpy(&pad[(size_t)k * D.stride], phi_field[i] + (size_t)k * q.nr, sizeof(float) * q.nr);
+      if (hipMemcpy(dphi, pad.data(), sizeof(float) * D.plane, hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(LBM_AXI_EDEVICE, "porosity field upload"));
+      D.phi = dphi;
+    }
+    if (h->check > 0) {
+      for (int s = 0; s < 2; ++s) {
+        D.mac[s] = (float*)dalloc(h, (size_t)3 * D.plane * 4, &err);
+        if (!D.mac[s]) return bail(fail(LBM_AXI_ENOMEM, "check buffers"));
+        if (hipMemset(D.mac[s], 0, (size_t)3 * D.plane * 4) != hipSuccess)
+          return bail(fail(LBM_AXI_EDEVICE, "check buffer clear"));
+      }
+    }
+    h->tile_first.push_back((int)tiles.size());
+    for (int k0 = 0; k0 < q.nz; k0 += tile_h)
+      for (int j0 = 0; j0 < q.nr; j0 += BX) tiles.push_back(make_int4(i, j0, k0, 0));
+    h->tile_count.push_back((int)tiles.size() - h->tile_first.back());
+  }
+  // XCD-aware order: block b -> tile (b % 8) * per + b / 8.
+  const int T = (int)tiles.size();
+  const int per = (T + 7) / 8;
+  std::vector<int4> order((size_t)per * 8, make_int4(-1, 0, 0, 0));
+  for (int b = 0; b < per * 8; ++b) {
+    const int t = (b % 8) * per + b / 8;
+    if (t < T) order[b] = tiles[t];
+  }
+  h->ntiles_launch = per * 8;
+  h->dtiles = (int4*)dalloc(h, sizeof(int4) * order.size(), &err);
+  h->dtiles_plain = (int4*)dalloc(h, sizeof(int4) * tiles.size(), &err);
+  h->ddesc = (InstDev*)dalloc(h, sizeof(InstDev) * n_inst, &err);
+  h->dstatus = (int*)dalloc(h, sizeof(int) * n_inst, &err);
+  h->dres = (DevResult*)dalloc(h, sizeof(DevResult) * n_inst, &err);
+  if (!h->dtiles || !h->dtiles_plain || !h->ddesc || !h->dstatus || !h->dres)
+    return bail(fail(LBM_AXI_ENOMEM, "descriptor arrays"));
+  HIPBAIL(hipMemcpy(h->dtiles, order.data(), sizeof(int4) * order.size(), hipMemcpyHostToDevice));
+  HIPBAIL(hipMemcpy(h->dtiles_plain, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice));
+  HIPBAIL(hipMemcpy(h->ddesc, h->hdesc.data(), sizeof(InstDev) * n_inst, hipMemcpyHostToDevice));
+  HIPBAIL(hipMemset(h->dstatus, 0, sizeof(int) * n_inst));
+  {
+    std::vector<DevResult> r0(n_inst);
+    for (auto& r : r0) {
+      r.res = r.res_u = r.res_T = HUGE_VAL;
+      r.nu_i = r.nu_o = r.u_rms = 0.0;
+      r.t_check = -1;
+      r.t_stop = -1;
+    }
+    HIPBAIL(hipMemcpy(h->dres, r0.data(), sizeof(DevResult) * n_inst, hipMemcpyHostToDevice));
+  }
+  // Reduction tiles: RZ rows per block.
+  if (h->check > 0) {
+    std::vector<ResTile> rts;
+    std::vector<int> first(2 * n_inst);
+    std::vector<double> tol(n_inst), nus(4 * n_inst);
+    std::vector<long long> mx(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+      const int nz = p[i].nz, nr = p[i].nr;
+      int rz = std::max(1, (int)((8192 + nr - 1) / nr));  // about 8k nodes per block
+      first[2 * i] = (int)rts.size();
+      for (int k0 = 0; k0 < nz; k0 += rz) rts.push_back(ResTile{i, k0, std::min(nz, k0 + rz), 0});
+      first[2 * i + 1] = (int)rts.size() - first[2 * i];
+      tol[i] = p[i].tol;
+      mx[i] = p[i].max_steps;
+      const double dT = p[i].delta_T != 0.0 ? p[i].delta_T : p[i].T_rmin - p[i].T_rmax;
+      const double H = nz - 1;
+      const bool walls = p[i].side_rmin == SIDE_WALL && p[i].side_rmax == SIDE_WALL && dT != 0.0 && H > 0;
+      nus[4 * i] = walls ? p[i].r0 / (H * dT) : 0.0;
+      nus[4 * i + 1] = (p[i].side_rmax == SIDE_WALL && dT != 0.0 && H > 0)
+                           ? (p[i].r0 + nr - 1) / (H * dT) : 0.0;
+      // residual scales: 1 / (Ma c_s) and 1 / |dT|
+      nus[4 * i + 2] = p[i].Ma > 0.0 ? 1.0 / (p[i].Ma * std::sqrt(1.0 / 3.0)) : 1.0;
+      nus[4 * i + 3] = dT != 0.0 ? 1.0 / std::fabs(dT) : 1.0;
+    }
+    h->nrt = (int)rts.size();
+    h->drt = (ResTile*)dalloc(h, sizeof(ResTile) * rts.size(), &err);
+    h->dpart = (double*)dalloc(h, sizeof(double) * 6 * rts.size(), &err);
+    h->dfirst = (int*)dalloc(h, sizeof(int) * first.size(), &err);
+    h->dtol = (double*)dalloc(h, sizeof(double) * n_inst, &err);
+    h->dnus = (double*)dalloc(h, sizeof(double) * 4 * n_inst, &err);
+    h->dmx = (long long*)dalloc(h, sizeof(long long) * n_inst, &err);
+    if (!h->drt || !h->dpart || !h->dfirst || !h->dtol || !h->dnus || !h->dmx)
+      return bail(fail(LBM_AXI_ENOMEM, "reduction arrays"));
+    HIPBAIL(hipMemcpy(h->drt, rts.data(), sizeof(ResTile) * rts.size(), hipMemcpyHostToDevice));
+    HIPBAIL(hipMemcpy(h->dfirst, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice));
+    HIPBAIL(hipMemcpy(h->dtol, tol.data(), sizeof(double) * n_inst, hipMemcpyHostToDevice));
+    HIPBAIL(hipMemcpy(h->dnus, nus.data(), sizeof(double) * 4 * n_inst, hipMemcpyHostToDevice));
+    HIPBAIL(hipMemcpy(h->dmx, mx.data(), sizeof(long long) * n_inst, hipMemcpyHostToDevice));
+  }
+  // Start state of every instance.
+  for (int i = 0; i < n_inst; ++i) {
+    float* dinit = nullptr;
+    if (init_uzurT && init_uzurT[i]) {
+      const size_t n = (size_t)p[i].nr * p[i].nz;
+      if (hipMalloc(&dinit, sizeof(float) * 3 * n) != hipSuccess)
+        return bail(fail(LBM_AXI_ENOMEM, "start-field staging"));
+      if (hipMemcpy(dinit, init_uzurT[i], sizeof(float) * 3 * n, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(dinit);
+        return bail(fail(LBM_AXI_EDEVICE, "start-field upload"));
+      }
+    }
+    int rc;
+    switch (h->storage) {
+      case LBM_STORE_FP32: rc = launch_init<float>(h, i, dinit, (float)p[i].T_init); break;
+      case LBM_STORE_FP16: rc = launch_init<__half>(h, i, dinit, (float)p[i].T_init); break;
+      default: rc = launch_init<__hip_bfloat16>(h, i, dinit, (float)p[i].T_init); break;
+    }
+    if (dinit) {
+      hipError_t e = hipStreamSynchronize(h->stream);
+      (void)hipFree(dinit);
+      if (e != hipSuccess) return bail(fail(LBM_AXI_EDEVICE, std::string("start state: ") + hipGetErrorString(e)));
+    }
+    if (rc) return bail(rc);
+  }
+  if (hipStreamSynchronize(h->stream) != hipSuccess)
+    return bail(fail(LBM_AXI_EDEVICE, "start state"));
+  *out = h;
+  return LBM_AXI_OK;
+#undef HIPBAIL
+}
+
+int lbm_axi_step(lbm_axi* h, int32_t nsteps) {
+  if (!h || nsteps < 0) return fail(LBM_AXI_EINVAL, "null handle or negative step count");
+  for (int32_t s = 0; s < nsteps; ++s) {
+    const long long n = h->t;
+    const bool odd = (n & 1) != 0;
+    int mode = MODE_STEP, slot = 0;
+    bool check = false;
+    if (h->check > 0) {
+      if ((n + 1) % h->check == 0) {  // the step before a check level
+        mode = MODE_STEP_MACRO;
+        slot = h->prev_slot;
+      } else if (n > 0 && n % h->check == 0) {  // a check level
+        mode = MODE_STEP_MACRO;
+        slot = 1 - h->prev_slot;
+        check = true;
+      }
+    }
+    if (h->timing) {
+      hipEvent_t e0, e1;
+      HIPCHK(hipEventCreate(&e0));
+      HIPCHK(hipEventCreate(&e1));
+      h->ev.emplace_back(e0, e1);
+      HIPCHK(hipEventRecord(e0, h->stream));
+    }
+    int rc = dispatch_step(h, odd, mode, slot);
+    if (rc) return rc;
+    if (h->timing) {
+      HIPCHK(hipEventRecord(h->ev.back().second, h->stream));
+      if (h->ev.size() >= 1024) {
+        double ms;
+        int64_t nl;
+        rc = lbm_axi_kernel_time(h, &ms, &nl);
+        if (rc) return rc;
+      }
+    }
+    if (check) {
+      k_resid<<<h->nrt, RB, 0, h->stream>>>(h->ddesc, h->drt, slot, h->dpart);
+      HIPCHK(hipGetLastError());
+      const int nb = (h->n_inst + 63) / 64;
+      k_final<<<nb, 64, 0, h->stream>>>(h->ddesc, h->dfirst, h->dpart, h->n_inst, n, h->dtol,
+                                         h->dmx, h->dnus, h->dstatus, h->dres);
+      HIPCHK(hipGetLastError());
+    }
+    h->t = n + 1;
+  }
+  return LBM_AXI_OK;
+}
+
+int lbm_axi_sync(lbm_axi* h) {
+  if (!h) return fail(LBM_AXI_EINVAL, "null handle");
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return LBM_AXI_OK;
+}
+
+int lbm_axi_residual(lbm_axi* h, double* res, double* nu_i, double* nu_o, int32_t* status) {
+  if (!h) return fail(LBM_AXI_EINVAL, "null handle");
+  std::vector<DevResult> r(h->n_inst);
+  std::vector<int> st(h->n_inst);
+  HIPCHK(hipMemcpyAsync(r.data(), h->dres, sizeof(DevResult) * h->n_inst, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(st.data(), h->dstatus, sizeof(int) * h->n_inst, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  for (int i = 0; i < h->n_inst; ++i) {
+    if (res) res[i] = r[i].res;
+    if (nu_i) nu_i[i] = r[i].nu_i;
+    if (nu_o) nu_o[i] = r[i].nu_o;
+    if (status) status[i] = st[i];
+  }
+  return LBM_AXI_OK;
+}
+
+int lbm_axi_info(lbm_axi* h, int32_t inst, int64_t* out) {
+  if (!h || !out || inst < 0 || inst >= h->n_inst) return fail(LBM_AXI_EINVAL, "bad handle, instance or output");
+  DevResult r;
+  int st = 0;
+  HIPCHK(hipMemcpyAsync(&r, h->dres + inst, sizeof(DevResult), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(&st, h->dstatus + inst, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  out[0] = st == RUN ? h->t : r.t_stop;
+  out[1] = r.t_check;
+  out[2] = st;
+  out[3] = (int64_t)h->bytes;
+  return LBM_AXI_OK;
+}
+
+int lbm_axi_macros(lbm_axi* h, int32_t inst, float* uz, float* ur, float* p, float* T,
+                   uint8_t* mask, int32_t dst_is_device) {
+  if (!h || inst < 0 || inst >= h->n_inst) return fail(LBM_AXI_EINVAL, "bad handle or instance");
+  int64_t info[4];
+  int rc = lbm_axi_info(h, inst, info);
+  if (rc) return rc;
+  const bool odd = (info[0] & 1) != 0;
+  const lbm_axi_params& q = h->prm[inst];
+  const size_t n = (size_t)q.nr * q.nz;
+  FieldOut fo{uz, ur, p, T, mask};
+  std::vector<void*> tmp;
+  if (!dst_is_device) {
+    float** fp[4] = {&fo.uz, &fo.ur, &fo.p, &fo.T};
+    for (float** f : fp)
+      if (*f) {
+        void* d = nullptr;
+        if (hipMalloc(&d, sizeof(float) * n) != hipSuccess) {
+          for (void* x : tmp) (void)hipFree(x);
+          return fail(LBM_AXI_ENOMEM, "field staging");
+        }
+        tmp.push_back(d);
+        *f = (float*)d;
+      }
+    if (fo.mask) {
+      void* d = nullptr;
+      if (hipMalloc(&d, n) != hipSuccess) {
+        for (void* x : tmp) (void)hipFree(x);
+        return fail(LBM_AXI_ENOMEM, "mask staging");
+      }
+      tmp.push_back(d);
+      fo.mask = (uint8_t*)d;
+    }
+  }
+  switch (h->storage) {
+    case LBM_STORE_FP32: rc = launch_fields<float>(h, inst, odd, fo); break;
+    case LBM_STORE_FP16: rc = launch_fields<__half>(h, inst, odd, fo); break;
+    default: rc = launch_fields<__hip_bfloat16>(h, inst, odd, fo); break;
+  }
+  if (!rc && !dst_is_device) {
+    hipError_t e = hipSuccess;
+    if (uz && e == hipSuccess) e = hipMemcpyAsync(uz, fo.uz, sizeof(float) * n, hipMemcpyDeviceToHost, h->stream);
+    if (ur && e == hipSuccess) e = hipMemcpyAsync(ur, fo.ur, sizeof(float) * n, hipMemcpyDeviceToHost, h->stream);
+    if (p && e == hipSuccess) e = hipMemcpyAsync(p, fo.p, sizeof(float) * n, hipMemcpyDeviceToHost, h->stream);
+    if (T && e == hipSuccess) e = hipMemcpyAsync(T, fo.T, sizeof(float) * n, hipMemcpyDeviceToHost, h->stream);
+    if (mask && e == hipSuccess) e = hipMemcpyAsync(mask, fo.mask, n, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) rc = fail(LBM_AXI_EDEVICE, std::string("field download: ") + hipGetErrorString(e));
+  }
+  for (void* x : tmp) (void)hipFree(x);
+  return rc;
+}
+
+int lbm_axi_set_timing(lbm_axi* h, int32_t on) {
+  if (!h) return fail(LBM_AXI_EINVAL, "null handle");
+  if (on && !h->timing) {
+    double ms;
+    int64_t nl;
+    int rc = lbm_axi_kernel_time(h, &ms, &nl);
+    if (rc) return rc;
+    h->timed_ms = 0.0;
+    h->timed_launches = 0;
+  }
+  h->timing = on != 0;
+  return LBM_AXI_OK;
+}
+
+int lbm_axi_kernel_time(lbm_axi* h, double* total_ms, int64_t* launches) {
+  if (!h) return fail(LBM_AXI_EINVAL, "null handle");
+  if (!h->ev.empty()) {
+    HIPCHK(hipEventSynchronize(h->ev.back().second));
+    for (auto& e : h->ev) {
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, e.first, e.second));
+      h->timed_ms += ms;
+      h->timed_launches += 1;
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    h->ev.clear();
+  }
+  if (total_ms) *total_ms = h->timed_ms;
+  if (launches) *launches = h->timed_launches;
+  return LBM_AXI_OK;
+}
+
+}  // extern "C"

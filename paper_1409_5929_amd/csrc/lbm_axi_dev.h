@@ -1,0 +1,596 @@
+// Per-node update of the axisymmetric D2Q9-MRT / D2Q5 lattice Boltzmann step
+// (Liu, He, Li, arXiv:1409.5929, Secs. 3.1-3.2), shared by the step, start
+// and field kernels of lbm_axi.hip.
+//
+// Storage.  One array of 14 planes per instance (f_0..f_8, then g_0..g_4),
+// each plane [nz][stride] with r fastest, updated in place with the AA
+// pattern: at even time levels the slot (i, x) holds the population f_i that
+// has arrived at x; an even step reads a node's own slots and writes f_i^+ to
+// its own slot opposite(i); an odd step reads f_i from slot opposite(i) of
+// x - e_i and writes f_i^+ to slot i of x + e_i.  Every thread writes exactly
+// the slots it read, so the update needs no second array and no barrier.
+//
+// Values.  The populations are r-weighted (Eq. 17, Eq. 26): f_i = r fhat_i.
+// A slot holds the deviation s_i = fhat_i - w_i (rest state rho = 1) in the
+// frame of the node that wrote it (the source x - e_i of an arriving
+// population).  The reader rescales to its own radius, fhat_i(x) =
+// (r_src / r)(w_i + s_i), so FP32 keeps its relative precision at any r and
+// the same representation serves FP16/BF16 storage (times a power of two).
+// Temperature slots hold g_i - wt_i T_s for a storage shift T_s.
+//
+// Axis.  With an axis at r_min the mirror row j = -1 is never stored: its
+// slot q at (-1, k) is the slot q* (e_r reversed) of (0, k).  In the writer's
+// frame the odd mirror f_i(-r) = -f_i*(r) of the r-weighted populations is
+// the plain copy fhat_i(-r) = fhat_i*(r), so the alias needs no arithmetic;
+// the reader's rescaling with r_src = -1/2 restores the sign.
+//
+// Walls.  Wall nodes (rows 0 / nr-1, columns 0 / nz-1) are reconstructed by
+// non-equilibrium extrapolation (Sec. 4) from a fluid neighbour B that owns
+// them (normal neighbour; diagonal one for corners).  B's thread computes the
+// wall node's post-collision populations from its own registers and writes
+// the ones that stream into fluid nodes to the AA slots the wall node would
+// have written.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbmaxi {
+
+enum { SIDE_WALL = 0, SIDE_AXIS = 1, SIDE_PERIODIC = 2 };
+enum { THERM_FIXED = 0, THERM_ADIABATIC = 1 };
+enum { RUN = 0, CONVERGED = 1, DIVERGED = 2, STALLED = 3 };
+enum { MODE_STEP = 0, MODE_STEP_MACRO = 1, MODE_FIELDS = 2 };
+enum { MASK_RMIN = 1, MASK_RMAX = 2, MASK_ZMIN = 4, MASK_ZMAX = 8, MASK_AXIS = 16 };
+
+// c_s^2 of D2Q9 (text after Eq. 25); weights of Eq. (32); D2Q5 weights of
+// Eq. (36) with wt_0 = 3/5 and c_sT^2 = 1/5.
+constexpr float CS2 = (float)(1.0 / 3.0);
+constexpr float W0 = (float)(4.0 / 9.0), W1 = (float)(1.0 / 9.0), W5 = (float)(1.0 / 36.0);
+constexpr float WT0 = (float)0.6, WT1 = (float)0.1;
+
+// Everything a kernel needs about one instance (uniform across a block, so
+// the compiler keeps it in scalar registers).
+struct InstDev {
+  int32_t nr, nz, stride, pad0;
+  int64_t plane;  // stride * nz
+  int32_t side_rmin, side_rmax, side_z;
+  int32_t therm_rmin, therm_rmax, therm_z;
+  int32_t src_printed;
+  int32_t phi_mode;  // 0 uniform, 1 field with Ergun F_phi, 2 field with constant F_phi
+  void* pop;         // 14 planes
+  const float* phi;  // [nz][stride] porosity field or null
+  float* mac[2];     // two check buffers, 3 planes each: u_z, u_r, T
+  float r0, T_ref, gbeta, accel_r, accel_z;
+  float T_s;          // temperature storage shift
+  float az_s;         // accel_z + gbeta (T_s - T_ref): buoyancy offset in theta = T - T_s
+  float c_tau;        // c_s^2 (tau_nu - 1/2)
+  float s_e, s_eps, s_j, s_q, s_nu;  // rates of Eq. (23)
+  float phiu, cD, cF; // uniform porosity, phi nu / K, phi F_phi / sqrt(K)
+  float C1, C2, C3;   // porosity-field coefficients of cD and cF
+  float tau_T, omc;   // omc = 1 / (tau_T + 1/2)
+  float T_rmin, T_rmax, T_zmin, T_zmax;
+  float st_scale, st_inv;  // storage scale 2^shift and its inverse
+};
+
+// Optional outputs of the field kernel ([nz][nr], unpadded).
+struct FieldOut {
+  float *uz, *ur, *p, *T;
+  uint8_t* mask;
+};
+
+// ---- storage types --------------------------------------------------------
+template <typename S>
+struct Store;
+template <>
+struct Store<float> {
+  __host__ __device__ static inline float ld(const float* p, int64_t i, float) { return p[i]; }
+  __host__ __device__ static inline void st(float* p, int64_t i, float v, float) { p[i] = v; }
+};
+template <>
+struct Store<__half> {
+  __host__ __device__ static inline float ld(const __half* p, int64_t i, float inv) {
+    return __half2float(p[i]) * inv;
+  }
+  __host__ __device__ static inline void st(__half* p, int64_t i, float v, float sc) {
+    p[i] = __float2half_rn(v * sc);
+  }
+};
+template <>
+struct Store<__hip_bfloat16> {
+  __host__ __device__ static inline float ld(const __hip_bfloat16* p, int64_t i, float inv) {
+    return __bfloat162float(p[i]) * inv;
+  }
+  __host__ __device__ static inline void st(__hip_bfloat16* p, int64_t i, float v, float sc) {
+    p[i] = __float2bfloat16(v * sc);
+  }
+};
+
+// ---- per-column constants (r is fixed along a thread's z loop) -------------
+struct RowC {
+  float r, inv_r;
+  float rp, op1, op5;  // sources at r - 1 (e_r = +1): ratio r_src / r, w (ratio - 1)
+  float rm, om1, om5;  // sources at r + 1 (e_r = -1)
+  float lr0b;          // (1 + c_s^2 (tau - 1/2) / r^2) / 2, Eq. (30) divided by r
+  float hcs2r;         // c_s^2 / (2 r), Eq. (29) divided by r rho
+  float ar0, ar1;      // a_r = ar0 - ar1 u_r, Eq. (25)
+  float omT1, omT3;    // D2Q5 rates for e_r = +1, -1 (after Eq. 33)
+  int cm, cp;          // column of x - e_r for e_r = +1 / -1 sources (after wrap or alias)
+  bool mir;            // x - (1, 0) is the axis mirror row
+};
+
+__host__ __device__ inline RowC make_row(const InstDev& D, int j) {
+  RowC R;
+  const double r = (double)D.r0 + j;
+  const double inv = 1.0 / r;
+  const bool rper = D.side_rmin == SIDE_PERIODIC;
+  R.cm = j - 1;
+  R.cp = j + 1;
+  R.mir = false;
+  double src_p = r - 1.0, src_m = r + 1.0;
+  if (j == 0) {
+    if (D.side_rmin == SIDE_AXIS) {
+      R.cm = 0;
+      R.mir = true;  // source radius r - 1 = -1/2 is the mirror row itself
+    } else if (rper) {
+      R.cm = D.nr - 1;
+      src_p = (double)D.r0 + (D.nr - 1);
+    }
+  }
+  if (j == D.nr - 1 && rper) {
+    R.cp = 0;
+    src_m = (double)D.r0;
+  }
+  R.r = (float)r;
+  R.inv_r = (float)inv;
+  R.rp = (float)(src_p * inv);
+  R.op1 = (float)((1.0 / 9.0) * (src_p - r) * inv);
+  R.op5 = (float)((1.0 / 36.0) * (src_p - r) * inv);
+  R.rm = (float)(src_m * inv);
+  R.om1 = (float)((1.0 / 9.0) * (src_m - r) * inv);
+  R.om5 = (float)((1.0 / 36.0) * (src_m - r) * inv);
+  R.lr0b = (float)(0.5 * (1.0 + (double)D.c_tau * inv * inv));
+  R.hcs2r = (float)(0.5 / 3.0 * inv);
+  R.ar0 = (float)(inv / 3.0);
+  R.ar1 = (float)(2.0 * (double)D.c_tau * inv * inv);
+  R.omT1 = (float)((double)D.omc * (1.0 + (double)D.tau_T * inv));
+  R.omT3 = (float)((double)D.omc * (1.0 - (double)D.tau_T * inv));
+  return R;
+}
+
+__host__ __device__ inline bool is_boundary(const InstDev& D, int j, int k) {
+  return (D.side_rmin == SIDE_WALL && j == 0) || (D.side_rmax == SIDE_WALL && j == D.nr - 1) ||
+         (D.side_z == SIDE_WALL && (k == 0 || k == D.nz - 1));
+}
+
+__host__ __device__ inline uint8_t node_mask(const InstDev& D, int j, int k) {
+  uint8_t m = 0;
+  if (D.side_rmin == SIDE_WALL && j == 0) m |= MASK_RMIN;
+  if (D.side_rmax == SIDE_WALL && j == D.nr - 1) m |= MASK_RMAX;
+  if (D.side_z == SIDE_WALL && k == 0) m |= MASK_ZMIN;
+  if (D.side_z == SIDE_WALL && k == D.nz - 1) m |= MASK_ZMAX;
+  if (D.side_rmin == SIDE_AXIS && j == 0) m |= MASK_AXIS;
+  return m;
+}
+
+// Porosity, phi nu / K and phi F_phi / sqrt(K) at a node (Eqs. 6, 8).
+__host__ __device__ inline void porosity(const InstDev& D, int64_t o, float& phi, float& cD,
+                                         float& cF) {
+  if (D.phi_mode == 0) {
+    phi = D.phiu;
+    cD = D.cD;
+    cF = D.cF;
+  } else {
+    phi = D.phi[o];
+    const float q = (1.0f - phi) / phi;
+    cD = D.C1 * q * q;
+    cF = D.phi_mode == 1 ? D.C2 * q / phi : D.C3 * (1.0f - phi) / sqrtf(phi);
+  }
+}
+
+// delta += M^{-1} X for moment increments X_1..X_8 (X_0 = 0); M^{-1} = M^T
+// diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4), M of Eq. (18).
+__host__ __device__ inline void back_transform(float d[9], float X1, float X2, float X3, float X4,
+                                               float X5, float X6, float X7, float X8) {
+  const float a1 = X1 * (float)(1.0 / 36.0), a2 = X2 * (float)(1.0 / 36.0);
+  const float a3 = X3 * (float)(1.0 / 6.0), a4 = X4 * (float)(1.0 / 12.0);
+  const float a5 = X5 * (float)(1.0 / 6.0), a6 = X6 * (float)(1.0 / 12.0);
+  const float a7 = X7 * 0.25f, a8 = X8 * 0.25f;
+  const float e = -a1 - 2.0f * a2;      // common part of directions 1-4
+  const float c = 2.0f * a1 + a2;       // common part of directions 5-8
+  const float pr = a3 + a4, pz = a5 + a6;
+  d[0] += -4.0f * a1 + 4.0f * a2;
+  d[1] += e + a3 - 2.0f * a4 + a7;
+  d[2] += e + a5 - 2.0f * a6 - a7;
+  d[3] += e - a3 + 2.0f * a4 + a7;
+  d[4] += e - a5 + 2.0f * a6 - a7;
+  d[5] += c + pr + pz + a8;
+  d[6] += c - pr + pz - a8;
+  d[7] += c - pr - pz + a8;
+  d[8] += c + pr - pz - a8;
+}
+
+// Moment-space source S / r of Eq. (24) with F~ = (F_r + a_r, F_z) (Eq. 25);
+// unless printed, the a_r part is not divided by phi (see the header).
+__host__ __device__ inline void source(bool printed, float rho, float ur, float uz, float iphi,
+                                       float Fr, float Fz, float ar, float& S1, float& S7,
+                                       float& S8) {
+  if (printed) {
+    const float Ftr = Fr + ar;
+    S1 = 6.0f * rho * (ur * Ftr + uz * Fz) * iphi;
+    S7 = 2.0f * rho * (ur * Ftr - uz * Fz) * iphi;
+    S8 = rho * (ur * Fz + uz * Ftr) * iphi;
+  } else {
+    S1 = 6.0f * rho * ((ur * Fr + uz * Fz) * iphi + ur * ar);
+    S7 = 2.0f * rho * ((ur * Fr - uz * Fz) * iphi + ur * ar);
+    S8 = rho * ((ur * Fz + uz * Fr) * iphi + uz * ar);
+  }
+}
+
+__host__ __device__ inline bool fluid_dest(const InstDev& D, int j, int& k) {
+  if (j < 0 || j >= D.nr) return false;
+  if (D.side_z == SIDE_PERIODIC) {
+    if (k < 0) k += D.nz;
+    if (k >= D.nz) k -= D.nz;
+  } else if (k < 0 || k >= D.nz) {
+    return false;
+  }
+  return !is_boundary(D, j, k);
+}
+
+// Fluid-node state kept for the wall nodes a thread owns.
+struct NodeState {
+  float drho, rho, ur, uz, theta, T;
+  float n1, n2, n3, n4, n5, n6, n7, n8;  // non-equilibrium moments / r
+  float t[5];                            // stored temperature slots
+};
+
+template <typename S, bool ODD>
+__host__ __device__ inline void store_wall(const InstDev& D, S* P, int jb, int kb, const float d[9],
+                                           const float tg[5]) {
+  constexpr int EXr[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  constexpr int EZr[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+  const int64_t pl = D.plane;
+  for (int i = 1; i < 9; ++i) {
+    int kd = kb + EZr[i];
+    if (!fluid_dest(D, jb + EXr[i], kd)) continue;
+    if (ODD)
+      Store<S>::st(P, i * pl + (int64_t)kd * D.stride + jb + EXr[i], d[i], D.st_scale);
+    else
+      Store<S>::st(P, OPP[i] * pl + (int64_t)kb * D.stride + jb, d[i], D.st_scale);
+  }
+  for (int i = 1; i < 5; ++i) {
+    int kd = kb + EZr[i];
+    if (!fluid_dest(D, jb + EXr[i], kd)) continue;
+    if (ODD)
+      Store<S>::st(P, (9 + i) * pl + (int64_t)kd * D.stride + jb + EXr[i], tg[i], D.st_scale);
+    else
+      Store<S>::st(P, (9 + OPP[i]) * pl + (int64_t)kb * D.stride + jb, tg[i], D.st_scale);
+  }
+}
+
+// Wall node b = x + (dr, dz) owned by fluid node x (non-equilibrium
+// extrapolation, Sec. 4): imposed rho_B, u = 0, wall temperature.
+template <typename S, bool ODD, int MODE>
+__host__ __device__ inline void wall_node(const InstDev& D, S* P, const NodeState& B, float rB,
+                                          int j, int k, int dr, int dz, int mac_slot,
+                                          const FieldOut& fo) {
+  const int jb = j + dr, kb = k + dz;
+  const float rb = rB + (float)dr;
+  const float inv_rb = 1.0f / rb;
+  const int64_t ob = (int64_t)kb * D.stride + jb;
+  const float phib = D.phi_mode == 0 ? D.phiu : D.phi[ob];
+  const uint8_t m = node_mask(D, jb, kb);
+  float Tb = B.T;
+  if ((m & MASK_RMIN) && D.therm_rmin == THERM_FIXED) Tb = D.T_rmin;
+  else if ((m & MASK_RMAX) && D.therm_rmax == THERM_FIXED) Tb = D.T_rmax;
+  else if ((m & MASK_ZMIN) && D.therm_z == THERM_FIXED) Tb = D.T_zmin;
+  else if ((m & MASK_ZMAX) && D.therm_z == THERM_FIXED) Tb = D.T_zmax;
+
+  if (MODE != MODE_FIELDS) {
+    // Flow: m+(b) = m^eq(b) + (I - L)(r_B / r_b) n(B) + (I - L/2) S(b), all / r_b.
+    const float Gz = D.gbeta * (Tb - D.T_ref) + D.accel_z;
+    const float Frb = phib * D.accel_r, Fzb = phib * Gz;
+    const float S3 = B.rho * (Frb + CS2 * inv_rb), S5 = B.rho * Fzb;
+    const float q = rB * inv_rb;
+    float d[9];
+    d[0] = W0 * B.drho;
+    d[1] = d[2] = d[3] = d[4] = W1 * B.drho;
+    d[5] = d[6] = d[7] = d[8] = W5 * B.drho;
+    back_transform(d, (1.0f - D.s_e) * q * B.n1, (1.0f - D.s_eps) * q * B.n2,
+                   (1.0f - D.s_j) * q * B.n3 + (1.0f - 0.5f * D.s_j) * S3,
+                   (1.0f - D.s_q) * q * B.n4 - (1.0f - 0.5f * D.s_q) * S3,
+                   (1.0f - D.s_j) * q * B.n5 + (1.0f - 0.5f * D.s_j) * S5,
+                   (1.0f - D.s_q) * q * B.n6 - (1.0f - 0.5f * D.s_q) * S5,
+                   (1.0f - D.s_nu) * q * B.n7, (1.0f - D.s_nu) * q * B.n8);
+    // Temperature: g+(b) = g^eq(T_b, 0) + (1 - omega_i(r_b)) g^neq(B).
+    const float eu[5] = {0.0f, B.ur, B.uz, -B.ur, -B.uz};
+    const float wt[5] = {WT0, WT1, WT1, WT1, WT1};
+    const float tb1 = D.tau_T * inv_rb;
+    const float om[5] = {D.omc, D.omc * (1.0f + tb1), D.omc, D.omc * (1.0f - tb1), D.omc};
+    float tg[5];
+    float qn[5];
+    for (int i = 1; i < 5; ++i) qn[i] = B.t[i] - wt[i] * B.theta;
+    qn[0] = -((qn[1] + qn[3]) + (qn[2] + qn[4]));
+    for (int i = 0; i < 5; ++i) {
+      const float gneq = qn[i] - 5.0f * wt[i] * B.T * eu[i];
+      tg[i] = wt[i] * (Tb - D.T_s) + (1.0f - om[i]) * gneq;
+    }
+    store_wall<S, ODD>(D, P, jb, kb, d, tg);
+  }
+  if (MODE == MODE_STEP_MACRO) {
+    float* mac = D.mac[mac_slot];
+    mac[ob] = 0.0f;
+    mac[D.plane + ob] = 0.0f;
+    mac[2 * D.plane + ob] = Tb;
+  }
+  if (MODE == MODE_FIELDS) {
+    const int64_t o = (int64_t)kb * D.nr + jb;
+    if (fo.uz) fo.uz[o] = 0.0f;
+    if (fo.ur) fo.ur[o] = 0.0f;
+    if (fo.p) fo.p[o] = B.rho * CS2 / phib;
+    if (fo.T) fo.T[o] = Tb;
+    if (fo.mask) fo.mask[o] = m;
+  }
+}
+
+// One fluid node (j, k) at one time step.
+template <typename S, bool ODD, int MODE>
+__host__ __device__ inline void node_update(const InstDev& D, const RowC& R, int j, int k,
+                                            int mac_slot, const FieldOut& fo) {
+  S* __restrict__ P = (S*)D.pop;
+  const int64_t pl = D.plane;
+  const int st = D.stride;
+  const float inv_sc = D.st_inv, sc = D.st_scale;
+  int km = k - 1, kp = k + 1;
+  if (D.side_z == SIDE_PERIODIC) {
+    if (km < 0) km += D.nz;
+    if (kp >= D.nz) kp -= D.nz;
+  }
+  const int64_t o = (int64_t)k * st + j;
+  const int64_t rowm = (int64_t)km * st, row0 = (int64_t)k * st, rowp = (int64_t)kp * st;
+
+  // ---- a1: load the populations arriving at x --------------------------------
+  float s[9], t[5];
+  if (!ODD) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) s[q] = Store<S>::ld(P, q * pl + o, inv_sc);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) t[q] = Store<S>::ld(P, (9 + q) * pl + o, inv_sc);
+  } else {
+    const int64_t cm = R.cm, cp = R.cp;
+    s[0] = Store<S>::ld(P, o, inv_sc);
+    s[1] = Store<S>::ld(P, (R.mir ? 1 : 3) * pl + row0 + cm, inv_sc);
+    s[2] = Store<S>::ld(P, 4 * pl + rowm + j, inv_sc);
+    s[3] = Store<S>::ld(P, 1 * pl + row0 + cp, inv_sc);
+    s[4] = Store<S>::ld(P, 2 * pl + rowp + j, inv_sc);
+    s[5] = Store<S>::ld(P, (R.mir ? 8 : 7) * pl + rowm + cm, inv_sc);
+    s[6] = Store<S>::ld(P, 8 * pl + rowm + cp, inv_sc);
+    s[7] = Store<S>::ld(P, 5 * pl + rowp + cp, inv_sc);
+    s[8] = Store<S>::ld(P, (R.mir ? 5 : 6) * pl + rowp + cm, inv_sc);
+    t[0] = Store<S>::ld(P, 9 * pl + o, inv_sc);
+    t[1] = Store<S>::ld(P, (R.mir ? 10 : 12) * pl + row0 + cm, inv_sc);
+    t[2] = Store<S>::ld(P, 13 * pl + rowm + j, inv_sc);
+    t[3] = Store<S>::ld(P, 10 * pl + row0 + cp, inv_sc);
+    t[4] = Store<S>::ld(P, 11 * pl + rowp + j, inv_sc);
+  }
+  float phi, cD, cF;
+  porosity(D, o, phi, cD, cF);
+
+  // Rescale to this node's frame: d_i = fhat_i - w_i.
+  float d[9];
+  d[0] = s[0];
+  d[2] = s[2];
+  d[4] = s[4];
+  d[1] = s[1] * R.rp + R.op1;
+  d[5] = s[5] * R.rp + R.op5;
+  d[8] = s[8] * R.rp + R.op5;
+  d[3] = s[3] * R.rm + R.om1;
+  d[6] = s[6] * R.rm + R.om5;
+  d[7] = s[7] * R.rm + R.om5;
+
+  // ---- a2: macroscopic values ------------------------------------------------
+  NodeState B;
+  const float sa = d[1] + d[2] + d[3] + d[4], sd = d[5] + d[6] + d[7] + d[8];
+  B.drho = d[0] + sa + sd;                                  // rho - 1, Eq. (26)
+  B.rho = 1.0f + B.drho;
+  const float inv_rho = 1.0f / B.rho;
+  const float Jr = d[1] - d[3] + d[5] - d[6] - d[7] + d[8];  // sum e_r f / r
+  const float Jz = d[2] - d[4] + d[5] + d[6] - d[7] - d[8];
+  B.theta = t[0] + t[1] + t[2] + t[3] + t[4];               // T - T_s, Eq. (38)
+  B.T = D.T_s + B.theta;
+  const float Gr = D.accel_r;
+  const float Gz = D.gbeta * B.theta + D.az_s;              // Eq. (7)
+  const float vr = Jr * inv_rho + R.hcs2r + 0.5f * phi * Gr;  // Eq. (29) / r
+  const float vz = Jz * inv_rho + 0.5f * phi * Gz;
+  const float lr0 = R.lr0b + 0.25f * cD;                    // Eq. (30) / r
+  const float lz0 = 0.5f + 0.25f * cD;
+  const float l1 = 0.5f * cF;
+  const float vm = sqrtf(vr * vr + vz * vz);
+  B.ur = vr / (lr0 + sqrtf(lr0 * lr0 + l1 * vm));           // Eq. (28)
+  B.uz = vz / (lz0 + sqrtf(lz0 * lz0 + l1 * vm));
+  const float ur = B.ur, uz = B.uz, rho = B.rho;
+
+  if (MODE == MODE_STEP_MACRO) {
+    float* mac = D.mac[mac_slot];
+    mac[o] = uz;
+    mac[pl + o] = ur;
+    mac[2 * pl + o] = B.T;
+  }
+  if (MODE == MODE_FIELDS) {
+    const int64_t oo = (int64_t)k * D.nr + j;
+    if (fo.uz) fo.uz[oo] = uz;
+    if (fo.ur) fo.ur[oo] = ur;
+    if (fo.p) fo.p[oo] = rho * CS2 / phi;
+    if (fo.T) fo.T[oo] = B.T;
+    if (fo.mask) fo.mask[oo] = node_mask(D, j, k);
+  }
+
+  // ---- a3: forces (Eq. 6) and the axisymmetric correction (Eq. 25) -----------
+  const float um = sqrtf(ur * ur + uz * uz);
+  const float drag = cD + cF * um;
+  const float Fr = phi * Gr - drag * ur;
+  const float Fz = phi * Gz - drag * uz;
+  const float ar = R.ar0 - R.ar1 * ur;
+
+  // ---- a4: moments of d and the non-equilibrium part (Eqs. 16-20) -----------
+  const float iphi = 1.0f / phi;
+  const float ru2 = rho * (ur * ur + uz * uz) * iphi;
+  B.n1 = (-4.0f * d[0] - sa + 2.0f * sd) + 2.0f * B.drho - 3.0f * ru2;
+  B.n2 = (4.0f * d[0] - 2.0f * sa + sd) - B.drho + 3.0f * ru2;
+  B.n3 = Jr - rho * ur;
+  B.n4 = (-2.0f * d[1] + 2.0f * d[3] + d[5] - d[6] - d[7] + d[8]) + rho * ur;
+  B.n5 = Jz - rho * uz;
+  B.n6 = (-2.0f * d[2] + 2.0f * d[4] + d[5] + d[6] - d[7] - d[8]) + rho * uz;
+  B.n7 = (d[1] - d[2] + d[3] - d[4]) - rho * (ur * ur - uz * uz) * iphi;
+  B.n8 = (d[5] - d[6] + d[7] - d[8]) - rho * ur * uz * iphi;
+
+  if (MODE != MODE_FIELDS) {
+    // ---- a5: source (Eq. 24) and relaxation (Eq. 21) --------------------------
+    float S1, S7, S8;
+    source(D.src_printed != 0, rho, ur, uz, iphi, Fr, Fz, ar, S1, S7, S8);
+    const float S3 = rho * (Fr + ar), S5 = rho * Fz;
+    // ---- a6: back-transform (Eq. 22) ------------------------------------------
+    back_transform(d, -D.s_e * B.n1 + (1.0f - 0.5f * D.s_e) * S1,
+                   -D.s_eps * B.n2 - (1.0f - 0.5f * D.s_eps) * S1,
+                   -D.s_j * B.n3 + (1.0f - 0.5f * D.s_j) * S3,
+                   -D.s_q * B.n4 - (1.0f - 0.5f * D.s_q) * S3,
+                   -D.s_j * B.n5 + (1.0f - 0.5f * D.s_j) * S5,
+                   -D.s_q * B.n6 - (1.0f - 0.5f * D.s_q) * S5,
+                   -D.s_nu * B.n7 + (1.0f - 0.5f * D.s_nu) * S7,
+                   -D.s_nu * B.n8 + (1.0f - 0.5f * D.s_nu) * S8);
+
+    // ---- a7: temperature collision (Eqs. 33-37) ------------------------------
+    // q_i = g_i - wt_i T is the part of g - g^eq that does not depend on u;
+    // q_0 is formed as -(q_1 + ... + q_4) so that the rounding of theta and of
+    // the FP32 weights cannot leak into sum_i g_i step after step.
+    const float Tn = B.T;
+    const float wT0 = WT0 * Tn, wT1 = WT1 * Tn;
+    const float psi = -ur * R.inv_r;
+    float tg[5];
+    {
+      const float e1 = 5.0f * ur, e2 = 5.0f * uz;
+      const float q1 = t[1] - WT1 * B.theta, q2 = t[2] - WT1 * B.theta;
+      const float q3 = t[3] - WT1 * B.theta, q4 = t[4] - WT1 * B.theta;
+      const float q0 = -((q1 + q3) + (q2 + q4));
+      tg[0] = t[0] - D.omc * q0 + psi * wT0;
+      tg[1] = t[1] - R.omT1 * (q1 - wT1 * e1) + psi * wT1 * (1.0f + e1);
+      tg[2] = t[2] - D.omc * (q2 - wT1 * e2) + psi * wT1 * (1.0f + e2);
+      tg[3] = t[3] - R.omT3 * (q3 + wT1 * e1) + psi * wT1 * (1.0f - e1);
+      tg[4] = t[4] - D.omc * (q4 + wT1 * e2) + psi * wT1 * (1.0f - e2);
+    }
+    for (int q = 0; q < 5; ++q) B.t[q] = t[q];
+
+    // ---- a9: stream and store --------------------------------------------------
+    if (!ODD) {
+      Store<S>::st(P, 0 * pl + o, d[0], sc);
+      Store<S>::st(P, 3 * pl + o, d[1], sc);
+      Store<S>::st(P, 4 * pl + o, d[2], sc);
+      Store<S>::st(P, 1 * pl + o, d[3], sc);
+      Store<S>::st(P, 2 * pl + o, d[4], sc);
+      Store<S>::st(P, 7 * pl + o, d[5], sc);
+      Store<S>::st(P, 8 * pl + o, d[6], sc);
+      Store<S>::st(P, 5 * pl + o, d[7], sc);
+      Store<S>::st(P, 6 * pl + o, d[8], sc);
+      Store<S>::st(P, 9 * pl + o, tg[0], sc);
+      Store<S>::st(P, 12 * pl + o, tg[1], sc);
+      Store<S>::st(P, 13 * pl + o, tg[2], sc);
+      Store<S>::st(P, 10 * pl + o, tg[3], sc);
+      Store<S>::st(P, 11 * pl + o, tg[4], sc);
+    } else {
+      const int64_t cm = R.cm, cp = R.cp;
+      Store<S>::st(P, o, d[0], sc);
+      Store<S>::st(P, 1 * pl + row0 + cp, d[1], sc);
+      Store<S>::st(P, 2 * pl + rowp + j, d[2], sc);
+      Store<S>::st(P, (R.mir ? 1 : 3) * pl + row0 + cm, d[3], sc);
+      Store<S>::st(P, 4 * pl + rowm + j, d[4], sc);
+      Store<S>::st(P, 5 * pl + rowp + cp, d[5], sc);
+      Store<S>::st(P, (R.mir ? 5 : 6) * pl + rowp + cm, d[6], sc);
+      Store<S>::st(P, (R.mir ? 8 : 7) * pl + rowm + cm, d[7], sc);
+      Store<S>::st(P, 8 * pl + rowm + cp, d[8], sc);
+      Store<S>::st(P, 9 * pl + o, tg[0], sc);
+      Store<S>::st(P, 10 * pl + row0 + cp, tg[1], sc);
+      Store<S>::st(P, 11 * pl + rowp + j, tg[2], sc);
+      Store<S>::st(P, (R.mir ? 10 : 12) * pl + row0 + cm, tg[3], sc);
+      Store<S>::st(P, 13 * pl + rowm + j, tg[4], sc);
+    }
+  } else {
+    for (int q = 0; q < 5; ++q) B.t[q] = t[q];
+  }
+
+  // ---- a8: wall nodes owned by this node ---------------------------------------
+  const bool own_rm = D.side_rmin == SIDE_WALL && j == 1;
+  const bool own_rp = D.side_rmax == SIDE_WALL && j == D.nr - 2;
+  const bool own_zm = D.side_z == SIDE_WALL && k == 1;
+  const bool own_zp = D.side_z == SIDE_WALL && k == D.nz - 2;
+  if (own_rm || own_rp || own_zm || own_zp) {
+    for (int dr = -1; dr <= 1; ++dr) {
+      if ((dr == -1 && !own_rm) || (dr == 1 && !own_rp)) continue;
+      for (int dz = -1; dz <= 1; ++dz) {
+        if (dr == 0 && dz == 0) continue;
+        if ((dz == -1 && !own_zm) || (dz == 1 && !own_zp)) continue;
+        wall_node<S, ODD, MODE>(D, P, B, R.r, j, k, dr, dz, mac_slot, fo);
+      }
+    }
+  }
+}
+
+// Start state of node (j, k) (reading: f = f^eq - S~/2, g = g^eq), written
+// in the even-time layout with every slot in its source's frame.
+template <typename S>
+__host__ __device__ inline void init_node(const InstDev& D, int j, int k, float uz, float ur,
+                                          float T) {
+  constexpr int EXr[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  constexpr int EZr[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  S* P = (S*)D.pop;
+  const int64_t o = (int64_t)k * D.stride + j;
+  const double r = (double)D.r0 + j;
+  float phi, cD, cF;
+  porosity(D, o, phi, cD, cF);
+  const float iphi = 1.0f / phi;
+  const float inv_r = (float)(1.0 / r);
+  const float theta = T - D.T_ref;
+  const float Gz = D.gbeta * theta + D.accel_z;
+  const float um = sqrtf(ur * ur + uz * uz);
+  const float Fr = phi * D.accel_r - (cD + cF * um) * ur;
+  const float Fz = phi * Gz - (cD + cF * um) * uz;
+  const float ar = CS2 * (1.0f - 2.0f * D.c_tau * 3.0f * ur * inv_r) * inv_r;
+  float S1, S7, S8;
+  source(D.src_printed != 0, 1.0f, ur, uz, iphi, Fr, Fz, ar, S1, S7, S8);
+  const float S3 = Fr + ar, S5 = Fz;
+  const float u2 = (ur * ur + uz * uz) * iphi;
+  // (m^eq - M w - S/2) / r at rho = 1
+  float d[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  back_transform(d, 3.0f * u2 - 0.5f * S1, -3.0f * u2 + 0.5f * S1, ur - 0.5f * S3,
+                 -ur + 0.5f * S3, uz - 0.5f * S5, -uz + 0.5f * S5,
+                 (ur * ur - uz * uz) * iphi - 0.5f * S7, ur * uz * iphi - 0.5f * S8);
+  const float w[9] = {W0, W1, W1, W1, W1, W5, W5, W5, W5};
+  for (int i = 0; i < 9; ++i) {
+    const int js = j - EXr[i];
+    int ks = k - EZr[i];
+    double rs = r - EXr[i];
+    bool inside = true;
+    if (js < 0) {
+      if (D.side_rmin == SIDE_PERIODIC) rs = (double)D.r0 + D.nr - 1;
+      else inside = D.side_rmin == SIDE_AXIS;
+    }
+    if (js >= D.nr) {
+      if (D.side_rmax == SIDE_PERIODIC) rs = (double)D.r0;
+      else inside = false;
+    }
+    if (D.side_z != SIDE_PERIODIC && (ks < 0 || ks >= D.nz)) inside = false;
+    float v = d[i];
+    if (inside && EXr[i] != 0) v = (float)(((double)w[i] + (double)d[i]) * (r / rs) - (double)w[i]);
+    Store<S>::st(P, i * D.plane + o, v, D.st_scale);
+  }
+  const float eu[5] = {0.0f, ur, uz, -ur, -uz};
+  const float wt[5] = {WT0, WT1, WT1, WT1, WT1};
+  for (int i = 0; i < 5; ++i)
+    Store<S>::st(P, (9 + i) * D.plane + o, wt[i] * (T * (1.0f + 5.0f * eu[i]) - D.T_s),
+                 D.st_scale);
+}
+
+}  // namespace lbmaxi

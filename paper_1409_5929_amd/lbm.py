@@ -1,0 +1,258 @@
+"""Python binding of the lbm_axi C-ABI (argument marshalling only).
+
+Every step of the method runs in the HIP kernels of ``liblbm_axi.so``; this
+module packs problem dictionaries into ``lbm_axi_params``, hands host arrays
+and a HIP stream to the library and unpacks what it returns.  PyTorch, when
+present, only supplies the stream and device buffers; it is imported before
+the library is loaded so that both share one HIP runtime.
+
+The entry points mirror ``include/lbm_axi.h``:
+  create -> Lattice(...), step -> Lattice.step, macros -> Lattice.fields,
+  residual -> Lattice.residual, info -> Lattice.info, destroy -> Lattice.close.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm_axi.so")
+
+SIDE = {"wall": 0, "axis": 1, "periodic": 2}
+THERM = {"fixed": 0, "adiabatic": 1}
+STORAGE = {"fp32": 0, "fp16": 1, "bf16": 2}
+RUN_STATE = {0: "running", 1: "converged", 2: "diverged", 3: "stalled"}
+
+
+class Params(ctypes.Structure):
+    """ctypes image of ``lbm_axi_params`` (field order and types as in the header)."""
+
+    _fields_ = [
+        ("nr", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("side_rmin", ctypes.c_int32), ("side_rmax", ctypes.c_int32), ("side_z", ctypes.c_int32),
+        ("therm_rmin", ctypes.c_int32), ("therm_rmax", ctypes.c_int32), ("therm_z", ctypes.c_int32),
+        ("storage", ctypes.c_int32), ("storage_shift", ctypes.c_int32),
+        ("check_interval", ctypes.c_int32), ("src_printed", ctypes.c_int32),
+        ("r0", ctypes.c_double), ("L", ctypes.c_double), ("phi", ctypes.c_double),
+        ("Da", ctypes.c_double), ("F_phi", ctypes.c_double), ("Ra", ctypes.c_double),
+        ("Pr", ctypes.c_double), ("J", ctypes.c_double), ("lambda_", ctypes.c_double),
+        ("sigma", ctypes.c_double), ("Ma", ctypes.c_double), ("tau_nu", ctypes.c_double),
+        ("accel_r", ctypes.c_double), ("accel_z", ctypes.c_double),
+        ("s_e", ctypes.c_double), ("s_eps", ctypes.c_double), ("s_q", ctypes.c_double),
+        ("s_j", ctypes.c_double),
+        ("T_rmin", ctypes.c_double), ("T_rmax", ctypes.c_double), ("T_zmin", ctypes.c_double),
+        ("T_zmax", ctypes.c_double), ("T_ref", ctypes.c_double), ("T_init", ctypes.c_double),
+        ("delta_T", ctypes.c_double), ("tol", ctypes.c_double), ("max_steps", ctypes.c_int64),
+    ]
+
+
+_ALIASES = {"lam": "lambda_", "lambda": "lambda_"}
+
+
+def make_params(cfg: dict, storage: str = "fp32", check_interval: int = 100, tol: float = 0.0,
+                max_steps: int = 0, storage_shift: int = 0) -> Params:
+    """Pack a problem dictionary (see ``lbm_inputs``) into ``lbm_axi_params``."""
+    p = Params()
+    lib = _load()
+    lib.lbm_axi_default_params(ctypes.byref(p))
+    for key, val in cfg.items():
+        name = _ALIASES.get(key, key)
+        if name.startswith("side_"):
+            val = SIDE[val] if isinstance(val, str) else int(val)
+        elif name.startswith("therm_"):
+            val = THERM[val] if isinstance(val, str) else int(val)
+        if not hasattr(p, name):
+            continue
+        setattr(p, name, val)
+    p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    p.storage_shift = int(storage_shift)
+    p.check_interval = int(check_interval)
+    p.tol = float(tol)
+    p.max_steps = int(max_steps)
+    return p
+
+
+_lib = None
+
+
+def _load():
+    """Load the HIP library; raise if it has not been built (no CPU fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    try:  # share torch's HIP runtime when torch is present
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() (or "
+                           "python -m paper_1409_5929_amd.build) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    fp = P(ctypes.c_float)
+    lib.lbm_axi_default_params.argtypes = [P(Params)]
+    lib.lbm_axi_default_params.restype = None
+    lib.lbm_axi_create.argtypes = [P(Params), ctypes.c_int32, P(fp), P(fp), ctypes.c_void_p,
+                                   P(ctypes.c_void_p)]
+    lib.lbm_axi_create.restype = ctypes.c_int
+    lib.lbm_axi_step.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    lib.lbm_axi_step.restype = ctypes.c_int
+    lib.lbm_axi_macros.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_int32]
+    lib.lbm_axi_macros.restype = ctypes.c_int
+    lib.lbm_axi_residual.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p]
+    lib.lbm_axi_residual.restype = ctypes.c_int
+    lib.lbm_axi_info.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_int64)]
+    lib.lbm_axi_info.restype = ctypes.c_int
+    lib.lbm_axi_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    lib.lbm_axi_set_timing.restype = ctypes.c_int
+    lib.lbm_axi_kernel_time.argtypes = [ctypes.c_void_p, P(ctypes.c_double), P(ctypes.c_int64)]
+    lib.lbm_axi_kernel_time.restype = ctypes.c_int
+    lib.lbm_axi_sync.argtypes = [ctypes.c_void_p]
+    lib.lbm_axi_sync.restype = ctypes.c_int
+    lib.lbm_axi_destroy.argtypes = [ctypes.c_void_p]
+    lib.lbm_axi_destroy.restype = None
+    lib.lbm_axi_last_error.argtypes = []
+    lib.lbm_axi_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+class LbmError(RuntimeError):
+    pass
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise LbmError(f"lbm_axi error {rc}: {_load().lbm_axi_last_error().decode()}")
+
+
+def _current_stream():
+    try:
+        import torch
+
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except ImportError:
+        pass
+    return ctypes.c_void_p(None)
+
+
+class Lattice:
+    """One handle holding one or several instances.
+
+    ``cfg`` is a problem dict or a list of them; ``phi`` an optional [nz, nr]
+    porosity array (or a list, entries may be None); ``init`` an optional
+    [3, nz, nr] array of (u_z, u_r, T) (or a list).  ``stream`` is a raw
+    hipStream_t value; by default torch's current stream.
+    """
+
+    def __init__(self, cfg, phi=None, init=None, storage="fp32", check_interval=100,
+                 tol=0.0, max_steps=0, storage_shift=0, stream=None):
+        lib = _load()
+        cfgs = list(cfg) if isinstance(cfg, (list, tuple)) else [cfg]
+        n = len(cfgs)
+        phis = list(phi) if isinstance(phi, (list, tuple)) else [phi] * (1 if n == 1 else 0)
+        inits = list(init) if isinstance(init, (list, tuple)) else [init] * (1 if n == 1 else 0)
+        if not phis:
+            phis = [None] * n
+        if not inits:
+            inits = [None] * n
+        self.shapes = [(int(c["nz"]), int(c["nr"])) for c in cfgs]
+        arr = (Params * n)()
+        for i, c in enumerate(cfgs):
+            arr[i] = make_params(c, storage, check_interval, tol, max_steps, storage_shift)
+        keep = []
+        fp = ctypes.POINTER(ctypes.c_float)
+        phi_ptrs = (fp * n)()
+        init_ptrs = (fp * n)()
+        for i in range(n):
+            nz, nr = self.shapes[i]
+            if phis[i] is not None:
+                a = np.ascontiguousarray(phis[i], dtype=np.float32)
+                assert a.shape == (nz, nr)
+                keep.append(a)
+                phi_ptrs[i] = a.ctypes.data_as(fp)
+            if inits[i] is not None:
+                a = np.ascontiguousarray(inits[i], dtype=np.float32)
+                assert a.shape == (3, nz, nr)
+                keep.append(a)
+                init_ptrs[i] = a.ctypes.data_as(fp)
+        h = ctypes.c_void_p()
+        st = ctypes.c_void_p(stream) if stream is not None else _current_stream()
+        _check(lib.lbm_axi_create(arr, n, phi_ptrs, init_ptrs, st, ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+        self.n_inst = n
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.lbm_axi_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def step(self, n: int = 1):
+        _check(self._lib.lbm_axi_step(self._h, int(n)))
+
+    def sync(self):
+        _check(self._lib.lbm_axi_sync(self._h))
+
+    def fields(self, inst: int = 0) -> dict:
+        """Host copies of u_z, u_r, p, T (float32) and the node classes (uint8)."""
+        nz, nr = self.shapes[inst]
+        out = {k: np.empty((nz, nr), dtype=np.float32) for k in ("uz", "ur", "p", "T")}
+        mask = np.empty((nz, nr), dtype=np.uint8)
+        _check(self._lib.lbm_axi_macros(self._h, int(inst), out["uz"].ctypes.data,
+                                        out["ur"].ctypes.data, out["p"].ctypes.data,
+                                        out["T"].ctypes.data, mask.ctypes.data, 0))
+        out["mask"] = mask
+        return out
+
+    def fields_device(self, inst: int = 0) -> dict:
+        """u_z, u_r, p, T as torch device tensors written on the handle's stream."""
+        import torch
+
+        nz, nr = self.shapes[inst]
+        out = {k: torch.empty((nz, nr), dtype=torch.float32, device="cuda")
+               for k in ("uz", "ur", "p", "T")}
+        _check(self._lib.lbm_axi_macros(self._h, int(inst), out["uz"].data_ptr(),
+                                        out["ur"].data_ptr(), out["p"].data_ptr(),
+                                        out["T"].data_ptr(), None, 1))
+        return out
+
+    def residual(self) -> dict:
+        n = self.n_inst
+        res, nui, nuo = np.empty(n), np.empty(n), np.empty(n)
+        st = np.empty(n, dtype=np.int32)
+        _check(self._lib.lbm_axi_residual(self._h, res.ctypes.data, nui.ctypes.data,
+                                          nuo.ctypes.data, st.ctypes.data))
+        return dict(res=res, nu_i=nui, nu_o=nuo, status=st)
+
+    def info(self, inst: int = 0) -> dict:
+        out = (ctypes.c_int64 * 4)()
+        _check(self._lib.lbm_axi_info(self._h, int(inst), out))
+        return dict(t=out[0], t_check=out[1], status=RUN_STATE[out[2]], device_bytes=out[3])
+
+    def set_timing(self, on: bool):
+        _check(self._lib.lbm_axi_set_timing(self._h, 1 if on else 0))
+
+    def kernel_time(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(self._lib.lbm_axi_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value

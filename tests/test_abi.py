@@ -1,0 +1,88 @@
+"""Host-side checks of the C ABI (no GPU work): the library loads, exports
+every entry point the header declares, its parameter struct has the layout of
+the header, and invalid problems are refused before any device call."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from tests.conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "lbm_axi.h")
+
+
+def _lib():
+    from paper_1409_5929_amd import lbm
+
+    if not os.path.exists(lbm.LIB_PATH):
+        pytest.skip("liblbm_axi.so not built (run __graft_entry__.build())")
+    return lbm._load(), lbm
+
+
+def test_library_exports_every_declared_symbol():
+    lib, _ = _lib()
+    text = open(HEADER).read()
+    names = sorted(set(re.findall(r"\b(lbm_axi_[a-z_]+)\s*\(", text)))
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in the header but not exported"
+
+
+def test_params_layout_matches_header(tmp_path):
+    """ctypes offsets of lbm_axi_params equal what a C compiler computes from the header."""
+    _, lbm = _lib()
+    fields = [f for f, _ in lbm.Params._fields_]
+    cname = {"lambda_": "lambda"}
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbm_axi.h"', "int main(void){",
+           'printf("%zu\\n", sizeof(lbm_axi_params));']
+    for f in fields:
+        src.append(f'printf("%zu\\n", offsetof(lbm_axi_params, {cname.get(f, f)}));')
+    src.append("return 0;}")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I" + os.path.join(ROOT, "include"), "-o", str(exe), str(c)])
+    vals = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert vals[0] == ctypes.sizeof(lbm.Params)
+    for f, off in zip(fields, vals[1:]):
+        assert getattr(lbm.Params, f).offset == off, f
+
+
+def test_default_params_are_the_papers_rates():
+    _, lbm = _lib()
+    p = lbm.make_params({"nr": 8, "nz": 8})
+    assert (p.s_e, p.s_eps, p.s_q, p.s_j) == (1.1, 1.1, 1.2, 1.0)
+    assert (p.J, p.lambda_, p.sigma, p.Ma) == (1.0, 1.0, 1.0, 0.1)
+
+
+@pytest.mark.parametrize("bad, code", [
+    (dict(nr=2), -1),                              # grid too small
+    (dict(sigma=2.0), -4),                         # heat-capacity ratio other than 1
+    (dict(side_rmin="axis", r0=1.0), -1),          # axis needs cell-centred rows
+    (dict(side_rmax="axis"), -1),                  # axis only at r_min
+    (dict(side_rmin="periodic"), -1),              # one-sided radial periodicity
+    (dict(phi=1.5), -1),                           # porosity out of range
+    (dict(tau_nu=0.0, Ra=0.0), -1),                # no way to set tau_nu
+    (dict(side_rmin="axis", r0=0.5, side_z="wall"), -4),  # axis with axial walls
+    (dict(storage=7), -1),
+])
+def test_invalid_problems_are_refused_without_a_device(bad, code):
+    lib, lbm = _lib()
+    cfg = dict(nr=16, nz=16, r0=10.0, L=15.0, tau_nu=0.8, phi=0.5, Da=1e-2)
+    storage = bad.pop("storage", 0)
+    cfg.update(bad)
+    p = lbm.make_params(cfg, storage=storage)
+    h = ctypes.c_void_p()
+    rc = lib.lbm_axi_create(ctypes.byref(p), 1, None, None, None, ctypes.byref(h))
+    assert rc == code
+    assert not h.value
+    assert lib.lbm_axi_last_error().decode()
+
+
+def test_null_handles_are_refused():
+    lib, _ = _lib()
+    assert lib.lbm_axi_step(None, 1) == -1
+    assert lib.lbm_axi_sync(None) == -1
+    lib.lbm_axi_destroy(None)  # allowed
