@@ -146,13 +146,10 @@ def main():
     esz = 4 if args.storage == "fp32" else 2
     fluid = (n - 2) * (n - 2)
     bytes_node = 28 * esz + 4  # 14 populations read + 14 written, porosity read
-    # launches that also write u_z, u_r, T for the residual (two per check interval)
-    macro_launches = 0
+    # launches that also write u_z, u_r, T for the check (one per check interval)
     t0 = args.warmup
-    for t in range(t0, t0 + args.steps):
-        if args.check_interval > 0 and ((t + 1) % args.check_interval == 0 or
-                                        (t > 0 and t % args.check_interval == 0)):
-            macro_launches += 1
+    macro_launches = sum(1 for t in range(t0, t0 + args.steps)
+                         if args.check_interval > 0 and t % args.check_interval == 0)
     alg_bytes = launches * fluid * bytes_node + macro_launches * 12 * n * n
     avg_ms = kern_ms / max(launches, 1)
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9

@@ -134,9 +134,10 @@ int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* 
 
 /*
  * Advance every running instance by nsteps time steps (asynchronous on the
- * handle's stream).  Every check_interval steps the residual and the wall
- * Nusselt numbers are computed on the device and the run state updated;
- * instances that stop are skipped from then on.
+ * handle's stream).  At every multiple of check_interval (from the second
+ * one on, counting step 0) the residual and the wall Nusselt numbers are
+ * computed on the device and the run state updated; instances that stop are
+ * skipped from then on.
  */
 int lbm_axi_step(lbm_axi* h, int32_t nsteps);
 
@@ -156,12 +157,14 @@ int lbm_axi_macros(lbm_axi* h, int32_t inst, float* uz, float* ur, float* p, flo
 /*
  * Latest check of every instance (waits for the stream).  Each pointer may be
  * NULL; arrays have n_inst entries.  The paper defines no convergence
- * criterion; res = max(R_u, R_T) with R_u = rms over the fluid nodes of
- * |u^n - u^{n-1}| divided by the characteristic velocity Ma c_s (text before
- * Eq. 39) and R_T = rms of T^n - T^{n-1} divided by dT (FP64 sums).  nu_i,
- * nu_o = Eq. (42) on the r_min and r_max walls (second-order one-sided dT/dr,
- * trapezoid rule, H = nz - 1).  status = lbm_axi_run_state.  Before the
- * first check res = +inf.
+ * criterion; at step n (a multiple N of check_interval) res = max(R_u, R_T)
+ * with R_u = rms over the fluid nodes of |u^n - u^{n-N}| / N divided by the
+ * characteristic velocity Ma c_s (text before Eq. 39) and R_T the same for T
+ * divided by dT (FP64 sums): the mean change per step over the interval, so
+ * that rounding flicker of FP32 storage does not set a floor.  nu_i, nu_o =
+ * Eq. (42) at step n on the r_min and r_max walls (second-order one-sided
+ * dT/dr, trapezoid rule, H = nz - 1).  status = lbm_axi_run_state.  Before
+ * the first check res = +inf.
  */
 int lbm_axi_residual(lbm_axi* h, double* res, double* nu_i, double* nu_o, int32_t* status);
 

@@ -73,6 +73,8 @@ def _load():
     lib.orc_time.restype = ctypes.c_long
     lib.orc_time.argtypes = [ctypes.c_void_p]
     lib.orc_macros.argtypes = [ctypes.c_void_p, d, d, d, d, d, P(ctypes.c_uint8)]
+    lib.orc_snapshot.argtypes = [ctypes.c_void_p]
+    lib.orc_snapshot.restype = None
     lib.orc_residual.restype = ctypes.c_int
     lib.orc_residual.argtypes = [ctypes.c_void_p, d]
     lib.orc_nusselt.argtypes = [ctypes.c_void_p, d, d]
@@ -170,7 +172,12 @@ class Oracle:
         out["mask"] = mask
         return out
 
+    def snapshot(self):
+        """Keep the current u and T; residual() measures the change since."""
+        self._lib.orc_snapshot(self._h)
+
     def residual(self):
+        """Mean change per step since the snapshot (rms, scaled by Ma c_s and dT)."""
         out = np.empty(3)
         if self._lib.orc_residual(self._h, _dptr(out)) != 0:
             return None

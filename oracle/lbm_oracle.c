@@ -129,7 +129,8 @@ typedef struct {
   double *fp, *gp;    /* post-collision scratch */
   double *fn, *gn;    /* streaming destination */
   double *rho, *ur, *uz, *T; /* macroscopic values at time t */
-  double *pur, *puz, *pT;    /* macroscopic values at time t-1 */
+  double *pur, *puz, *pT;    /* macroscopic values at the snapshot time */
+  long t_snap;
   int have_prev;
   uint8_t* mask;
   long t;
@@ -552,13 +553,18 @@ void orc_step(orc_state* s, int nsteps) {
   for (int it = 0; it < nsteps; ++it) {
     collide_all(s);
     stream_all(s);
-    memcpy(s->pur, s->ur, sizeof(double) * s->n);
-    memcpy(s->puz, s->uz, sizeof(double) * s->n);
-    memcpy(s->pT, s->T, sizeof(double) * s->n);
-    s->have_prev = 1;
     s->t += 1;
     compute_all_macros(s);
   }
+}
+
+/* Keep the current velocity and temperature for orc_residual. */
+void orc_snapshot(orc_state* s) {
+  memcpy(s->pur, s->ur, sizeof(double) * s->n);
+  memcpy(s->puz, s->uz, sizeof(double) * s->n);
+  memcpy(s->pT, s->T, sizeof(double) * s->n);
+  s->t_snap = s->t;
+  s->have_prev = 1;
 }
 
 long orc_time(const orc_state* s) { return s->t; }
@@ -577,15 +583,16 @@ void orc_macros(const orc_state* s, double* uz, double* ur, double* p, double* T
 }
 
 /*
- * Steady-state residual between times t-1 and t over the N fluid nodes (the
- * paper gives no criterion): the root-mean-square change per step of the
- * velocity and of the temperature, scaled by the characteristic velocity
- * U = Ma c_s (text before Eq. 39) and by the temperature difference dT:
- * out[0] = sqrt(sum |u^t - u^{t-1}|^2 / N) / U, out[1] = the same for T / dT,
- * out[2] = max of both.  Returns -1 before the first step.
+ * Steady-state residual between the snapshot time t0 and the current time t
+ * over the N fluid nodes (the paper gives no criterion): the root-mean-square
+ * change per step, sqrt(sum |u^t - u^t0|^2 / N) / (t - t0), scaled by the
+ * characteristic velocity U = Ma c_s (text before Eq. 39) in out[0], the same
+ * for T scaled by dT in out[1], out[2] = max of both.  Returns -1 without a
+ * snapshot or when t = t0.
  */
 int orc_residual(const orc_state* s, double* out) {
-  if (!s->have_prev) return -1;
+  if (!s->have_prev || s->t == s->t_snap) return -1;
+  const double steps = (double)(s->t - s->t_snap);
   double du = 0, dT = 0;
   long nf = 0;
   for (int idx = 0; idx < s->n; ++idx) {
@@ -599,8 +606,8 @@ int orc_residual(const orc_state* s, double* out) {
   double U = s->p.Ma > 0.0 ? s->p.Ma * sqrt(CS2) : 1.0;
   double Tc = s->p.delta_T != 0.0 ? fabs(s->p.delta_T) : fabs(s->p.T_rmin - s->p.T_rmax);
   if (Tc == 0.0) Tc = 1.0;
-  out[0] = nf ? sqrt(du / nf) / U : 0.0;
-  out[1] = nf ? sqrt(dT / nf) / Tc : 0.0;
+  out[0] = nf ? sqrt(du / nf) / (U * steps) : 0.0;
+  out[1] = nf ? sqrt(dT / nf) / (Tc * steps) : 0.0;
   out[2] = out[0] > out[1] ? out[0] : out[1];
   return 0;
 }

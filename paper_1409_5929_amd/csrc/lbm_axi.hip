@@ -86,7 +86,6 @@ struct lbm_axi {
   DevResult* dres = nullptr;
   int* dfirst = nullptr;        // per-instance first reduction tile and count
   long long t = 0;              // global time level
-  int prev_slot = 0;            // check buffer holding the step before a check
   size_t bytes = 0;
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -208,11 +207,12 @@ __global__ __launch_bounds__(RB) void k_resid(const InstDev* __restrict__ descs,
 }
 
 // Per instance: sum its partials in order, form the residual (root-mean-
-// square change per step of u and T over the fluid nodes, scaled by Ma c_s
-// and dT) and the Nusselt numbers, update the run state.
+// square change of u and T over the fluid nodes since the previous check,
+// per step, scaled by Ma c_s and dT) and the Nusselt numbers, update the run
+// state.
 __global__ void k_final(const InstDev* __restrict__ descs, const int* __restrict__ first,
                         const double* __restrict__ part, int n_inst, long long t,
-                        const double* __restrict__ tol, const long long* __restrict__ max_steps,
+                        double per_step, const double* __restrict__ tol, const long long* __restrict__ max_steps,
                         const double* __restrict__ nu_scale, int* __restrict__ status,
                         DevResult* __restrict__ out) {
   const int inst = blockIdx.x * blockDim.x + threadIdx.x;
@@ -222,8 +222,8 @@ __global__ void k_final(const InstDev* __restrict__ descs, const int* __restrict
   for (int b = b0; b < b0 + nb; ++b)
     for (int q = 0; q < 6; ++q) a[q] += part[(int64_t)b * 6 + q];
   const double nf = a[1] > 0.0 ? a[1] : 1.0;
-  const double ru = sqrt(a[0] / nf) * nu_scale[4 * inst + 2];
-  const double rT = sqrt(a[2] / nf) * nu_scale[4 * inst + 3];
+  const double ru = sqrt(a[0] / nf) * nu_scale[4 * inst + 2] * per_step;
+  const double rT = sqrt(a[2] / nf) * nu_scale[4 * inst + 3] * per_step;
   double res = ru > rT ? ru : rT;
   if (ru != ru || rT != rT) res = ru + rT;  // NaN propagates
   DevResult r = out[inst];
@@ -569,17 +569,15 @@ int lbm_axi_step(lbm_axi* h, int32_t nsteps) {
   for (int32_t s = 0; s < nsteps; ++s) {
     const long long n = h->t;
     const bool odd = (n & 1) != 0;
+    // At every multiple of the check interval the step also writes u_z, u_r,
+    // T into one of two buffers (alternating); from the second one on, the
+    // check compares them with the previous multiple's.
     int mode = MODE_STEP, slot = 0;
     bool check = false;
-    if (h->check > 0) {
-      if ((n + 1) % h->check == 0) {  // the step before a check level
-        mode = MODE_STEP_MACRO;
-        slot = h->prev_slot;
-      } else if (n > 0 && n % h->check == 0) {  // a check level
-        mode = MODE_STEP_MACRO;
-        slot = 1 - h->prev_slot;
-        check = true;
-      }
+    if (h->check > 0 && n % h->check == 0) {
+      mode = MODE_STEP_MACRO;
+      slot = (int)((n / h->check) & 1);
+      check = n > 0;
     }
     if (h->timing) {
       hipEvent_t e0, e1;
@@ -603,8 +601,9 @@ int lbm_axi_step(lbm_axi* h, int32_t nsteps) {
       k_resid<<<h->nrt, RB, 0, h->stream>>>(h->ddesc, h->drt, slot, h->dpart);
       HIPCHK(hipGetLastError());
       const int nb = (h->n_inst + 63) / 64;
-      k_final<<<nb, 64, 0, h->stream>>>(h->ddesc, h->dfirst, h->dpart, h->n_inst, n, h->dtol,
-                                         h->dmx, h->dnus, h->dstatus, h->dres);
+      k_final<<<nb, 64, 0, h->stream>>>(h->ddesc, h->dfirst, h->dpart, h->n_inst, n,
+                                         1.0 / h->check, h->dtol, h->dmx, h->dnus, h->dstatus,
+                                         h->dres);
       HIPCHK(hipGetLastError());
     }
     h->t = n + 1;

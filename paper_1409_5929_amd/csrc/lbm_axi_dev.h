@@ -11,12 +11,16 @@
 // the slots it read, so the update needs no second array and no barrier.
 //
 // Values.  The populations are r-weighted (Eq. 17, Eq. 26): f_i = r fhat_i.
-// A slot holds the deviation s_i = fhat_i - w_i (rest state rho = 1) in the
-// frame of the node that wrote it (the source x - e_i of an arriving
-// population).  The reader rescales to its own radius, fhat_i(x) =
-// (r_src / r)(w_i + s_i), so FP32 keeps its relative precision at any r and
-// the same representation serves FP16/BF16 storage (times a power of two).
-// Temperature slots hold g_i - wt_i T_s for a storage shift T_s.
+// A slot holds the deviation of fhat_i from the scheme's quiescent state
+// (rho = 1, u = 0, only the axisymmetric term a_r acting), in the frame of
+// the node that wrote it (the source x - e_i of an arriving population).
+// That state is fhat_i = w_i (1 + e_ir / (2 r)) after collision and
+// w_i (1 - e_ir / (2 r)) before it; streaming maps the first onto the second
+// exactly (r_src = r - e_ir), so the reader only rescales the deviation,
+// d_i = (r_src / r) s_i, and the collision maps zero deviations onto zero.
+// FP32 thus keeps its relative precision at any r, also next to the axis,
+// and the same representation serves FP16/BF16 storage (times a power of
+// two).  Temperature slots hold g_i - wt_i T_s for a storage shift T_s.
 //
 // Axis.  With an axis at r_min the mirror row j = -1 is never stored: its
 // slot q at (-1, k) is the slot q* (e_r reversed) of (0, k).  In the writer's
@@ -111,8 +115,8 @@ struct Store<__hip_bfloat16> {
 // ---- per-column constants (r is fixed along a thread's z loop) -------------
 struct RowC {
   float r, inv_r;
-  float rp, op1, op5;  // sources at r - 1 (e_r = +1): ratio r_src / r, w (ratio - 1)
-  float rm, om1, om5;  // sources at r + 1 (e_r = -1)
+  float rp, op1, op5;  // sources of e_r = +1 populations: ratio r_src / r, offsets
+  float rm, om1, om5;  // sources of e_r = -1 populations (offsets vanish unless r wraps)
   float lr0b;          // (1 + c_s^2 (tau - 1/2) / r^2) / 2, Eq. (30) divided by r
   float hcs2r;         // c_s^2 / (2 r), Eq. (29) divided by r rho
   float ar0, ar1;      // a_r = ar0 - ar1 u_r, Eq. (25)
@@ -145,12 +149,14 @@ __host__ __device__ inline RowC make_row(const InstDev& D, int j) {
   }
   R.r = (float)r;
   R.inv_r = (float)inv;
+  // d = (r_src / r) s + w (r_src - r + e_r) / r: the offset is zero unless
+  // the source sits across a radial wrap (r_src != r - e_r).
   R.rp = (float)(src_p * inv);
-  R.op1 = (float)((1.0 / 9.0) * (src_p - r) * inv);
-  R.op5 = (float)((1.0 / 36.0) * (src_p - r) * inv);
+  R.op1 = (float)((1.0 / 9.0) * (src_p - r + 1.0) * inv);
+  R.op5 = (float)((1.0 / 36.0) * (src_p - r + 1.0) * inv);
   R.rm = (float)(src_m * inv);
-  R.om1 = (float)((1.0 / 9.0) * (src_m - r) * inv);
-  R.om5 = (float)((1.0 / 36.0) * (src_m - r) * inv);
+  R.om1 = (float)((1.0 / 9.0) * (src_m - r - 1.0) * inv);
+  R.om5 = (float)((1.0 / 36.0) * (src_m - r - 1.0) * inv);
   R.lr0b = (float)(0.5 * (1.0 + (double)D.c_tau * inv * inv));
   R.hcs2r = (float)(0.5 / 3.0 * inv);
   R.ar0 = (float)(inv / 3.0);
@@ -296,13 +302,14 @@ __host__ __device__ inline void wall_node(const InstDev& D, S* P, const NodeStat
     const float Frb = phib * D.accel_r, Fzb = phib * Gz;
     const float S3 = B.rho * (Frb + CS2 * inv_rb), S5 = B.rho * Fzb;
     const float q = rB * inv_rb;
+    const float hb = 0.5f * CS2 * inv_rb;  // quiescent reference: moment 3 +hb, moment 4 -hb
     float d[9];
     d[0] = W0 * B.drho;
     d[1] = d[2] = d[3] = d[4] = W1 * B.drho;
     d[5] = d[6] = d[7] = d[8] = W5 * B.drho;
     back_transform(d, (1.0f - D.s_e) * q * B.n1, (1.0f - D.s_eps) * q * B.n2,
-                   (1.0f - D.s_j) * q * B.n3 + (1.0f - 0.5f * D.s_j) * S3,
-                   (1.0f - D.s_q) * q * B.n4 - (1.0f - 0.5f * D.s_q) * S3,
+                   (1.0f - D.s_j) * q * B.n3 + (1.0f - 0.5f * D.s_j) * S3 - hb,
+                   (1.0f - D.s_q) * q * B.n4 - (1.0f - 0.5f * D.s_q) * S3 + hb,
                    (1.0f - D.s_j) * q * B.n5 + (1.0f - 0.5f * D.s_j) * S5,
                    (1.0f - D.s_q) * q * B.n6 - (1.0f - 0.5f * D.s_q) * S5,
                    (1.0f - D.s_nu) * q * B.n7, (1.0f - D.s_nu) * q * B.n8);
@@ -380,7 +387,7 @@ __host__ __device__ inline void node_update(const InstDev& D, const RowC& R, int
   float phi, cD, cF;
   porosity(D, o, phi, cD, cF);
 
-  // Rescale to this node's frame: d_i = fhat_i - w_i.
+  // Rescale to this node's frame: d_i = fhat_i - w_i (1 - e_ir / (2 r)).
   float d[9];
   d[0] = s[0];
   d[2] = s[2];
@@ -398,13 +405,14 @@ __host__ __device__ inline void node_update(const InstDev& D, const RowC& R, int
   B.drho = d[0] + sa + sd;                                  // rho - 1, Eq. (26)
   B.rho = 1.0f + B.drho;
   const float inv_rho = 1.0f / B.rho;
-  const float Jr = d[1] - d[3] + d[5] - d[6] - d[7] + d[8];  // sum e_r f / r
+  // sum e_r f / r = Jr - c_s^2 / (2 r); sum e_z f / r = Jz
+  const float Jr = d[1] - d[3] + d[5] - d[6] - d[7] + d[8];
   const float Jz = d[2] - d[4] + d[5] + d[6] - d[7] - d[8];
   B.theta = t[0] + t[1] + t[2] + t[3] + t[4];               // T - T_s, Eq. (38)
   B.T = D.T_s + B.theta;
   const float Gr = D.accel_r;
   const float Gz = D.gbeta * B.theta + D.az_s;              // Eq. (7)
-  const float vr = Jr * inv_rho + R.hcs2r + 0.5f * phi * Gr;  // Eq. (29) / r
+  const float vr = (Jr + R.hcs2r * B.drho) * inv_rho + 0.5f * phi * Gr;  // Eq. (29) / r
   const float vz = Jz * inv_rho + 0.5f * phi * Gz;
   const float lr0 = R.lr0b + 0.25f * cD;                    // Eq. (30) / r
   const float lz0 = 0.5f + 0.25f * cD;
@@ -441,8 +449,9 @@ __host__ __device__ inline void node_update(const InstDev& D, const RowC& R, int
   const float ru2 = rho * (ur * ur + uz * uz) * iphi;
   B.n1 = (-4.0f * d[0] - sa + 2.0f * sd) + 2.0f * B.drho - 3.0f * ru2;
   B.n2 = (4.0f * d[0] - 2.0f * sa + sd) - B.drho + 3.0f * ru2;
-  B.n3 = Jr - rho * ur;
-  B.n4 = (-2.0f * d[1] + 2.0f * d[3] + d[5] - d[6] - d[7] + d[8]) + rho * ur;
+  const float m4 = -2.0f * d[1] + 2.0f * d[3] + d[5] - d[6] - d[7] + d[8];
+  B.n3 = (Jr - R.hcs2r) - rho * ur;
+  B.n4 = (m4 + R.hcs2r) + rho * ur;
   B.n5 = Jz - rho * uz;
   B.n6 = (-2.0f * d[2] + 2.0f * d[4] + d[5] + d[6] - d[7] - d[8]) + rho * uz;
   B.n7 = (d[1] - d[2] + d[3] - d[4]) - rho * (ur * ur - uz * uz) * iphi;
@@ -452,12 +461,19 @@ __host__ __device__ inline void node_update(const InstDev& D, const RowC& R, int
     // ---- a5: source (Eq. 24) and relaxation (Eq. 21) --------------------------
     float S1, S7, S8;
     source(D.src_printed != 0, rho, ur, uz, iphi, Fr, Fz, ar, S1, S7, S8);
-    const float S3 = rho * (Fr + ar), S5 = rho * Fz;
+    const float S5 = rho * Fz;
+    // The radial-momentum and radial-flux increments are written so that the
+    // quiescent parts (c_s^2 / (2 r) in n_3, n_4 and c_s^2 / r in S_3) and
+    // the change of reference state (-c_s^2 / r in moment 3, +c_s^2 / r in
+    // moment 4) cancel exactly: what remains scales with rho - 1 and u.
+    const float S3d = rho * (Fr - R.ar1 * ur);  // S_3 minus its quiescent part rho c_s^2 / r
+    const float X3 = -D.s_j * (Jr - rho * ur) + (1.0f - 0.5f * D.s_j) * S3d +
+                     (2.0f - D.s_j) * R.hcs2r * B.drho;
+    const float X4 = -D.s_q * (m4 + rho * ur) - (1.0f - 0.5f * D.s_q) * S3d -
+                     (2.0f - D.s_q) * R.hcs2r * B.drho;
     // ---- a6: back-transform (Eq. 22) ------------------------------------------
     back_transform(d, -D.s_e * B.n1 + (1.0f - 0.5f * D.s_e) * S1,
-                   -D.s_eps * B.n2 - (1.0f - 0.5f * D.s_eps) * S1,
-                   -D.s_j * B.n3 + (1.0f - 0.5f * D.s_j) * S3,
-                   -D.s_q * B.n4 - (1.0f - 0.5f * D.s_q) * S3,
+                   -D.s_eps * B.n2 - (1.0f - 0.5f * D.s_eps) * S1, X3, X4,
                    -D.s_j * B.n5 + (1.0f - 0.5f * D.s_j) * S5,
                    -D.s_q * B.n6 - (1.0f - 0.5f * D.s_q) * S5,
                    -D.s_nu * B.n7 + (1.0f - 0.5f * D.s_nu) * S7,
@@ -560,12 +576,14 @@ __host__ __device__ inline void init_node(const InstDev& D, int j, int k, float 
   const float ar = CS2 * (1.0f - 2.0f * D.c_tau * 3.0f * ur * inv_r) * inv_r;
   float S1, S7, S8;
   source(D.src_printed != 0, 1.0f, ur, uz, iphi, Fr, Fz, ar, S1, S7, S8);
-  const float S3 = Fr + ar, S5 = Fz;
+  const float S3d = Fr - 2.0f * D.c_tau * ur * inv_r * inv_r;  // S_3 - c_s^2 / r at rho = 1
+  const float S5 = Fz;
   const float u2 = (ur * ur + uz * uz) * iphi;
-  // (m^eq - M w - S/2) / r at rho = 1
+  // (m^eq - S/2) / r at rho = 1 minus the moments of the pre-collision
+  // quiescent state (1, -2, 1, -c_s^2 / (2r), c_s^2 / (2r), 0, 0, 0, 0)
   float d[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  back_transform(d, 3.0f * u2 - 0.5f * S1, -3.0f * u2 + 0.5f * S1, ur - 0.5f * S3,
-                 -ur + 0.5f * S3, uz - 0.5f * S5, -uz + 0.5f * S5,
+  back_transform(d, 3.0f * u2 - 0.5f * S1, -3.0f * u2 + 0.5f * S1, ur - 0.5f * S3d,
+                 -ur + 0.5f * S3d, uz - 0.5f * S5, -uz + 0.5f * S5,
                  (ur * ur - uz * uz) * iphi - 0.5f * S7, ur * uz * iphi - 0.5f * S8);
   const float w[9] = {W0, W1, W1, W1, W1, W5, W5, W5, W5};
   for (int i = 0; i < 9; ++i) {
@@ -582,8 +600,10 @@ __host__ __device__ inline void init_node(const InstDev& D, int j, int k, float 
       else inside = false;
     }
     if (D.side_z != SIDE_PERIODIC && (ks < 0 || ks >= D.nz)) inside = false;
+    // stored in the source frame: s = (d - w (r_src - r + e) / r) r / r_src
     float v = d[i];
-    if (inside && EXr[i] != 0) v = (float)(((double)w[i] + (double)d[i]) * (r / rs) - (double)w[i]);
+    if (inside && EXr[i] != 0)
+      v = (float)(((double)d[i] - (double)w[i] * (rs - r + EXr[i]) / r) * (r / rs));
     Store<S>::st(P, i * D.plane + o, v, D.st_scale);
   }
   const float eu[5] = {0.0f, ur, uz, -ur, -uz};

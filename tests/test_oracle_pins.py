@@ -225,6 +225,7 @@ def test_quiescent_annulus_stays_at_rest(oracle_mod):
 
 def _run_to_steady(o, tol, chunk=1000, max_steps=400_000, key="res_u"):
     while o.t < max_steps:
+        o.snapshot()
         o.step(chunk)
         if o.residual()[key] < tol:
             break
