@@ -58,6 +58,26 @@ def measured_traffic(storage: str):
     return e["bytes_per_launch"]
 
 
+def device_copy_gbs(torch, stream, nbytes: int = 2 << 30, reps: int = 5) -> float:
+    """Bandwidth of a plain device-to-device copy on the same stream (bytes
+    read plus bytes written per second): what streaming code reaches here."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    best = float("inf")
+    with torch.cuda.stream(stream):
+        dst.copy_(src)
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            dst.copy_(src)
+            e1.record(stream)
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    return 2 * nbytes / (best * 1e-3) / 1e9
+
+
 def cpu_baseline(cfg, phi, seconds: float):
     """The FP64 oracle on a 1024 x 1024 corner of the same problem (inner
     wall, bottom wall), stepped until `seconds` of work are done."""
@@ -142,6 +162,7 @@ def main():
     res = lat.residual()
     info = lat.info()
     lat.close()
+    copy_gbs = device_copy_gbs(torch, stream)
 
     esz = 4 if args.storage == "fp32" else 2
     fluid = (n - 2) * (n - 2)
@@ -185,6 +206,8 @@ def main():
             "bytes_per_node": bytes_node,
             "avg_launch_ms": round(avg_ms, 5),
             "launches": launches,
+            "copy_gbs": round(copy_gbs, 1),
+            "frac_of_copy": round(achieved / copy_gbs, 4),
         },
         "residual": float(res["res"][0]),
         "nu_i": float(res["nu_i"][0]),

@@ -184,6 +184,15 @@ int lbm_axi_info(lbm_axi* h, int32_t inst, int64_t* out);
 int lbm_axi_set_timing(lbm_axi* h, int32_t on);
 int lbm_axi_kernel_time(lbm_axi* h, double* total_ms, int64_t* launches);
 
+/*
+ * Launch shape of the step kernel: blocks of 64 lanes along r by 4 waves,
+ * each thread updating kz nodes along z (1 <= kz <= 64; default 4), and at
+ * most blocks_per_cu blocks resident per compute unit (0: no cap; 1..64).
+ * Waits for the stream and rebuilds the tile lists; results do not depend
+ * on it.
+ */
+int lbm_axi_set_tiles(lbm_axi* h, int32_t kz, int32_t blocks_per_cu);
+
 /* Wait for the handle's stream. */
 int lbm_axi_sync(lbm_axi* h);
 

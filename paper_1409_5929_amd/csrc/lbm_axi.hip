@@ -66,15 +66,18 @@ struct lbm_axi {
   int storage = 0;
   int check = 0;
   int kz = 4;
+  int lds_bytes = 0;            // dynamic LDS per step block (caps blocks per CU)
+  int lds_per_cu = 0;           // LDS of one compute unit
+  int lds_per_block = 0;        // largest LDS one block may reserve
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::vector<lbm_axi_params> prm;
   std::vector<InstDev> hdesc;
   InstDev* ddesc = nullptr;
   std::vector<void*> allocs;
-  int4* dtiles = nullptr;       // XCD-ordered tiles of all instances
+  int4* dtiles = nullptr;       // XCD-ordered tiles of all instances (own allocation)
   int ntiles_launch = 0;
-  int4* dtiles_plain = nullptr; // tiles in instance order
+  int4* dtiles_plain = nullptr; // tiles in instance order (own allocation)
   std::vector<int> tile_first, tile_count;
   ResTile* drt = nullptr;
   int nrt = 0;
@@ -94,6 +97,7 @@ struct lbm_axi {
 };
 
 // ---- kernels ------------------------------------------------------------------
+
 
 template <typename S, bool ODD, int MODE>
 __global__ __launch_bounds__(BX* BY) void k_step(const InstDev* __restrict__ descs,
@@ -164,8 +168,8 @@ __global__ __launch_bounds__(RB) void k_resid(const InstDev* __restrict__ descs,
                                               double* __restrict__ part) {
   const ResTile rt = rts[blockIdx.x];
   const InstDev D = descs[rt.inst];
-  const float* cu = D.mac[cur];
-  const float* pv = D.mac[1 - cur];
+  const float* cu = cur ? D.mac[1] : D.mac[0];
+  const float* pv = cur ? D.mac[0] : D.mac[1];
   const int64_t pl = D.plane;
   double a[6] = {0, 0, 0, 0, 0, 0};
   for (int k = rt.k0; k < rt.k1; ++k) {
@@ -206,21 +210,35 @@ __global__ __launch_bounds__(RB) void k_resid(const InstDev* __restrict__ descs,
   }
 }
 
-// Per instance: sum its partials in order, form the residual (root-mean-
-// square change of u and T over the fluid nodes since the previous check,
-// per step, scaled by Ma c_s and dT) and the Nusselt numbers, update the run
-// state.
-__global__ void k_final(const InstDev* __restrict__ descs, const int* __restrict__ first,
-                        const double* __restrict__ part, int n_inst, long long t,
-                        double per_step, const double* __restrict__ tol, const long long* __restrict__ max_steps,
-                        const double* __restrict__ nu_scale, int* __restrict__ status,
-                        DevResult* __restrict__ out) {
-  const int inst = blockIdx.x * blockDim.x + threadIdx.x;
-  if (inst >= n_inst) return;
+// Per instance (one block each): sum its partials in a fixed order, form the
+// residual (root-mean-square change of u and T over the fluid nodes since the
+// previous check, per step, scaled by Ma c_s and dT) and the Nusselt numbers,
+// update the run state.
+__global__ __launch_bounds__(RB) void k_final(const int* __restrict__ first,
+                                              const double* __restrict__ part, long long t,
+                                              double per_step, const double* __restrict__ tol,
+                                              const long long* __restrict__ max_steps,
+                                              const double* __restrict__ nu_scale,
+                                              int* __restrict__ status,
+                                              DevResult* __restrict__ out) {
+  const int inst = blockIdx.x;
   double a[6] = {0, 0, 0, 0, 0, 0};
   const int b0 = first[2 * inst], nb = first[2 * inst + 1];
-  for (int b = b0; b < b0 + nb; ++b)
+  for (int b = b0 + (int)threadIdx.x; b < b0 + nb; b += RB)
     for (int q = 0; q < 6; ++q) a[q] += part[(int64_t)b * 6 + q];
+  __shared__ double sh[RB / 64][6];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int q = 0; q < 6; ++q) {
+    const double v = wave_sum(a[q]);
+    if (lane == 0) sh[w][q] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int q = 0; q < 6; ++q) {
+    double v = 0.0;
+    for (int i = 0; i < RB / 64; ++i) v += sh[i][q];
+    a[q] = v;
+  }
   const double nf = a[1] > 0.0 ? a[1] : 1.0;
   const double ru = sqrt(a[0] / nf) * nu_scale[4 * inst + 2] * per_step;
   const double rT = sqrt(a[2] / nf) * nu_scale[4 * inst + 3] * per_step;
@@ -234,14 +252,14 @@ __global__ void k_final(const InstDev* __restrict__ descs, const int* __restrict
   r.nu_o = -nu_scale[4 * inst + 1] * a[5];
   r.u_rms = sqrt(a[3] / nf);
   r.t_check = t;
-  int s = status[inst];
-  if (s == RUN) {
-    if (!isfinite(res)) s = DIVERGED;
-    else if (res <= tol[inst]) s = CONVERGED;
-    else if (max_steps[inst] > 0 && t + 1 >= max_steps[inst]) s = STALLED;
-    if (s != RUN) {
+  int st = status[inst];
+  if (st == RUN) {
+    if (!isfinite(res)) st = DIVERGED;
+    else if (res <= tol[inst]) st = CONVERGED;
+    else if (max_steps[inst] > 0 && t + 1 >= max_steps[inst]) st = STALLED;
+    if (st != RUN) {
       r.t_stop = t + 1;
-      status[inst] = s;
+      status[inst] = st;
     }
   }
   out[inst] = r;
@@ -298,14 +316,14 @@ int launch_step(lbm_axi* h, bool odd, int mode, int slot) {
   const FieldOut fo{nullptr, nullptr, nullptr, nullptr, nullptr};
   if (!odd) {
     if (mode == MODE_STEP)
-      k_step<S, false, MODE_STEP><<<h->ntiles_launch, blk, 0, h->stream>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo);
+      k_step<S, false, MODE_STEP><<<h->ntiles_launch, blk, h->lds_bytes, h->stream>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo);
     else
-      k_step<S, false, MODE_STEP_MACRO><<<h->ntiles_launch, blk, 0, h->stream>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo);
+      k_step<S, false, MODE_STEP_MACRO><<<h->ntiles_launch, blk, h->lds_bytes, h->stream>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo);
   } else {
     if (mode == MODE_STEP)
-      k_step<S, true, MODE_STEP><<<h->ntiles_launch, blk, 0, h->stream>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo);
+      k_step<S, true, MODE_STEP><<<h->ntiles_launch, blk, h->lds_bytes, h->stream>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo);
     else
-      k_step<S, true, MODE_STEP_MACRO><<<h->ntiles_launch, blk, 0, h->stream>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo);
+      k_step<S, true, MODE_STEP_MACRO><<<h->ntiles_launch, blk, h->lds_bytes, h->stream>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo);
   }
   HIPCHK(hipGetLastError());
   return LBM_AXI_OK;
@@ -332,6 +350,51 @@ int launch_init(lbm_axi* h, int inst, const float* dinit, float T_init) {
   else
     k_init_uniform<S><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->kz, T_init, inst);
   HIPCHK(hipGetLastError());
+  return LBM_AXI_OK;
+}
+
+// Tiles of BX lanes along r by BY * kz rows along z, for every instance.
+// Launch order: block b takes tile (b % 8) * ceil(T / 8) + b / 8, so that
+// the 8 XCDs, which receive blocks round-robin, each sweep a contiguous run
+// of tiles (neighbouring rows share that XCD's L2).
+int build_tiles(lbm_axi* h, int kz) {
+  std::vector<int4> tiles;
+  std::vector<int> first, count;
+  const int tile_h = BY * kz;
+  for (int i = 0; i < h->n_inst; ++i) {
+    const lbm_axi_params& q = h->prm[i];
+    first.push_back((int)tiles.size());
+    for (int k0 = 0; k0 < q.nz; k0 += tile_h)
+      for (int j0 = 0; j0 < q.nr; j0 += BX) tiles.push_back(make_int4(i, j0, k0, 0));
+    count.push_back((int)tiles.size() - first.back());
+  }
+  const int T = (int)tiles.size();
+  const int per = (T + 7) / 8;
+  std::vector<int4> order((size_t)per * 8, make_int4(-1, 0, 0, 0));
+  for (int b = 0; b < per * 8; ++b) {
+    const int t = (b % 8) * per + b / 8;
+    if (t < T) order[b] = tiles[t];
+  }
+  int4 *dt = nullptr, *dp = nullptr;
+  if (hipMalloc(&dt, sizeof(int4) * order.size()) != hipSuccess ||
+      hipMalloc(&dp, sizeof(int4) * tiles.size()) != hipSuccess) {
+    if (dt) (void)hipFree(dt);
+    return fail(LBM_AXI_ENOMEM, "tile lists");
+  }
+  if (hipMemcpy(dt, order.data(), sizeof(int4) * order.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dp, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(dt);
+    (void)hipFree(dp);
+    return fail(LBM_AXI_EDEVICE, "tile list upload");
+  }
+  if (h->dtiles) (void)hipFree(h->dtiles);
+  if (h->dtiles_plain) (void)hipFree(h->dtiles_plain);
+  h->dtiles = dt;
+  h->dtiles_plain = dp;
+  h->ntiles_launch = per * 8;
+  h->tile_first = first;
+  h->tile_count = count;
+  h->kz = kz;
   return LBM_AXI_OK;
 }
 
@@ -378,6 +441,8 @@ void lbm_axi_destroy(lbm_axi* h) {
     (void)hipEventDestroy(e.second);
   }
   for (void* p : h->allocs) (void)hipFree(p);
+  if (h->dtiles) (void)hipFree(h->dtiles);
+  if (h->dtiles_plain) (void)hipFree(h->dtiles_plain);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
 }
@@ -417,6 +482,15 @@ int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* 
     if (e_ != hipSuccess)                                                                   \
       return bail(fail(LBM_AXI_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_))); \
   } while (0)
+  {
+    int dev = 0, lds = 0, ldsb = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ldsb, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      return bail(fail(LBM_AXI_EDEVICE, "device query failed"));
+    h->lds_per_cu = lds;
+    h->lds_per_block = ldsb;
+  }
   if (hip_stream) {
     h->stream = (hipStream_t)hip_stream;
   } else {
@@ -427,8 +501,6 @@ int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* 
   const size_t esz = h->storage == LBM_STORE_FP32 ? 4 : 2;
   hipError_t err = hipSuccess;
   h->hdesc.resize(n_inst);
-  std::vector<int4> tiles;
-  const int tile_h = BY * h->kz;
   for (int i = 0; i < n_inst; ++i) {
     const lbm_axi_params& q = p[i];
     InstDev& D = h->hdesc[i];
@@ -458,29 +530,15 @@ int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* 
           return bail(fail(LBM_AXI_EDEVICE, "check buffer clear"));
       }
     }
-    h->tile_first.push_back((int)tiles.size());
-    for (int k0 = 0; k0 < q.nz; k0 += tile_h)
-      for (int j0 = 0; j0 < q.nr; j0 += BX) tiles.push_back(make_int4(i, j0, k0, 0));
-    h->tile_count.push_back((int)tiles.size() - h->tile_first.back());
   }
-  // XCD-aware order: block b -> tile (b % 8) * per + b / 8.
-  const int T = (int)tiles.size();
-  const int per = (T + 7) / 8;
-  std::vector<int4> order((size_t)per * 8, make_int4(-1, 0, 0, 0));
-  for (int b = 0; b < per * 8; ++b) {
-    const int t = (b % 8) * per + b / 8;
-    if (t < T) order[b] = tiles[t];
+  {
+    const int rc = build_tiles(h, h->kz);
+    if (rc) return bail(rc);
   }
-  h->ntiles_launch = per * 8;
-  h->dtiles = (int4*)dalloc(h, sizeof(int4) * order.size(), &err);
-  h->dtiles_plain = (int4*)dalloc(h, sizeof(int4) * tiles.size(), &err);
   h->ddesc = (InstDev*)dalloc(h, sizeof(InstDev) * n_inst, &err);
   h->dstatus = (int*)dalloc(h, sizeof(int) * n_inst, &err);
   h->dres = (DevResult*)dalloc(h, sizeof(DevResult) * n_inst, &err);
-  if (!h->dtiles || !h->dtiles_plain || !h->ddesc || !h->dstatus || !h->dres)
-    return bail(fail(LBM_AXI_ENOMEM, "descriptor arrays"));
-  HIPBAIL(hipMemcpy(h->dtiles, order.data(), sizeof(int4) * order.size(), hipMemcpyHostToDevice));
-  HIPBAIL(hipMemcpy(h->dtiles_plain, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice));
+  if (!h->ddesc || !h->dstatus || !h->dres) return bail(fail(LBM_AXI_ENOMEM, "descriptor arrays"));
   HIPBAIL(hipMemcpy(h->ddesc, h->hdesc.data(), sizeof(InstDev) * n_inst, hipMemcpyHostToDevice));
   HIPBAIL(hipMemset(h->dstatus, 0, sizeof(int) * n_inst));
   {
@@ -600,15 +658,25 @@ int lbm_axi_step(lbm_axi* h, int32_t nsteps) {
     if (check) {
       k_resid<<<h->nrt, RB, 0, h->stream>>>(h->ddesc, h->drt, slot, h->dpart);
       HIPCHK(hipGetLastError());
-      const int nb = (h->n_inst + 63) / 64;
-      k_final<<<nb, 64, 0, h->stream>>>(h->ddesc, h->dfirst, h->dpart, h->n_inst, n,
-                                         1.0 / h->check, h->dtol, h->dmx, h->dnus, h->dstatus,
-                                         h->dres);
+      k_final<<<h->n_inst, RB, 0, h->stream>>>(h->dfirst, h->dpart, n, 1.0 / h->check, h->dtol,
+                                                h->dmx, h->dnus, h->dstatus, h->dres);
       HIPCHK(hipGetLastError());
     }
     h->t = n + 1;
   }
   return LBM_AXI_OK;
+}
+
+int lbm_axi_set_tiles(lbm_axi* h, int32_t kz, int32_t blocks_per_cu) {
+  if (!h || kz < 1 || kz > 64 || blocks_per_cu < 0 || blocks_per_cu > 64)
+    return fail(LBM_AXI_EINVAL, "bad handle, kz out of [1, 64] or blocks_per_cu out of [0, 64]");
+  HIPCHK(hipStreamSynchronize(h->stream));
+  // Reserving LDS that the kernel does not use caps the blocks resident on a
+  // compute unit; this is the only effect of blocks_per_cu.
+  int lds = blocks_per_cu > 0 ? h->lds_per_cu / blocks_per_cu / 256 * 256 : 0;
+  if (blocks_per_cu > 0 && lds * (blocks_per_cu + 1) <= h->lds_per_cu) lds += 256;
+  h->lds_bytes = lds < h->lds_per_block ? lds : h->lds_per_block;
+  return build_tiles(h, kz);
 }
 
 int lbm_axi_sync(lbm_axi* h) {

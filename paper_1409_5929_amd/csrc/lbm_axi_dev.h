@@ -329,7 +329,7 @@ __host__ __device__ inline void wall_node(const InstDev& D, S* P, const NodeStat
     store_wall<S, ODD>(D, P, jb, kb, d, tg);
   }
   if (MODE == MODE_STEP_MACRO) {
-    float* mac = D.mac[mac_slot];
+    float* mac = mac_slot ? D.mac[1] : D.mac[0];  // select, not index: keeps D out of scratch
     mac[ob] = 0.0f;
     mac[D.plane + ob] = 0.0f;
     mac[2 * D.plane + ob] = Tb;
@@ -423,7 +423,7 @@ __host__ __device__ inline void node_update(const InstDev& D, const RowC& R, int
   const float ur = B.ur, uz = B.uz, rho = B.rho;
 
   if (MODE == MODE_STEP_MACRO) {
-    float* mac = D.mac[mac_slot];
+    float* mac = mac_slot ? D.mac[1] : D.mac[0];  // select, not index: keeps D out of scratch
     mac[o] = uz;
     mac[pl + o] = ur;
     mac[2 * pl + o] = B.T;

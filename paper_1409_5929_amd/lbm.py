@@ -112,6 +112,8 @@ def _load():
     lib.lbm_axi_set_timing.restype = ctypes.c_int
     lib.lbm_axi_kernel_time.argtypes = [ctypes.c_void_p, P(ctypes.c_double), P(ctypes.c_int64)]
     lib.lbm_axi_kernel_time.restype = ctypes.c_int
+    lib.lbm_axi_set_tiles.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]
+    lib.lbm_axi_set_tiles.restype = ctypes.c_int
     lib.lbm_axi_sync.argtypes = [ctypes.c_void_p]
     lib.lbm_axi_sync.restype = ctypes.c_int
     lib.lbm_axi_destroy.argtypes = [ctypes.c_void_p]
@@ -247,6 +249,11 @@ class Lattice:
         out = (ctypes.c_int64 * 4)()
         _check(self._lib.lbm_axi_info(self._h, int(inst), out))
         return dict(t=out[0], t_check=out[1], status=RUN_STATE[out[2]], device_bytes=out[3])
+
+    def set_tiles(self, kz: int, blocks_per_cu: int = 0):
+        """Launch shape of the step kernel: nodes per thread along z and a cap
+        on resident blocks per compute unit (0: none).  Results do not change."""
+        _check(self._lib.lbm_axi_set_tiles(self._h, int(kz), int(blocks_per_cu)))
 
     def set_timing(self, on: bool):
         _check(self._lib.lbm_axi_set_timing(self._h, 1 if on else 0))
