@@ -164,9 +164,9 @@ def main():
     lat.close()
     copy_gbs = device_copy_gbs(torch, stream)
 
-    esz = 4 if args.storage == "fp32" else 2
     fluid = (n - 2) * (n - 2)
-    bytes_node = 28 * esz + 4  # 14 populations read + 14 written, porosity read
+    # 14 populations read + 14 written, porosity read; g_0 stays FP32 in 16-bit storage
+    bytes_node = 116 if args.storage == "fp32" else 26 * 2 + 2 * 4 + 4
     # launches that also write u_z, u_r, T for the check (one per check interval)
     t0 = args.warmup
     macro_launches = sum(1 for t in range(t0, t0 + args.steps)

@@ -193,6 +193,50 @@ int lbm_axi_kernel_time(lbm_axi* h, double* total_ms, int64_t* launches);
  */
 int lbm_axi_set_tiles(lbm_axi* h, int32_t kz, int32_t blocks_per_cu);
 
+/*
+ * Change the storage type of every instance's populations (LBM_STORE_*),
+ * keeping the state: each slot keeps its value, converted to the new type
+ * (rounded to nearest), with temperature slots moved to the new type's shift.
+ * storage_shift means what it means in the parameter struct (0: the type's
+ * default; 0..24).  The intended use is a precision handoff: iterate in
+ * 16-bit storage while the solution still changes by more than the storage
+ * noise, then finish in FP32.
+ * Waits for the stream; allocates the new arrays before freeing the old ones,
+ * so on LBM_AXI_ENOMEM the handle is unchanged.  Step count, the last check
+ * and the check buffers carry over; converged and stalled instances are set
+ * running again (diverged ones stay diverged).
+ */
+int lbm_axi_set_storage(lbm_axi* h, int32_t storage, int32_t storage_shift);
+
+/*
+ * Step graphs: lbm_axi_step sends every run of `steps` consecutive plain
+ * steps (starting at an even time level, no check step inside) through one
+ * captured HIP graph, replayed on the handle's stream; check steps and the
+ * rest are launched one by one.  Results are identical either way.  steps is
+ * even, 0..4096; 0 disables graphs; default 32.  Launch timing
+ * (lbm_axi_set_timing) bypasses the graphs.  Waits for the stream.
+ */
+int lbm_axi_set_graph(lbm_axi* h, int32_t steps);
+
+/*
+ * Drops instances that are no longer running (converged, diverged, stalled)
+ * from the step launch, so that a batch whose instances finish at different
+ * times stops paying for the finished ones.  Reads the run states (waits for
+ * the stream).  *n_running (may be NULL) receives the number still running.
+ */
+int lbm_axi_compact(lbm_axi* h, int32_t* n_running);
+
+/*
+ * Autotuner of the step launch: runs trial_steps real steps (they advance
+ * the solution) with each candidate launch shape (nodes per thread along z
+ * in {1, 2, 4, 8, 16} x resident-block cap in {none, 2, 4} per compute unit),
+ * timing every step launch with HIP events, and keeps the fastest.  The
+ * chosen shape and its mean step-launch time (ms) are returned through the
+ * pointers (each may be NULL).  15 x trial_steps steps are taken in all.
+ */
+int lbm_axi_autotune(lbm_axi* h, int32_t trial_steps, int32_t* kz_out, int32_t* bpc_out,
+                     double* ms_out);
+
 /* Wait for the handle's stream. */
 int lbm_axi_sync(lbm_axi* h);
 

@@ -94,6 +94,12 @@ struct lbm_axi {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
   double timed_ms = 0.0;
   long long timed_launches = 0;
+  std::vector<char> active;     // instances in the launch list (empty: all)
+  long long* dclk = nullptr;    // device clock of captured step graphs
+  int graph_steps = 32;         // steps per captured graph (0: no graphs)
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
 };
 
 // ---- kernels ------------------------------------------------------------------
@@ -103,7 +109,11 @@ template <typename S, bool ODD, int MODE>
 __global__ __launch_bounds__(BX* BY) void k_step(const InstDev* __restrict__ descs,
                                                  const int4* __restrict__ tiles,
                                                  const int* __restrict__ status, int kz,
-                                                 int mac_slot, FieldOut fo) {
+                                                 int mac_slot, FieldOut fo, uint32_t seed,
+                                                 const long long* __restrict__ clk, int off) {
+  // Inside a captured step graph the time level comes from the device clock
+  // (set before every replay) plus the step's offset in the graph.
+  if (clk) seed = step_seed(*clk + off);
   const int4 tl = tiles[blockIdx.x];
   if (tl.x < 0) return;
   if (MODE != MODE_FIELDS && status[tl.x] != RUN) return;
@@ -117,8 +127,13 @@ __global__ __launch_bounds__(BX* BY) void k_step(const InstDev* __restrict__ des
     const int k = tl.z + (int)threadIdx.y + BY * i;
     if (k >= D.nz) break;
     if (zwall && (k == 0 || k == D.nz - 1)) continue;
-    node_update<S, ODD, MODE>(D, R, j, k, mac_slot, fo);
+    node_update<S, ODD, MODE>(D, R, j, k, mac_slot, fo, seed);
   }
+}
+
+// Sets the device clock read by captured step graphs.
+__global__ void k_setclock(long long* clk, long long t) {
+  if (threadIdx.x == 0) *clk = t;
 }
 
 template <typename S>
@@ -154,6 +169,28 @@ __global__ __launch_bounds__(BX* BY) void k_init_uniform(const InstDev* __restri
     if (k >= D.nz) break;
     init_node<S>(D, j, k, 0.0f, 0.0f, T_init);
   }
+}
+
+// Storage conversion of one instance: every slot keeps its deviation; the
+// temperature slots move from the shift T_s of the source storage to that of
+// the target (g_i - wt_i T_s).  Walls' slots are converted like any other.
+template <typename Si, typename So>
+__global__ __launch_bounds__(RB) void k_convert(const InstDev Di, const InstDev Do) {
+  const int64_t o = (int64_t)blockIdx.x * RB + threadIdx.x;
+  if (o >= Di.plane || (int)(o % Di.stride) >= Di.nr) return;
+  const Si* P = (const Si*)Di.pop;
+  So* Q = (So*)Do.pop;
+  const int64_t pl = Di.plane;
+  const float dT = Di.T_s - Do.T_s;
+#pragma unroll
+  for (int q = 0; q < 9; ++q)
+    Store<So>::st(Q, q * pl + o, Store<Si>::ld(P, q * pl + o, Di.st_inv), Do.st_scale);
+  const float g0 = Di.g0[o] + WT0 * dT;
+#pragma unroll
+  for (int q = 1; q < 5; ++q)
+    Store<So>::st(Q, (9 + q) * pl + o, Store<Si>::ld(P, (9 + q) * pl + o, Di.st_inv) + WT1 * dT,
+                  Do.st_scale);
+  Do.g0[o] = g0;  // after the loads: in FP32 both g_0 planes may be plane 9 of one array
 }
 
 __device__ inline double wave_sum(double v) {
@@ -311,19 +348,20 @@ void* dalloc(lbm_axi* h, size_t bytes, hipError_t* err) {
 }
 
 template <typename S>
-int launch_step(lbm_axi* h, bool odd, int mode, int slot) {
+int launch_step(lbm_axi* h, bool odd, int mode, int slot, uint32_t seed, hipStream_t st,
+                const long long* clk, int off) {
   const dim3 blk(BX, BY);
   const FieldOut fo{nullptr, nullptr, nullptr, nullptr, nullptr};
   if (!odd) {
     if (mode == MODE_STEP)
-      k_step<S, false, MODE_STEP><<<h->ntiles_launch, blk, h->lds_bytes, h->stream>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo);
+      k_step<S, false, MODE_STEP><<<h->ntiles_launch, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo, seed, clk, off);
     else
-      k_step<S, false, MODE_STEP_MACRO><<<h->ntiles_launch, blk, h->lds_bytes, h->stream>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo);
+      k_step<S, false, MODE_STEP_MACRO><<<h->ntiles_launch, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo, seed, clk, off);
   } else {
     if (mode == MODE_STEP)
-      k_step<S, true, MODE_STEP><<<h->ntiles_launch, blk, h->lds_bytes, h->stream>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo);
+      k_step<S, true, MODE_STEP><<<h->ntiles_launch, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo, seed, clk, off);
     else
-      k_step<S, true, MODE_STEP_MACRO><<<h->ntiles_launch, blk, h->lds_bytes, h->stream>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo);
+      k_step<S, true, MODE_STEP_MACRO><<<h->ntiles_launch, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo, seed, clk, off);
   }
   HIPCHK(hipGetLastError());
   return LBM_AXI_OK;
@@ -334,9 +372,9 @@ int launch_fields(lbm_axi* h, int inst, bool odd, const FieldOut& fo) {
   const dim3 blk(BX, BY);
   const int4* tl = h->dtiles_plain + h->tile_first[inst];
   if (!odd)
-    k_step<S, false, MODE_FIELDS><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->dstatus, h->kz, 0, fo);
+    k_step<S, false, MODE_FIELDS><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->dstatus, h->kz, 0, fo, 0u, nullptr, 0);
   else
-    k_step<S, true, MODE_FIELDS><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->dstatus, h->kz, 0, fo);
+    k_step<S, true, MODE_FIELDS><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->dstatus, h->kz, 0, fo, 0u, nullptr, 0);
   HIPCHK(hipGetLastError());
   return LBM_AXI_OK;
 }
@@ -357,23 +395,29 @@ int launch_init(lbm_axi* h, int inst, const float* dinit, float T_init) {
 // Launch order: block b takes tile (b % 8) * ceil(T / 8) + b / 8, so that
 // the 8 XCDs, which receive blocks round-robin, each sweep a contiguous run
 // of tiles (neighbouring rows share that XCD's L2).
+// Only instances flagged in h->active (all when it is empty) enter the launch
+// list; the per-instance list (field output) always holds every instance.
 int build_tiles(lbm_axi* h, int kz) {
-  std::vector<int4> tiles;
+  std::vector<int4> tiles, live;
   std::vector<int> first, count;
   const int tile_h = BY * kz;
   for (int i = 0; i < h->n_inst; ++i) {
     const lbm_axi_params& q = h->prm[i];
+    const bool on = h->active.empty() || h->active[i];
     first.push_back((int)tiles.size());
     for (int k0 = 0; k0 < q.nz; k0 += tile_h)
-      for (int j0 = 0; j0 < q.nr; j0 += BX) tiles.push_back(make_int4(i, j0, k0, 0));
+      for (int j0 = 0; j0 < q.nr; j0 += BX) {
+        tiles.push_back(make_int4(i, j0, k0, 0));
+        if (on) live.push_back(tiles.back());
+      }
     count.push_back((int)tiles.size() - first.back());
   }
-  const int T = (int)tiles.size();
-  const int per = (T + 7) / 8;
+  const int T = (int)live.size();
+  const int per = T > 0 ? (T + 7) / 8 : 1;
   std::vector<int4> order((size_t)per * 8, make_int4(-1, 0, 0, 0));
   for (int b = 0; b < per * 8; ++b) {
     const int t = (b % 8) * per + b / 8;
-    if (t < T) order[b] = tiles[t];
+    if (t < T) order[b] = live[t];
   }
   int4 *dt = nullptr, *dp = nullptr;
   if (hipMalloc(&dt, sizeof(int4) * order.size()) != hipSuccess ||
@@ -398,12 +442,71 @@ int build_tiles(lbm_axi* h, int kz) {
   return LBM_AXI_OK;
 }
 
-int dispatch_step(lbm_axi* h, bool odd, int mode, int slot) {
+int dispatch_step(lbm_axi* h, bool odd, int mode, int slot, uint32_t seed,
+                  hipStream_t st = nullptr, const long long* clk = nullptr, int off = 0) {
+  if (!st) st = h->stream;
   switch (h->storage) {
-    case LBM_STORE_FP32: return launch_step<float>(h, odd, mode, slot);
-    case LBM_STORE_FP16: return launch_step<__half>(h, odd, mode, slot);
-    default: return launch_step<__hip_bfloat16>(h, odd, mode, slot);
+    case LBM_STORE_FP32: return launch_step<float>(h, odd, mode, slot, seed, st, clk, off);
+    case LBM_STORE_FP16: return launch_step<__half>(h, odd, mode, slot, seed, st, clk, off);
+    default: return launch_step<__hip_bfloat16>(h, odd, mode, slot, seed, st, clk, off);
   }
+}
+
+void drop_graph(lbm_axi* h) {
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->gexec = nullptr;
+  h->graph = nullptr;
+}
+
+// Captures graph_steps plain steps starting at an even time level (parity
+// even, odd, even, ...), each reading its time level from the device clock.
+int capture_graph(lbm_axi* h) {
+  drop_graph(h);
+  if (!h->cap_stream && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return fail(LBM_AXI_EDEVICE, "capture stream");
+  HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  int rc = LBM_AXI_OK;
+  for (int i = 0; i < h->graph_steps && rc == LBM_AXI_OK; ++i)
+    rc = dispatch_step(h, (i & 1) != 0, MODE_STEP, 0, 0u, h->cap_stream, h->dclk, i);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess || !g) return fail(LBM_AXI_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  h->graph = g;
+  if (hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+    drop_graph(h);
+    return fail(LBM_AXI_EDEVICE, "graph instantiation");
+  }
+  return LBM_AXI_OK;
+}
+
+template <typename Si, typename So>
+void launch_convert(lbm_axi* h, const InstDev& Di, const InstDev& Do) {
+  const int64_t nb = (Di.plane + RB - 1) / RB;
+  k_convert<Si, So><<<(unsigned)nb, RB, 0, h->stream>>>(Di, Do);
+}
+
+template <typename Si>
+void launch_convert_to(lbm_axi* h, int to, const InstDev& Di, const InstDev& Do) {
+  switch (to) {
+    case LBM_STORE_FP32: launch_convert<Si, float>(h, Di, Do); break;
+    case LBM_STORE_FP16: launch_convert<Si, __half>(h, Di, Do); break;
+    default: launch_convert<Si, __hip_bfloat16>(h, Di, Do); break;
+  }
+}
+
+void release(lbm_axi* h, void* p, size_t bytes) {
+  for (size_t i = 0; i < h->allocs.size(); ++i)
+    if (h->allocs[i] == p) {
+      h->allocs.erase(h->allocs.begin() + (long)i);
+      (void)hipFree(p);
+      h->bytes -= bytes;
+      return;
+    }
 }
 
 }  // namespace
@@ -440,6 +543,8 @@ void lbm_axi_destroy(lbm_axi* h) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
   }
+  drop_graph(h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   for (void* p : h->allocs) (void)hipFree(p);
   if (h->dtiles) (void)hipFree(h->dtiles);
   if (h->dtiles_plain) (void)hipFree(h->dtiles_plain);
@@ -512,6 +617,12 @@ int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* 
     }
     D.pop = dalloc(h, (size_t)14 * D.plane * esz, &err);
     if (!D.pop) return bail(fail(LBM_AXI_ENOMEM, std::string("population array: ") + hipGetErrorString(err)));
+    if (h->storage == LBM_STORE_FP32) {
+      D.g0 = (float*)D.pop + 9 * D.plane;
+    } else {
+      D.g0 = (float*)dalloc(h, (size_t)D.plane * 4, &err);
+      if (!D.g0) return bail(fail(LBM_AXI_ENOMEM, std::string("g_0 plane: ") + hipGetErrorString(err)));
+    }
     if (field) {
       float* dphi = (float*)dalloc(h, (size_t)D.plane * 4, &err);
       if (!dphi) return bail(fail(LBM_AXI_ENOMEM, "porosity field"));
@@ -537,8 +648,10 @@ int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* 
   }
   h->ddesc = (InstDev*)dalloc(h, sizeof(InstDev) * n_inst, &err);
   h->dstatus = (int*)dalloc(h, sizeof(int) * n_inst, &err);
+  h->dclk = (long long*)dalloc(h, sizeof(long long), &err);
   h->dres = (DevResult*)dalloc(h, sizeof(DevResult) * n_inst, &err);
-  if (!h->ddesc || !h->dstatus || !h->dres) return bail(fail(LBM_AXI_ENOMEM, "descriptor arrays"));
+  if (!h->ddesc || !h->dstatus || !h->dres || !h->dclk)
+    return bail(fail(LBM_AXI_ENOMEM, "descriptor arrays"));
   HIPBAIL(hipMemcpy(h->ddesc, h->hdesc.data(), sizeof(InstDev) * n_inst, hipMemcpyHostToDevice));
   HIPBAIL(hipMemset(h->dstatus, 0, sizeof(int) * n_inst));
   {
@@ -624,8 +737,24 @@ int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* 
 
 int lbm_axi_step(lbm_axi* h, int32_t nsteps) {
   if (!h || nsteps < 0) return fail(LBM_AXI_EINVAL, "null handle or negative step count");
-  for (int32_t s = 0; s < nsteps; ++s) {
+  const long long t_end = h->t + nsteps;
+  while (h->t < t_end) {
     const long long n = h->t;
+    // A run of graph_steps plain steps from an even level with no check step
+    // inside goes through the captured graph (not while timing launches).
+    const int G = h->graph_steps;
+    if (G >= 2 && !h->timing && (n & 1) == 0 && n + G <= t_end &&
+        (h->check <= 0 || (n + h->check - 1) / h->check * h->check >= n + G)) {
+      if (!h->gexec) {
+        const int rc = capture_graph(h);
+        if (rc) return rc;
+      }
+      k_setclock<<<1, 1, 0, h->stream>>>(h->dclk, n);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipGraphLaunch(h->gexec, h->stream));
+      h->t = n + G;
+      continue;
+    }
     const bool odd = (n & 1) != 0;
     // At every multiple of the check interval the step also writes u_z, u_r,
     // T into one of two buffers (alternating); from the second one on, the
@@ -644,7 +773,8 @@ int lbm_axi_step(lbm_axi* h, int32_t nsteps) {
       h->ev.emplace_back(e0, e1);
       HIPCHK(hipEventRecord(e0, h->stream));
     }
-    int rc = dispatch_step(h, odd, mode, slot);
+    // random bits of this step for stochastic rounding (16-bit storage)
+    int rc = dispatch_step(h, odd, mode, slot, step_seed(n));
     if (rc) return rc;
     if (h->timing) {
       HIPCHK(hipEventRecord(h->ev.back().second, h->stream));
@@ -667,6 +797,137 @@ int lbm_axi_step(lbm_axi* h, int32_t nsteps) {
   return LBM_AXI_OK;
 }
 
+int lbm_axi_set_graph(lbm_axi* h, int32_t steps) {
+  if (!h || steps < 0 || steps > 4096 || (steps & 1))
+    return fail(LBM_AXI_EINVAL, "bad handle or graph steps not an even number in [0, 4096]");
+  HIPCHK(hipStreamSynchronize(h->stream));
+  drop_graph(h);
+  h->graph_steps = steps;
+  return LBM_AXI_OK;
+}
+
+int lbm_axi_compact(lbm_axi* h, int32_t* n_running) {
+  if (!h) return fail(LBM_AXI_EINVAL, "null handle");
+  std::vector<int> st(h->n_inst);
+  HIPCHK(hipMemcpyAsync(st.data(), h->dstatus, sizeof(int) * h->n_inst, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  std::vector<char> act(h->n_inst);
+  int nr = 0;
+  for (int i = 0; i < h->n_inst; ++i) {
+    act[i] = st[i] == RUN;
+    nr += act[i];
+  }
+  if (n_running) *n_running = nr;
+  if (act == h->active || (h->active.empty() && nr == h->n_inst)) return LBM_AXI_OK;
+  h->active = act;
+  drop_graph(h);
+  return build_tiles(h, h->kz);
+}
+
+int lbm_axi_autotune(lbm_axi* h, int32_t trial_steps, int32_t* kz_out, int32_t* bpc_out,
+                     double* ms_out) {
+  if (!h || trial_steps < 1) return fail(LBM_AXI_EINVAL, "null handle or trial_steps < 1");
+  static const int KZ[] = {1, 2, 4, 8, 16};
+  static const int BPC[] = {0, 2, 4};
+  const bool was_timing = h->timing;
+  double best = HUGE_VAL;
+  int bk = h->kz, bb = 0;
+  for (int kz : KZ)
+    for (int bpc : BPC) {
+      int rc = lbm_axi_set_tiles(h, kz, bpc);
+      if (rc) return rc;
+      h->timing = false;
+      rc = lbm_axi_set_timing(h, 1);  // restarts the launch timer
+      if (rc) return rc;
+      rc = lbm_axi_step(h, trial_steps);
+      if (rc) return rc;
+      double ms = 0.0;
+      int64_t nl = 0;
+      rc = lbm_axi_kernel_time(h, &ms, &nl);
+      if (rc) return rc;
+      const double per = nl > 0 ? ms / (double)nl : HUGE_VAL;
+      if (per < best) {
+        best = per;
+        bk = kz;
+        bb = bpc;
+      }
+    }
+  h->timing = false;
+  int rc = lbm_axi_set_timing(h, was_timing ? 1 : 0);
+  if (rc) return rc;
+  rc = lbm_axi_set_tiles(h, bk, bb);
+  if (rc) return rc;
+  if (kz_out) *kz_out = bk;
+  if (bpc_out) *bpc_out = bb;
+  if (ms_out) *ms_out = best;
+  return LBM_AXI_OK;
+}
+
+int lbm_axi_set_storage(lbm_axi* h, int32_t storage, int32_t storage_shift) {
+  if (!h || storage < LBM_STORE_FP32 || storage > LBM_STORE_BF16 || storage_shift < 0 ||
+      storage_shift > 24)
+    return fail(LBM_AXI_EINVAL, "bad handle, storage type or storage_shift out of [0, 24]");
+  HIPCHK(hipStreamSynchronize(h->stream));
+  drop_graph(h);
+  const int from = h->storage;
+  const size_t esz_o = from == LBM_STORE_FP32 ? 4 : 2;
+  const size_t esz_n = storage == LBM_STORE_FP32 ? 4 : 2;
+  std::vector<InstDev> nd(h->n_inst);
+  std::vector<lbm_axi_params> np(h->prm);
+  hipError_t err = hipSuccess;
+  // Allocate everything first: on failure the handle is left as it was.
+  for (int i = 0; i < h->n_inst; ++i) {
+    np[i].storage = storage;
+    np[i].storage_shift = storage_shift;
+    std::string msg;
+    const InstDev& Do = h->hdesc[i];
+    InstDev& Dn = nd[i];
+    int rc = describe(np[i], Do.phi != nullptr, Dn, msg);
+    void* pop = rc ? nullptr : dalloc(h, (size_t)14 * Dn.plane * esz_n, &err);
+    float* g0 = nullptr;
+    if (pop) g0 = storage == LBM_STORE_FP32 ? (float*)pop + 9 * Dn.plane
+                                            : (float*)dalloc(h, (size_t)Dn.plane * 4, &err);
+    if (rc || !pop || !g0) {
+      for (int k = 0; k <= i; ++k) {
+        if (nd[k].pop) release(h, nd[k].pop, (size_t)14 * nd[k].plane * esz_n);
+        if (nd[k].g0 && storage != LBM_STORE_FP32) release(h, nd[k].g0, (size_t)nd[k].plane * 4);
+      }
+      if (pop) release(h, pop, (size_t)14 * Dn.plane * esz_n);
+      return fail(rc ? rc : LBM_AXI_ENOMEM, rc ? msg : "population array for the new storage");
+    }
+    Dn.pop = pop;
+    Dn.g0 = g0;
+    Dn.phi = Do.phi;
+    Dn.mac[0] = Do.mac[0];
+    Dn.mac[1] = Do.mac[1];
+  }
+  for (int i = 0; i < h->n_inst; ++i) {
+    switch (from) {
+      case LBM_STORE_FP32: launch_convert_to<float>(h, storage, h->hdesc[i], nd[i]); break;
+      case LBM_STORE_FP16: launch_convert_to<__half>(h, storage, h->hdesc[i], nd[i]); break;
+      default: launch_convert_to<__hip_bfloat16>(h, storage, h->hdesc[i], nd[i]); break;
+    }
+    HIPCHK(hipGetLastError());
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  for (int i = 0; i < h->n_inst; ++i) {
+    const InstDev& Do = h->hdesc[i];
+    if (from != LBM_STORE_FP32) release(h, Do.g0, (size_t)Do.plane * 4);
+    release(h, Do.pop, (size_t)14 * Do.plane * esz_o);
+  }
+  h->hdesc = nd;
+  h->prm = np;
+  h->storage = storage;
+  HIPCHK(hipMemcpy(h->ddesc, h->hdesc.data(), sizeof(InstDev) * h->n_inst, hipMemcpyHostToDevice));
+  // Converged or stalled runs continue in the new storage; diverged ones stay.
+  std::vector<int> st(h->n_inst);
+  HIPCHK(hipMemcpy(st.data(), h->dstatus, sizeof(int) * h->n_inst, hipMemcpyDeviceToHost));
+  for (int& v : st)
+    if (v == CONVERGED || v == STALLED) v = RUN;
+  HIPCHK(hipMemcpy(h->dstatus, st.data(), sizeof(int) * h->n_inst, hipMemcpyHostToDevice));
+  return LBM_AXI_OK;
+}
+
 int lbm_axi_set_tiles(lbm_axi* h, int32_t kz, int32_t blocks_per_cu) {
   if (!h || kz < 1 || kz > 64 || blocks_per_cu < 0 || blocks_per_cu > 64)
     return fail(LBM_AXI_EINVAL, "bad handle, kz out of [1, 64] or blocks_per_cu out of [0, 64]");
@@ -676,6 +937,7 @@ int lbm_axi_set_tiles(lbm_axi* h, int32_t kz, int32_t blocks_per_cu) {
   int lds = blocks_per_cu > 0 ? h->lds_per_cu / blocks_per_cu / 256 * 256 : 0;
   if (blocks_per_cu > 0 && lds * (blocks_per_cu + 1) <= h->lds_per_cu) lds += 256;
   h->lds_bytes = lds < h->lds_per_block ? lds : h->lds_per_block;
+  drop_graph(h);
   return build_tiles(h, kz);
 }
 

@@ -65,6 +65,9 @@ struct InstDev {
   int32_t src_printed;
   int32_t phi_mode;  // 0 uniform, 1 field with Ergun F_phi, 2 field with constant F_phi
   void* pop;         // 14 planes
+  float* g0;         // plane of g_0 - wt_0 T_s in FP32 for every storage type: plane 9 of
+                     // pop in FP32, its own plane otherwise (g_0 never streams and carries
+                     // most of T, so 16 bits there would dominate the error of T)
   const float* phi;  // [nz][stride] porosity field or null
   float* mac[2];     // two check buffers, 3 planes each: u_z, u_r, T
   float r0, T_ref, gbeta, accel_r, accel_z;
@@ -86,12 +89,24 @@ struct FieldOut {
 };
 
 // ---- storage types --------------------------------------------------------
+// st() rounds to nearest even; st_sr() rounds stochastically with 32 random
+// bits r: the FP32 value is rounded away from zero with probability equal to
+// its distance from the 16-bit value below (in magnitude) over the 16-bit
+// spacing, so that the stored value is unbiased.  Adding the random bits to
+// the FP32 bit pattern below the 16-bit mantissa and truncating does exactly
+// that (the carry moves into the next mantissa step or exponent); results in
+// the FP16 subnormal range (|v sc| < 2^-14) are rounded to nearest after.
+// Deterministic rounding lets a slowly varying population round back to its
+// old value step after step, so a run freezes short of its steady state.
 template <typename S>
 struct Store;
 template <>
 struct Store<float> {
   __host__ __device__ static inline float ld(const float* p, int64_t i, float) { return p[i]; }
   __host__ __device__ static inline void st(float* p, int64_t i, float v, float) { p[i] = v; }
+  __host__ __device__ static inline void st_sr(float* p, int64_t i, float v, float, uint32_t) {
+    p[i] = v;
+  }
 };
 template <>
 struct Store<__half> {
@@ -101,6 +116,11 @@ struct Store<__half> {
   __host__ __device__ static inline void st(__half* p, int64_t i, float v, float sc) {
     p[i] = __float2half_rn(v * sc);
   }
+  __host__ __device__ static inline void st_sr(__half* p, int64_t i, float v, float sc,
+                                               uint32_t r) {
+    const uint32_t b = (__float_as_uint(v * sc) + (r >> 19)) & 0xFFFFE000u;  // 13 dropped bits
+    p[i] = __float2half_rn(__uint_as_float(b));
+  }
 };
 template <>
 struct Store<__hip_bfloat16> {
@@ -109,6 +129,36 @@ struct Store<__hip_bfloat16> {
   }
   __host__ __device__ static inline void st(__hip_bfloat16* p, int64_t i, float v, float sc) {
     p[i] = __float2bfloat16(v * sc);
+  }
+  __host__ __device__ static inline void st_sr(__hip_bfloat16* p, int64_t i, float v, float sc,
+                                               uint32_t r) {
+    const uint32_t b = (__float_as_uint(v * sc) + (r >> 16)) & 0xFFFF0000u;  // 16 dropped bits
+    p[i] = __float2bfloat16(__uint_as_float(b));
+  }
+};
+
+// Random bits for stochastic rounding: a 32-bit integer hash (xorshift-
+// multiply finaliser, Wellons' "lowbias32" constants) of the step seed and
+// the node's offset seeds a per-node linear congruential stream (Knuth's
+// MMIX multiplier and increment, low 32 bits); each store takes the high
+// bits of the next state.
+__host__ __device__ inline uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+// Random bits of time level n (one value per step, shared by all nodes).
+__host__ __device__ inline uint32_t step_seed(long long n) {
+  return mix32((uint32_t)n * 0x9E3779B9u + (uint32_t)((unsigned long long)n >> 32));
+}
+struct Dither {
+  uint32_t s;
+  __host__ __device__ inline uint32_t next() {
+    s = s * 1664525u + 1013904223u;
+    return s;
   }
 };
 
@@ -255,7 +305,7 @@ struct NodeState {
 
 template <typename S, bool ODD>
 __host__ __device__ inline void store_wall(const InstDev& D, S* P, int jb, int kb, const float d[9],
-                                           const float tg[5]) {
+                                           const float tg[5], Dither& rn) {
   constexpr int EXr[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
   constexpr int EZr[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
   constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
@@ -264,17 +314,19 @@ __host__ __device__ inline void store_wall(const InstDev& D, S* P, int jb, int k
     int kd = kb + EZr[i];
     if (!fluid_dest(D, jb + EXr[i], kd)) continue;
     if (ODD)
-      Store<S>::st(P, i * pl + (int64_t)kd * D.stride + jb + EXr[i], d[i], D.st_scale);
+      Store<S>::st_sr(P, i * pl + (int64_t)kd * D.stride + jb + EXr[i], d[i], D.st_scale, rn.next());
     else
-      Store<S>::st(P, OPP[i] * pl + (int64_t)kb * D.stride + jb, d[i], D.st_scale);
+      Store<S>::st_sr(P, OPP[i] * pl + (int64_t)kb * D.stride + jb, d[i], D.st_scale, rn.next());
   }
   for (int i = 1; i < 5; ++i) {
     int kd = kb + EZr[i];
     if (!fluid_dest(D, jb + EXr[i], kd)) continue;
     if (ODD)
-      Store<S>::st(P, (9 + i) * pl + (int64_t)kd * D.stride + jb + EXr[i], tg[i], D.st_scale);
+      Store<S>::st_sr(P, (9 + i) * pl + (int64_t)kd * D.stride + jb + EXr[i], tg[i], D.st_scale,
+                      rn.next());
     else
-      Store<S>::st(P, (9 + OPP[i]) * pl + (int64_t)kb * D.stride + jb, tg[i], D.st_scale);
+      Store<S>::st_sr(P, (9 + OPP[i]) * pl + (int64_t)kb * D.stride + jb, tg[i], D.st_scale,
+                      rn.next());
   }
 }
 
@@ -283,7 +335,7 @@ __host__ __device__ inline void store_wall(const InstDev& D, S* P, int jb, int k
 template <typename S, bool ODD, int MODE>
 __host__ __device__ inline void wall_node(const InstDev& D, S* P, const NodeState& B, float rB,
                                           int j, int k, int dr, int dz, int mac_slot,
-                                          const FieldOut& fo) {
+                                          const FieldOut& fo, Dither& rn) {
   const int jb = j + dr, kb = k + dz;
   const float rb = rB + (float)dr;
   const float inv_rb = 1.0f / rb;
@@ -326,7 +378,7 @@ __host__ __device__ inline void wall_node(const InstDev& D, S* P, const NodeStat
       const float gneq = qn[i] - 5.0f * wt[i] * B.T * eu[i];
       tg[i] = wt[i] * (Tb - D.T_s) + (1.0f - om[i]) * gneq;
     }
-    store_wall<S, ODD>(D, P, jb, kb, d, tg);
+    store_wall<S, ODD>(D, P, jb, kb, d, tg, rn);
   }
   if (MODE == MODE_STEP_MACRO) {
     float* mac = mac_slot ? D.mac[1] : D.mac[0];  // select, not index: keeps D out of scratch
@@ -345,9 +397,10 @@ __host__ __device__ inline void wall_node(const InstDev& D, S* P, const NodeStat
 }
 
 // One fluid node (j, k) at one time step.
+// seed: random bits of this step for stochastic rounding of 16-bit storage.
 template <typename S, bool ODD, int MODE>
 __host__ __device__ inline void node_update(const InstDev& D, const RowC& R, int j, int k,
-                                            int mac_slot, const FieldOut& fo) {
+                                            int mac_slot, const FieldOut& fo, uint32_t seed) {
   S* __restrict__ P = (S*)D.pop;
   const int64_t pl = D.plane;
   const int st = D.stride;
@@ -358,15 +411,17 @@ __host__ __device__ inline void node_update(const InstDev& D, const RowC& R, int
     if (kp >= D.nz) kp -= D.nz;
   }
   const int64_t o = (int64_t)k * st + j;
+  Dither rn{mix32(seed ^ (uint32_t)o)};
   const int64_t rowm = (int64_t)km * st, row0 = (int64_t)k * st, rowp = (int64_t)kp * st;
 
-  // ---- a1: load the populations arriving at x --------------------------------
+  // ---- load the populations arriving at x --------------------------------
   float s[9], t[5];
   if (!ODD) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) s[q] = Store<S>::ld(P, q * pl + o, inv_sc);
+    t[0] = D.g0[o];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) t[q] = Store<S>::ld(P, (9 + q) * pl + o, inv_sc);
+    for (int q = 1; q < 5; ++q) t[q] = Store<S>::ld(P, (9 + q) * pl + o, inv_sc);
   } else {
     const int64_t cm = R.cm, cp = R.cp;
     s[0] = Store<S>::ld(P, o, inv_sc);
@@ -378,7 +433,7 @@ __host__ __device__ inline void node_update(const InstDev& D, const RowC& R, int
     s[6] = Store<S>::ld(P, 8 * pl + rowm + cp, inv_sc);
     s[7] = Store<S>::ld(P, 5 * pl + rowp + cp, inv_sc);
     s[8] = Store<S>::ld(P, (R.mir ? 5 : 6) * pl + rowp + cm, inv_sc);
-    t[0] = Store<S>::ld(P, 9 * pl + o, inv_sc);
+    t[0] = D.g0[o];
     t[1] = Store<S>::ld(P, (R.mir ? 10 : 12) * pl + row0 + cm, inv_sc);
     t[2] = Store<S>::ld(P, 13 * pl + rowm + j, inv_sc);
     t[3] = Store<S>::ld(P, 10 * pl + row0 + cp, inv_sc);
@@ -399,7 +454,7 @@ __host__ __device__ inline void node_update(const InstDev& D, const RowC& R, int
   d[6] = s[6] * R.rm + R.om5;
   d[7] = s[7] * R.rm + R.om5;
 
-  // ---- a2: macroscopic values ------------------------------------------------
+  // ---- macroscopic values ------------------------------------------------
   NodeState B;
   const float sa = d[1] + d[2] + d[3] + d[4], sd = d[5] + d[6] + d[7] + d[8];
   B.drho = d[0] + sa + sd;                                  // rho - 1, Eq. (26)
@@ -437,14 +492,14 @@ __host__ __device__ inline void node_update(const InstDev& D, const RowC& R, int
     if (fo.mask) fo.mask[oo] = node_mask(D, j, k);
   }
 
-  // ---- a3: forces (Eq. 6) and the axisymmetric correction (Eq. 25) -----------
+  // ---- forces (Eq. 6) and the axisymmetric correction (Eq. 25) -----------
   const float um = sqrtf(ur * ur + uz * uz);
   const float drag = cD + cF * um;
   const float Fr = phi * Gr - drag * ur;
   const float Fz = phi * Gz - drag * uz;
   const float ar = R.ar0 - R.ar1 * ur;
 
-  // ---- a4: moments of d and the non-equilibrium part (Eqs. 16-20) -----------
+  // ---- moments of d and the non-equilibrium part (Eqs. 16-20) -----------
   const float iphi = 1.0f / phi;
   const float ru2 = rho * (ur * ur + uz * uz) * iphi;
   B.n1 = (-4.0f * d[0] - sa + 2.0f * sd) + 2.0f * B.drho - 3.0f * ru2;
@@ -458,7 +513,7 @@ __host__ __device__ inline void node_update(const InstDev& D, const RowC& R, int
   B.n8 = (d[5] - d[6] + d[7] - d[8]) - rho * ur * uz * iphi;
 
   if (MODE != MODE_FIELDS) {
-    // ---- a5: source (Eq. 24) and relaxation (Eq. 21) --------------------------
+    // ---- source (Eq. 24) and relaxation (Eq. 21) --------------------------
     float S1, S7, S8;
     source(D.src_printed != 0, rho, ur, uz, iphi, Fr, Fz, ar, S1, S7, S8);
     const float S5 = rho * Fz;
@@ -471,7 +526,7 @@ __host__ __device__ inline void node_update(const InstDev& D, const RowC& R, int
                      (2.0f - D.s_j) * R.hcs2r * B.drho;
     const float X4 = -D.s_q * (m4 + rho * ur) - (1.0f - 0.5f * D.s_q) * S3d -
                      (2.0f - D.s_q) * R.hcs2r * B.drho;
-    // ---- a6: back-transform (Eq. 22) ------------------------------------------
+    // ---- back-transform (Eq. 22) ------------------------------------------
     back_transform(d, -D.s_e * B.n1 + (1.0f - 0.5f * D.s_e) * S1,
                    -D.s_eps * B.n2 - (1.0f - 0.5f * D.s_eps) * S1, X3, X4,
                    -D.s_j * B.n5 + (1.0f - 0.5f * D.s_j) * S5,
@@ -479,7 +534,7 @@ __host__ __device__ inline void node_update(const InstDev& D, const RowC& R, int
                    -D.s_nu * B.n7 + (1.0f - 0.5f * D.s_nu) * S7,
                    -D.s_nu * B.n8 + (1.0f - 0.5f * D.s_nu) * S8);
 
-    // ---- a7: temperature collision (Eqs. 33-37) ------------------------------
+    // ---- temperature collision (Eqs. 33-37) ------------------------------
     // q_i = g_i - wt_i T is the part of g - g^eq that does not depend on u;
     // q_0 is formed as -(q_1 + ... + q_4) so that the rounding of theta and of
     // the FP32 weights cannot leak into sum_i g_i step after step.
@@ -500,44 +555,44 @@ __host__ __device__ inline void node_update(const InstDev& D, const RowC& R, int
     }
     for (int q = 0; q < 5; ++q) B.t[q] = t[q];
 
-    // ---- a9: stream and store --------------------------------------------------
+    // ---- stream and store --------------------------------------------------
     if (!ODD) {
-      Store<S>::st(P, 0 * pl + o, d[0], sc);
-      Store<S>::st(P, 3 * pl + o, d[1], sc);
-      Store<S>::st(P, 4 * pl + o, d[2], sc);
-      Store<S>::st(P, 1 * pl + o, d[3], sc);
-      Store<S>::st(P, 2 * pl + o, d[4], sc);
-      Store<S>::st(P, 7 * pl + o, d[5], sc);
-      Store<S>::st(P, 8 * pl + o, d[6], sc);
-      Store<S>::st(P, 5 * pl + o, d[7], sc);
-      Store<S>::st(P, 6 * pl + o, d[8], sc);
-      Store<S>::st(P, 9 * pl + o, tg[0], sc);
-      Store<S>::st(P, 12 * pl + o, tg[1], sc);
-      Store<S>::st(P, 13 * pl + o, tg[2], sc);
-      Store<S>::st(P, 10 * pl + o, tg[3], sc);
-      Store<S>::st(P, 11 * pl + o, tg[4], sc);
+      Store<S>::st_sr(P, 0 * pl + o, d[0], sc, rn.next());
+      Store<S>::st_sr(P, 3 * pl + o, d[1], sc, rn.next());
+      Store<S>::st_sr(P, 4 * pl + o, d[2], sc, rn.next());
+      Store<S>::st_sr(P, 1 * pl + o, d[3], sc, rn.next());
+      Store<S>::st_sr(P, 2 * pl + o, d[4], sc, rn.next());
+      Store<S>::st_sr(P, 7 * pl + o, d[5], sc, rn.next());
+      Store<S>::st_sr(P, 8 * pl + o, d[6], sc, rn.next());
+      Store<S>::st_sr(P, 5 * pl + o, d[7], sc, rn.next());
+      Store<S>::st_sr(P, 6 * pl + o, d[8], sc, rn.next());
+      D.g0[o] = tg[0];
+      Store<S>::st_sr(P, 12 * pl + o, tg[1], sc, rn.next());
+      Store<S>::st_sr(P, 13 * pl + o, tg[2], sc, rn.next());
+      Store<S>::st_sr(P, 10 * pl + o, tg[3], sc, rn.next());
+      Store<S>::st_sr(P, 11 * pl + o, tg[4], sc, rn.next());
     } else {
       const int64_t cm = R.cm, cp = R.cp;
-      Store<S>::st(P, o, d[0], sc);
-      Store<S>::st(P, 1 * pl + row0 + cp, d[1], sc);
-      Store<S>::st(P, 2 * pl + rowp + j, d[2], sc);
-      Store<S>::st(P, (R.mir ? 1 : 3) * pl + row0 + cm, d[3], sc);
-      Store<S>::st(P, 4 * pl + rowm + j, d[4], sc);
-      Store<S>::st(P, 5 * pl + rowp + cp, d[5], sc);
-      Store<S>::st(P, (R.mir ? 5 : 6) * pl + rowp + cm, d[6], sc);
-      Store<S>::st(P, (R.mir ? 8 : 7) * pl + rowm + cm, d[7], sc);
-      Store<S>::st(P, 8 * pl + rowm + cp, d[8], sc);
-      Store<S>::st(P, 9 * pl + o, tg[0], sc);
-      Store<S>::st(P, 10 * pl + row0 + cp, tg[1], sc);
-      Store<S>::st(P, 11 * pl + rowp + j, tg[2], sc);
-      Store<S>::st(P, (R.mir ? 10 : 12) * pl + row0 + cm, tg[3], sc);
-      Store<S>::st(P, 13 * pl + rowm + j, tg[4], sc);
+      Store<S>::st_sr(P, o, d[0], sc, rn.next());
+      Store<S>::st_sr(P, 1 * pl + row0 + cp, d[1], sc, rn.next());
+      Store<S>::st_sr(P, 2 * pl + rowp + j, d[2], sc, rn.next());
+      Store<S>::st_sr(P, (R.mir ? 1 : 3) * pl + row0 + cm, d[3], sc, rn.next());
+      Store<S>::st_sr(P, 4 * pl + rowm + j, d[4], sc, rn.next());
+      Store<S>::st_sr(P, 5 * pl + rowp + cp, d[5], sc, rn.next());
+      Store<S>::st_sr(P, (R.mir ? 5 : 6) * pl + rowp + cm, d[6], sc, rn.next());
+      Store<S>::st_sr(P, (R.mir ? 8 : 7) * pl + rowm + cm, d[7], sc, rn.next());
+      Store<S>::st_sr(P, 8 * pl + rowm + cp, d[8], sc, rn.next());
+      D.g0[o] = tg[0];
+      Store<S>::st_sr(P, 10 * pl + row0 + cp, tg[1], sc, rn.next());
+      Store<S>::st_sr(P, 11 * pl + rowp + j, tg[2], sc, rn.next());
+      Store<S>::st_sr(P, (R.mir ? 10 : 12) * pl + row0 + cm, tg[3], sc, rn.next());
+      Store<S>::st_sr(P, 13 * pl + rowm + j, tg[4], sc, rn.next());
     }
   } else {
     for (int q = 0; q < 5; ++q) B.t[q] = t[q];
   }
 
-  // ---- a8: wall nodes owned by this node ---------------------------------------
+  // ---- wall nodes owned by this node ---------------------------------------
   const bool own_rm = D.side_rmin == SIDE_WALL && j == 1;
   const bool own_rp = D.side_rmax == SIDE_WALL && j == D.nr - 2;
   const bool own_zm = D.side_z == SIDE_WALL && k == 1;
@@ -548,7 +603,7 @@ __host__ __device__ inline void node_update(const InstDev& D, const RowC& R, int
       for (int dz = -1; dz <= 1; ++dz) {
         if (dr == 0 && dz == 0) continue;
         if ((dz == -1 && !own_zm) || (dz == 1 && !own_zp)) continue;
-        wall_node<S, ODD, MODE>(D, P, B, R.r, j, k, dr, dz, mac_slot, fo);
+        wall_node<S, ODD, MODE>(D, P, B, R.r, j, k, dr, dz, mac_slot, fo, rn);
       }
     }
   }
@@ -608,7 +663,8 @@ __host__ __device__ inline void init_node(const InstDev& D, int j, int k, float 
   }
   const float eu[5] = {0.0f, ur, uz, -ur, -uz};
   const float wt[5] = {WT0, WT1, WT1, WT1, WT1};
-  for (int i = 0; i < 5; ++i)
+  D.g0[o] = wt[0] * (T - D.T_s);
+  for (int i = 1; i < 5; ++i)
     Store<S>::st(P, (9 + i) * D.plane + o, wt[i] * (T * (1.0f + 5.0f * eu[i]) - D.T_s),
                  D.st_scale);
 }

@@ -69,8 +69,8 @@ def make_params(cfg: dict, storage: str = "fp32", check_interval: int = 100, tol
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
     p.storage_shift = int(storage_shift)
     p.check_interval = int(check_interval)
-    p.tol = float(tol)
-    p.max_steps = int(max_steps)
+    p.tol = float(cfg.get("tol", tol))  # a problem may carry its own stopping rule
+    p.max_steps = int(cfg.get("max_steps", max_steps))
     return p
 
 
@@ -114,6 +114,15 @@ def _load():
     lib.lbm_axi_kernel_time.restype = ctypes.c_int
     lib.lbm_axi_set_tiles.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]
     lib.lbm_axi_set_tiles.restype = ctypes.c_int
+    lib.lbm_axi_set_storage.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]
+    lib.lbm_axi_set_storage.restype = ctypes.c_int
+    lib.lbm_axi_set_graph.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    lib.lbm_axi_set_graph.restype = ctypes.c_int
+    lib.lbm_axi_compact.argtypes = [ctypes.c_void_p, P(ctypes.c_int32)]
+    lib.lbm_axi_compact.restype = ctypes.c_int
+    lib.lbm_axi_autotune.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_int32),
+                                     P(ctypes.c_int32), P(ctypes.c_double)]
+    lib.lbm_axi_autotune.restype = ctypes.c_int
     lib.lbm_axi_sync.argtypes = [ctypes.c_void_p]
     lib.lbm_axi_sync.restype = ctypes.c_int
     lib.lbm_axi_destroy.argtypes = [ctypes.c_void_p]
@@ -254,6 +263,30 @@ class Lattice:
         """Launch shape of the step kernel: nodes per thread along z and a cap
         on resident blocks per compute unit (0: none).  Results do not change."""
         _check(self._lib.lbm_axi_set_tiles(self._h, int(kz), int(blocks_per_cu)))
+
+    def set_storage(self, storage: str, storage_shift: int = 0):
+        """Convert the populations to another storage type ("fp32", "fp16",
+        "bf16") in place, keeping the state (precision handoff)."""
+        code = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        _check(self._lib.lbm_axi_set_storage(self._h, code, int(storage_shift)))
+        self.storage = storage
+
+    def set_graph(self, steps: int):
+        """Steps per captured step graph (even, 0 disables)."""
+        _check(self._lib.lbm_axi_set_graph(self._h, int(steps)))
+
+    def compact(self) -> int:
+        """Drop finished instances from the step launch; returns the number running."""
+        n = ctypes.c_int32()
+        _check(self._lib.lbm_axi_compact(self._h, ctypes.byref(n)))
+        return n.value
+
+    def autotune(self, trial_steps: int = 20) -> dict:
+        """Time every candidate launch shape on real steps and keep the fastest."""
+        kz, bpc, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(self._lib.lbm_axi_autotune(self._h, int(trial_steps), ctypes.byref(kz),
+                                          ctypes.byref(bpc), ctypes.byref(ms)))
+        return dict(kz=kz.value, blocks_per_cu=bpc.value, ms=ms.value)
 
     def set_timing(self, on: bool):
         _check(self._lib.lbm_axi_set_timing(self._h, 1 if on else 0))

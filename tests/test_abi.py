@@ -85,4 +85,9 @@ def test_null_handles_are_refused():
     lib, _ = _lib()
     assert lib.lbm_axi_step(None, 1) == -1
     assert lib.lbm_axi_sync(None) == -1
+    assert lib.lbm_axi_set_storage(None, 1, 0) == -1
+    assert lib.lbm_axi_set_tiles(None, 4, 0) == -1
+    assert lib.lbm_axi_set_graph(None, 32) == -1
+    assert lib.lbm_axi_compact(None, None) == -1
+    assert lib.lbm_axi_autotune(None, 1, None, None, None) == -1
     lib.lbm_axi_destroy(None)  # allowed

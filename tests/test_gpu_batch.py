@@ -1,0 +1,105 @@
+"""Batched instances, captured step graphs, launch compaction and the launch
+autotuner.  None of them may change a result: every comparison here is
+bit-exact against the plain one-launch-per-step path, and a sample of the
+sweep instances is compared with the FP64 oracle."""
+import numpy as np
+import pytest
+
+import lbm_inputs as li
+from tests.parity import TOL_FP32, assert_parity
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("uz", "ur", "p", "T", "mask")
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1409_5929_amd import lbm
+
+    lbm._load()
+    return lbm
+
+
+def same(a, b, label):
+    for k in KEYS:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=f"{label}: {k}")
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+@pytest.mark.parametrize("G", [8, 32])
+def test_graph_replays_match_one_launch_per_step(L, storage, G):
+    """Replays with eager check steps, field reads and synchronisations in
+    between; every replay checked against the eager path."""
+    cfgs = [li.annulus(nr=96, nz=72, Ra=1e5, Da=1e-3), li.annulus(nr=40, nz=130, Ra=1e4, Da=1e-5, Rstar=5.0)]
+    eager = L.Lattice(cfgs, storage=storage, check_interval=50)
+    eager.set_graph(0)
+    graph = L.Lattice(cfgs, storage=storage, check_interval=50)
+    graph.set_graph(G)
+    for chunk in (1, 37, 64, 100, 3, 200):  # odd starts and ends, several replays per chunk
+        eager.step(chunk)
+        graph.step(chunk)
+        for i in range(2):
+            same(eager.fields(i), graph.fields(i), f"{storage} G={G} after {eager.info()['t']}")
+        re, rg = eager.residual(), graph.residual()
+        for k in ("res", "nu_i", "nu_o", "status"):
+            np.testing.assert_array_equal(re[k], rg[k])
+    eager.close()
+    graph.close()
+
+
+def test_compaction_keeps_running_instances_exact(L):
+    """Instance 1 is a quiescent conduction-free annulus (uniform T at the
+    wall temperature): its residual is zero at the first check, it
+    converges and is dropped from the launch; the others are unchanged."""
+    quiet = li.annulus(nr=64, nz=64, Ra=1e4, Da=1e-3)
+    quiet.update(T_rmin=0.0, T_rmax=0.0, T_init=0.0, T_ref=0.0, tol=1e-12)
+    cfgs = [li.annulus(nr=96, nz=72, Ra=1e5, Da=1e-3), quiet, li.annulus(nr=33, nz=97, Ra=1e6, Da=1e-2)]
+    a = L.Lattice(cfgs, check_interval=20)
+    b = L.Lattice(cfgs, check_interval=20)
+    a.step(61)
+    b.step(61)
+    assert b.info(1)["status"] == "converged"
+    assert b.compact() == 2
+    a.step(150)
+    b.step(150)
+    for i in (0, 2):
+        same(a.fields(i), b.fields(i), f"instance {i}")
+    assert b.info(1)["t"] == a.info(1)["t"]
+    same(a.fields(1), b.fields(1), "converged instance")
+    a.close()
+    b.close()
+
+
+def test_autotune_does_not_change_results(L):
+    cfg = li.annulus(nr=130, nz=90, Ra=1e5, Da=1e-3)
+    a = L.Lattice(cfg, storage="fp16", check_interval=25)
+    choice = a.autotune(trial_steps=4)
+    assert choice["kz"] in (1, 2, 4, 8, 16) and choice["blocks_per_cu"] in (0, 2, 4)
+    assert choice["ms"] > 0
+    a.step(11)
+    b = L.Lattice(cfg, storage="fp16", check_interval=25)
+    b.step(15 * 4 + 11)
+    same(a.fields(), b.fields(), "autotuned")
+    np.testing.assert_array_equal(a.residual()["res"], b.residual()["res"])
+    a.close()
+    b.close()
+
+
+def test_sweep_batch_against_oracle(L, oracle_mod):
+    """48 instances of the sweep distribution (grids up to 160) in one
+    handle; three of them compared with the oracle after 200 steps."""
+    cfgs = li.sweep(n_inst=48, seed=1409, sizes=np.arange(32, 161, 32))
+    lat = L.Lattice(cfgs, check_interval=100)
+    lat.step(200)
+    picks = [0, 17, 47]
+    got = {i: lat.fields(i) for i in picks}
+    lat.close()
+    for i in picks:
+        o = oracle_mod.Oracle(cfgs[i])
+        o.step(200)
+        assert_parity(got[i], o.macros(), tol=TOL_FP32, label=f"sweep instance {i}")
+        o.close()
