@@ -78,6 +78,74 @@ def device_copy_gbs(torch, stream, nbytes: int = 2 << 30, reps: int = 5) -> floa
     return 2 * nbytes / (best * 1e-3) / 1e9
 
 
+def storage_variant(Lattice, cfg, phi, storage, steps, warmup, check, stream):
+    """The same 8192^2 problem with 16-bit population storage (FP32 arithmetic):
+    MLUPS and the step kernel's algorithmic bandwidth (64 B per node)."""
+    import torch
+
+    n = cfg["nr"]
+    lat = Lattice(cfg, phi=phi, storage=storage, check_interval=check, stream=stream.cuda_stream)
+    lat.step(warmup)
+    lat.set_timing(True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lat.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    kern_ms, launches = lat.kernel_time()
+    lat.close()
+    bpn = 26 * 2 + 2 * 4 + 4
+    return {"storage": storage, "mlups": round(n * n * steps / (total_ms * 1e-3) / 1e6, 1),
+            "ms_per_step": round(total_ms / steps, 5), "avg_launch_ms": round(kern_ms / launches, 5),
+            "bytes_per_node": bpn,
+            "achieved_gbs": round((n - 2) ** 2 * bpn / (kern_ms / launches * 1e-3) / 1e9, 1)}
+
+
+def sweep_batch(Lattice, n_inst, steps, stream):
+    """The batched parameter sweep: n_inst annuli of uneven grids and
+    parameters in one handle, FP16 storage, launch shape from the autotuner,
+    step graphs; aggregate MLUPS over a fixed number of steps."""
+    import numpy as np
+    import torch
+
+    import lbm_inputs as li
+
+    cfgs = li.sweep(n_inst=n_inst, seed=1409)
+    nodes = int(sum(c["nr"] * c["nz"] for c in cfgs))
+    fluid = int(sum((c["nr"] - 2) * (c["nz"] - 2) for c in cfgs))
+    t0 = time.perf_counter()
+    lat = Lattice(cfgs, storage="fp16", check_interval=1000, tol=1e-8, max_steps=2_000_000,
+                  stream=stream.cuda_stream)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    tune = lat.autotune(trial_steps=10)
+    lat.step(2 - lat.info()["t"] % 2)  # graphs start at even levels
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lat.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    st = lat.residual()["status"]
+    lat.close()
+    bpn = 26 * 2 + 2 * 4
+    return {"instances": n_inst, "nodes": nodes, "storage": "fp16", "steps": steps,
+            "mlups": round(nodes * steps / (ms * 1e-3) / 1e6, 1),
+            "ms_per_step": round(ms / steps, 5),
+            "achieved_gbs": round(fluid * bpn / (ms / steps * 1e-3) / 1e9, 1),
+            "bytes_per_node": bpn,
+            "autotune": {"kz": tune["kz"], "blocks_per_cu": tune["blocks_per_cu"],
+                         "step_ms": round(tune["ms"], 5)},
+            "create_s": round(t_create, 2),
+            "status_counts": {k: int(np.sum(st == v)) for k, v in
+                              (("running", 0), ("converged", 1), ("diverged", 2), ("stalled", 3))}}
+
+
 def cpu_baseline(cfg, phi, seconds: float):
     """The FP64 oracle on a 1024 x 1024 corner of the same problem (inner
     wall, bottom wall), stepped until `seconds` of work are done."""
@@ -113,6 +181,10 @@ def main():
     ap.add_argument("--check-interval", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the FP16/BF16 storage runs and the batched sweep")
+    ap.add_argument("--sweep-instances", type=int, default=1024)
+    ap.add_argument("--sweep-steps", type=int, default=1000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 2 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -163,6 +235,15 @@ def main():
     info = lat.info()
     lat.close()
     copy_gbs = device_copy_gbs(torch, stream)
+    variants = sweep = None
+    if not args.no_variants and args.storage == "fp32":
+        variants = []
+        for st in ("fp16", "bf16"):
+            log(f"storage variant {st}")
+            variants.append(storage_variant(Lattice, cfg, phi.astype(np.float32), st, args.steps // 2,
+                                            args.warmup, args.check_interval, stream))
+        log(f"batched sweep: {args.sweep_instances} instances")
+        sweep = sweep_batch(Lattice, args.sweep_instances, args.sweep_steps, stream)
 
     fluid = (n - 2) * (n - 2)
     # 14 populations read + 14 written, porosity read; g_0 stays FP32 in 16-bit storage
@@ -209,6 +290,8 @@ def main():
             "copy_gbs": round(copy_gbs, 1),
             "frac_of_copy": round(achieved / copy_gbs, 4),
         },
+        "storage_variants": variants,
+        "sweep": sweep,
         "residual": float(res["res"][0]),
         "nu_i": float(res["nu_i"][0]),
         "t": int(info["t"]),

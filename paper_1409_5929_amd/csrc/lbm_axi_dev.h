@@ -92,12 +92,16 @@ struct FieldOut {
 // st() rounds to nearest even; st_sr() rounds stochastically with 32 random
 // bits r: the FP32 value is rounded away from zero with probability equal to
 // its distance from the 16-bit value below (in magnitude) over the 16-bit
-// spacing, so that the stored value is unbiased.  Adding the random bits to
-// the FP32 bit pattern below the 16-bit mantissa and truncating does exactly
-// that (the carry moves into the next mantissa step or exponent); results in
+// spacing, so that the stored value is unbiased.  Deterministic rounding lets
+// a slowly varying population round back to its old value step after step,
+// so a run freezes short of its steady state.  On the device this is one
+// gfx950 conversion instruction (v_cvt_sr_f16_f32 / v_cvt_sr_bf16_f32, which
+// take the random bits as an operand).  The host version adds the random
+// bits to the FP32 bit pattern below the 16-bit mantissa and truncates (the
+// carry moves into the next mantissa step or exponent); there, results in
 // the FP16 subnormal range (|v sc| < 2^-14) are rounded to nearest after.
-// Deterministic rounding lets a slowly varying population round back to its
-// old value step after step, so a run freezes short of its steady state.
+typedef _Float16 lbm_h2 __attribute__((ext_vector_type(2)));
+typedef __bf16 lbm_b2 __attribute__((ext_vector_type(2)));
 template <typename S>
 struct Store;
 template <>
@@ -118,8 +122,13 @@ struct Store<__half> {
   }
   __host__ __device__ static inline void st_sr(__half* p, int64_t i, float v, float sc,
                                                uint32_t r) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const lbm_h2 h = __builtin_amdgcn_cvt_sr_f16_f32(lbm_h2{0, 0}, v * sc, r, false);
+    p[i] = __builtin_bit_cast(__half, h[0]);
+#else
     const uint32_t b = (__float_as_uint(v * sc) + (r >> 19)) & 0xFFFFE000u;  // 13 dropped bits
     p[i] = __float2half_rn(__uint_as_float(b));
+#endif
   }
 };
 template <>
@@ -132,16 +141,22 @@ struct Store<__hip_bfloat16> {
   }
   __host__ __device__ static inline void st_sr(__hip_bfloat16* p, int64_t i, float v, float sc,
                                                uint32_t r) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const lbm_b2 h = __builtin_amdgcn_cvt_sr_bf16_f32(lbm_b2{0, 0}, v * sc, r, false);
+    p[i] = __builtin_bit_cast(__hip_bfloat16, h[0]);
+#else
     const uint32_t b = (__float_as_uint(v * sc) + (r >> 16)) & 0xFFFF0000u;  // 16 dropped bits
     p[i] = __float2bfloat16(__uint_as_float(b));
+#endif
   }
 };
 
 // Random bits for stochastic rounding: a 32-bit integer hash (xorshift-
 // multiply finaliser, Wellons' "lowbias32" constants) of the step seed and
 // the node's offset seeds a per-node linear congruential stream (Knuth's
-// MMIX multiplier and increment, low 32 bits); each store takes the high
-// bits of the next state.
+// MMIX multiplier and increment, mod 2^32).  The roundings use only the
+// high 16 bits of their random operand (13 for FP16), so each state feeds
+// two stores: the state itself, then its low half moved up.
 __host__ __device__ inline uint32_t mix32(uint32_t x) {
   x ^= x >> 16;
   x *= 0x7feb352du;
@@ -156,8 +171,15 @@ __host__ __device__ inline uint32_t step_seed(long long n) {
 }
 struct Dither {
   uint32_t s;
+  bool low = false;  // the low half of s is still unused
+  __host__ __device__ explicit Dither(uint32_t seed) : s(seed) {}
   __host__ __device__ inline uint32_t next() {
+    if (low) {
+      low = false;
+      return s << 16;
+    }
     s = s * 1664525u + 1013904223u;
+    low = true;
     return s;
   }
 };
@@ -411,7 +433,7 @@ __host__ __device__ inline void node_update(const InstDev& D, const RowC& R, int
     if (kp >= D.nz) kp -= D.nz;
   }
   const int64_t o = (int64_t)k * st + j;
-  Dither rn{mix32(seed ^ (uint32_t)o)};
+  Dither rn(mix32(seed ^ (uint32_t)o));
   const int64_t rowm = (int64_t)km * st, row0 = (int64_t)k * st, rowp = (int64_t)kp * st;
 
   // ---- load the populations arriving at x --------------------------------
