@@ -130,3 +130,50 @@ def sweep(n_inst: int = 1024, seed: int = 1409, sizes=None) -> list:
         out.append(annulus(nr=nr, nz=nz, Rstar=Rstar, phi=phi, Da=Da, Ra=Ra, Pr=Pr,
                            F_phi=ERGUN))
     return out
+
+
+# ---- warm-start network inputs -------------------------------------------------
+
+def no_init_params(widths, seed: int = 1409) -> np.ndarray:
+    """Seeded initial weights of the warm-start network, float32, packed layer
+    by layer as W[cout][cin][k][k] then b[cout].  He-normal weights
+    (std sqrt(2 / (cin k^2))), zero biases; the 1x1 output layer is scaled
+    down by 10 so that the untrained network predicts nearly zero."""
+    c1, c2, c3, c4 = widths
+    shapes = [(6, c1, 3), (c1, c2, 3), (c2, c3, 3), (c3, c4, 3), (c4, c3, 3), (c3, c2, 3),
+              (c2, c1, 3), (c1, 3, 1)]
+    rng = np.random.default_rng(seed)
+    out = []
+    for i, (ci, co, k) in enumerate(shapes):
+        std = np.sqrt(2.0 / (ci * k * k)) * (0.1 if i == len(shapes) - 1 else 1.0)
+        out.append(rng.standard_normal(co * ci * k * k) * std)
+        out.append(np.zeros(co))
+    return np.concatenate(out).astype(np.float32)
+
+
+U_SCALE = 0.1 / math.sqrt(3.0)  # characteristic velocity Ma c_s of the annulus problems
+
+
+def no_features(cfg: dict) -> np.ndarray:
+    """Six [nz, nr] feature planes of an annulus problem: normalised log10 Ra,
+    log10 Da, porosity, log10 Pr, ln R*, and the radius r / r_o of each node."""
+    nz, nr = int(cfg["nz"]), int(cfg["nr"])
+    r0, L = float(cfg["r0"]), float(cfg["L"])
+    rstar = (r0 + L) / r0
+    vals = [(math.log10(cfg["Ra"]) - 4.5) / 1.5, (math.log10(cfg["Da"]) + 4.0) / 2.0,
+            (cfg["phi"] - 0.625) / 0.325, math.log10(cfg["Pr"]), math.log(rstar) / math.log(10.0)]
+    out = np.empty((6, nz, nr), dtype=np.float32)
+    for i, v in enumerate(vals):
+        out[i] = v
+    out[5] = ((r0 + np.arange(nr)) / (r0 + L))[None, :]
+    return out
+
+
+def no_targets(fields: dict) -> np.ndarray:
+    """(u_z / U, u_r / U, T) planes of a field dict, float32 [3, nz, nr]."""
+    return np.stack([fields["uz"] / U_SCALE, fields["ur"] / U_SCALE, fields["T"]]).astype(np.float32)
+
+
+def no_fields(pred: np.ndarray) -> np.ndarray:
+    """Inverse of no_targets: start fields (u_z, u_r, T) [3, nz, nr] from a prediction."""
+    return np.stack([pred[0] * U_SCALE, pred[1] * U_SCALE, pred[2]]).astype(np.float32)
