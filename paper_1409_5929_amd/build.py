@@ -1,4 +1,6 @@
-"""Build ``liblbm_axi.so`` (HIP, gfx950) in place next to this file.
+"""Build the HIP libraries (gfx950) in place next to this file:
+``liblbm_axi.so`` (the lattice Boltzmann step) and ``liblbm_no.so`` (the
+warm-start network).
 
     python -m paper_1409_5929_amd.build
 """
@@ -10,9 +12,10 @@ import sys
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
-SOURCES = [os.path.join(_HERE, "csrc", "lbm_axi.hip")]
-HEADERS = [os.path.join(_HERE, "csrc", h) for h in ("lbm_axi_dev.h", "lbm_axi_desc.h")] + [
-    os.path.join(_ROOT, "include", "lbm_axi.h")]
+LIBS = {  # target -> sources
+    os.path.join(_HERE, "liblbm_axi.so"): [os.path.join(_HERE, "csrc", "lbm_axi.hip")],
+    os.path.join(_HERE, "liblbm_no.so"): [os.path.join(_HERE, "csrc", "lbm_no.hip")],
+}
 TARGET = os.path.join(_HERE, "liblbm_axi.so")
 
 HIPCC_FLAGS = [
@@ -25,15 +28,16 @@ HIPCC_FLAGS = [
 
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = TARGET + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-I" + os.path.join(_ROOT, "include"), "-o", tmp, *SOURCES]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed for " + " ".join(SOURCES))
-    os.replace(tmp, TARGET)
+    for target, sources in LIBS.items():
+        tmp = target + ".tmp"
+        cmd = [hipcc, *HIPCC_FLAGS, "-I" + os.path.join(_ROOT, "include"), "-o", tmp, *sources]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("hipcc failed for " + " ".join(sources))
+        os.replace(tmp, target)
     return TARGET
 
 

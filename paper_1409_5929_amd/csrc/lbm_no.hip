@@ -1,0 +1,629 @@
+// Warm-start network of the lattice Boltzmann solver: forward pass, loss,
+// backward pass and Adam on gfx950 (layer definitions in include/lbm_no.h).
+//
+// Every convolution is an im2col gather followed by one GEMM on MFMA
+// (v_mfma_f32_16x16x16_bf16: bfloat16 operands, FP32 accumulation):
+//   forward          z[o][p]   = sum_k W[o][k] col[k][p] + b[o]
+//   input gradient   dcol[k][p] = sum_o W[o][k] dz[o][p], then a col2im gather
+//   weight gradient  dW[o][k]  = sum_p dz[o][p] col[k][p] (split over p)
+// with k = (cin, ky, kx) and p = (batch, y, x).  Activations are kept
+// channel-major, [C][batch][H][W], so each GEMM output is the next layer's
+// input without a transpose.  Reductions (bias gradients, split partials,
+// loss) run in a fixed order, so results do not depend on scheduling.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm_no.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define NOCHK(call)                                                                     \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess) return fail(LBM_NO_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef uint16_t bf16_t;  // bfloat16 bit pattern
+
+__host__ __device__ inline bf16_t to_bf16(float v) {  // round to nearest even (finite inputs)
+  uint32_t u = __builtin_bit_cast(uint32_t, v);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (bf16_t)(u >> 16);
+}
+__device__ inline float ldf(const float* p, int64_t i) { return p[i]; }
+__device__ inline float ldf(const bf16_t* p, int64_t i) { return __uint_as_float((uint32_t)p[i] << 16); }
+
+constexpr int BM = 64, BN = 64, BK = 32, NT = 256;
+constexpr int LDK = BK + 8;  // padded LDS rows (bf16 elements)
+constexpr int EW = 256;      // threads of the elementwise kernels
+
+// C[m][n] = sum_k A(m, k) B(k, n) (+ bias[m] in split 0), A(m, k) = A[m sam + k sak],
+// B(k, n) = B[k sbk + n sbn].  Split z covers k in [z kchunk, (z + 1) kchunk)
+// and writes C + z cz.  Block: 64 x 64 outputs, four waves of 32 x 32, each
+// as 2 x 2 MFMA 16 x 16 tiles.  Tiles are staged in LDS as bfloat16 with k
+// contiguous (B transposed), zero-filled outside the matrices.
+template <typename TA, typename TB>
+__global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, const TA* __restrict__ A,
+                                             int64_t sam, int64_t sak, const TB* __restrict__ B,
+                                             int64_t sbk, int64_t sbn, float* __restrict__ C,
+                                             int64_t ldc, int64_t cz, int kchunk,
+                                             const float* __restrict__ bias) {
+  __shared__ bf16_t As[BM][LDK];
+  __shared__ bf16_t Bs[BN][LDK];
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int kb = blockIdx.z * kchunk;
+  const int ke = min(K, kb + kchunk);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  v4f acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = kb; k0 < ke; k0 += BK) {
+    for (int e = tid; e < BM * BK; e += NT) {  // neighbouring threads along A's contiguous index
+      const int r = sak == 1 ? e / BK : e % BM;
+      const int c = sak == 1 ? e % BK : e / BM;
+      const int gm = m0 + r, gk = k0 + c;
+      As[r][c] = (gm < M && gk < ke) ? to_bf16(ldf(A, (int64_t)gm * sam + (int64_t)gk * sak)) : (bf16_t)0;
+    }
+    for (int e = tid; e < BN * BK; e += NT) {
+      const int n = sbk == 1 ? e / BK : e % BN;
+      const int c = sbk == 1 ? e % BK : e / BN;
+      const int gn = n0 + n, gk = k0 + c;
+      Bs[n][c] = (gn < N && gk < ke) ? to_bf16(ldf(B, (int64_t)gk * sbk + (int64_t)gn * sbn)) : (bf16_t)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      const int kq = kk + 4 * (lane >> 4);
+      v4s a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const bf16_t* s = &As[wm + i * 16 + (lane & 15)][kq];
+        a[i] = v4s{(short)s[0], (short)s[1], (short)s[2], (short)s[3]};
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const bf16_t* s = &Bs[wn + j * 16 + (lane & 15)][kq];
+        b[j] = v4s{(short)s[0], (short)s[1], (short)s[2], (short)s[3]};
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  float* Cz = C + (int64_t)blockIdx.z * cz;
+  // result layout of a 16 x 16 tile: lane holds column lane % 16, rows 4 (lane / 16) + q
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int q = 0; q < 4; ++q) {
+        const int gm = m0 + wm + i * 16 + 4 * (lane >> 4) + q;
+        const int gn = n0 + wn + j * 16 + (lane & 15);
+        if (gm < M && gn < N)
+          Cz[(int64_t)gm * ldc + gn] = acc[i][j][q] + ((bias && blockIdx.z == 0) ? bias[gm] : 0.0f);
+      }
+}
+
+// col[kidx][p] for kidx = (c, ky, kx), p = (b, oy, ox): the input value under
+// tap (ky, kx) of output (oy, ox), zero outside; with up, the input is the
+// 2x nearest-neighbour upsampling of x.  x is [b][c][y][x] (nchw) or
+// [c][b][y][x].
+template <bool NCHW>
+__global__ __launch_bounds__(EW) void k_im2col(const float* __restrict__ x, int C, int Bt, int H,
+                                               int W, int up, int k, int s, int pad, int Ho,
+                                               int Wo, bf16_t* __restrict__ col) {
+  const int64_t P = (int64_t)Bt * Ho * Wo;
+  const int64_t p = (int64_t)blockIdx.x * EW + threadIdx.x;
+  if (p >= P) return;
+  const int kidx = blockIdx.y;
+  const int c = kidx / (k * k), t = kidx % (k * k), ky = t / k, kx = t % k;
+  const int ox = (int)(p % Wo);
+  const int64_t q = p / Wo;
+  const int oy = (int)(q % Ho);
+  const int b = (int)(q / Ho);
+  const int He = up ? 2 * H : H, We = up ? 2 * W : W;
+  const int iy = oy * s + ky - pad, ix = ox * s + kx - pad;
+  float v = 0.0f;
+  if (iy >= 0 && iy < He && ix >= 0 && ix < We) {
+    const int sy = up ? iy >> 1 : iy, sx = up ? ix >> 1 : ix;
+    const int64_t i = NCHW ? (((int64_t)b * C + c) * H + sy) * W + sx
+                           : (((int64_t)c * Bt + b) * H + sy) * W + sx;
+    v = x[i];
+  }
+  col[(int64_t)kidx * P + p] = to_bf16(v);
+}
+
+// Adjoint of k_im2col (channel-major x): dx[c][b][y][x] (+)= sum of the dcol
+// entries that read x[c][b][y][x], gathered (no atomics).
+__global__ __launch_bounds__(EW) void k_col2im(const float* __restrict__ dcol, int C, int Bt, int H,
+                                               int W, int up, int k, int s, int pad, int Ho,
+                                               int Wo, float* __restrict__ dx, int accumulate) {
+  const int64_t n = (int64_t)C * Bt * H * W;
+  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
+  if (i >= n) return;
+  const int sx = (int)(i % W);
+  int64_t q = i / W;
+  const int sy = (int)(q % H);
+  q /= H;
+  const int b = (int)(q % Bt);
+  const int c = (int)(q / Bt);
+  const int64_t P = (int64_t)Bt * Ho * Wo;
+  const int nu = up ? 2 : 1;
+  float acc = 0.0f;
+  for (int uy = 0; uy < nu; ++uy)
+    for (int ux = 0; ux < nu; ++ux) {
+      const int iy = up ? 2 * sy + uy : sy, ix = up ? 2 * sx + ux : sx;
+      for (int ky = 0; ky < k; ++ky) {
+        const int ty = iy + pad - ky;
+        if (ty < 0 || ty % s) continue;
+        const int oy = ty / s;
+        if (oy >= Ho) continue;
+        for (int kx = 0; kx < k; ++kx) {
+          const int tx = ix + pad - kx;
+          if (tx < 0 || tx % s) continue;
+          const int ox = tx / s;
+          if (ox >= Wo) continue;
+          acc += dcol[(int64_t)((c * k + ky) * k + kx) * P + ((int64_t)b * Ho + oy) * Wo + ox];
+        }
+      }
+    }
+  dx[i] = accumulate ? dx[i] + acc : acc;
+}
+
+// a = relu(z) (or z) + skip
+__global__ __launch_bounds__(EW) void k_act(const float* __restrict__ z, const float* __restrict__ skip,
+                                            float* __restrict__ a, int64_t n, int relu) {
+  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
+  if (i >= n) return;
+  float v = z[i];
+  if (relu) v = fmaxf(v, 0.0f);
+  a[i] = skip ? v + skip[i] : v;
+}
+
+// dz = da where z > 0 (relu) or da; written over z
+__global__ __launch_bounds__(EW) void k_act_bwd(const float* __restrict__ da, float* __restrict__ z,
+                                                int64_t n, int relu) {
+  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
+  if (i >= n) return;
+  z[i] = (!relu || z[i] > 0.0f) ? da[i] : 0.0f;
+}
+
+// dst (+)= src
+__global__ __launch_bounds__(EW) void k_copy_add(float* __restrict__ dst, const float* __restrict__ src,
+                                                 int64_t n, int accumulate) {
+  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
+  if (i >= n) return;
+  dst[i] = accumulate ? dst[i] + src[i] : src[i];
+}
+
+__device__ inline float block_sum(float v, float* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  float t = 0.0f;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+  return t;
+}
+
+// db[o] = sum_p dz[o][p]: one block per channel, fixed order.
+__global__ __launch_bounds__(EW) void k_bias_grad(const float* __restrict__ dz, int64_t P,
+                                                  float* __restrict__ db) {
+  __shared__ float sh[EW / 64];
+  const float* row = dz + (int64_t)blockIdx.x * P;
+  float v = 0.0f;
+  for (int64_t p = threadIdx.x; p < P; p += EW) v += row[p];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) db[blockIdx.x] = v;
+}
+
+// out[i] = sum_s part[s][i]
+__global__ __launch_bounds__(EW) void k_sum_splits(const float* __restrict__ part, int S, int64_t n,
+                                                   float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
+  if (i >= n) return;
+  float v = 0.0f;
+  for (int s = 0; s < S; ++s) v += part[(int64_t)s * n + i];
+  out[i] = v;
+}
+
+// y is [3][b][hw] (channel-major), t is [b][3][hw]: dy = 2 (y - t) / n and
+// per-block partial sums of (y - t)^2 in FP64.
+__global__ __launch_bounds__(EW) void k_loss(const float* __restrict__ y, const float* __restrict__ t,
+                                             int Bt, int64_t HW, float* __restrict__ dy,
+                                             double* __restrict__ part) {
+  __shared__ double sh[EW / 64];
+  const int64_t n = 3 * (int64_t)Bt * HW;
+  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
+  double e2 = 0.0;
+  if (i < n) {
+    const int64_t hw = i % HW, q = i / HW;
+    const int64_t b = q % Bt, c = q / Bt;
+    const float d = y[i] - t[(b * 3 + c) * HW + hw];
+    dy[i] = 2.0f * d / (float)n;
+    e2 = (double)d * d;
+  }
+  for (int off = 32; off > 0; off >>= 1) e2 += __shfl_xor(e2, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = e2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < EW / 64; ++k) s += sh[k];
+    part[blockIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(EW) void k_loss_final(const double* __restrict__ part, int64_t nb,
+                                                   int64_t n, double* __restrict__ out) {
+  __shared__ double sh[EW / 64];
+  double v = 0.0;
+  for (int64_t i = threadIdx.x; i < nb; i += EW) v += part[i];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < EW / 64; ++k) s += sh[k];
+    *out = s / (double)n;
+  }
+}
+
+// [3][b][hw] -> [b][3][hw]
+__global__ __launch_bounds__(EW) void k_to_nchw(const float* __restrict__ y, int Bt, int64_t HW,
+                                                float* __restrict__ out) {
+  const int64_t n = 3 * (int64_t)Bt * HW;
+  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
+  if (i >= n) return;
+  const int64_t hw = i % HW, q = i / HW;
+  const int64_t c = q % 3, b = q / 3;
+  out[i] = y[(c * Bt + b) * HW + hw];
+}
+
+// Adam with bias correction c1 = 1 - beta1^t, c2 = 1 - beta2^t; refreshes
+// the bfloat16 copy of the weights.
+__global__ __launch_bounds__(EW) void k_adam(float* __restrict__ p, const float* __restrict__ g,
+                                             float* __restrict__ m, float* __restrict__ v, int64_t n,
+                                             float lr, float b1, float b2, float eps, float c1, float c2,
+                                             bf16_t* __restrict__ pb) {
+  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  p[i] = pi;
+  pb[i] = to_bf16(pi);
+}
+
+__global__ __launch_bounds__(EW) void k_to_bf16(const float* __restrict__ p, int64_t n,
+                                                bf16_t* __restrict__ pb) {
+  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
+  if (i < n) pb[i] = to_bf16(p[i]);
+}
+
+struct Layer {
+  int cin, cout, k, s, up, relu, skip;
+  int Hs, Ws;    // source size (before upsampling)
+  int Ho, Wo;    // output size
+  int64_t woff, boff;
+};
+
+unsigned grid1(int64_t n) { return (unsigned)((n + EW - 1) / EW); }
+
+}  // namespace
+
+struct lbm_no {
+  int widths[4];
+  int H = 0, W = 0, maxB = 0;
+  int64_t npar = 0;
+  std::vector<Layer> L;
+  hipStream_t stream = nullptr;
+  std::vector<void*> allocs;
+  float *par = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
+  bf16_t* parb = nullptr;
+  std::vector<float*> z, a, da;  // per layer, [cout][B][Ho][Wo]
+  bf16_t* col = nullptr;
+  float* dcol = nullptr;
+  float* split = nullptr;
+  int64_t split_n = 0;
+  double* lpart = nullptr;
+  double* dloss = nullptr;
+  long long adam_t = 0;
+};
+
+namespace {
+
+constexpr int KCHUNK = 8192;  // reduction length of one weight-gradient split
+
+void* nalloc(lbm_no* h, size_t bytes) {
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes < 256 ? 256 : bytes) != hipSuccess) return nullptr;
+  h->allocs.push_back(p);
+  return p;
+}
+
+void specs(const int* w, int H, int W, std::vector<Layer>& L, int64_t& npar) {
+  const int c1 = w[0], c2 = w[1], c3 = w[2], c4 = w[3];
+  const int def[8][7] = {{6, c1, 3, 1, 0, 1, -1},  {c1, c2, 3, 2, 0, 1, -1}, {c2, c3, 3, 2, 0, 1, -1},
+                         {c3, c4, 3, 2, 0, 1, -1}, {c4, c3, 3, 1, 1, 1, 2},  {c3, c2, 3, 1, 1, 1, 1},
+                         {c2, c1, 3, 1, 1, 1, 0},  {c1, 3, 1, 1, 0, 0, -1}};
+  L.clear();
+  npar = 0;
+  int h = H, ww = W;
+  for (auto& d : def) {
+    Layer l{d[0], d[1], d[2], d[3], d[4], d[5], d[6], h, ww, 0, 0, 0, 0};
+    const int he = l.up ? 2 * h : h, we = l.up ? 2 * ww : ww;
+    const int pad = (l.k - 1) / 2;
+    l.Ho = (he + 2 * pad - l.k) / l.s + 1;
+    l.Wo = (we + 2 * pad - l.k) / l.s + 1;
+    l.woff = npar;
+    npar += (int64_t)l.cout * l.cin * l.k * l.k;
+    l.boff = npar;
+    npar += l.cout;
+    L.push_back(l);
+    h = l.Ho;
+    ww = l.Wo;
+  }
+}
+
+template <typename TA, typename TB>
+int gemm(lbm_no* h, int M, int N, int K, const TA* A, int64_t sam, int64_t sak, const TB* B,
+         int64_t sbk, int64_t sbn, float* C, int64_t ldc, int64_t cz, int splits, int kchunk,
+         const float* bias) {
+  if (M <= 0 || N <= 0 || K <= 0) return LBM_NO_OK;
+  const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)splits);
+  k_gemm<TA, TB><<<grid, NT, 0, h->stream>>>(M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, cz, kchunk, bias);
+  NOCHK(hipGetLastError());
+  return LBM_NO_OK;
+}
+
+int im2col(lbm_no* h, const Layer& l, const float* src, bool nchw, int Bt) {
+  const int64_t P = (int64_t)Bt * l.Ho * l.Wo;
+  const int K = l.cin * l.k * l.k;
+  const dim3 grid(grid1(P), (unsigned)K);
+  if (nchw)
+    k_im2col<true><<<grid, EW, 0, h->stream>>>(src, l.cin, Bt, l.Hs, l.Ws, l.up, l.k, l.s, (l.k - 1) / 2, l.Ho, l.Wo, h->col);
+  else
+    k_im2col<false><<<grid, EW, 0, h->stream>>>(src, l.cin, Bt, l.Hs, l.Ws, l.up, l.k, l.s, (l.k - 1) / 2, l.Ho, l.Wo, h->col);
+  NOCHK(hipGetLastError());
+  return LBM_NO_OK;
+}
+
+int forward_internal(lbm_no* h, const float* x, int Bt) {
+  for (size_t li = 0; li < h->L.size(); ++li) {
+    const Layer& l = h->L[li];
+    const int64_t P = (int64_t)Bt * l.Ho * l.Wo;
+    const int K = l.cin * l.k * l.k;
+    int rc = im2col(h, l, li == 0 ? x : h->a[li - 1], li == 0, Bt);
+    if (rc) return rc;
+    rc = gemm<bf16_t, bf16_t>(h, l.cout, (int)P, K, h->parb + l.woff, K, 1, h->col, P, 1, h->z[li], P, 0, 1,
+                              K, h->par + l.boff);
+    if (rc) return rc;
+    const int64_t n = (int64_t)l.cout * P;
+    k_act<<<grid1(n), EW, 0, h->stream>>>(h->z[li], l.skip >= 0 ? h->a[l.skip] : nullptr, h->a[li], n, l.relu);
+    NOCHK(hipGetLastError());
+  }
+  return LBM_NO_OK;
+}
+
+int check_batch(lbm_no* h, int Bt) {
+  if (!h) return fail(LBM_NO_EINVAL, "null handle");
+  if (Bt < 1 || Bt > h->maxB) return fail(LBM_NO_EINVAL, "batch out of [1, max_batch]");
+  return LBM_NO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_no_last_error(void) { return g_err.c_str(); }
+
+int lbm_no_param_count(const int32_t* widths, int64_t* count) {
+  if (!widths || !count) return fail(LBM_NO_EINVAL, "null argument");
+  for (int i = 0; i < 4; ++i)
+    if (widths[i] < 1 || widths[i] > 1024) return fail(LBM_NO_EINVAL, "widths out of [1, 1024]");
+  std::vector<Layer> L;
+  int w[4] = {widths[0], widths[1], widths[2], widths[3]};
+  specs(w, 8, 8, L, *count);
+  return LBM_NO_OK;
+}
+
+void lbm_no_destroy(lbm_no* h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  for (void* p : h->allocs) (void)hipFree(p);
+  delete h;
+}
+
+int lbm_no_create(const int32_t* widths, int32_t height, int32_t width, int32_t max_batch,
+                  const float* params, void* hip_stream, lbm_no** out) {
+  if (out) *out = nullptr;
+  if (!widths || !params || !out) return fail(LBM_NO_EINVAL, "null argument");
+  for (int i = 0; i < 4; ++i)
+    if (widths[i] < 1 || widths[i] > 1024) return fail(LBM_NO_EINVAL, "widths out of [1, 1024]");
+  if (height < 8 || width < 8 || height > 2048 || width > 2048 || height % 8 || width % 8)
+    return fail(LBM_NO_EINVAL, "height and width must be multiples of 8 in [8, 2048]");
+  if (max_batch < 1 || (int64_t)max_batch * height * width > (1ll << 31) / 64)
+    return fail(LBM_NO_EINVAL, "max_batch out of range");
+  lbm_no* h = new lbm_no();
+  auto bail = [&](int rc) {
+    lbm_no_destroy(h);
+    return rc;
+  };
+  for (int i = 0; i < 4; ++i) h->widths[i] = widths[i];
+  h->H = height;
+  h->W = width;
+  h->maxB = max_batch;
+  specs(h->widths, height, width, h->L, h->npar);
+  h->stream = (hipStream_t)hip_stream;  // NULL: the null stream (torch's default stream)
+  const size_t np = (size_t)h->npar;
+  h->par = (float*)nalloc(h, np * 4);
+  h->grad = (float*)nalloc(h, np * 4);
+  h->m = (float*)nalloc(h, np * 4);
+  h->v = (float*)nalloc(h, np * 4);
+  h->parb = (bf16_t*)nalloc(h, np * 2);
+  if (!h->par || !h->grad || !h->m || !h->v || !h->parb) return bail(fail(LBM_NO_ENOMEM, "parameters"));
+  int64_t colmax = 0, splitmax = 0;
+  for (const Layer& l : h->L) {
+    const int64_t P = (int64_t)max_batch * l.Ho * l.Wo;
+    const size_t n = (size_t)l.cout * P * 4;
+    float* zl = (float*)nalloc(h, n);
+    float* al = (float*)nalloc(h, n);
+    float* dl = (float*)nalloc(h, n);
+    if (!zl || !al || !dl) return bail(fail(LBM_NO_ENOMEM, "activations"));
+    h->z.push_back(zl);
+    h->a.push_back(al);
+    h->da.push_back(dl);
+    const int64_t K = (int64_t)l.cin * l.k * l.k;
+    colmax = std::max(colmax, K * P);
+    const int64_t S = (P + KCHUNK - 1) / KCHUNK;
+    splitmax = std::max(splitmax, S * l.cout * K);
+  }
+  h->col = (bf16_t*)nalloc(h, (size_t)colmax * 2);
+  h->dcol = (float*)nalloc(h, (size_t)colmax * 4);
+  h->split = (float*)nalloc(h, (size_t)splitmax * 4);
+  h->split_n = splitmax;
+  const int64_t lb = (3 * (int64_t)max_batch * height * width + EW - 1) / EW;
+  h->lpart = (double*)nalloc(h, (size_t)lb * 8);
+  h->dloss = (double*)nalloc(h, 8);
+  if (!h->col || !h->dcol || !h->split || !h->lpart || !h->dloss) return bail(fail(LBM_NO_ENOMEM, "work space"));
+  const int rc = lbm_no_set_params(h, params);
+  if (rc) return bail(rc);
+  *out = h;
+  return LBM_NO_OK;
+}
+
+int lbm_no_set_params(lbm_no* h, const float* params) {
+  if (!h || !params) return fail(LBM_NO_EINVAL, "null argument");
+  const size_t np = (size_t)h->npar;
+  NOCHK(hipMemcpyAsync(h->par, params, np * 4, hipMemcpyHostToDevice, h->stream));
+  NOCHK(hipMemsetAsync(h->m, 0, np * 4, h->stream));
+  NOCHK(hipMemsetAsync(h->v, 0, np * 4, h->stream));
+  NOCHK(hipMemsetAsync(h->grad, 0, np * 4, h->stream));
+  k_to_bf16<<<grid1(h->npar), EW, 0, h->stream>>>(h->par, h->npar, h->parb);
+  NOCHK(hipGetLastError());
+  NOCHK(hipStreamSynchronize(h->stream));
+  h->adam_t = 0;
+  return LBM_NO_OK;
+}
+
+int lbm_no_forward(lbm_no* h, const float* x, int32_t batch, float* y) {
+  int rc = check_batch(h, batch);
+  if (rc) return rc;
+  if (!x || !y) return fail(LBM_NO_EINVAL, "null tensor");
+  rc = forward_internal(h, x, batch);
+  if (rc) return rc;
+  const int64_t HW = (int64_t)h->H * h->W;
+  k_to_nchw<<<grid1(3 * batch * HW), EW, 0, h->stream>>>(h->a.back(), batch, HW, y);
+  NOCHK(hipGetLastError());
+  return LBM_NO_OK;
+}
+
+int lbm_no_gradients(lbm_no* h, const float* x, const float* target, int32_t batch, double* loss) {
+  int rc = check_batch(h, batch);
+  if (rc) return rc;
+  if (!x || !target) return fail(LBM_NO_EINVAL, "null tensor");
+  rc = forward_internal(h, x, batch);
+  if (rc) return rc;
+  const int nl = (int)h->L.size();
+  const int64_t HW = (int64_t)h->H * h->W;
+  const int64_t nout = 3 * (int64_t)batch * HW;
+  const int64_t nb = (nout + EW - 1) / EW;
+  k_loss<<<(unsigned)nb, EW, 0, h->stream>>>(h->a[nl - 1], target, batch, HW, h->da[nl - 1], h->lpart);
+  NOCHK(hipGetLastError());
+  k_loss_final<<<1, EW, 0, h->stream>>>(h->lpart, nb, nout, h->dloss);
+  NOCHK(hipGetLastError());
+  std::vector<char> have(nl, 0);  // activation gradient already written
+  have[nl - 1] = 1;
+  for (int li = nl - 1; li >= 0; --li) {
+    const Layer& l = h->L[li];
+    const int64_t P = (int64_t)batch * l.Ho * l.Wo;
+    const int K = l.cin * l.k * l.k;
+    const int64_t n = (int64_t)l.cout * P;
+    // dz over z; the skip passes da on unchanged
+    k_act_bwd<<<grid1(n), EW, 0, h->stream>>>(h->da[li], h->z[li], n, l.relu);
+    NOCHK(hipGetLastError());
+    if (l.skip >= 0) {
+      k_copy_add<<<grid1(n), EW, 0, h->stream>>>(h->da[l.skip], h->da[li], n, have[l.skip]);
+      NOCHK(hipGetLastError());
+      have[l.skip] = 1;
+    }
+    rc = im2col(h, l, li == 0 ? x : h->a[li - 1], li == 0, batch);
+    if (rc) return rc;
+    // weight gradient, split over p, partials summed in order
+    const int S = (int)((P + KCHUNK - 1) / KCHUNK);
+    const int64_t mn = (int64_t)l.cout * K;
+    if ((int64_t)S * mn > h->split_n) return fail(LBM_NO_EINVAL, "split work space too small");
+    rc = gemm<float, bf16_t>(h, l.cout, K, (int)P, h->z[li], P, 1, h->col, 1, P, h->split, K, mn, S, KCHUNK,
+                             nullptr);
+    if (rc) return rc;
+    k_sum_splits<<<grid1(mn), EW, 0, h->stream>>>(h->split, S, mn, h->grad + l.woff);
+    NOCHK(hipGetLastError());
+    k_bias_grad<<<(unsigned)l.cout, EW, 0, h->stream>>>(h->z[li], P, h->grad + l.boff);
+    NOCHK(hipGetLastError());
+    if (li == 0) break;  // no gradient with respect to the input
+    // input gradient: dcol = W^T dz, then the col2im gather into da[li - 1]
+    rc = gemm<bf16_t, float>(h, K, (int)P, l.cout, h->parb + l.woff, 1, K, h->z[li], P, 1, h->dcol, P, 0, 1,
+                             l.cout, nullptr);
+    if (rc) return rc;
+    const int64_t ns = (int64_t)l.cin * batch * l.Hs * l.Ws;
+    k_col2im<<<grid1(ns), EW, 0, h->stream>>>(h->dcol, l.cin, batch, l.Hs, l.Ws, l.up, l.k, l.s, (l.k - 1) / 2,
+                                              l.Ho, l.Wo, h->da[li - 1], have[li - 1]);
+    NOCHK(hipGetLastError());
+    have[li - 1] = 1;
+  }
+  if (loss) {
+    NOCHK(hipMemcpyAsync(loss, h->dloss, 8, hipMemcpyDeviceToHost, h->stream));
+    NOCHK(hipStreamSynchronize(h->stream));
+  }
+  return LBM_NO_OK;
+}
+
+int lbm_no_adam(lbm_no* h, float lr, float beta1, float beta2, float eps) {
+  if (!h || !(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+    return fail(LBM_NO_EINVAL, "bad handle or Adam hyper-parameters");
+  h->adam_t += 1;
+  const float c1 = (float)(1.0 - std::pow((double)beta1, (double)h->adam_t));
+  const float c2 = (float)(1.0 - std::pow((double)beta2, (double)h->adam_t));
+  k_adam<<<grid1(h->npar), EW, 0, h->stream>>>(h->par, h->grad, h->m, h->v, h->npar, lr, beta1, beta2, eps, c1,
+                                               c2, h->parb);
+  NOCHK(hipGetLastError());
+  return LBM_NO_OK;
+}
+
+int lbm_no_get(lbm_no* h, int32_t which, float* host_out) {
+  if (!h || !host_out || which < 0 || which > 1) return fail(LBM_NO_EINVAL, "bad argument");
+  NOCHK(hipMemcpyAsync(host_out, which == 0 ? h->par : h->grad, (size_t)h->npar * 4, hipMemcpyDeviceToHost,
+                       h->stream));
+  NOCHK(hipStreamSynchronize(h->stream));
+  return LBM_NO_OK;
+}
+
+int lbm_no_sync(lbm_no* h) {
+  if (!h) return fail(LBM_NO_EINVAL, "null handle");
+  NOCHK(hipStreamSynchronize(h->stream));
+  return LBM_NO_OK;
+}
+
+}  // extern "C"

@@ -91,3 +91,25 @@ def test_null_handles_are_refused():
     assert lib.lbm_axi_compact(None, None) == -1
     assert lib.lbm_axi_autotune(None, 1, None, None, None) == -1
     lib.lbm_axi_destroy(None)  # allowed
+
+
+def test_network_library_exports_and_counts_parameters():
+    from oracle import no_oracle as N
+    from paper_1409_5929_amd import no
+
+    if not os.path.exists(no.LIB_PATH):
+        pytest.skip("liblbm_no.so not built (run __graft_entry__.build())")
+    lib = no._load()
+    text = open(os.path.join(ROOT, "include", "lbm_no.h")).read()
+    names = sorted(set(re.findall(r"\b(lbm_no_[a-z_]+)\s*\(", text)))
+    assert len(names) >= 8
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in lbm_no.h but not exported"
+    for w in [(8, 16, 24, 32), (48, 96, 192, 384), (1, 1, 1, 1)]:
+        assert no.param_count(w) == N.param_count(w)
+    bad = (ctypes.c_int32 * 4)(0, 1, 1, 1)
+    n = ctypes.c_int64()
+    assert lib.lbm_no_param_count(bad, ctypes.byref(n)) == -1
+    assert lib.lbm_no_forward(None, None, 1, None) == -1
+    assert lib.lbm_no_adam(None, 1e-3, 0.9, 0.999, 1e-8) == -1
+    lib.lbm_no_destroy(None)

@@ -1,0 +1,122 @@
+"""GPU warm-start network (HIP, MFMA bf16 GEMMs) against its FP64 oracle.
+
+Tolerance: the GEMMs round weights and activations to bfloat16 (8
+significant bits, relative rounding error <= 2^-9 per operand, so <= 2^-8 per
+product) and accumulate in FP32.  Errors of independent products add in
+quadrature within a sum and compound over the 8 layers, about sqrt(8) 2^-8 =
+1.1e-2 of the signal; the bound used is 3e-2 relative L2."""
+import numpy as np
+import pytest
+
+import lbm_inputs as li
+from oracle import no_oracle as N
+
+pytestmark = pytest.mark.gpu
+TOL = 3e-2
+WIDTHS = (8, 16, 24, 32)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1409_5929_amd import no
+
+    no._load()
+    return torch
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def problem(seed=8, B=3, H=32, W=40):
+    rng = np.random.default_rng(seed)
+    params = li.no_init_params(WIDTHS, seed=seed)
+    params = params + (0.05 * rng.standard_normal(params.size)).astype(np.float32)  # biases nonzero
+    x = rng.standard_normal((B, 6, H, W)).astype(np.float32)
+    t = rng.standard_normal((B, 3, H, W)).astype(np.float32)
+    return params, x, t
+
+
+def test_forward_matches_oracle(torch):
+    from paper_1409_5929_amd.no import WarmStartNet
+
+    params, x, _ = problem()
+    net = WarmStartNet(WIDTHS, 32, 40, 4, params)
+    y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
+    net.close()
+    ref, _ = N.forward(params.astype(np.float64), WIDTHS, x.astype(np.float64))
+    e = rel(y, ref)
+    print(f"forward rel L2 {e:.2e}", flush=True)
+    assert e <= TOL
+
+
+def test_gradients_match_oracle(torch):
+    from paper_1409_5929_amd.no import WarmStartNet
+
+    params, x, t = problem(seed=9)
+    net = WarmStartNet(WIDTHS, 32, 40, 4, params)
+    loss = net.gradients(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
+    g = net.grads()
+    net.close()
+    lref, gref = N.loss_and_grads(params.astype(np.float64), WIDTHS, x.astype(np.float64), t.astype(np.float64))
+    assert abs(loss - lref) <= TOL * lref
+    e = rel(g, gref)
+    print(f"loss {loss:.6f} (oracle {lref:.6f}); gradient rel L2 {e:.2e}", flush=True)
+    assert e <= TOL
+    # every layer's weights and biases separately
+    o = 0
+    for ci, co, k, *_ in N.layer_specs(WIDTHS):
+        for n in (co * ci * k * k, co):
+            assert rel(g[o:o + n], gref[o:o + n]) <= 2 * TOL, (o, n)
+            o += n
+
+
+def test_adam_step_matches_oracle(torch):
+    from paper_1409_5929_amd.no import WarmStartNet
+
+    params, x, t = problem(seed=10)
+    net = WarmStartNet(WIDTHS, 32, 40, 4, params)
+    net.gradients(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
+    g = net.grads().astype(np.float64)
+    net.adam(1e-3)
+    p1 = net.params()
+    net.close()
+    z = np.zeros_like(g)
+    ref, _, _ = N.adam_step(params.astype(np.float64), g, z, z, 1, lr=1e-3)
+    np.testing.assert_allclose(p1, ref, rtol=1e-5, atol=1e-8)
+
+
+def test_training_reduces_loss(torch):
+    """Fitting a smooth target field: 60 Adam steps on one batch cut the loss
+    by more than 10x."""
+    from paper_1409_5929_amd.no import WarmStartNet
+
+    B, H, W = 4, 32, 32
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal((B, 6, 1, 1)).astype(np.float32) * np.ones((1, 1, H, W), np.float32)
+    yy, xx = np.meshgrid(np.linspace(0, 1, H), np.linspace(0, 1, W), indexing="ij")
+    t = np.stack([np.stack([np.sin(3 * xx + b), np.cos(2 * yy - b), xx * yy]) for b in range(B)]).astype(np.float32)
+    net = WarmStartNet(WIDTHS, H, W, B, li.no_init_params(WIDTHS, seed=12))
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    l0 = net.gradients(xd, td)
+    for _ in range(60):
+        net.adam(3e-3)
+        loss = net.gradients(xd, td)
+    net.close()
+    print(f"loss {l0:.4f} -> {loss:.4f}", flush=True)
+    assert loss < 0.1 * l0
+
+
+def test_invalid_arguments_are_refused(torch):
+    from paper_1409_5929_amd.no import NoError, WarmStartNet
+
+    params, _, _ = problem()
+    with pytest.raises(NoError):
+        WarmStartNet(WIDTHS, 30, 40, 4, params)  # height not a multiple of 8
+    net = WarmStartNet(WIDTHS, 32, 40, 2, params)
+    with pytest.raises(NoError):
+        net.forward(torch.zeros((3, 6, 32, 40), device="cuda"))  # batch above max_batch
+    net.close()
