@@ -146,6 +146,34 @@ def sweep_batch(Lattice, n_inst, steps, stream):
                               (("running", 0), ("converged", 1), ("diverged", 2), ("stalled", 3))}}
 
 
+def time_to_steady(n_problems, cap):
+    """Time to steady state (res <= 1e-8) of 128^2 annuli of the sweep
+    distribution (held-out problems of the warm-start network's training
+    run), cold start against the network's predicted start; the warm wall
+    time includes the prediction."""
+    import numpy as np
+    import torch
+
+    from paper_1409_5929_amd import warmstart as ws
+    from paper_1409_5929_amd.no import WarmStartNet
+
+    cfgs = ws.problems(2048 + 128, 1409)[2048:2048 + n_problems]
+    net = WarmStartNet(ws.WIDTHS, ws.GRID, ws.GRID, 32, ws.load_weights(ws.WEIGHTS))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pred = ws.predict(net, cfgs)
+    t_pred = time.perf_counter() - t0
+    net.close()
+    cold = ws.solve(cfgs, max_steps=cap, fields=False)
+    warm = ws.solve(cfgs, init=list(pred), max_steps=cap, fields=False)
+    ok = (cold["status"] == 1) & (warm["status"] == 1)
+    c = ws.compare(cold, warm, ok)
+    c.update(problems=n_problems, grid=ws.GRID, tol=1e-8, max_steps=cap,
+             converged_cold=int((cold["status"] == 1).sum()), converged_warm=int((warm["status"] == 1).sum()),
+             predict_s=round(t_pred, 3), wall_warm_s=round(warm["wall"] + t_pred, 3))
+    return c
+
+
 def cpu_baseline(cfg, phi, seconds: float):
     """The FP64 oracle on a 1024 x 1024 corner of the same problem (inner
     wall, bottom wall), stepped until `seconds` of work are done."""
@@ -185,6 +213,8 @@ def main():
                     help="skip the FP16/BF16 storage runs and the batched sweep")
     ap.add_argument("--sweep-instances", type=int, default=1024)
     ap.add_argument("--sweep-steps", type=int, default=1000)
+    ap.add_argument("--steady-problems", type=int, default=32)
+    ap.add_argument("--steady-max-steps", type=int, default=600_000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 2 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -235,7 +265,7 @@ def main():
     info = lat.info()
     lat.close()
     copy_gbs = device_copy_gbs(torch, stream)
-    variants = sweep = None
+    variants = sweep = steady = None
     if not args.no_variants and args.storage == "fp32":
         variants = []
         for st in ("fp16", "bf16"):
@@ -244,6 +274,8 @@ def main():
                                             args.warmup, args.check_interval, stream))
         log(f"batched sweep: {args.sweep_instances} instances")
         sweep = sweep_batch(Lattice, args.sweep_instances, args.sweep_steps, stream)
+        log(f"time to steady: {args.steady_problems} problems, cold vs warm start")
+        steady = time_to_steady(args.steady_problems, args.steady_max_steps)
 
     fluid = (n - 2) * (n - 2)
     # 14 populations read + 14 written, porosity read; g_0 stays FP32 in 16-bit storage
@@ -292,6 +324,7 @@ def main():
         },
         "storage_variants": variants,
         "sweep": sweep,
+        "time_to_steady": steady,
         "residual": float(res["res"][0]),
         "nu_i": float(res["nu_i"][0]),
         "t": int(info["t"]),

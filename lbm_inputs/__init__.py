@@ -169,11 +169,28 @@ def no_features(cfg: dict) -> np.ndarray:
     return out
 
 
-def no_targets(fields: dict) -> np.ndarray:
-    """(u_z / U, u_r / U, T) planes of a field dict, float32 [3, nz, nr]."""
-    return np.stack([fields["uz"] / U_SCALE, fields["ur"] / U_SCALE, fields["T"]]).astype(np.float32)
+def conduction_T(cfg: dict) -> np.ndarray:
+    """Temperature of pure radial conduction between the walls,
+    T = T_o + (T_i - T_o) ln(r_o / r) / ln R*, as an [nz, nr] plane."""
+    nz, nr = int(cfg["nz"]), int(cfg["nr"])
+    r0, L = float(cfg["r0"]), float(cfg["L"])
+    r = r0 + np.arange(nr)
+    prof = np.log((r0 + L) / r) / np.log((r0 + L) / r0)
+    return np.repeat((cfg["T_rmax"] + (cfg["T_rmin"] - cfg["T_rmax"]) * prof)[None, :], nz, axis=0)
 
 
-def no_fields(pred: np.ndarray) -> np.ndarray:
+T_SCALE = 4.0  # departures of T from conduction are ~4x smaller than u / U
+
+
+def no_targets(fields: dict, cfg: dict) -> np.ndarray:
+    """Network targets of a field dict, float32 [3, nz, nr]: u_z / U, u_r / U
+    and T_SCALE times the departure of T from radial conduction (so that a
+    zero output is the conduction start)."""
+    return np.stack([fields["uz"] / U_SCALE, fields["ur"] / U_SCALE,
+                     T_SCALE * (fields["T"] - conduction_T(cfg))]).astype(np.float32)
+
+
+def no_fields(pred: np.ndarray, cfg: dict) -> np.ndarray:
     """Inverse of no_targets: start fields (u_z, u_r, T) [3, nz, nr] from a prediction."""
-    return np.stack([pred[0] * U_SCALE, pred[1] * U_SCALE, pred[2]]).astype(np.float32)
+    return np.stack([pred[0] * U_SCALE, pred[1] * U_SCALE,
+                     pred[2] / T_SCALE + conduction_T(cfg)]).astype(np.float32)

@@ -68,3 +68,32 @@ def test_feature_planes():
     assert f.shape == (6, 128, 128)
     np.testing.assert_allclose(f[:5, 0, 0], [1.0, 1.0, 1.0, 0.0, np.log(2) / np.log(10)], rtol=1e-6)
     np.testing.assert_allclose(f[5, 0, [0, -1]], [0.5, 1.0], rtol=1e-6)
+
+
+def test_conduction_profile_closed_form():
+    """T = T_o + (T_i - T_o) ln(r_o / r) / ln R*: wall values, and r dT/dr
+    constant (zero divergence of the radial conduction flux)."""
+    cfg = li.annulus(nr=65, nz=8, Rstar=3.0)
+    T = li.conduction_T(cfg)[0]
+    r = cfg["r0"] + np.arange(65)
+    assert abs(T[0] - cfg["T_rmin"]) < 1e-12 and abs(T[-1] - cfg["T_rmax"]) < 1e-12
+    flux = r * np.gradient(T, r)
+    np.testing.assert_allclose(flux[2:-2], flux[2], rtol=1e-3)
+
+
+def test_targets_and_fields_are_inverse():
+    cfg = li.annulus(nr=32, nz=24, Rstar=2.0)
+    rng = np.random.default_rng(2)
+    f = {k: rng.standard_normal((24, 32)).astype(np.float32) for k in ("uz", "ur", "T")}
+    back = li.no_fields(li.no_targets(f, cfg), cfg)
+    for i, k in enumerate(("uz", "ur", "T")):
+        np.testing.assert_allclose(back[i], f[k], rtol=1e-5, atol=1e-6)
+
+
+def test_committed_weights_load_in_bfloat16():
+    from paper_1409_5929_amd import warmstart as ws
+
+    p = ws.load_weights(ws.WEIGHTS)
+    assert p.size == N.param_count(ws.WIDTHS)
+    assert np.isfinite(p).all()
+    assert (p.view(np.uint32) & 0xFFFF == 0).all()  # bfloat16 values
