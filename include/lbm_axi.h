@@ -186,8 +186,9 @@ int lbm_axi_kernel_time(lbm_axi* h, double* total_ms, int64_t* launches);
 
 /*
  * Launch shape of the step kernel: blocks of 64 lanes along r by 4 waves,
- * each thread updating kz nodes along z (1 <= kz <= 64; default 4), and at
- * most blocks_per_cu blocks resident per compute unit (0: no cap; 1..64).
+ * each thread updating kz nodes along z (1 <= kz <= 64; default 4 in FP32
+ * storage, 16 in 16-bit storage), and at most blocks_per_cu blocks resident
+ * per compute unit (0: no cap; 1..64).
  * Waits for the stream and rebuilds the tile lists; results do not depend
  * on it.
  */

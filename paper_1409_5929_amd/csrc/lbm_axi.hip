@@ -123,11 +123,37 @@ __global__ __launch_bounds__(BX* BY) void k_step(const InstDev* __restrict__ des
   if ((D.side_rmin == SIDE_WALL && j == 0) || (D.side_rmax == SIDE_WALL && j == D.nr - 1)) return;
   const RowC R = make_row(D, j);
   const bool zwall = D.side_z == SIDE_WALL;
-  for (int i = 0; i < kz; ++i) {
-    const int k = tl.z + (int)threadIdx.y + BY * i;
-    if (k >= D.nz) break;
-    if (zwall && (k == 0 || k == D.nz - 1)) continue;
-    node_update<S, ODD, MODE>(D, R, j, k, mac_slot, fo, seed);
+  // Fluid nodes of this thread's strip: k = kbeg, kbeg + BY, ... < kend.
+  const int k0 = tl.z + (int)threadIdx.y;
+  int kbeg = k0, kend = min(k0 + BY * kz, D.nz);
+  if (zwall) {
+    if (kbeg == 0) kbeg += BY;
+    if (kend == D.nz && (D.nz - 1 - k0) % BY == 0) kend = D.nz - 1;  // top wall row in this strip
+  }
+  // The two-stage pipeline below pays off only for the FP32 odd step: there
+  // the loads are scattered over three rows and the registers allow it (even
+  // steps would exceed 256 VGPRs; 16-bit steps would lose a wave per SIMD).
+  if (MODE == MODE_FIELDS || !ODD || sizeof(S) != 4) {
+    for (int k = kbeg; k < kend; k += BY) node_update<S, ODD, MODE>(D, R, j, k, mac_slot, fo, seed);
+    return;
+  }
+  if (kbeg >= kend) return;
+  // Two-stage pipeline: the next node's loads are in flight while this node
+  // is updated (each slot belongs to one node of the step, so the order of
+  // one thread's loads and stores across its nodes does not matter).
+  float s[9], t[5], ph;
+  node_load<S, ODD>(D, R, j, kbeg, s, t, ph);
+  for (int k = kbeg; k < kend; k += BY) {
+    float sn[9], tn[5], phn = 0.0f;
+    const bool more = k + BY < kend;
+    if (more) node_load<S, ODD>(D, R, j, k + BY, sn, tn, phn);
+    node_update_loaded<S, ODD, MODE>(D, R, j, k, mac_slot, fo, seed, s, t, ph);
+    if (!more) break;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) s[q] = sn[q];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) t[q] = tn[q];
+    ph = phn;
   }
 }
 
@@ -575,6 +601,7 @@ int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* 
   lbm_axi* h = new lbm_axi();
   h->n_inst = n_inst;
   h->storage = p[0].storage;
+  h->kz = h->storage == LBM_STORE_FP32 ? 4 : 16;  // measured best at 8192^2; lbm_axi_autotune refines
   h->check = p[0].check_interval;
   h->prm.assign(p, p + n_inst);
   auto bail = [&](int rc) {

@@ -254,6 +254,21 @@ __host__ __device__ inline uint8_t node_mask(const InstDev& D, int j, int k) {
 }
 
 // Porosity, phi nu / K and phi F_phi / sqrt(K) at a node (Eqs. 6, 8).
+// From the porosity value of the node (phi_raw: the field value, or unused
+// when the porosity is uniform).
+__host__ __device__ inline void porosity_of(const InstDev& D, float phi_raw, float& phi, float& cD,
+                                            float& cF) {
+  if (D.phi_mode == 0) {
+    phi = D.phiu;
+    cD = D.cD;
+    cF = D.cF;
+  } else {
+    phi = phi_raw;
+    const float q = (1.0f - phi) / phi;
+    cD = D.C1 * q * q;
+    cF = D.phi_mode == 1 ? D.C2 * q / phi : D.C3 * (1.0f - phi) / sqrtf(phi);
+  }
+}
 __host__ __device__ inline void porosity(const InstDev& D, int64_t o, float& phi, float& cD,
                                          float& cF) {
   if (D.phi_mode == 0) {
@@ -418,26 +433,24 @@ __host__ __device__ inline void wall_node(const InstDev& D, S* P, const NodeStat
   }
 }
 
-// One fluid node (j, k) at one time step.
-// seed: random bits of this step for stochastic rounding of 16-bit storage.
-template <typename S, bool ODD, int MODE>
-__host__ __device__ inline void node_update(const InstDev& D, const RowC& R, int j, int k,
-                                            int mac_slot, const FieldOut& fo, uint32_t seed) {
-  S* __restrict__ P = (S*)D.pop;
+// The populations arriving at fluid node (j, k) (as stored, unscaled to
+// FP32) and its porosity value.  Each slot is read and written by one node
+// only in a step, so these loads may be issued before earlier nodes of the
+// same thread are updated.
+template <typename S, bool ODD>
+__host__ __device__ inline void node_load(const InstDev& D, const RowC& R, int j, int k, float s[9],
+                                          float t[5], float& phi_raw) {
+  const S* __restrict__ P = (const S*)D.pop;
   const int64_t pl = D.plane;
   const int st = D.stride;
-  const float inv_sc = D.st_inv, sc = D.st_scale;
+  const float inv_sc = D.st_inv;
   int km = k - 1, kp = k + 1;
   if (D.side_z == SIDE_PERIODIC) {
     if (km < 0) km += D.nz;
     if (kp >= D.nz) kp -= D.nz;
   }
   const int64_t o = (int64_t)k * st + j;
-  Dither rn(mix32(seed ^ (uint32_t)o));
   const int64_t rowm = (int64_t)km * st, row0 = (int64_t)k * st, rowp = (int64_t)kp * st;
-
-  // ---- load the populations arriving at x --------------------------------
-  float s[9], t[5];
   if (!ODD) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) s[q] = Store<S>::ld(P, q * pl + o, inv_sc);
@@ -461,8 +474,32 @@ __host__ __device__ inline void node_update(const InstDev& D, const RowC& R, int
     t[3] = Store<S>::ld(P, 10 * pl + row0 + cp, inv_sc);
     t[4] = Store<S>::ld(P, 11 * pl + rowp + j, inv_sc);
   }
+  phi_raw = D.phi_mode == 0 ? 0.0f : D.phi[o];
+}
+
+// One fluid node (j, k) at one time step, from its loaded populations s, t
+// and porosity value.  seed: random bits of this step for stochastic
+// rounding of 16-bit storage.
+template <typename S, bool ODD, int MODE>
+__host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC& R, int j, int k,
+                                                   int mac_slot, const FieldOut& fo, uint32_t seed,
+                                                   const float s[9], const float t_in[5],
+                                                   float phi_raw) {
+  S* __restrict__ P = (S*)D.pop;
+  const int64_t pl = D.plane;
+  const int st = D.stride;
+  const float sc = D.st_scale;
+  int km = k - 1, kp = k + 1;
+  if (D.side_z == SIDE_PERIODIC) {
+    if (km < 0) km += D.nz;
+    if (kp >= D.nz) kp -= D.nz;
+  }
+  const int64_t o = (int64_t)k * st + j;
+  Dither rn(mix32(seed ^ (uint32_t)o));
+  const int64_t rowm = (int64_t)km * st, row0 = (int64_t)k * st, rowp = (int64_t)kp * st;
+  float t[5] = {t_in[0], t_in[1], t_in[2], t_in[3], t_in[4]};
   float phi, cD, cF;
-  porosity(D, o, phi, cD, cF);
+  porosity_of(D, phi_raw, phi, cD, cF);
 
   // Rescale to this node's frame: d_i = fhat_i - w_i (1 - e_ir / (2 r)).
   float d[9];
@@ -629,6 +666,15 @@ __host__ __device__ inline void node_update(const InstDev& D, const RowC& R, int
       }
     }
   }
+}
+
+// One fluid node (j, k) at one time step (load, then update).
+template <typename S, bool ODD, int MODE>
+__host__ __device__ inline void node_update(const InstDev& D, const RowC& R, int j, int k,
+                                            int mac_slot, const FieldOut& fo, uint32_t seed) {
+  float s[9], t[5], ph;
+  node_load<S, ODD>(D, R, j, k, s, t, ph);
+  node_update_loaded<S, ODD, MODE>(D, R, j, k, mac_slot, fo, seed, s, t, ph);
 }
 
 // Start state of node (j, k) (reading: f = f^eq - S~/2, g = g^eq), written
