@@ -95,6 +95,7 @@ struct lbm_axi {
   double timed_ms = 0.0;
   long long timed_launches = 0;
   std::vector<char> active;     // instances in the launch list (empty: all)
+  bool buf = false;             // step kernels use buffer addressing (all arrays below 4 GiB)
   long long* dclk = nullptr;    // device clock of captured step graphs
   int graph_steps = 32;         // steps per captured graph (0: no graphs)
   hipStream_t cap_stream = nullptr;
@@ -105,7 +106,7 @@ struct lbm_axi {
 // ---- kernels ------------------------------------------------------------------
 
 
-template <typename S, bool ODD, int MODE>
+template <typename S, bool ODD, int MODE, bool BUF>
 __global__ __launch_bounds__(BX* BY) void k_step(const InstDev* __restrict__ descs,
                                                  const int4* __restrict__ tiles,
                                                  const int* __restrict__ status, int kz,
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(BX* BY) void k_step(const InstDev* __restrict__ des
   // the loads are scattered over three rows and the registers allow it (even
   // steps would exceed 256 VGPRs; 16-bit steps would lose a wave per SIMD).
   if (MODE == MODE_FIELDS || !ODD || sizeof(S) != 4) {
-    for (int k = kbeg; k < kend; k += BY) node_update<S, ODD, MODE>(D, R, j, k, mac_slot, fo, seed);
+    for (int k = kbeg; k < kend; k += BY) node_update<S, ODD, MODE, BUF>(D, R, j, k, mac_slot, fo, seed);
     return;
   }
   if (kbeg >= kend) return;
@@ -142,12 +143,12 @@ __global__ __launch_bounds__(BX* BY) void k_step(const InstDev* __restrict__ des
   // is updated (each slot belongs to one node of the step, so the order of
   // one thread's loads and stores across its nodes does not matter).
   float s[9], t[5], ph;
-  node_load<S, ODD>(D, R, j, kbeg, s, t, ph);
+  node_load<S, ODD, BUF>(D, R, j, kbeg, s, t, ph);
   for (int k = kbeg; k < kend; k += BY) {
     float sn[9], tn[5], phn = 0.0f;
     const bool more = k + BY < kend;
-    if (more) node_load<S, ODD>(D, R, j, k + BY, sn, tn, phn);
-    node_update_loaded<S, ODD, MODE>(D, R, j, k, mac_slot, fo, seed, s, t, ph);
+    if (more) node_load<S, ODD, BUF>(D, R, j, k + BY, sn, tn, phn);
+    node_update_loaded<S, ODD, MODE, BUF>(D, R, j, k, mac_slot, fo, seed, s, t, ph);
     if (!more) break;
 #pragma unroll
     for (int q = 0; q < 9; ++q) s[q] = sn[q];
@@ -364,6 +365,15 @@ int validate(const lbm_axi_params& p, int i) {
   return LBM_AXI_OK;
 }
 
+// Byte size for buffer addressing (32-bit offsets), 0 when 4 GiB or more.
+uint32_t pop_bytes32(size_t bytes) { return bytes < 0xFFFFFFFFull ? (uint32_t)bytes : 0u; }
+
+bool all_buffer_addressable(const lbm_axi* h) {
+  for (const InstDev& D : h->hdesc)
+    if (D.pop_bytes == 0) return false;
+  return !h->hdesc.empty() && h->storage != LBM_STORE_FP32;
+}
+
 void* dalloc(lbm_axi* h, size_t bytes, hipError_t* err) {
   void* p = nullptr;
   *err = hipMalloc(&p, bytes);
@@ -373,24 +383,37 @@ void* dalloc(lbm_axi* h, size_t bytes, hipError_t* err) {
   return p;
 }
 
-template <typename S>
-int launch_step(lbm_axi* h, bool odd, int mode, int slot, uint32_t seed, hipStream_t st,
+template <typename S, bool BUF>
+int launch_step_b(lbm_axi* h, bool odd, int mode, int slot, uint32_t seed, hipStream_t st,
                 const long long* clk, int off) {
   const dim3 blk(BX, BY);
   const FieldOut fo{nullptr, nullptr, nullptr, nullptr, nullptr};
   if (!odd) {
     if (mode == MODE_STEP)
-      k_step<S, false, MODE_STEP><<<h->ntiles_launch, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo, seed, clk, off);
+      k_step<S, false, MODE_STEP, BUF><<<h->ntiles_launch, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo, seed, clk, off);
     else
-      k_step<S, false, MODE_STEP_MACRO><<<h->ntiles_launch, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo, seed, clk, off);
+      k_step<S, false, MODE_STEP_MACRO, BUF><<<h->ntiles_launch, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo, seed, clk, off);
   } else {
     if (mode == MODE_STEP)
-      k_step<S, true, MODE_STEP><<<h->ntiles_launch, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo, seed, clk, off);
+      k_step<S, true, MODE_STEP, BUF><<<h->ntiles_launch, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo, seed, clk, off);
     else
-      k_step<S, true, MODE_STEP_MACRO><<<h->ntiles_launch, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo, seed, clk, off);
+      k_step<S, true, MODE_STEP_MACRO, BUF><<<h->ntiles_launch, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo, seed, clk, off);
   }
   HIPCHK(hipGetLastError());
   return LBM_AXI_OK;
+}
+
+// 16-bit storage: buffer addressing when every instance's population array
+// is below 4 GiB (measured 12 % faster at 8192^2).  FP32 keeps flat
+// addressing: there the buffer form, though lighter on registers, measured
+// 15 % slower.
+template <typename S>
+int launch_step(lbm_axi* h, bool odd, int mode, int slot, uint32_t seed, hipStream_t st,
+                const long long* clk, int off) {
+  if constexpr (sizeof(S) == 2) {
+    if (h->buf) return launch_step_b<S, true>(h, odd, mode, slot, seed, st, clk, off);
+  }
+  return launch_step_b<S, false>(h, odd, mode, slot, seed, st, clk, off);
 }
 
 template <typename S>
@@ -398,9 +421,9 @@ int launch_fields(lbm_axi* h, int inst, bool odd, const FieldOut& fo) {
   const dim3 blk(BX, BY);
   const int4* tl = h->dtiles_plain + h->tile_first[inst];
   if (!odd)
-    k_step<S, false, MODE_FIELDS><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->dstatus, h->kz, 0, fo, 0u, nullptr, 0);
+    k_step<S, false, MODE_FIELDS, false><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->dstatus, h->kz, 0, fo, 0u, nullptr, 0);
   else
-    k_step<S, true, MODE_FIELDS><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->dstatus, h->kz, 0, fo, 0u, nullptr, 0);
+    k_step<S, true, MODE_FIELDS, false><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->dstatus, h->kz, 0, fo, 0u, nullptr, 0);
   HIPCHK(hipGetLastError());
   return LBM_AXI_OK;
 }
@@ -643,6 +666,7 @@ int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* 
       if (rc) return bail(fail(rc, msg));
     }
     D.pop = dalloc(h, (size_t)14 * D.plane * esz, &err);
+    D.pop_bytes = pop_bytes32((size_t)14 * D.plane * esz);
     if (!D.pop) return bail(fail(LBM_AXI_ENOMEM, std::string("population array: ") + hipGetErrorString(err)));
     if (h->storage == LBM_STORE_FP32) {
       D.g0 = (float*)D.pop + 9 * D.plane;
@@ -680,6 +704,7 @@ int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* 
   if (!h->ddesc || !h->dstatus || !h->dres || !h->dclk)
     return bail(fail(LBM_AXI_ENOMEM, "descriptor arrays"));
   HIPBAIL(hipMemcpy(h->ddesc, h->hdesc.data(), sizeof(InstDev) * n_inst, hipMemcpyHostToDevice));
+  h->buf = all_buffer_addressable(h);
   HIPBAIL(hipMemset(h->dstatus, 0, sizeof(int) * n_inst));
   {
     std::vector<DevResult> r0(n_inst);
@@ -923,6 +948,7 @@ int lbm_axi_set_storage(lbm_axi* h, int32_t storage, int32_t storage_shift) {
       return fail(rc ? rc : LBM_AXI_ENOMEM, rc ? msg : "population array for the new storage");
     }
     Dn.pop = pop;
+    Dn.pop_bytes = pop_bytes32((size_t)14 * Dn.plane * esz_n);
     Dn.g0 = g0;
     Dn.phi = Do.phi;
     Dn.mac[0] = Do.mac[0];
@@ -945,6 +971,7 @@ int lbm_axi_set_storage(lbm_axi* h, int32_t storage, int32_t storage_shift) {
   h->hdesc = nd;
   h->prm = np;
   h->storage = storage;
+  h->buf = all_buffer_addressable(h);
   HIPCHK(hipMemcpy(h->ddesc, h->hdesc.data(), sizeof(InstDev) * h->n_inst, hipMemcpyHostToDevice));
   // Converged or stalled runs continue in the new storage; diverged ones stay.
   std::vector<int> st(h->n_inst);

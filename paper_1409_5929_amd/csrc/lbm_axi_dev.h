@@ -41,6 +41,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace lbmaxi {
 
 enum { SIDE_WALL = 0, SIDE_AXIS = 1, SIDE_PERIODIC = 2 };
@@ -65,6 +67,7 @@ struct InstDev {
   int32_t src_printed;
   int32_t phi_mode;  // 0 uniform, 1 field with Ergun F_phi, 2 field with constant F_phi
   void* pop;         // 14 planes
+  uint32_t pop_bytes;  // size of pop in bytes when below 4 GiB (buffer addressing), else 0
   float* g0;         // plane of g_0 - wt_0 T_s in FP32 for every storage type: plane 9 of
                      // pop in FP32, its own plane otherwise (g_0 never streams and carries
                      // most of T, so 16 bits there would dominate the error of T)
@@ -165,6 +168,71 @@ __host__ __device__ inline uint32_t mix32(uint32_t x) {
   x ^= x >> 16;
   return x;
 }
+// ---- population access --------------------------------------------------
+// PopAcc<S, false>: flat addressing through a pointer (64-bit addresses per
+// lane).  PopAcc<S, true>: buffer addressing, one descriptor in scalar
+// registers per instance and 32-bit byte offsets per lane (half the address
+// registers; the hardware also drops accesses outside the array), usable when
+// the population array is below 4 GiB.
+template <typename S, bool BUF>
+struct PopAcc;
+template <typename S>
+struct PopAcc<S, false> {
+  S* P;
+  float inv, sc;
+  __host__ __device__ explicit PopAcc(const InstDev& D) : P((S*)D.pop), inv(D.st_inv), sc(D.st_scale) {}
+  __host__ __device__ float ld(int64_t i) const { return Store<S>::ld(P, i, inv); }
+  __host__ __device__ void st(int64_t i, float v, uint32_t r) const { Store<S>::st_sr(P, i, v, sc, r); }
+};
+template <typename S>
+struct PopAcc<S, true> {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __amdgpu_buffer_rsrc_t rs;
+#endif
+  float inv, sc;
+  __host__ __device__ explicit PopAcc(const InstDev& D) : inv(D.st_inv), sc(D.st_scale) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    rs = __builtin_amdgcn_make_buffer_rsrc(D.pop, (short)0, (int)D.pop_bytes, 0x00020000);
+#endif
+  }
+  __host__ __device__ float ld(int64_t i) const {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const int off = (int)((uint32_t)i * (uint32_t)sizeof(S));
+    if constexpr (std::is_same<S, float>::value) {
+      return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+    } else {
+      const uint16_t b = (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0);
+      if constexpr (std::is_same<S, __half>::value)
+        return __half2float(__builtin_bit_cast(__half, b)) * inv;
+      else
+        return __uint_as_float((uint32_t)b << 16) * inv;
+    }
+#else
+    (void)i;
+    return 0.0f;
+#endif
+  }
+  __host__ __device__ void st(int64_t i, float v, uint32_t r) const {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const int off = (int)((uint32_t)i * (uint32_t)sizeof(S));
+    if constexpr (std::is_same<S, float>::value) {
+      (void)r;
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, off, 0, 0);
+    } else if constexpr (std::is_same<S, __half>::value) {
+      const lbm_h2 h = __builtin_amdgcn_cvt_sr_f16_f32(lbm_h2{0, 0}, v * sc, r, false);
+      __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h[0]), rs, off, 0, 0);
+    } else {
+      const lbm_b2 h = __builtin_amdgcn_cvt_sr_bf16_f32(lbm_b2{0, 0}, v * sc, r, false);
+      __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h[0]), rs, off, 0, 0);
+    }
+#else
+    (void)i;
+    (void)v;
+    (void)r;
+#endif
+  }
+};
+
 // Random bits of time level n (one value per step, shared by all nodes).
 __host__ __device__ inline uint32_t step_seed(long long n) {
   return mix32((uint32_t)n * 0x9E3779B9u + (uint32_t)((unsigned long long)n >> 32));
@@ -340,8 +408,8 @@ struct NodeState {
   float t[5];                            // stored temperature slots
 };
 
-template <typename S, bool ODD>
-__host__ __device__ inline void store_wall(const InstDev& D, S* P, int jb, int kb, const float d[9],
+template <typename S, bool ODD, typename A>
+__host__ __device__ inline void store_wall(const InstDev& D, const A& P, int jb, int kb, const float d[9],
                                            const float tg[5], Dither& rn) {
   constexpr int EXr[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
   constexpr int EZr[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
@@ -351,26 +419,24 @@ __host__ __device__ inline void store_wall(const InstDev& D, S* P, int jb, int k
     int kd = kb + EZr[i];
     if (!fluid_dest(D, jb + EXr[i], kd)) continue;
     if (ODD)
-      Store<S>::st_sr(P, i * pl + (int64_t)kd * D.stride + jb + EXr[i], d[i], D.st_scale, rn.next());
+      P.st(i * pl + (int64_t)kd * D.stride + jb + EXr[i], d[i], rn.next());
     else
-      Store<S>::st_sr(P, OPP[i] * pl + (int64_t)kb * D.stride + jb, d[i], D.st_scale, rn.next());
+      P.st(OPP[i] * pl + (int64_t)kb * D.stride + jb, d[i], rn.next());
   }
   for (int i = 1; i < 5; ++i) {
     int kd = kb + EZr[i];
     if (!fluid_dest(D, jb + EXr[i], kd)) continue;
     if (ODD)
-      Store<S>::st_sr(P, (9 + i) * pl + (int64_t)kd * D.stride + jb + EXr[i], tg[i], D.st_scale,
-                      rn.next());
+      P.st((9 + i) * pl + (int64_t)kd * D.stride + jb + EXr[i], tg[i], rn.next());
     else
-      Store<S>::st_sr(P, (9 + OPP[i]) * pl + (int64_t)kb * D.stride + jb, tg[i], D.st_scale,
-                      rn.next());
+      P.st((9 + OPP[i]) * pl + (int64_t)kb * D.stride + jb, tg[i], rn.next());
   }
 }
 
 // Wall node b = x + (dr, dz) owned by fluid node x (non-equilibrium
 // extrapolation, Sec. 4): imposed rho_B, u = 0, wall temperature.
-template <typename S, bool ODD, int MODE>
-__host__ __device__ inline void wall_node(const InstDev& D, S* P, const NodeState& B, float rB,
+template <typename S, bool ODD, int MODE, typename A>
+__host__ __device__ inline void wall_node(const InstDev& D, const A& P, const NodeState& B, float rB,
                                           int j, int k, int dr, int dz, int mac_slot,
                                           const FieldOut& fo, Dither& rn) {
   const int jb = j + dr, kb = k + dz;
@@ -437,13 +503,12 @@ __host__ __device__ inline void wall_node(const InstDev& D, S* P, const NodeStat
 // FP32) and its porosity value.  Each slot is read and written by one node
 // only in a step, so these loads may be issued before earlier nodes of the
 // same thread are updated.
-template <typename S, bool ODD>
+template <typename S, bool ODD, bool BUF = false>
 __host__ __device__ inline void node_load(const InstDev& D, const RowC& R, int j, int k, float s[9],
                                           float t[5], float& phi_raw) {
-  const S* __restrict__ P = (const S*)D.pop;
+  const PopAcc<S, BUF> P(D);
   const int64_t pl = D.plane;
   const int st = D.stride;
-  const float inv_sc = D.st_inv;
   int km = k - 1, kp = k + 1;
   if (D.side_z == SIDE_PERIODIC) {
     if (km < 0) km += D.nz;
@@ -453,26 +518,26 @@ __host__ __device__ inline void node_load(const InstDev& D, const RowC& R, int j
   const int64_t rowm = (int64_t)km * st, row0 = (int64_t)k * st, rowp = (int64_t)kp * st;
   if (!ODD) {
 #pragma unroll
-    for (int q = 0; q < 9; ++q) s[q] = Store<S>::ld(P, q * pl + o, inv_sc);
+    for (int q = 0; q < 9; ++q) s[q] = P.ld(q * pl + o);
     t[0] = D.g0[o];
 #pragma unroll
-    for (int q = 1; q < 5; ++q) t[q] = Store<S>::ld(P, (9 + q) * pl + o, inv_sc);
+    for (int q = 1; q < 5; ++q) t[q] = P.ld((9 + q) * pl + o);
   } else {
     const int64_t cm = R.cm, cp = R.cp;
-    s[0] = Store<S>::ld(P, o, inv_sc);
-    s[1] = Store<S>::ld(P, (R.mir ? 1 : 3) * pl + row0 + cm, inv_sc);
-    s[2] = Store<S>::ld(P, 4 * pl + rowm + j, inv_sc);
-    s[3] = Store<S>::ld(P, 1 * pl + row0 + cp, inv_sc);
-    s[4] = Store<S>::ld(P, 2 * pl + rowp + j, inv_sc);
-    s[5] = Store<S>::ld(P, (R.mir ? 8 : 7) * pl + rowm + cm, inv_sc);
-    s[6] = Store<S>::ld(P, 8 * pl + rowm + cp, inv_sc);
-    s[7] = Store<S>::ld(P, 5 * pl + rowp + cp, inv_sc);
-    s[8] = Store<S>::ld(P, (R.mir ? 5 : 6) * pl + rowp + cm, inv_sc);
+    s[0] = P.ld(o);
+    s[1] = P.ld((R.mir ? 1 : 3) * pl + row0 + cm);
+    s[2] = P.ld(4 * pl + rowm + j);
+    s[3] = P.ld(1 * pl + row0 + cp);
+    s[4] = P.ld(2 * pl + rowp + j);
+    s[5] = P.ld((R.mir ? 8 : 7) * pl + rowm + cm);
+    s[6] = P.ld(8 * pl + rowm + cp);
+    s[7] = P.ld(5 * pl + rowp + cp);
+    s[8] = P.ld((R.mir ? 5 : 6) * pl + rowp + cm);
     t[0] = D.g0[o];
-    t[1] = Store<S>::ld(P, (R.mir ? 10 : 12) * pl + row0 + cm, inv_sc);
-    t[2] = Store<S>::ld(P, 13 * pl + rowm + j, inv_sc);
-    t[3] = Store<S>::ld(P, 10 * pl + row0 + cp, inv_sc);
-    t[4] = Store<S>::ld(P, 11 * pl + rowp + j, inv_sc);
+    t[1] = P.ld((R.mir ? 10 : 12) * pl + row0 + cm);
+    t[2] = P.ld(13 * pl + rowm + j);
+    t[3] = P.ld(10 * pl + row0 + cp);
+    t[4] = P.ld(11 * pl + rowp + j);
   }
   phi_raw = D.phi_mode == 0 ? 0.0f : D.phi[o];
 }
@@ -480,15 +545,14 @@ __host__ __device__ inline void node_load(const InstDev& D, const RowC& R, int j
 // One fluid node (j, k) at one time step, from its loaded populations s, t
 // and porosity value.  seed: random bits of this step for stochastic
 // rounding of 16-bit storage.
-template <typename S, bool ODD, int MODE>
+template <typename S, bool ODD, int MODE, bool BUF = false>
 __host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC& R, int j, int k,
                                                    int mac_slot, const FieldOut& fo, uint32_t seed,
                                                    const float s[9], const float t_in[5],
                                                    float phi_raw) {
-  S* __restrict__ P = (S*)D.pop;
+  const PopAcc<S, BUF> P(D);
   const int64_t pl = D.plane;
   const int st = D.stride;
-  const float sc = D.st_scale;
   int km = k - 1, kp = k + 1;
   if (D.side_z == SIDE_PERIODIC) {
     if (km < 0) km += D.nz;
@@ -616,36 +680,36 @@ __host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC&
 
     // ---- stream and store --------------------------------------------------
     if (!ODD) {
-      Store<S>::st_sr(P, 0 * pl + o, d[0], sc, rn.next());
-      Store<S>::st_sr(P, 3 * pl + o, d[1], sc, rn.next());
-      Store<S>::st_sr(P, 4 * pl + o, d[2], sc, rn.next());
-      Store<S>::st_sr(P, 1 * pl + o, d[3], sc, rn.next());
-      Store<S>::st_sr(P, 2 * pl + o, d[4], sc, rn.next());
-      Store<S>::st_sr(P, 7 * pl + o, d[5], sc, rn.next());
-      Store<S>::st_sr(P, 8 * pl + o, d[6], sc, rn.next());
-      Store<S>::st_sr(P, 5 * pl + o, d[7], sc, rn.next());
-      Store<S>::st_sr(P, 6 * pl + o, d[8], sc, rn.next());
+      P.st(0 * pl + o, d[0], rn.next());
+      P.st(3 * pl + o, d[1], rn.next());
+      P.st(4 * pl + o, d[2], rn.next());
+      P.st(1 * pl + o, d[3], rn.next());
+      P.st(2 * pl + o, d[4], rn.next());
+      P.st(7 * pl + o, d[5], rn.next());
+      P.st(8 * pl + o, d[6], rn.next());
+      P.st(5 * pl + o, d[7], rn.next());
+      P.st(6 * pl + o, d[8], rn.next());
       D.g0[o] = tg[0];
-      Store<S>::st_sr(P, 12 * pl + o, tg[1], sc, rn.next());
-      Store<S>::st_sr(P, 13 * pl + o, tg[2], sc, rn.next());
-      Store<S>::st_sr(P, 10 * pl + o, tg[3], sc, rn.next());
-      Store<S>::st_sr(P, 11 * pl + o, tg[4], sc, rn.next());
+      P.st(12 * pl + o, tg[1], rn.next());
+      P.st(13 * pl + o, tg[2], rn.next());
+      P.st(10 * pl + o, tg[3], rn.next());
+      P.st(11 * pl + o, tg[4], rn.next());
     } else {
       const int64_t cm = R.cm, cp = R.cp;
-      Store<S>::st_sr(P, o, d[0], sc, rn.next());
-      Store<S>::st_sr(P, 1 * pl + row0 + cp, d[1], sc, rn.next());
-      Store<S>::st_sr(P, 2 * pl + rowp + j, d[2], sc, rn.next());
-      Store<S>::st_sr(P, (R.mir ? 1 : 3) * pl + row0 + cm, d[3], sc, rn.next());
-      Store<S>::st_sr(P, 4 * pl + rowm + j, d[4], sc, rn.next());
-      Store<S>::st_sr(P, 5 * pl + rowp + cp, d[5], sc, rn.next());
-      Store<S>::st_sr(P, (R.mir ? 5 : 6) * pl + rowp + cm, d[6], sc, rn.next());
-      Store<S>::st_sr(P, (R.mir ? 8 : 7) * pl + rowm + cm, d[7], sc, rn.next());
-      Store<S>::st_sr(P, 8 * pl + rowm + cp, d[8], sc, rn.next());
+      P.st(o, d[0], rn.next());
+      P.st(1 * pl + row0 + cp, d[1], rn.next());
+      P.st(2 * pl + rowp + j, d[2], rn.next());
+      P.st((R.mir ? 1 : 3) * pl + row0 + cm, d[3], rn.next());
+      P.st(4 * pl + rowm + j, d[4], rn.next());
+      P.st(5 * pl + rowp + cp, d[5], rn.next());
+      P.st((R.mir ? 5 : 6) * pl + rowp + cm, d[6], rn.next());
+      P.st((R.mir ? 8 : 7) * pl + rowm + cm, d[7], rn.next());
+      P.st(8 * pl + rowm + cp, d[8], rn.next());
       D.g0[o] = tg[0];
-      Store<S>::st_sr(P, 10 * pl + row0 + cp, tg[1], sc, rn.next());
-      Store<S>::st_sr(P, 11 * pl + rowp + j, tg[2], sc, rn.next());
-      Store<S>::st_sr(P, (R.mir ? 10 : 12) * pl + row0 + cm, tg[3], sc, rn.next());
-      Store<S>::st_sr(P, 13 * pl + rowm + j, tg[4], sc, rn.next());
+      P.st(10 * pl + row0 + cp, tg[1], rn.next());
+      P.st(11 * pl + rowp + j, tg[2], rn.next());
+      P.st((R.mir ? 10 : 12) * pl + row0 + cm, tg[3], rn.next());
+      P.st(13 * pl + rowm + j, tg[4], rn.next());
     }
   } else {
     for (int q = 0; q < 5; ++q) B.t[q] = t[q];
@@ -669,12 +733,12 @@ __host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC&
 }
 
 // One fluid node (j, k) at one time step (load, then update).
-template <typename S, bool ODD, int MODE>
+template <typename S, bool ODD, int MODE, bool BUF = false>
 __host__ __device__ inline void node_update(const InstDev& D, const RowC& R, int j, int k,
                                             int mac_slot, const FieldOut& fo, uint32_t seed) {
   float s[9], t[5], ph;
-  node_load<S, ODD>(D, R, j, k, s, t, ph);
-  node_update_loaded<S, ODD, MODE>(D, R, j, k, mac_slot, fo, seed, s, t, ph);
+  node_load<S, ODD, BUF>(D, R, j, k, s, t, ph);
+  node_update_loaded<S, ODD, MODE, BUF>(D, R, j, k, mac_slot, fo, seed, s, t, ph);
 }
 
 // Start state of node (j, k) (reading: f = f^eq - S~/2, g = g^eq), written
