@@ -229,8 +229,9 @@ def main():
                     help="also run one plain 2 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(see the sharding notes in DESIGN.md); rerun with --gpus 1.", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(one large problem would be cut into z-slabs with a halo exchange per step; "
+              "batches would be split by instance); rerun with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -954,15 +954,23 @@ int lbm_axi_set_storage(lbm_axi* h, int32_t storage, int32_t storage_shift) {
     Dn.mac[0] = Do.mac[0];
     Dn.mac[1] = Do.mac[1];
   }
-  for (int i = 0; i < h->n_inst; ++i) {
+  hipError_t ce = hipSuccess;
+  for (int i = 0; i < h->n_inst && ce == hipSuccess; ++i) {
     switch (from) {
       case LBM_STORE_FP32: launch_convert_to<float>(h, storage, h->hdesc[i], nd[i]); break;
       case LBM_STORE_FP16: launch_convert_to<__half>(h, storage, h->hdesc[i], nd[i]); break;
       default: launch_convert_to<__hip_bfloat16>(h, storage, h->hdesc[i], nd[i]); break;
     }
-    HIPCHK(hipGetLastError());
+    ce = hipGetLastError();
   }
-  HIPCHK(hipStreamSynchronize(h->stream));
+  if (ce == hipSuccess) ce = hipStreamSynchronize(h->stream);
+  if (ce != hipSuccess) {  // keep the old state; drop the new arrays
+    for (int k = 0; k < h->n_inst; ++k) {
+      if (storage != LBM_STORE_FP32) release(h, nd[k].g0, (size_t)nd[k].plane * 4);
+      release(h, nd[k].pop, (size_t)14 * nd[k].plane * esz_n);
+    }
+    return fail(LBM_AXI_EDEVICE, std::string("storage conversion: ") + hipGetErrorString(ce));
+  }
   for (int i = 0; i < h->n_inst; ++i) {
     const InstDev& Do = h->hdesc[i];
     if (from != LBM_STORE_FP32) release(h, Do.g0, (size_t)Do.plane * 4);
