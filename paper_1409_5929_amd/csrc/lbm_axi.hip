@@ -8,14 +8,20 @@
 //              integrals (wave shuffles, then LDS across the block's waves)
 //   k_final    per-instance reduction of the partials, run-state update
 //   k_init     start state
+//   k_convert  storage conversion (FP32 / FP16 / BF16) of one instance
+//   k_setclock device clock read by captured step graphs
 //   k_step<MODE_FIELDS>  macroscopic fields of one instance (no population writes)
 //
 // Launch geometry: blocks of 64 x 4 threads; lanes run along r (coalesced
-// rows), the 4 waves take interleaved z rows, and each thread walks KZ rows
-// so that its per-radius constants are computed once.  Tiles of all
+// rows), the 4 waves take interleaved z rows, and each thread walks kz rows
+// so that its per-radius constants are computed once.  Tiles of all running
 // instances form one list; block b takes tile (b % 8) * ceil(T / 8) + b / 8,
 // so that each of the 8 XCDs (blocks are dealt to XCDs round-robin) sweeps a
 // contiguous band of rows and neighbouring tiles share its L2.
+//
+// Stepping: runs of plain steps replay a captured HIP graph (kernels only);
+// steps that fall on a check, and every step while launches are timed, are
+// launched one by one.  Both give identical results.
 #include <hip/hip_runtime.h>
 
 #include <cmath>

@@ -20,7 +20,9 @@
 // d_i = (r_src / r) s_i, and the collision maps zero deviations onto zero.
 // FP32 thus keeps its relative precision at any r, also next to the axis,
 // and the same representation serves FP16/BF16 storage (times a power of
-// two).  Temperature slots hold g_i - wt_i T_s for a storage shift T_s.
+// two, rounded stochastically).  Temperature slots hold g_i - wt_i T_s for a
+// storage shift T_s; the resting temperature population g_0 (which never
+// streams) lives in an FP32 plane of its own in every storage type.
 //
 // Axis.  With an axis at r_min the mirror row j = -1 is never stored: its
 // slot q at (-1, k) is the slot q* (e_r reversed) of (0, k).  In the writer's
