@@ -44,23 +44,23 @@ __host__ __device__ inline bf16_t to_bf16(float v) {  // round to nearest even (
   u += 0x7FFFu + ((u >> 16) & 1u);
   return (bf16_t)(u >> 16);
 }
-__device__ inline float ldf(const float* p, int64_t i) { return p[i]; }
-__device__ inline float ldf(const bf16_t* p, int64_t i) { return __uint_as_float((uint32_t)p[i] << 16); }
 
-constexpr int BM = 64, BN = 64, BK = 32, NT = 256;
+constexpr int BM = 128, BN = 128, BK = 32, NT = 256;
 constexpr int LDK = BK + 8;  // padded LDS rows (bf16 elements)
 constexpr int EW = 256;      // threads of the elementwise kernels
 
-// C[m][n] = sum_k A(m, k) B(k, n) (+ bias[m] in split 0), A(m, k) = A[m sam + k sak],
-// B(k, n) = B[k sbk + n sbn].  Split z covers k in [z kchunk, (z + 1) kchunk)
-// and writes C + z cz.  Block: 64 x 64 outputs, four waves of 32 x 32, each
-// as 2 x 2 MFMA 16 x 16 tiles.  Tiles are staged in LDS as bfloat16 with k
-// contiguous (B transposed), zero-filled outside the matrices.
-template <typename TA, typename TB>
-__global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, const TA* __restrict__ A,
-                                             int64_t sam, int64_t sak, const TB* __restrict__ B,
-                                             int64_t sbk, int64_t sbn, float* __restrict__ C,
-                                             int64_t ldc, int64_t cz, int kchunk,
+// C[m][n] = sum_k A(m, k) B(k, n) (+ bias[m] in split 0) on bfloat16 operands.
+// AK: A is k-contiguous, A(m, k) = A[m lda + k]; otherwise A(m, k) = A[k lda + m].
+// BKC: B is k-contiguous, B(k, n) = B[n ldb + k]; otherwise B(k, n) = B[k ldb + n].
+// Split z covers k in [z kchunk, (z + 1) kchunk) and writes C + z cz.
+// Block: 128 x 128 outputs, four waves of 64 x 64, each as 4 x 4 MFMA
+// 16 x 16 x 16 tiles.  Operands move as pairs of bf16 (4-byte loads: every
+// leading dimension, K and the contiguous extent are even), staged in LDS
+// with k contiguous (B transposed), zero outside the matrices.
+template <bool AK, bool BKC>
+__global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, const bf16_t* __restrict__ A,
+                                             int64_t lda, const bf16_t* __restrict__ B, int64_t ldb,
+                                             float* __restrict__ C, int64_t ldc, int64_t cz, int kchunk,
                                              const float* __restrict__ bias) {
   __shared__ bf16_t As[BM][LDK];
   __shared__ bf16_t Bs[BN][LDK];
@@ -68,50 +68,80 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, const TA* __re
   const int kb = blockIdx.z * kchunk;
   const int ke = min(K, kb + kchunk);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  v4f acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  v4f acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
   for (int k0 = kb; k0 < ke; k0 += BK) {
-    for (int e = tid; e < BM * BK; e += NT) {  // neighbouring threads along A's contiguous index
-      const int r = sak == 1 ? e / BK : e % BM;
-      const int c = sak == 1 ? e % BK : e / BM;
-      const int gm = m0 + r, gk = k0 + c;
-      As[r][c] = (gm < M && gk < ke) ? to_bf16(ldf(A, (int64_t)gm * sam + (int64_t)gk * sak)) : (bf16_t)0;
+    // A tile: 128 x 32 = 2048 pairs, 8 per thread
+#pragma unroll
+    for (int it = 0; it < BM * BK / 2 / NT; ++it) {
+      const int e = tid + it * NT;
+      if (AK) {  // pairs along k
+        const int r = e / (BK / 2), c = 2 * (e % (BK / 2));
+        const int gm = m0 + r, gk = k0 + c;
+        uint32_t v = 0;
+        if (gm < M && gk < ke) v = *(const uint32_t*)(A + (int64_t)gm * lda + gk);
+        *(uint32_t*)&As[r][c] = v;
+      } else {  // pairs along m
+        const int c = e / (BM / 2), r = 2 * (e % (BM / 2));
+        const int gm = m0 + r, gk = k0 + c;
+        uint32_t v = 0;
+        if (gm < M && gk < ke) v = *(const uint32_t*)(A + (int64_t)gk * lda + gm);
+        As[r][c] = (bf16_t)(v & 0xFFFFu);
+        As[r + 1][c] = (bf16_t)(v >> 16);
+      }
     }
-    for (int e = tid; e < BN * BK; e += NT) {
-      const int n = sbk == 1 ? e / BK : e % BN;
-      const int c = sbk == 1 ? e % BK : e / BN;
-      const int gn = n0 + n, gk = k0 + c;
-      Bs[n][c] = (gn < N && gk < ke) ? to_bf16(ldf(B, (int64_t)gk * sbk + (int64_t)gn * sbn)) : (bf16_t)0;
+#pragma unroll
+    for (int it = 0; it < BN * BK / 2 / NT; ++it) {
+      const int e = tid + it * NT;
+      if (BKC) {  // pairs along k
+        const int n = e / (BK / 2), c = 2 * (e % (BK / 2));
+        const int gn = n0 + n, gk = k0 + c;
+        uint32_t v = 0;
+        if (gn < N && gk < ke) v = *(const uint32_t*)(B + (int64_t)gn * ldb + gk);
+        *(uint32_t*)&Bs[n][c] = v;
+      } else {  // pairs along n
+        const int c = e / (BN / 2), n = 2 * (e % (BN / 2));
+        const int gn = n0 + n, gk = k0 + c;
+        uint32_t v = 0;
+        if (gn < N && gk < ke) v = *(const uint32_t*)(B + (int64_t)gk * ldb + gn);
+        Bs[n][c] = (bf16_t)(v & 0xFFFFu);
+        Bs[n + 1][c] = (bf16_t)(v >> 16);
+      }
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
       const int kq = kk + 4 * (lane >> 4);
-      v4s a[2], b[2];
+      v4s a[4], b[4];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const bf16_t* s = &As[wm + i * 16 + (lane & 15)][kq];
-        a[i] = v4s{(short)s[0], (short)s[1], (short)s[2], (short)s[3]};
+      for (int i = 0; i < 4; ++i) {
+        const bf16_t* p = &As[wm + i * 16 + (lane & 15)][kq];
+        a[i] = v4s{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const bf16_t* s = &Bs[wn + j * 16 + (lane & 15)][kq];
-        b[j] = v4s{(short)s[0], (short)s[1], (short)s[2], (short)s[3]};
+      for (int j = 0; j < 4; ++j) {
+        const bf16_t* p = &Bs[wn + j * 16 + (lane & 15)][kq];
+        b[j] = v4s{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < 4; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
   float* Cz = C + (int64_t)blockIdx.z * cz;
   // result layout of a 16 x 16 tile: lane holds column lane % 16, rows 4 (lane / 16) + q
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int gm = m0 + wm + i * 16 + 4 * (lane >> 4) + q;
         const int gn = n0 + wn + j * 16 + (lane & 15);
@@ -196,12 +226,15 @@ __global__ __launch_bounds__(EW) void k_act(const float* __restrict__ z, const f
   a[i] = skip ? v + skip[i] : v;
 }
 
-// dz = da where z > 0 (relu) or da; written over z
+// dz = da where z > 0 (relu) or da; written over z, and as bfloat16 (the
+// GEMM operand) into dz16
 __global__ __launch_bounds__(EW) void k_act_bwd(const float* __restrict__ da, float* __restrict__ z,
-                                                int64_t n, int relu) {
+                                                bf16_t* __restrict__ dz16, int64_t n, int relu) {
   const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
   if (i >= n) return;
-  z[i] = (!relu || z[i] > 0.0f) ? da[i] : 0.0f;
+  const float v = (!relu || z[i] > 0.0f) ? da[i] : 0.0f;
+  z[i] = v;
+  dz16[i] = to_bf16(v);
 }
 
 // dst (+)= src
@@ -344,6 +377,7 @@ struct lbm_no {
   bf16_t* parb = nullptr;
   std::vector<float*> z, a, da;  // per layer, [cout][B][Ho][Wo]
   bf16_t* col = nullptr;
+  bf16_t* dz16 = nullptr;  // bfloat16 copy of the current layer's dz
   float* dcol = nullptr;
   float* split = nullptr;
   int64_t split_n = 0;
@@ -387,13 +421,17 @@ void specs(const int* w, int H, int W, std::vector<Layer>& L, int64_t& npar) {
   }
 }
 
-template <typename TA, typename TB>
-int gemm(lbm_no* h, int M, int N, int K, const TA* A, int64_t sam, int64_t sak, const TB* B,
-         int64_t sbk, int64_t sbn, float* C, int64_t ldc, int64_t cz, int splits, int kchunk,
-         const float* bias) {
+template <bool AK, bool BKC>
+int gemm(lbm_no* h, int M, int N, int K, const bf16_t* A, int64_t lda, const bf16_t* B, int64_t ldb,
+         float* C, int64_t ldc, int64_t cz, int splits, int kchunk, const float* bias) {
   if (M <= 0 || N <= 0 || K <= 0) return LBM_NO_OK;
+  // operands move as bf16 pairs along their contiguous index: that extent,
+  // the leading dimensions and the split length must be even
+  const bool odd = ((lda | ldb | kchunk) & 1) || ((AK || BKC) && (K & 1)) || (!AK && (M & 1)) ||
+                   (!BKC && (N & 1));
+  if (odd) return fail(LBM_NO_EINVAL, "GEMM extents along paired indices must be even");
   const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)splits);
-  k_gemm<TA, TB><<<grid, NT, 0, h->stream>>>(M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, cz, kchunk, bias);
+  k_gemm<AK, BKC><<<grid, NT, 0, h->stream>>>(M, N, K, A, lda, B, ldb, C, ldc, cz, kchunk, bias);
   NOCHK(hipGetLastError());
   return LBM_NO_OK;
 }
@@ -417,8 +455,9 @@ int forward_internal(lbm_no* h, const float* x, int Bt) {
     const int K = l.cin * l.k * l.k;
     int rc = im2col(h, l, li == 0 ? x : h->a[li - 1], li == 0, Bt);
     if (rc) return rc;
-    rc = gemm<bf16_t, bf16_t>(h, l.cout, (int)P, K, h->parb + l.woff, K, 1, h->col, P, 1, h->z[li], P, 0, 1,
-                              K, h->par + l.boff);
+    // z[o][p] = W[o][k] col[k][p]: A k-contiguous, B n-contiguous
+    rc = gemm<true, false>(h, l.cout, (int)P, K, h->parb + l.woff, K, h->col, P, h->z[li], P, 0, 1,
+                           K, h->par + l.boff);
     if (rc) return rc;
     const int64_t n = (int64_t)l.cout * P;
     k_act<<<grid1(n), EW, 0, h->stream>>>(h->z[li], l.skip >= 0 ? h->a[l.skip] : nullptr, h->a[li], n, l.relu);
@@ -461,7 +500,8 @@ int lbm_no_create(const int32_t* widths, int32_t height, int32_t width, int32_t 
   if (out) *out = nullptr;
   if (!widths || !params || !out) return fail(LBM_NO_EINVAL, "null argument");
   for (int i = 0; i < 4; ++i)
-    if (widths[i] < 1 || widths[i] > 1024) return fail(LBM_NO_EINVAL, "widths out of [1, 1024]");
+    if (widths[i] < 2 || widths[i] > 1024 || (widths[i] & 1))
+      return fail(LBM_NO_EINVAL, "widths must be even, in [2, 1024]");
   if (height < 8 || width < 8 || height > 2048 || width > 2048 || height % 8 || width % 8)
     return fail(LBM_NO_EINVAL, "height and width must be multiples of 8 in [8, 2048]");
   if (max_batch < 1 || (int64_t)max_batch * height * width > (1ll << 31) / 64)
@@ -484,10 +524,11 @@ int lbm_no_create(const int32_t* widths, int32_t height, int32_t width, int32_t 
   h->v = (float*)nalloc(h, np * 4);
   h->parb = (bf16_t*)nalloc(h, np * 2);
   if (!h->par || !h->grad || !h->m || !h->v || !h->parb) return bail(fail(LBM_NO_ENOMEM, "parameters"));
-  int64_t colmax = 0, splitmax = 0;
+  int64_t colmax = 0, splitmax = 0, actmax = 0;
   for (const Layer& l : h->L) {
     const int64_t P = (int64_t)max_batch * l.Ho * l.Wo;
     const size_t n = (size_t)l.cout * P * 4;
+    actmax = std::max(actmax, (int64_t)l.cout * P);
     float* zl = (float*)nalloc(h, n);
     float* al = (float*)nalloc(h, n);
     float* dl = (float*)nalloc(h, n);
@@ -502,12 +543,14 @@ int lbm_no_create(const int32_t* widths, int32_t height, int32_t width, int32_t 
   }
   h->col = (bf16_t*)nalloc(h, (size_t)colmax * 2);
   h->dcol = (float*)nalloc(h, (size_t)colmax * 4);
+  h->dz16 = (bf16_t*)nalloc(h, (size_t)actmax * 2);
   h->split = (float*)nalloc(h, (size_t)splitmax * 4);
   h->split_n = splitmax;
   const int64_t lb = (3 * (int64_t)max_batch * height * width + EW - 1) / EW;
   h->lpart = (double*)nalloc(h, (size_t)lb * 8);
   h->dloss = (double*)nalloc(h, 8);
-  if (!h->col || !h->dcol || !h->split || !h->lpart || !h->dloss) return bail(fail(LBM_NO_ENOMEM, "work space"));
+  if (!h->col || !h->dcol || !h->dz16 || !h->split || !h->lpart || !h->dloss)
+    return bail(fail(LBM_NO_ENOMEM, "work space"));
   const int rc = lbm_no_set_params(h, params);
   if (rc) return bail(rc);
   *out = h;
@@ -562,7 +605,7 @@ int lbm_no_gradients(lbm_no* h, const float* x, const float* target, int32_t bat
     const int K = l.cin * l.k * l.k;
     const int64_t n = (int64_t)l.cout * P;
     // dz over z; the skip passes da on unchanged
-    k_act_bwd<<<grid1(n), EW, 0, h->stream>>>(h->da[li], h->z[li], n, l.relu);
+    k_act_bwd<<<grid1(n), EW, 0, h->stream>>>(h->da[li], h->z[li], h->dz16, n, l.relu);
     NOCHK(hipGetLastError());
     if (l.skip >= 0) {
       k_copy_add<<<grid1(n), EW, 0, h->stream>>>(h->da[l.skip], h->da[li], n, have[l.skip]);
@@ -575,8 +618,8 @@ int lbm_no_gradients(lbm_no* h, const float* x, const float* target, int32_t bat
     const int S = (int)((P + KCHUNK - 1) / KCHUNK);
     const int64_t mn = (int64_t)l.cout * K;
     if ((int64_t)S * mn > h->split_n) return fail(LBM_NO_EINVAL, "split work space too small");
-    rc = gemm<float, bf16_t>(h, l.cout, K, (int)P, h->z[li], P, 1, h->col, 1, P, h->split, K, mn, S, KCHUNK,
-                             nullptr);
+    // dW[o][k] = dz[o][p] col[k][p]: A k(=p)-contiguous, B k(=p)-contiguous
+    rc = gemm<true, true>(h, l.cout, K, (int)P, h->dz16, P, h->col, P, h->split, K, mn, S, KCHUNK, nullptr);
     if (rc) return rc;
     k_sum_splits<<<grid1(mn), EW, 0, h->stream>>>(h->split, S, mn, h->grad + l.woff);
     NOCHK(hipGetLastError());
@@ -584,8 +627,9 @@ int lbm_no_gradients(lbm_no* h, const float* x, const float* target, int32_t bat
     NOCHK(hipGetLastError());
     if (li == 0) break;  // no gradient with respect to the input
     // input gradient: dcol = W^T dz, then the col2im gather into da[li - 1]
-    rc = gemm<bf16_t, float>(h, K, (int)P, l.cout, h->parb + l.woff, 1, K, h->z[li], P, 1, h->dcol, P, 0, 1,
-                             l.cout, nullptr);
+    // dcol[k][p] = W[o][k] dz[o][p]: A m(=k)-contiguous, B n(=p)-contiguous
+    rc = gemm<false, false>(h, K, (int)P, l.cout, h->parb + l.woff, K, h->dz16, P, h->dcol, P, 0, 1,
+                            l.cout + (l.cout & 1), nullptr);  // one split covering all of cout
     if (rc) return rc;
     const int64_t ns = (int64_t)l.cin * batch * l.Hs * l.Ws;
     k_col2im<<<grid1(ns), EW, 0, h->stream>>>(h->dcol, l.cin, batch, l.Hs, l.Ws, l.up, l.k, l.s, (l.k - 1) / 2,

@@ -116,6 +116,8 @@ def test_invalid_arguments_are_refused(torch):
     params, _, _ = problem()
     with pytest.raises(NoError):
         WarmStartNet(WIDTHS, 30, 40, 4, params)  # height not a multiple of 8
+    with pytest.raises(NoError):  # odd widths (operands move as bf16 pairs)
+        WarmStartNet((7, 16, 24, 32), 32, 40, 4, li.no_init_params((7, 16, 24, 32)))
     net = WarmStartNet(WIDTHS, 32, 40, 2, params)
     with pytest.raises(NoError):
         net.forward(torch.zeros((3, 6, 32, 40), device="cuda"))  # batch above max_batch
