@@ -27,6 +27,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -564,6 +566,19 @@ void release(lbm_axi* h, void* p, size_t bytes) {
     }
 }
 
+// Host-side failures (allocation) become error codes: nothing may unwind
+// through the C ABI.
+template <typename F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return fail(LBM_AXI_ENOMEM, "host memory exhausted");
+  } catch (const std::exception& e) {
+    return fail(LBM_AXI_EDEVICE, e.what());
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -609,404 +624,418 @@ void lbm_axi_destroy(lbm_axi* h) {
 
 int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* phi_field,
                    const float* const* init_uzurT, void* hip_stream, lbm_axi** out) {
-  if (out) *out = nullptr;
-  if (!p || !out || n_inst < 1) return fail(LBM_AXI_EINVAL, "null argument or n_inst < 1");
-  for (int i = 0; i < n_inst; ++i) {
-    int rc = validate(p[i], i);
-    if (rc) return rc;
-    if (p[i].storage != p[0].storage)
-      return fail(LBM_AXI_EINVAL, "all instances must use the same storage");
-    if (p[i].check_interval != p[0].check_interval)
-      return fail(LBM_AXI_EINVAL, "all instances must use the same check_interval");
-    if (phi_field && phi_field[i]) {
-      if (!(p[i].phi > 0.0 && p[i].phi < 1.0))
-        return fail(LBM_AXI_EINVAL, "a porosity field needs a reference porosity in (0, 1)");
-      const int64_t n = (int64_t)p[i].nr * p[i].nz;
-      for (int64_t c = 0; c < n; ++c)
-        if (!(phi_field[i][c] > 0.0f && phi_field[i][c] < 1.0f))
-          return fail(LBM_AXI_EINVAL, "porosity field values must lie in (0, 1)");
-    }
-  }
-  lbm_axi* h = new lbm_axi();
-  h->n_inst = n_inst;
-  h->storage = p[0].storage;
-  h->kz = h->storage == LBM_STORE_FP32 ? 4 : 16;  // measured best at 8192^2; lbm_axi_autotune refines
-  h->check = p[0].check_interval;
-  h->prm.assign(p, p + n_inst);
-  auto bail = [&](int rc) {
-    lbm_axi_destroy(h);
-    return rc;
-  };
-#define HIPBAIL(call)                                                                       \
-  do {                                                                                      \
-    hipError_t e_ = (call);                                                                 \
-    if (e_ != hipSuccess)                                                                   \
-      return bail(fail(LBM_AXI_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_))); \
-  } while (0)
-  {
-    int dev = 0, lds = 0, ldsb = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
-        hipDeviceGetAttribute(&ldsb, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-      return bail(fail(LBM_AXI_EDEVICE, "device query failed"));
-    h->lds_per_cu = lds;
-    h->lds_per_block = ldsb;
-  }
-  if (hip_stream) {
-    h->stream = (hipStream_t)hip_stream;
-  } else {
-    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess)
-      return bail(fail(LBM_AXI_EDEVICE, "hipStreamCreate failed"));
-    h->own_stream = true;
-  }
-  const size_t esz = h->storage == LBM_STORE_FP32 ? 4 : 2;
-  hipError_t err = hipSuccess;
-  h->hdesc.resize(n_inst);
-  for (int i = 0; i < n_inst; ++i) {
-    const lbm_axi_params& q = p[i];
-    InstDev& D = h->hdesc[i];
-    const bool field = phi_field && phi_field[i];
-    {
-      std::string msg;
-      const int rc = describe(q, field, D, msg);
-      if (rc) return bail(fail(rc, msg));
-    }
-    D.pop = dalloc(h, (size_t)14 * D.plane * esz, &err);
-    D.pop_bytes = pop_bytes32((size_t)14 * D.plane * esz);
-    if (!D.pop) return bail(fail(LBM_AXI_ENOMEM, std::string("population array: ") + hipGetErrorString(err)));
-    if (h->storage == LBM_STORE_FP32) {
-      D.g0 = (float*)D.pop + 9 * D.plane;
-    } else {
-      D.g0 = (float*)dalloc(h, (size_t)D.plane * 4, &err);
-      if (!D.g0) return bail(fail(LBM_AXI_ENOMEM, std::string("g_0 plane: ") + hipGetErrorString(err)));
-    }
-    if (field) {
-      float* dphi = (float*)dalloc(h, (size_t)D.plane * 4, &err);
-      if (!dphi) return bail(fail(LBM_AXI_ENOMEM, "porosity field"));
-      std::vector<float> pad((size_t)D.plane, q.phi);
-      for (int k = 0; k < q.nz; ++k)
-        std::memcpy(&pad[(size_t)k * D.stride], phi_field[i] + (size_t)k * q.nr, sizeof(float) * q.nr);
-      if (hipMemcpy(dphi, pad.data(), sizeof(float) * D.plane, hipMemcpyHostToDevice) != hipSuccess)
-        return bail(fail(LBM_AXI_EDEVICE, "porosity field upload"));
-      D.phi = dphi;
-    }
-    if (h->check > 0) {
-      for (int s = 0; s < 2; ++s) {
-        D.mac[s] = (float*)dalloc(h, (size_t)3 * D.plane * 4, &err);
-        if (!D.mac[s]) return bail(fail(LBM_AXI_ENOMEM, "check buffers"));
-        if (hipMemset(D.mac[s], 0, (size_t)3 * D.plane * 4) != hipSuccess)
-          return bail(fail(LBM_AXI_EDEVICE, "check buffer clear"));
-      }
-    }
-  }
-  {
-    const int rc = build_tiles(h, h->kz);
-    if (rc) return bail(rc);
-  }
-  h->ddesc = (InstDev*)dalloc(h, sizeof(InstDev) * n_inst, &err);
-  h->dstatus = (int*)dalloc(h, sizeof(int) * n_inst, &err);
-  h->dclk = (long long*)dalloc(h, sizeof(long long), &err);
-  h->dres = (DevResult*)dalloc(h, sizeof(DevResult) * n_inst, &err);
-  if (!h->ddesc || !h->dstatus || !h->dres || !h->dclk)
-    return bail(fail(LBM_AXI_ENOMEM, "descriptor arrays"));
-  HIPBAIL(hipMemcpy(h->ddesc, h->hdesc.data(), sizeof(InstDev) * n_inst, hipMemcpyHostToDevice));
-  h->buf = all_buffer_addressable(h);
-  HIPBAIL(hipMemset(h->dstatus, 0, sizeof(int) * n_inst));
-  {
-    std::vector<DevResult> r0(n_inst);
-    for (auto& r : r0) {
-      r.res = r.res_u = r.res_T = HUGE_VAL;
-      r.nu_i = r.nu_o = r.u_rms = 0.0;
-      r.t_check = -1;
-      r.t_stop = -1;
-    }
-    HIPBAIL(hipMemcpy(h->dres, r0.data(), sizeof(DevResult) * n_inst, hipMemcpyHostToDevice));
-  }
-  // Reduction tiles: RZ rows per block.
-  if (h->check > 0) {
-    std::vector<ResTile> rts;
-    std::vector<int> first(2 * n_inst);
-    std::vector<double> tol(n_inst), nus(4 * n_inst);
-    std::vector<long long> mx(n_inst);
+  return guarded([&]() -> int {
+    if (out) *out = nullptr;
+    if (!p || !out || n_inst < 1) return fail(LBM_AXI_EINVAL, "null argument or n_inst < 1");
     for (int i = 0; i < n_inst; ++i) {
-      const int nz = p[i].nz, nr = p[i].nr;
-      int rz = std::max(1, (int)((8192 + nr - 1) / nr));  // about 8k nodes per block
-      first[2 * i] = (int)rts.size();
-      for (int k0 = 0; k0 < nz; k0 += rz) rts.push_back(ResTile{i, k0, std::min(nz, k0 + rz), 0});
-      first[2 * i + 1] = (int)rts.size() - first[2 * i];
-      tol[i] = p[i].tol;
-      mx[i] = p[i].max_steps;
-      const double dT = p[i].delta_T != 0.0 ? p[i].delta_T : p[i].T_rmin - p[i].T_rmax;
-      const double H = nz - 1;
-      const bool walls = p[i].side_rmin == SIDE_WALL && p[i].side_rmax == SIDE_WALL && dT != 0.0 && H > 0;
-      nus[4 * i] = walls ? p[i].r0 / (H * dT) : 0.0;
-      nus[4 * i + 1] = (p[i].side_rmax == SIDE_WALL && dT != 0.0 && H > 0)
-                           ? (p[i].r0 + nr - 1) / (H * dT) : 0.0;
-      // residual scales: 1 / (Ma c_s) and 1 / |dT|
-      nus[4 * i + 2] = p[i].Ma > 0.0 ? 1.0 / (p[i].Ma * std::sqrt(1.0 / 3.0)) : 1.0;
-      nus[4 * i + 3] = dT != 0.0 ? 1.0 / std::fabs(dT) : 1.0;
-    }
-    h->nrt = (int)rts.size();
-    h->drt = (ResTile*)dalloc(h, sizeof(ResTile) * rts.size(), &err);
-    h->dpart = (double*)dalloc(h, sizeof(double) * 6 * rts.size(), &err);
-    h->dfirst = (int*)dalloc(h, sizeof(int) * first.size(), &err);
-    h->dtol = (double*)dalloc(h, sizeof(double) * n_inst, &err);
-    h->dnus = (double*)dalloc(h, sizeof(double) * 4 * n_inst, &err);
-    h->dmx = (long long*)dalloc(h, sizeof(long long) * n_inst, &err);
-    if (!h->drt || !h->dpart || !h->dfirst || !h->dtol || !h->dnus || !h->dmx)
-      return bail(fail(LBM_AXI_ENOMEM, "reduction arrays"));
-    HIPBAIL(hipMemcpy(h->drt, rts.data(), sizeof(ResTile) * rts.size(), hipMemcpyHostToDevice));
-    HIPBAIL(hipMemcpy(h->dfirst, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice));
-    HIPBAIL(hipMemcpy(h->dtol, tol.data(), sizeof(double) * n_inst, hipMemcpyHostToDevice));
-    HIPBAIL(hipMemcpy(h->dnus, nus.data(), sizeof(double) * 4 * n_inst, hipMemcpyHostToDevice));
-    HIPBAIL(hipMemcpy(h->dmx, mx.data(), sizeof(long long) * n_inst, hipMemcpyHostToDevice));
-  }
-  // Start state of every instance.
-  for (int i = 0; i < n_inst; ++i) {
-    float* dinit = nullptr;
-    if (init_uzurT && init_uzurT[i]) {
-      const size_t n = (size_t)p[i].nr * p[i].nz;
-      if (hipMalloc(&dinit, sizeof(float) * 3 * n) != hipSuccess)
-        return bail(fail(LBM_AXI_ENOMEM, "start-field staging"));
-      if (hipMemcpy(dinit, init_uzurT[i], sizeof(float) * 3 * n, hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(dinit);
-        return bail(fail(LBM_AXI_EDEVICE, "start-field upload"));
+      int rc = validate(p[i], i);
+      if (rc) return rc;
+      if (p[i].storage != p[0].storage)
+        return fail(LBM_AXI_EINVAL, "all instances must use the same storage");
+      if (p[i].check_interval != p[0].check_interval)
+        return fail(LBM_AXI_EINVAL, "all instances must use the same check_interval");
+      if (phi_field && phi_field[i]) {
+        if (!(p[i].phi > 0.0 && p[i].phi < 1.0))
+          return fail(LBM_AXI_EINVAL, "a porosity field needs a reference porosity in (0, 1)");
+        const int64_t n = (int64_t)p[i].nr * p[i].nz;
+        for (int64_t c = 0; c < n; ++c)
+          if (!(phi_field[i][c] > 0.0f && phi_field[i][c] < 1.0f))
+            return fail(LBM_AXI_EINVAL, "porosity field values must lie in (0, 1)");
       }
     }
-    int rc;
-    switch (h->storage) {
-      case LBM_STORE_FP32: rc = launch_init<float>(h, i, dinit, (float)p[i].T_init); break;
-      case LBM_STORE_FP16: rc = launch_init<__half>(h, i, dinit, (float)p[i].T_init); break;
-      default: rc = launch_init<__hip_bfloat16>(h, i, dinit, (float)p[i].T_init); break;
+    lbm_axi* h = new lbm_axi();
+    h->n_inst = n_inst;
+    h->storage = p[0].storage;
+    h->kz = h->storage == LBM_STORE_FP32 ? 4 : 16;  // measured best at 8192^2; lbm_axi_autotune refines
+    h->check = p[0].check_interval;
+    h->prm.assign(p, p + n_inst);
+    auto bail = [&](int rc) {
+      lbm_axi_destroy(h);
+      return rc;
+    };
+  #define HIPBAIL(call)                                                                       \
+    do {                                                                                      \
+      hipError_t e_ = (call);                                                                 \
+      if (e_ != hipSuccess)                                                                   \
+        return bail(fail(LBM_AXI_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_))); \
+    } while (0)
+    {
+      int dev = 0, lds = 0, ldsb = 0;
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+          hipDeviceGetAttribute(&ldsb, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return bail(fail(LBM_AXI_EDEVICE, "device query failed"));
+      h->lds_per_cu = lds;
+      h->lds_per_block = ldsb;
     }
-    if (dinit) {
-      hipError_t e = hipStreamSynchronize(h->stream);
-      (void)hipFree(dinit);
-      if (e != hipSuccess) return bail(fail(LBM_AXI_EDEVICE, std::string("start state: ") + hipGetErrorString(e)));
+    if (hip_stream) {
+      h->stream = (hipStream_t)hip_stream;
+    } else {
+      if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(LBM_AXI_EDEVICE, "hipStreamCreate failed"));
+      h->own_stream = true;
     }
-    if (rc) return bail(rc);
-  }
-  if (hipStreamSynchronize(h->stream) != hipSuccess)
-    return bail(fail(LBM_AXI_EDEVICE, "start state"));
-  *out = h;
-  return LBM_AXI_OK;
-#undef HIPBAIL
+    const size_t esz = h->storage == LBM_STORE_FP32 ? 4 : 2;
+    hipError_t err = hipSuccess;
+    h->hdesc.resize(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+      const lbm_axi_params& q = p[i];
+      InstDev& D = h->hdesc[i];
+      const bool field = phi_field && phi_field[i];
+      {
+        std::string msg;
+        const int rc = describe(q, field, D, msg);
+        if (rc) return bail(fail(rc, msg));
+      }
+      D.pop = dalloc(h, (size_t)14 * D.plane * esz, &err);
+      D.pop_bytes = pop_bytes32((size_t)14 * D.plane * esz);
+      if (!D.pop) return bail(fail(LBM_AXI_ENOMEM, std::string("population array: ") + hipGetErrorString(err)));
+      if (h->storage == LBM_STORE_FP32) {
+        D.g0 = (float*)D.pop + 9 * D.plane;
+      } else {
+        D.g0 = (float*)dalloc(h, (size_t)D.plane * 4, &err);
+        if (!D.g0) return bail(fail(LBM_AXI_ENOMEM, std::string("g_0 plane: ") + hipGetErrorString(err)));
+      }
+      if (field) {
+        float* dphi = (float*)dalloc(h, (size_t)D.plane * 4, &err);
+        if (!dphi) return bail(fail(LBM_AXI_ENOMEM, "porosity field"));
+        std::vector<float> pad((size_t)D.plane, q.phi);
+        for (int k = 0; k < q.nz; ++k)
+          std::memcpy(&pad[(size_t)k * D.stride], phi_field[i] + (size_t)k * q.nr, sizeof(float) * q.nr);
+        if (hipMemcpy(dphi, pad.data(), sizeof(float) * D.plane, hipMemcpyHostToDevice) != hipSuccess)
+          return bail(fail(LBM_AXI_EDEVICE, "porosity field upload"));
+        D.phi = dphi;
+      }
+      if (h->check > 0) {
+        for (int s = 0; s < 2; ++s) {
+          D.mac[s] = (float*)dalloc(h, (size_t)3 * D.plane * 4, &err);
+          if (!D.mac[s]) return bail(fail(LBM_AXI_ENOMEM, "check buffers"));
+          if (hipMemset(D.mac[s], 0, (size_t)3 * D.plane * 4) != hipSuccess)
+            return bail(fail(LBM_AXI_EDEVICE, "check buffer clear"));
+        }
+      }
+    }
+    {
+      const int rc = build_tiles(h, h->kz);
+      if (rc) return bail(rc);
+    }
+    h->ddesc = (InstDev*)dalloc(h, sizeof(InstDev) * n_inst, &err);
+    h->dstatus = (int*)dalloc(h, sizeof(int) * n_inst, &err);
+    h->dclk = (long long*)dalloc(h, sizeof(long long), &err);
+    h->dres = (DevResult*)dalloc(h, sizeof(DevResult) * n_inst, &err);
+    if (!h->ddesc || !h->dstatus || !h->dres || !h->dclk)
+      return bail(fail(LBM_AXI_ENOMEM, "descriptor arrays"));
+    HIPBAIL(hipMemcpy(h->ddesc, h->hdesc.data(), sizeof(InstDev) * n_inst, hipMemcpyHostToDevice));
+    h->buf = all_buffer_addressable(h);
+    HIPBAIL(hipMemset(h->dstatus, 0, sizeof(int) * n_inst));
+    {
+      std::vector<DevResult> r0(n_inst);
+      for (auto& r : r0) {
+        r.res = r.res_u = r.res_T = HUGE_VAL;
+        r.nu_i = r.nu_o = r.u_rms = 0.0;
+        r.t_check = -1;
+        r.t_stop = -1;
+      }
+      HIPBAIL(hipMemcpy(h->dres, r0.data(), sizeof(DevResult) * n_inst, hipMemcpyHostToDevice));
+    }
+    // Reduction tiles: RZ rows per block.
+    if (h->check > 0) {
+      std::vector<ResTile> rts;
+      std::vector<int> first(2 * n_inst);
+      std::vector<double> tol(n_inst), nus(4 * n_inst);
+      std::vector<long long> mx(n_inst);
+      for (int i = 0; i < n_inst; ++i) {
+        const int nz = p[i].nz, nr = p[i].nr;
+        int rz = std::max(1, (int)((8192 + nr - 1) / nr));  // about 8k nodes per block
+        first[2 * i] = (int)rts.size();
+        for (int k0 = 0; k0 < nz; k0 += rz) rts.push_back(ResTile{i, k0, std::min(nz, k0 + rz), 0});
+        first[2 * i + 1] = (int)rts.size() - first[2 * i];
+        tol[i] = p[i].tol;
+        mx[i] = p[i].max_steps;
+        const double dT = p[i].delta_T != 0.0 ? p[i].delta_T : p[i].T_rmin - p[i].T_rmax;
+        const double H = nz - 1;
+        const bool walls = p[i].side_rmin == SIDE_WALL && p[i].side_rmax == SIDE_WALL && dT != 0.0 && H > 0;
+        nus[4 * i] = walls ? p[i].r0 / (H * dT) : 0.0;
+        nus[4 * i + 1] = (p[i].side_rmax == SIDE_WALL && dT != 0.0 && H > 0)
+                             ? (p[i].r0 + nr - 1) / (H * dT) : 0.0;
+        // residual scales: 1 / (Ma c_s) and 1 / |dT|
+        nus[4 * i + 2] = p[i].Ma > 0.0 ? 1.0 / (p[i].Ma * std::sqrt(1.0 / 3.0)) : 1.0;
+        nus[4 * i + 3] = dT != 0.0 ? 1.0 / std::fabs(dT) : 1.0;
+      }
+      h->nrt = (int)rts.size();
+      h->drt = (ResTile*)dalloc(h, sizeof(ResTile) * rts.size(), &err);
+      h->dpart = (double*)dalloc(h, sizeof(double) * 6 * rts.size(), &err);
+      h->dfirst = (int*)dalloc(h, sizeof(int) * first.size(), &err);
+      h->dtol = (double*)dalloc(h, sizeof(double) * n_inst, &err);
+      h->dnus = (double*)dalloc(h, sizeof(double) * 4 * n_inst, &err);
+      h->dmx = (long long*)dalloc(h, sizeof(long long) * n_inst, &err);
+      if (!h->drt || !h->dpart || !h->dfirst || !h->dtol || !h->dnus || !h->dmx)
+        return bail(fail(LBM_AXI_ENOMEM, "reduction arrays"));
+      HIPBAIL(hipMemcpy(h->drt, rts.data(), sizeof(ResTile) * rts.size(), hipMemcpyHostToDevice));
+      HIPBAIL(hipMemcpy(h->dfirst, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice));
+      HIPBAIL(hipMemcpy(h->dtol, tol.data(), sizeof(double) * n_inst, hipMemcpyHostToDevice));
+      HIPBAIL(hipMemcpy(h->dnus, nus.data(), sizeof(double) * 4 * n_inst, hipMemcpyHostToDevice));
+      HIPBAIL(hipMemcpy(h->dmx, mx.data(), sizeof(long long) * n_inst, hipMemcpyHostToDevice));
+    }
+    // Start state of every instance.
+    for (int i = 0; i < n_inst; ++i) {
+      float* dinit = nullptr;
+      if (init_uzurT && init_uzurT[i]) {
+        const size_t n = (size_t)p[i].nr * p[i].nz;
+        if (hipMalloc(&dinit, sizeof(float) * 3 * n) != hipSuccess)
+          return bail(fail(LBM_AXI_ENOMEM, "start-field staging"));
+        if (hipMemcpy(dinit, init_uzurT[i], sizeof(float) * 3 * n, hipMemcpyHostToDevice) != hipSuccess) {
+          (void)hipFree(dinit);
+          return bail(fail(LBM_AXI_EDEVICE, "start-field upload"));
+        }
+      }
+      int rc;
+      switch (h->storage) {
+        case LBM_STORE_FP32: rc = launch_init<float>(h, i, dinit, (float)p[i].T_init); break;
+        case LBM_STORE_FP16: rc = launch_init<__half>(h, i, dinit, (float)p[i].T_init); break;
+        default: rc = launch_init<__hip_bfloat16>(h, i, dinit, (float)p[i].T_init); break;
+      }
+      if (dinit) {
+        hipError_t e = hipStreamSynchronize(h->stream);
+        (void)hipFree(dinit);
+        if (e != hipSuccess) return bail(fail(LBM_AXI_EDEVICE, std::string("start state: ") + hipGetErrorString(e)));
+      }
+      if (rc) return bail(rc);
+    }
+    if (hipStreamSynchronize(h->stream) != hipSuccess)
+      return bail(fail(LBM_AXI_EDEVICE, "start state"));
+    *out = h;
+    return LBM_AXI_OK;
+  #undef HIPBAIL
+  });
 }
 
 int lbm_axi_step(lbm_axi* h, int32_t nsteps) {
-  if (!h || nsteps < 0) return fail(LBM_AXI_EINVAL, "null handle or negative step count");
-  const long long t_end = h->t + nsteps;
-  while (h->t < t_end) {
-    const long long n = h->t;
-    // A run of graph_steps plain steps from an even level with no check step
-    // inside goes through the captured graph (not while timing launches).
-    const int G = h->graph_steps;
-    if (G >= 2 && !h->timing && (n & 1) == 0 && n + G <= t_end &&
-        (h->check <= 0 || (n + h->check - 1) / h->check * h->check >= n + G)) {
-      if (!h->gexec) {
-        const int rc = capture_graph(h);
-        if (rc) return rc;
+  return guarded([&]() -> int {
+    if (!h || nsteps < 0) return fail(LBM_AXI_EINVAL, "null handle or negative step count");
+    const long long t_end = h->t + nsteps;
+    while (h->t < t_end) {
+      const long long n = h->t;
+      // A run of graph_steps plain steps from an even level with no check step
+      // inside goes through the captured graph (not while timing launches).
+      const int G = h->graph_steps;
+      if (G >= 2 && !h->timing && (n & 1) == 0 && n + G <= t_end &&
+          (h->check <= 0 || (n + h->check - 1) / h->check * h->check >= n + G)) {
+        if (!h->gexec) {
+          const int rc = capture_graph(h);
+          if (rc) return rc;
+        }
+        k_setclock<<<1, 1, 0, h->stream>>>(h->dclk, n);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipGraphLaunch(h->gexec, h->stream));
+        h->t = n + G;
+        continue;
       }
-      k_setclock<<<1, 1, 0, h->stream>>>(h->dclk, n);
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipGraphLaunch(h->gexec, h->stream));
-      h->t = n + G;
-      continue;
-    }
-    const bool odd = (n & 1) != 0;
-    // At every multiple of the check interval the step also writes u_z, u_r,
-    // T into one of two buffers (alternating); from the second one on, the
-    // check compares them with the previous multiple's.
-    int mode = MODE_STEP, slot = 0;
-    bool check = false;
-    if (h->check > 0 && n % h->check == 0) {
-      mode = MODE_STEP_MACRO;
-      slot = (int)((n / h->check) & 1);
-      check = n > 0;
-    }
-    if (h->timing) {
-      hipEvent_t e0, e1;
-      HIPCHK(hipEventCreate(&e0));
-      HIPCHK(hipEventCreate(&e1));
-      h->ev.emplace_back(e0, e1);
-      HIPCHK(hipEventRecord(e0, h->stream));
-    }
-    // random bits of this step for stochastic rounding (16-bit storage)
-    int rc = dispatch_step(h, odd, mode, slot, step_seed(n));
-    if (rc) return rc;
-    if (h->timing) {
-      HIPCHK(hipEventRecord(h->ev.back().second, h->stream));
-      if (h->ev.size() >= 1024) {
-        double ms;
-        int64_t nl;
-        rc = lbm_axi_kernel_time(h, &ms, &nl);
-        if (rc) return rc;
+      const bool odd = (n & 1) != 0;
+      // At every multiple of the check interval the step also writes u_z, u_r,
+      // T into one of two buffers (alternating); from the second one on, the
+      // check compares them with the previous multiple's.
+      int mode = MODE_STEP, slot = 0;
+      bool check = false;
+      if (h->check > 0 && n % h->check == 0) {
+        mode = MODE_STEP_MACRO;
+        slot = (int)((n / h->check) & 1);
+        check = n > 0;
       }
+      if (h->timing) {
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        h->ev.emplace_back(e0, e1);
+        HIPCHK(hipEventRecord(e0, h->stream));
+      }
+      // random bits of this step for stochastic rounding (16-bit storage)
+      int rc = dispatch_step(h, odd, mode, slot, step_seed(n));
+      if (rc) return rc;
+      if (h->timing) {
+        HIPCHK(hipEventRecord(h->ev.back().second, h->stream));
+        if (h->ev.size() >= 1024) {
+          double ms;
+          int64_t nl;
+          rc = lbm_axi_kernel_time(h, &ms, &nl);
+          if (rc) return rc;
+        }
+      }
+      if (check) {
+        k_resid<<<h->nrt, RB, 0, h->stream>>>(h->ddesc, h->drt, slot, h->dpart);
+        HIPCHK(hipGetLastError());
+        k_final<<<h->n_inst, RB, 0, h->stream>>>(h->dfirst, h->dpart, n, 1.0 / h->check, h->dtol,
+                                                  h->dmx, h->dnus, h->dstatus, h->dres);
+        HIPCHK(hipGetLastError());
+      }
+      h->t = n + 1;
     }
-    if (check) {
-      k_resid<<<h->nrt, RB, 0, h->stream>>>(h->ddesc, h->drt, slot, h->dpart);
-      HIPCHK(hipGetLastError());
-      k_final<<<h->n_inst, RB, 0, h->stream>>>(h->dfirst, h->dpart, n, 1.0 / h->check, h->dtol,
-                                                h->dmx, h->dnus, h->dstatus, h->dres);
-      HIPCHK(hipGetLastError());
-    }
-    h->t = n + 1;
-  }
-  return LBM_AXI_OK;
+    return LBM_AXI_OK;
+  });
 }
 
 int lbm_axi_set_graph(lbm_axi* h, int32_t steps) {
-  if (!h || steps < 0 || steps > 4096 || (steps & 1))
-    return fail(LBM_AXI_EINVAL, "bad handle or graph steps not an even number in [0, 4096]");
-  HIPCHK(hipStreamSynchronize(h->stream));
-  drop_graph(h);
-  h->graph_steps = steps;
-  return LBM_AXI_OK;
+  return guarded([&]() -> int {
+    if (!h || steps < 0 || steps > 4096 || (steps & 1))
+      return fail(LBM_AXI_EINVAL, "bad handle or graph steps not an even number in [0, 4096]");
+    HIPCHK(hipStreamSynchronize(h->stream));
+    drop_graph(h);
+    h->graph_steps = steps;
+    return LBM_AXI_OK;
+  });
 }
 
 int lbm_axi_compact(lbm_axi* h, int32_t* n_running) {
-  if (!h) return fail(LBM_AXI_EINVAL, "null handle");
-  std::vector<int> st(h->n_inst);
-  HIPCHK(hipMemcpyAsync(st.data(), h->dstatus, sizeof(int) * h->n_inst, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
-  std::vector<char> act(h->n_inst);
-  int nr = 0;
-  for (int i = 0; i < h->n_inst; ++i) {
-    act[i] = st[i] == RUN;
-    nr += act[i];
-  }
-  if (n_running) *n_running = nr;
-  if (act == h->active || (h->active.empty() && nr == h->n_inst)) return LBM_AXI_OK;
-  h->active = act;
-  drop_graph(h);
-  return build_tiles(h, h->kz);
+  return guarded([&]() -> int {
+    if (!h) return fail(LBM_AXI_EINVAL, "null handle");
+    std::vector<int> st(h->n_inst);
+    HIPCHK(hipMemcpyAsync(st.data(), h->dstatus, sizeof(int) * h->n_inst, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    std::vector<char> act(h->n_inst);
+    int nr = 0;
+    for (int i = 0; i < h->n_inst; ++i) {
+      act[i] = st[i] == RUN;
+      nr += act[i];
+    }
+    if (n_running) *n_running = nr;
+    if (act == h->active || (h->active.empty() && nr == h->n_inst)) return LBM_AXI_OK;
+    h->active = act;
+    drop_graph(h);
+    return build_tiles(h, h->kz);
+  });
 }
 
 int lbm_axi_autotune(lbm_axi* h, int32_t trial_steps, int32_t* kz_out, int32_t* bpc_out,
                      double* ms_out) {
-  if (!h || trial_steps < 1) return fail(LBM_AXI_EINVAL, "null handle or trial_steps < 1");
-  static const int KZ[] = {1, 2, 4, 8, 16};
-  static const int BPC[] = {0, 2, 4};
-  const bool was_timing = h->timing;
-  double best = HUGE_VAL;
-  int bk = h->kz, bb = 0;
-  for (int kz : KZ)
-    for (int bpc : BPC) {
-      int rc = lbm_axi_set_tiles(h, kz, bpc);
-      if (rc) return rc;
-      h->timing = false;
-      rc = lbm_axi_set_timing(h, 1);  // restarts the launch timer
-      if (rc) return rc;
-      rc = lbm_axi_step(h, trial_steps);
-      if (rc) return rc;
-      double ms = 0.0;
-      int64_t nl = 0;
-      rc = lbm_axi_kernel_time(h, &ms, &nl);
-      if (rc) return rc;
-      const double per = nl > 0 ? ms / (double)nl : HUGE_VAL;
-      if (per < best) {
-        best = per;
-        bk = kz;
-        bb = bpc;
+  return guarded([&]() -> int {
+    if (!h || trial_steps < 1) return fail(LBM_AXI_EINVAL, "null handle or trial_steps < 1");
+    static const int KZ[] = {1, 2, 4, 8, 16};
+    static const int BPC[] = {0, 2, 4};
+    const bool was_timing = h->timing;
+    double best = HUGE_VAL;
+    int bk = h->kz, bb = 0;
+    for (int kz : KZ)
+      for (int bpc : BPC) {
+        int rc = lbm_axi_set_tiles(h, kz, bpc);
+        if (rc) return rc;
+        h->timing = false;
+        rc = lbm_axi_set_timing(h, 1);  // restarts the launch timer
+        if (rc) return rc;
+        rc = lbm_axi_step(h, trial_steps);
+        if (rc) return rc;
+        double ms = 0.0;
+        int64_t nl = 0;
+        rc = lbm_axi_kernel_time(h, &ms, &nl);
+        if (rc) return rc;
+        const double per = nl > 0 ? ms / (double)nl : HUGE_VAL;
+        if (per < best) {
+          best = per;
+          bk = kz;
+          bb = bpc;
+        }
       }
-    }
-  h->timing = false;
-  int rc = lbm_axi_set_timing(h, was_timing ? 1 : 0);
-  if (rc) return rc;
-  rc = lbm_axi_set_tiles(h, bk, bb);
-  if (rc) return rc;
-  if (kz_out) *kz_out = bk;
-  if (bpc_out) *bpc_out = bb;
-  if (ms_out) *ms_out = best;
-  return LBM_AXI_OK;
+    h->timing = false;
+    int rc = lbm_axi_set_timing(h, was_timing ? 1 : 0);
+    if (rc) return rc;
+    rc = lbm_axi_set_tiles(h, bk, bb);
+    if (rc) return rc;
+    if (kz_out) *kz_out = bk;
+    if (bpc_out) *bpc_out = bb;
+    if (ms_out) *ms_out = best;
+    return LBM_AXI_OK;
+  });
 }
 
 int lbm_axi_set_storage(lbm_axi* h, int32_t storage, int32_t storage_shift) {
-  if (!h || storage < LBM_STORE_FP32 || storage > LBM_STORE_BF16 || storage_shift < 0 ||
-      storage_shift > 24)
-    return fail(LBM_AXI_EINVAL, "bad handle, storage type or storage_shift out of [0, 24]");
-  HIPCHK(hipStreamSynchronize(h->stream));
-  drop_graph(h);
-  const int from = h->storage;
-  const size_t esz_o = from == LBM_STORE_FP32 ? 4 : 2;
-  const size_t esz_n = storage == LBM_STORE_FP32 ? 4 : 2;
-  std::vector<InstDev> nd(h->n_inst);
-  std::vector<lbm_axi_params> np(h->prm);
-  hipError_t err = hipSuccess;
-  // Allocate everything first: on failure the handle is left as it was.
-  for (int i = 0; i < h->n_inst; ++i) {
-    np[i].storage = storage;
-    np[i].storage_shift = storage_shift;
-    std::string msg;
-    const InstDev& Do = h->hdesc[i];
-    InstDev& Dn = nd[i];
-    int rc = describe(np[i], Do.phi != nullptr, Dn, msg);
-    void* pop = rc ? nullptr : dalloc(h, (size_t)14 * Dn.plane * esz_n, &err);
-    float* g0 = nullptr;
-    if (pop) g0 = storage == LBM_STORE_FP32 ? (float*)pop + 9 * Dn.plane
-                                            : (float*)dalloc(h, (size_t)Dn.plane * 4, &err);
-    if (rc || !pop || !g0) {
-      for (int k = 0; k <= i; ++k) {
-        if (nd[k].pop) release(h, nd[k].pop, (size_t)14 * nd[k].plane * esz_n);
-        if (nd[k].g0 && storage != LBM_STORE_FP32) release(h, nd[k].g0, (size_t)nd[k].plane * 4);
+  return guarded([&]() -> int {
+    if (!h || storage < LBM_STORE_FP32 || storage > LBM_STORE_BF16 || storage_shift < 0 ||
+        storage_shift > 24)
+      return fail(LBM_AXI_EINVAL, "bad handle, storage type or storage_shift out of [0, 24]");
+    HIPCHK(hipStreamSynchronize(h->stream));
+    drop_graph(h);
+    const int from = h->storage;
+    const size_t esz_o = from == LBM_STORE_FP32 ? 4 : 2;
+    const size_t esz_n = storage == LBM_STORE_FP32 ? 4 : 2;
+    std::vector<InstDev> nd(h->n_inst);
+    std::vector<lbm_axi_params> np(h->prm);
+    hipError_t err = hipSuccess;
+    // Allocate everything first: on failure the handle is left as it was.
+    for (int i = 0; i < h->n_inst; ++i) {
+      np[i].storage = storage;
+      np[i].storage_shift = storage_shift;
+      std::string msg;
+      const InstDev& Do = h->hdesc[i];
+      InstDev& Dn = nd[i];
+      int rc = describe(np[i], Do.phi != nullptr, Dn, msg);
+      void* pop = rc ? nullptr : dalloc(h, (size_t)14 * Dn.plane * esz_n, &err);
+      float* g0 = nullptr;
+      if (pop) g0 = storage == LBM_STORE_FP32 ? (float*)pop + 9 * Dn.plane
+                                              : (float*)dalloc(h, (size_t)Dn.plane * 4, &err);
+      if (rc || !pop || !g0) {
+        for (int k = 0; k <= i; ++k) {
+          if (nd[k].pop) release(h, nd[k].pop, (size_t)14 * nd[k].plane * esz_n);
+          if (nd[k].g0 && storage != LBM_STORE_FP32) release(h, nd[k].g0, (size_t)nd[k].plane * 4);
+        }
+        if (pop) release(h, pop, (size_t)14 * Dn.plane * esz_n);
+        return fail(rc ? rc : LBM_AXI_ENOMEM, rc ? msg : "population array for the new storage");
       }
-      if (pop) release(h, pop, (size_t)14 * Dn.plane * esz_n);
-      return fail(rc ? rc : LBM_AXI_ENOMEM, rc ? msg : "population array for the new storage");
+      Dn.pop = pop;
+      Dn.pop_bytes = pop_bytes32((size_t)14 * Dn.plane * esz_n);
+      Dn.g0 = g0;
+      Dn.phi = Do.phi;
+      Dn.mac[0] = Do.mac[0];
+      Dn.mac[1] = Do.mac[1];
     }
-    Dn.pop = pop;
-    Dn.pop_bytes = pop_bytes32((size_t)14 * Dn.plane * esz_n);
-    Dn.g0 = g0;
-    Dn.phi = Do.phi;
-    Dn.mac[0] = Do.mac[0];
-    Dn.mac[1] = Do.mac[1];
-  }
-  hipError_t ce = hipSuccess;
-  for (int i = 0; i < h->n_inst && ce == hipSuccess; ++i) {
-    switch (from) {
-      case LBM_STORE_FP32: launch_convert_to<float>(h, storage, h->hdesc[i], nd[i]); break;
-      case LBM_STORE_FP16: launch_convert_to<__half>(h, storage, h->hdesc[i], nd[i]); break;
-      default: launch_convert_to<__hip_bfloat16>(h, storage, h->hdesc[i], nd[i]); break;
+    hipError_t ce = hipSuccess;
+    for (int i = 0; i < h->n_inst && ce == hipSuccess; ++i) {
+      switch (from) {
+        case LBM_STORE_FP32: launch_convert_to<float>(h, storage, h->hdesc[i], nd[i]); break;
+        case LBM_STORE_FP16: launch_convert_to<__half>(h, storage, h->hdesc[i], nd[i]); break;
+        default: launch_convert_to<__hip_bfloat16>(h, storage, h->hdesc[i], nd[i]); break;
+      }
+      ce = hipGetLastError();
     }
-    ce = hipGetLastError();
-  }
-  if (ce == hipSuccess) ce = hipStreamSynchronize(h->stream);
-  if (ce != hipSuccess) {  // keep the old state; drop the new arrays
-    for (int k = 0; k < h->n_inst; ++k) {
-      if (storage != LBM_STORE_FP32) release(h, nd[k].g0, (size_t)nd[k].plane * 4);
-      release(h, nd[k].pop, (size_t)14 * nd[k].plane * esz_n);
+    if (ce == hipSuccess) ce = hipStreamSynchronize(h->stream);
+    if (ce != hipSuccess) {  // keep the old state; drop the new arrays
+      for (int k = 0; k < h->n_inst; ++k) {
+        if (storage != LBM_STORE_FP32) release(h, nd[k].g0, (size_t)nd[k].plane * 4);
+        release(h, nd[k].pop, (size_t)14 * nd[k].plane * esz_n);
+      }
+      return fail(LBM_AXI_EDEVICE, std::string("storage conversion: ") + hipGetErrorString(ce));
     }
-    return fail(LBM_AXI_EDEVICE, std::string("storage conversion: ") + hipGetErrorString(ce));
-  }
-  for (int i = 0; i < h->n_inst; ++i) {
-    const InstDev& Do = h->hdesc[i];
-    if (from != LBM_STORE_FP32) release(h, Do.g0, (size_t)Do.plane * 4);
-    release(h, Do.pop, (size_t)14 * Do.plane * esz_o);
-  }
-  h->hdesc = nd;
-  h->prm = np;
-  h->storage = storage;
-  h->buf = all_buffer_addressable(h);
-  HIPCHK(hipMemcpy(h->ddesc, h->hdesc.data(), sizeof(InstDev) * h->n_inst, hipMemcpyHostToDevice));
-  // Converged or stalled runs continue in the new storage; diverged ones stay.
-  std::vector<int> st(h->n_inst);
-  HIPCHK(hipMemcpy(st.data(), h->dstatus, sizeof(int) * h->n_inst, hipMemcpyDeviceToHost));
-  for (int& v : st)
-    if (v == CONVERGED || v == STALLED) v = RUN;
-  HIPCHK(hipMemcpy(h->dstatus, st.data(), sizeof(int) * h->n_inst, hipMemcpyHostToDevice));
-  return LBM_AXI_OK;
+    for (int i = 0; i < h->n_inst; ++i) {
+      const InstDev& Do = h->hdesc[i];
+      if (from != LBM_STORE_FP32) release(h, Do.g0, (size_t)Do.plane * 4);
+      release(h, Do.pop, (size_t)14 * Do.plane * esz_o);
+    }
+    h->hdesc = nd;
+    h->prm = np;
+    h->storage = storage;
+    h->buf = all_buffer_addressable(h);
+    HIPCHK(hipMemcpy(h->ddesc, h->hdesc.data(), sizeof(InstDev) * h->n_inst, hipMemcpyHostToDevice));
+    // Converged or stalled runs continue in the new storage; diverged ones stay.
+    std::vector<int> st(h->n_inst);
+    HIPCHK(hipMemcpy(st.data(), h->dstatus, sizeof(int) * h->n_inst, hipMemcpyDeviceToHost));
+    for (int& v : st)
+      if (v == CONVERGED || v == STALLED) v = RUN;
+    HIPCHK(hipMemcpy(h->dstatus, st.data(), sizeof(int) * h->n_inst, hipMemcpyHostToDevice));
+    return LBM_AXI_OK;
+  });
 }
 
 int lbm_axi_set_tiles(lbm_axi* h, int32_t kz, int32_t blocks_per_cu) {
-  if (!h || kz < 1 || kz > 64 || blocks_per_cu < 0 || blocks_per_cu > 64)
-    return fail(LBM_AXI_EINVAL, "bad handle, kz out of [1, 64] or blocks_per_cu out of [0, 64]");
-  HIPCHK(hipStreamSynchronize(h->stream));
-  // Reserving LDS that the kernel does not use caps the blocks resident on a
-  // compute unit; this is the only effect of blocks_per_cu.
-  int lds = blocks_per_cu > 0 ? h->lds_per_cu / blocks_per_cu / 256 * 256 : 0;
-  if (blocks_per_cu > 0 && lds * (blocks_per_cu + 1) <= h->lds_per_cu) lds += 256;
-  h->lds_bytes = lds < h->lds_per_block ? lds : h->lds_per_block;
-  drop_graph(h);
-  return build_tiles(h, kz);
+  return guarded([&]() -> int {
+    if (!h || kz < 1 || kz > 64 || blocks_per_cu < 0 || blocks_per_cu > 64)
+      return fail(LBM_AXI_EINVAL, "bad handle, kz out of [1, 64] or blocks_per_cu out of [0, 64]");
+    HIPCHK(hipStreamSynchronize(h->stream));
+    // Reserving LDS that the kernel does not use caps the blocks resident on a
+    // compute unit; this is the only effect of blocks_per_cu.
+    int lds = blocks_per_cu > 0 ? h->lds_per_cu / blocks_per_cu / 256 * 256 : 0;
+    if (blocks_per_cu > 0 && lds * (blocks_per_cu + 1) <= h->lds_per_cu) lds += 256;
+    h->lds_bytes = lds < h->lds_per_block ? lds : h->lds_per_block;
+    drop_graph(h);
+    return build_tiles(h, kz);
+  });
 }
 
 int lbm_axi_sync(lbm_axi* h) {
@@ -1016,19 +1045,21 @@ int lbm_axi_sync(lbm_axi* h) {
 }
 
 int lbm_axi_residual(lbm_axi* h, double* res, double* nu_i, double* nu_o, int32_t* status) {
-  if (!h) return fail(LBM_AXI_EINVAL, "null handle");
-  std::vector<DevResult> r(h->n_inst);
-  std::vector<int> st(h->n_inst);
-  HIPCHK(hipMemcpyAsync(r.data(), h->dres, sizeof(DevResult) * h->n_inst, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipMemcpyAsync(st.data(), h->dstatus, sizeof(int) * h->n_inst, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
-  for (int i = 0; i < h->n_inst; ++i) {
-    if (res) res[i] = r[i].res;
-    if (nu_i) nu_i[i] = r[i].nu_i;
-    if (nu_o) nu_o[i] = r[i].nu_o;
-    if (status) status[i] = st[i];
-  }
-  return LBM_AXI_OK;
+  return guarded([&]() -> int {
+    if (!h) return fail(LBM_AXI_EINVAL, "null handle");
+    std::vector<DevResult> r(h->n_inst);
+    std::vector<int> st(h->n_inst);
+    HIPCHK(hipMemcpyAsync(r.data(), h->dres, sizeof(DevResult) * h->n_inst, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(st.data(), h->dstatus, sizeof(int) * h->n_inst, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int i = 0; i < h->n_inst; ++i) {
+      if (res) res[i] = r[i].res;
+      if (nu_i) nu_i[i] = r[i].nu_i;
+      if (nu_o) nu_o[i] = r[i].nu_o;
+      if (status) status[i] = st[i];
+    }
+    return LBM_AXI_OK;
+  });
 }
 
 int lbm_axi_info(lbm_axi* h, int32_t inst, int64_t* out) {
@@ -1047,87 +1078,93 @@ int lbm_axi_info(lbm_axi* h, int32_t inst, int64_t* out) {
 
 int lbm_axi_macros(lbm_axi* h, int32_t inst, float* uz, float* ur, float* p, float* T,
                    uint8_t* mask, int32_t dst_is_device) {
-  if (!h || inst < 0 || inst >= h->n_inst) return fail(LBM_AXI_EINVAL, "bad handle or instance");
-  int64_t info[4];
-  int rc = lbm_axi_info(h, inst, info);
-  if (rc) return rc;
-  const bool odd = (info[0] & 1) != 0;
-  const lbm_axi_params& q = h->prm[inst];
-  const size_t n = (size_t)q.nr * q.nz;
-  FieldOut fo{uz, ur, p, T, mask};
-  std::vector<void*> tmp;
-  if (!dst_is_device) {
-    float** fp[4] = {&fo.uz, &fo.ur, &fo.p, &fo.T};
-    for (float** f : fp)
-      if (*f) {
+  return guarded([&]() -> int {
+    if (!h || inst < 0 || inst >= h->n_inst) return fail(LBM_AXI_EINVAL, "bad handle or instance");
+    int64_t info[4];
+    int rc = lbm_axi_info(h, inst, info);
+    if (rc) return rc;
+    const bool odd = (info[0] & 1) != 0;
+    const lbm_axi_params& q = h->prm[inst];
+    const size_t n = (size_t)q.nr * q.nz;
+    FieldOut fo{uz, ur, p, T, mask};
+    std::vector<void*> tmp;
+    if (!dst_is_device) {
+      float** fp[4] = {&fo.uz, &fo.ur, &fo.p, &fo.T};
+      for (float** f : fp)
+        if (*f) {
+          void* d = nullptr;
+          if (hipMalloc(&d, sizeof(float) * n) != hipSuccess) {
+            for (void* x : tmp) (void)hipFree(x);
+            return fail(LBM_AXI_ENOMEM, "field staging");
+          }
+          tmp.push_back(d);
+          *f = (float*)d;
+        }
+      if (fo.mask) {
         void* d = nullptr;
-        if (hipMalloc(&d, sizeof(float) * n) != hipSuccess) {
+        if (hipMalloc(&d, n) != hipSuccess) {
           for (void* x : tmp) (void)hipFree(x);
-          return fail(LBM_AXI_ENOMEM, "field staging");
+          return fail(LBM_AXI_ENOMEM, "mask staging");
         }
         tmp.push_back(d);
-        *f = (float*)d;
+        fo.mask = (uint8_t*)d;
       }
-    if (fo.mask) {
-      void* d = nullptr;
-      if (hipMalloc(&d, n) != hipSuccess) {
-        for (void* x : tmp) (void)hipFree(x);
-        return fail(LBM_AXI_ENOMEM, "mask staging");
-      }
-      tmp.push_back(d);
-      fo.mask = (uint8_t*)d;
     }
-  }
-  switch (h->storage) {
-    case LBM_STORE_FP32: rc = launch_fields<float>(h, inst, odd, fo); break;
-    case LBM_STORE_FP16: rc = launch_fields<__half>(h, inst, odd, fo); break;
-    default: rc = launch_fields<__hip_bfloat16>(h, inst, odd, fo); break;
-  }
-  if (!rc && !dst_is_device) {
-    hipError_t e = hipSuccess;
-    if (uz && e == hipSuccess) e = hipMemcpyAsync(uz, fo.uz, sizeof(float) * n, hipMemcpyDeviceToHost, h->stream);
-    if (ur && e == hipSuccess) e = hipMemcpyAsync(ur, fo.ur, sizeof(float) * n, hipMemcpyDeviceToHost, h->stream);
-    if (p && e == hipSuccess) e = hipMemcpyAsync(p, fo.p, sizeof(float) * n, hipMemcpyDeviceToHost, h->stream);
-    if (T && e == hipSuccess) e = hipMemcpyAsync(T, fo.T, sizeof(float) * n, hipMemcpyDeviceToHost, h->stream);
-    if (mask && e == hipSuccess) e = hipMemcpyAsync(mask, fo.mask, n, hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) rc = fail(LBM_AXI_EDEVICE, std::string("field download: ") + hipGetErrorString(e));
-  }
-  for (void* x : tmp) (void)hipFree(x);
-  return rc;
+    switch (h->storage) {
+      case LBM_STORE_FP32: rc = launch_fields<float>(h, inst, odd, fo); break;
+      case LBM_STORE_FP16: rc = launch_fields<__half>(h, inst, odd, fo); break;
+      default: rc = launch_fields<__hip_bfloat16>(h, inst, odd, fo); break;
+    }
+    if (!rc && !dst_is_device) {
+      hipError_t e = hipSuccess;
+      if (uz && e == hipSuccess) e = hipMemcpyAsync(uz, fo.uz, sizeof(float) * n, hipMemcpyDeviceToHost, h->stream);
+      if (ur && e == hipSuccess) e = hipMemcpyAsync(ur, fo.ur, sizeof(float) * n, hipMemcpyDeviceToHost, h->stream);
+      if (p && e == hipSuccess) e = hipMemcpyAsync(p, fo.p, sizeof(float) * n, hipMemcpyDeviceToHost, h->stream);
+      if (T && e == hipSuccess) e = hipMemcpyAsync(T, fo.T, sizeof(float) * n, hipMemcpyDeviceToHost, h->stream);
+      if (mask && e == hipSuccess) e = hipMemcpyAsync(mask, fo.mask, n, hipMemcpyDeviceToHost, h->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+      if (e != hipSuccess) rc = fail(LBM_AXI_EDEVICE, std::string("field download: ") + hipGetErrorString(e));
+    }
+    for (void* x : tmp) (void)hipFree(x);
+    return rc;
+  });
 }
 
 int lbm_axi_set_timing(lbm_axi* h, int32_t on) {
-  if (!h) return fail(LBM_AXI_EINVAL, "null handle");
-  if (on && !h->timing) {
-    double ms;
-    int64_t nl;
-    int rc = lbm_axi_kernel_time(h, &ms, &nl);
-    if (rc) return rc;
-    h->timed_ms = 0.0;
-    h->timed_launches = 0;
-  }
-  h->timing = on != 0;
-  return LBM_AXI_OK;
+  return guarded([&]() -> int {
+    if (!h) return fail(LBM_AXI_EINVAL, "null handle");
+    if (on && !h->timing) {
+      double ms;
+      int64_t nl;
+      int rc = lbm_axi_kernel_time(h, &ms, &nl);
+      if (rc) return rc;
+      h->timed_ms = 0.0;
+      h->timed_launches = 0;
+    }
+    h->timing = on != 0;
+    return LBM_AXI_OK;
+  });
 }
 
 int lbm_axi_kernel_time(lbm_axi* h, double* total_ms, int64_t* launches) {
-  if (!h) return fail(LBM_AXI_EINVAL, "null handle");
-  if (!h->ev.empty()) {
-    HIPCHK(hipEventSynchronize(h->ev.back().second));
-    for (auto& e : h->ev) {
-      float ms = 0.0f;
-      HIPCHK(hipEventElapsedTime(&ms, e.first, e.second));
-      h->timed_ms += ms;
-      h->timed_launches += 1;
-      (void)hipEventDestroy(e.first);
-      (void)hipEventDestroy(e.second);
+  return guarded([&]() -> int {
+    if (!h) return fail(LBM_AXI_EINVAL, "null handle");
+    if (!h->ev.empty()) {
+      HIPCHK(hipEventSynchronize(h->ev.back().second));
+      for (auto& e : h->ev) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, e.first, e.second));
+        h->timed_ms += ms;
+        h->timed_launches += 1;
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+      }
+      h->ev.clear();
     }
-    h->ev.clear();
-  }
-  if (total_ms) *total_ms = h->timed_ms;
-  if (launches) *launches = h->timed_launches;
-  return LBM_AXI_OK;
+    if (total_ms) *total_ms = h->timed_ms;
+    if (launches) *launches = h->timed_launches;
+    return LBM_AXI_OK;
+  });
 }
 
 }  // extern "C"

@@ -15,6 +15,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -472,6 +474,19 @@ int check_batch(lbm_no* h, int Bt) {
   return LBM_NO_OK;
 }
 
+// Host-side failures (allocation) become error codes: nothing may unwind
+// through the C ABI.
+template <typename F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return fail(LBM_NO_ENOMEM, "host memory exhausted");
+  } catch (const std::exception& e) {
+    return fail(LBM_NO_EDEVICE, e.what());
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -497,171 +512,183 @@ void lbm_no_destroy(lbm_no* h) {
 
 int lbm_no_create(const int32_t* widths, int32_t height, int32_t width, int32_t max_batch,
                   const float* params, void* hip_stream, lbm_no** out) {
-  if (out) *out = nullptr;
-  if (!widths || !params || !out) return fail(LBM_NO_EINVAL, "null argument");
-  for (int i = 0; i < 4; ++i)
-    if (widths[i] < 2 || widths[i] > 1024 || (widths[i] & 1))
-      return fail(LBM_NO_EINVAL, "widths must be even, in [2, 1024]");
-  if (height < 8 || width < 8 || height > 2048 || width > 2048 || height % 8 || width % 8)
-    return fail(LBM_NO_EINVAL, "height and width must be multiples of 8 in [8, 2048]");
-  if (max_batch < 1 || (int64_t)max_batch * height * width > (1ll << 31) / 64)
-    return fail(LBM_NO_EINVAL, "max_batch out of range");
-  lbm_no* h = new lbm_no();
-  auto bail = [&](int rc) {
-    lbm_no_destroy(h);
-    return rc;
-  };
-  for (int i = 0; i < 4; ++i) h->widths[i] = widths[i];
-  h->H = height;
-  h->W = width;
-  h->maxB = max_batch;
-  specs(h->widths, height, width, h->L, h->npar);
-  h->stream = (hipStream_t)hip_stream;  // NULL: the null stream (torch's default stream)
-  const size_t np = (size_t)h->npar;
-  h->par = (float*)nalloc(h, np * 4);
-  h->grad = (float*)nalloc(h, np * 4);
-  h->m = (float*)nalloc(h, np * 4);
-  h->v = (float*)nalloc(h, np * 4);
-  h->parb = (bf16_t*)nalloc(h, np * 2);
-  if (!h->par || !h->grad || !h->m || !h->v || !h->parb) return bail(fail(LBM_NO_ENOMEM, "parameters"));
-  int64_t colmax = 0, splitmax = 0, actmax = 0;
-  for (const Layer& l : h->L) {
-    const int64_t P = (int64_t)max_batch * l.Ho * l.Wo;
-    const size_t n = (size_t)l.cout * P * 4;
-    actmax = std::max(actmax, (int64_t)l.cout * P);
-    float* zl = (float*)nalloc(h, n);
-    float* al = (float*)nalloc(h, n);
-    float* dl = (float*)nalloc(h, n);
-    if (!zl || !al || !dl) return bail(fail(LBM_NO_ENOMEM, "activations"));
-    h->z.push_back(zl);
-    h->a.push_back(al);
-    h->da.push_back(dl);
-    const int64_t K = (int64_t)l.cin * l.k * l.k;
-    colmax = std::max(colmax, K * P);
-    const int64_t S = (P + KCHUNK - 1) / KCHUNK;
-    splitmax = std::max(splitmax, S * l.cout * K);
-  }
-  h->col = (bf16_t*)nalloc(h, (size_t)colmax * 2);
-  h->dcol = (float*)nalloc(h, (size_t)colmax * 4);
-  h->dz16 = (bf16_t*)nalloc(h, (size_t)actmax * 2);
-  h->split = (float*)nalloc(h, (size_t)splitmax * 4);
-  h->split_n = splitmax;
-  const int64_t lb = (3 * (int64_t)max_batch * height * width + EW - 1) / EW;
-  h->lpart = (double*)nalloc(h, (size_t)lb * 8);
-  h->dloss = (double*)nalloc(h, 8);
-  if (!h->col || !h->dcol || !h->dz16 || !h->split || !h->lpart || !h->dloss)
-    return bail(fail(LBM_NO_ENOMEM, "work space"));
-  const int rc = lbm_no_set_params(h, params);
-  if (rc) return bail(rc);
-  *out = h;
-  return LBM_NO_OK;
+  return guarded([&]() -> int {
+    if (out) *out = nullptr;
+    if (!widths || !params || !out) return fail(LBM_NO_EINVAL, "null argument");
+    for (int i = 0; i < 4; ++i)
+      if (widths[i] < 2 || widths[i] > 1024 || (widths[i] & 1))
+        return fail(LBM_NO_EINVAL, "widths must be even, in [2, 1024]");
+    if (height < 8 || width < 8 || height > 2048 || width > 2048 || height % 8 || width % 8)
+      return fail(LBM_NO_EINVAL, "height and width must be multiples of 8 in [8, 2048]");
+    if (max_batch < 1 || (int64_t)max_batch * height * width > (1ll << 31) / 64)
+      return fail(LBM_NO_EINVAL, "max_batch out of range");
+    lbm_no* h = new lbm_no();
+    auto bail = [&](int rc) {
+      lbm_no_destroy(h);
+      return rc;
+    };
+    for (int i = 0; i < 4; ++i) h->widths[i] = widths[i];
+    h->H = height;
+    h->W = width;
+    h->maxB = max_batch;
+    specs(h->widths, height, width, h->L, h->npar);
+    h->stream = (hipStream_t)hip_stream;  // NULL: the null stream (torch's default stream)
+    const size_t np = (size_t)h->npar;
+    h->par = (float*)nalloc(h, np * 4);
+    h->grad = (float*)nalloc(h, np * 4);
+    h->m = (float*)nalloc(h, np * 4);
+    h->v = (float*)nalloc(h, np * 4);
+    h->parb = (bf16_t*)nalloc(h, np * 2);
+    if (!h->par || !h->grad || !h->m || !h->v || !h->parb) return bail(fail(LBM_NO_ENOMEM, "parameters"));
+    int64_t colmax = 0, splitmax = 0, actmax = 0;
+    for (const Layer& l : h->L) {
+      const int64_t P = (int64_t)max_batch * l.Ho * l.Wo;
+      const size_t n = (size_t)l.cout * P * 4;
+      actmax = std::max(actmax, (int64_t)l.cout * P);
+      float* zl = (float*)nalloc(h, n);
+      float* al = (float*)nalloc(h, n);
+      float* dl = (float*)nalloc(h, n);
+      if (!zl || !al || !dl) return bail(fail(LBM_NO_ENOMEM, "activations"));
+      h->z.push_back(zl);
+      h->a.push_back(al);
+      h->da.push_back(dl);
+      const int64_t K = (int64_t)l.cin * l.k * l.k;
+      colmax = std::max(colmax, K * P);
+      const int64_t S = (P + KCHUNK - 1) / KCHUNK;
+      splitmax = std::max(splitmax, S * l.cout * K);
+    }
+    h->col = (bf16_t*)nalloc(h, (size_t)colmax * 2);
+    h->dcol = (float*)nalloc(h, (size_t)colmax * 4);
+    h->dz16 = (bf16_t*)nalloc(h, (size_t)actmax * 2);
+    h->split = (float*)nalloc(h, (size_t)splitmax * 4);
+    h->split_n = splitmax;
+    const int64_t lb = (3 * (int64_t)max_batch * height * width + EW - 1) / EW;
+    h->lpart = (double*)nalloc(h, (size_t)lb * 8);
+    h->dloss = (double*)nalloc(h, 8);
+    if (!h->col || !h->dcol || !h->dz16 || !h->split || !h->lpart || !h->dloss)
+      return bail(fail(LBM_NO_ENOMEM, "work space"));
+    const int rc = lbm_no_set_params(h, params);
+    if (rc) return bail(rc);
+    *out = h;
+    return LBM_NO_OK;
+  });
 }
 
 int lbm_no_set_params(lbm_no* h, const float* params) {
-  if (!h || !params) return fail(LBM_NO_EINVAL, "null argument");
-  const size_t np = (size_t)h->npar;
-  NOCHK(hipMemcpyAsync(h->par, params, np * 4, hipMemcpyHostToDevice, h->stream));
-  NOCHK(hipMemsetAsync(h->m, 0, np * 4, h->stream));
-  NOCHK(hipMemsetAsync(h->v, 0, np * 4, h->stream));
-  NOCHK(hipMemsetAsync(h->grad, 0, np * 4, h->stream));
-  k_to_bf16<<<grid1(h->npar), EW, 0, h->stream>>>(h->par, h->npar, h->parb);
-  NOCHK(hipGetLastError());
-  NOCHK(hipStreamSynchronize(h->stream));
-  h->adam_t = 0;
-  return LBM_NO_OK;
+  return guarded([&]() -> int {
+    if (!h || !params) return fail(LBM_NO_EINVAL, "null argument");
+    const size_t np = (size_t)h->npar;
+    NOCHK(hipMemcpyAsync(h->par, params, np * 4, hipMemcpyHostToDevice, h->stream));
+    NOCHK(hipMemsetAsync(h->m, 0, np * 4, h->stream));
+    NOCHK(hipMemsetAsync(h->v, 0, np * 4, h->stream));
+    NOCHK(hipMemsetAsync(h->grad, 0, np * 4, h->stream));
+    k_to_bf16<<<grid1(h->npar), EW, 0, h->stream>>>(h->par, h->npar, h->parb);
+    NOCHK(hipGetLastError());
+    NOCHK(hipStreamSynchronize(h->stream));
+    h->adam_t = 0;
+    return LBM_NO_OK;
+  });
 }
 
 int lbm_no_forward(lbm_no* h, const float* x, int32_t batch, float* y) {
-  int rc = check_batch(h, batch);
-  if (rc) return rc;
-  if (!x || !y) return fail(LBM_NO_EINVAL, "null tensor");
-  rc = forward_internal(h, x, batch);
-  if (rc) return rc;
-  const int64_t HW = (int64_t)h->H * h->W;
-  k_to_nchw<<<grid1(3 * batch * HW), EW, 0, h->stream>>>(h->a.back(), batch, HW, y);
-  NOCHK(hipGetLastError());
-  return LBM_NO_OK;
+  return guarded([&]() -> int {
+    int rc = check_batch(h, batch);
+    if (rc) return rc;
+    if (!x || !y) return fail(LBM_NO_EINVAL, "null tensor");
+    rc = forward_internal(h, x, batch);
+    if (rc) return rc;
+    const int64_t HW = (int64_t)h->H * h->W;
+    k_to_nchw<<<grid1(3 * batch * HW), EW, 0, h->stream>>>(h->a.back(), batch, HW, y);
+    NOCHK(hipGetLastError());
+    return LBM_NO_OK;
+  });
 }
 
 int lbm_no_gradients(lbm_no* h, const float* x, const float* target, int32_t batch, double* loss) {
-  int rc = check_batch(h, batch);
-  if (rc) return rc;
-  if (!x || !target) return fail(LBM_NO_EINVAL, "null tensor");
-  rc = forward_internal(h, x, batch);
-  if (rc) return rc;
-  const int nl = (int)h->L.size();
-  const int64_t HW = (int64_t)h->H * h->W;
-  const int64_t nout = 3 * (int64_t)batch * HW;
-  const int64_t nb = (nout + EW - 1) / EW;
-  k_loss<<<(unsigned)nb, EW, 0, h->stream>>>(h->a[nl - 1], target, batch, HW, h->da[nl - 1], h->lpart);
-  NOCHK(hipGetLastError());
-  k_loss_final<<<1, EW, 0, h->stream>>>(h->lpart, nb, nout, h->dloss);
-  NOCHK(hipGetLastError());
-  std::vector<char> have(nl, 0);  // activation gradient already written
-  have[nl - 1] = 1;
-  for (int li = nl - 1; li >= 0; --li) {
-    const Layer& l = h->L[li];
-    const int64_t P = (int64_t)batch * l.Ho * l.Wo;
-    const int K = l.cin * l.k * l.k;
-    const int64_t n = (int64_t)l.cout * P;
-    // dz over z; the skip passes da on unchanged
-    k_act_bwd<<<grid1(n), EW, 0, h->stream>>>(h->da[li], h->z[li], h->dz16, n, l.relu);
+  return guarded([&]() -> int {
+    int rc = check_batch(h, batch);
+    if (rc) return rc;
+    if (!x || !target) return fail(LBM_NO_EINVAL, "null tensor");
+    rc = forward_internal(h, x, batch);
+    if (rc) return rc;
+    const int nl = (int)h->L.size();
+    const int64_t HW = (int64_t)h->H * h->W;
+    const int64_t nout = 3 * (int64_t)batch * HW;
+    const int64_t nb = (nout + EW - 1) / EW;
+    k_loss<<<(unsigned)nb, EW, 0, h->stream>>>(h->a[nl - 1], target, batch, HW, h->da[nl - 1], h->lpart);
     NOCHK(hipGetLastError());
-    if (l.skip >= 0) {
-      k_copy_add<<<grid1(n), EW, 0, h->stream>>>(h->da[l.skip], h->da[li], n, have[l.skip]);
+    k_loss_final<<<1, EW, 0, h->stream>>>(h->lpart, nb, nout, h->dloss);
+    NOCHK(hipGetLastError());
+    std::vector<char> have(nl, 0);  // activation gradient already written
+    have[nl - 1] = 1;
+    for (int li = nl - 1; li >= 0; --li) {
+      const Layer& l = h->L[li];
+      const int64_t P = (int64_t)batch * l.Ho * l.Wo;
+      const int K = l.cin * l.k * l.k;
+      const int64_t n = (int64_t)l.cout * P;
+      // dz over z; the skip passes da on unchanged
+      k_act_bwd<<<grid1(n), EW, 0, h->stream>>>(h->da[li], h->z[li], h->dz16, n, l.relu);
       NOCHK(hipGetLastError());
-      have[l.skip] = 1;
+      if (l.skip >= 0) {
+        k_copy_add<<<grid1(n), EW, 0, h->stream>>>(h->da[l.skip], h->da[li], n, have[l.skip]);
+        NOCHK(hipGetLastError());
+        have[l.skip] = 1;
+      }
+      rc = im2col(h, l, li == 0 ? x : h->a[li - 1], li == 0, batch);
+      if (rc) return rc;
+      // weight gradient, split over p, partials summed in order
+      const int S = (int)((P + KCHUNK - 1) / KCHUNK);
+      const int64_t mn = (int64_t)l.cout * K;
+      if ((int64_t)S * mn > h->split_n) return fail(LBM_NO_EINVAL, "split work space too small");
+      // dW[o][k] = dz[o][p] col[k][p]: A k(=p)-contiguous, B k(=p)-contiguous
+      rc = gemm<true, true>(h, l.cout, K, (int)P, h->dz16, P, h->col, P, h->split, K, mn, S, KCHUNK, nullptr);
+      if (rc) return rc;
+      k_sum_splits<<<grid1(mn), EW, 0, h->stream>>>(h->split, S, mn, h->grad + l.woff);
+      NOCHK(hipGetLastError());
+      k_bias_grad<<<(unsigned)l.cout, EW, 0, h->stream>>>(h->z[li], P, h->grad + l.boff);
+      NOCHK(hipGetLastError());
+      if (li == 0) break;  // no gradient with respect to the input
+      // input gradient: dcol = W^T dz, then the col2im gather into da[li - 1]
+      // dcol[k][p] = W[o][k] dz[o][p]: A m(=k)-contiguous, B n(=p)-contiguous
+      rc = gemm<false, false>(h, K, (int)P, l.cout, h->parb + l.woff, K, h->dz16, P, h->dcol, P, 0, 1,
+                              l.cout + (l.cout & 1), nullptr);  // one split covering all of cout
+      if (rc) return rc;
+      const int64_t ns = (int64_t)l.cin * batch * l.Hs * l.Ws;
+      k_col2im<<<grid1(ns), EW, 0, h->stream>>>(h->dcol, l.cin, batch, l.Hs, l.Ws, l.up, l.k, l.s, (l.k - 1) / 2,
+                                                l.Ho, l.Wo, h->da[li - 1], have[li - 1]);
+      NOCHK(hipGetLastError());
+      have[li - 1] = 1;
     }
-    rc = im2col(h, l, li == 0 ? x : h->a[li - 1], li == 0, batch);
-    if (rc) return rc;
-    // weight gradient, split over p, partials summed in order
-    const int S = (int)((P + KCHUNK - 1) / KCHUNK);
-    const int64_t mn = (int64_t)l.cout * K;
-    if ((int64_t)S * mn > h->split_n) return fail(LBM_NO_EINVAL, "split work space too small");
-    // dW[o][k] = dz[o][p] col[k][p]: A k(=p)-contiguous, B k(=p)-contiguous
-    rc = gemm<true, true>(h, l.cout, K, (int)P, h->dz16, P, h->col, P, h->split, K, mn, S, KCHUNK, nullptr);
-    if (rc) return rc;
-    k_sum_splits<<<grid1(mn), EW, 0, h->stream>>>(h->split, S, mn, h->grad + l.woff);
-    NOCHK(hipGetLastError());
-    k_bias_grad<<<(unsigned)l.cout, EW, 0, h->stream>>>(h->z[li], P, h->grad + l.boff);
-    NOCHK(hipGetLastError());
-    if (li == 0) break;  // no gradient with respect to the input
-    // input gradient: dcol = W^T dz, then the col2im gather into da[li - 1]
-    // dcol[k][p] = W[o][k] dz[o][p]: A m(=k)-contiguous, B n(=p)-contiguous
-    rc = gemm<false, false>(h, K, (int)P, l.cout, h->parb + l.woff, K, h->dz16, P, h->dcol, P, 0, 1,
-                            l.cout + (l.cout & 1), nullptr);  // one split covering all of cout
-    if (rc) return rc;
-    const int64_t ns = (int64_t)l.cin * batch * l.Hs * l.Ws;
-    k_col2im<<<grid1(ns), EW, 0, h->stream>>>(h->dcol, l.cin, batch, l.Hs, l.Ws, l.up, l.k, l.s, (l.k - 1) / 2,
-                                              l.Ho, l.Wo, h->da[li - 1], have[li - 1]);
-    NOCHK(hipGetLastError());
-    have[li - 1] = 1;
-  }
-  if (loss) {
-    NOCHK(hipMemcpyAsync(loss, h->dloss, 8, hipMemcpyDeviceToHost, h->stream));
-    NOCHK(hipStreamSynchronize(h->stream));
-  }
-  return LBM_NO_OK;
+    if (loss) {
+      NOCHK(hipMemcpyAsync(loss, h->dloss, 8, hipMemcpyDeviceToHost, h->stream));
+      NOCHK(hipStreamSynchronize(h->stream));
+    }
+    return LBM_NO_OK;
+  });
 }
 
 int lbm_no_adam(lbm_no* h, float lr, float beta1, float beta2, float eps) {
-  if (!h || !(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
-    return fail(LBM_NO_EINVAL, "bad handle or Adam hyper-parameters");
-  h->adam_t += 1;
-  const float c1 = (float)(1.0 - std::pow((double)beta1, (double)h->adam_t));
-  const float c2 = (float)(1.0 - std::pow((double)beta2, (double)h->adam_t));
-  k_adam<<<grid1(h->npar), EW, 0, h->stream>>>(h->par, h->grad, h->m, h->v, h->npar, lr, beta1, beta2, eps, c1,
-                                               c2, h->parb);
-  NOCHK(hipGetLastError());
-  return LBM_NO_OK;
+  return guarded([&]() -> int {
+    if (!h || !(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+      return fail(LBM_NO_EINVAL, "bad handle or Adam hyper-parameters");
+    h->adam_t += 1;
+    const float c1 = (float)(1.0 - std::pow((double)beta1, (double)h->adam_t));
+    const float c2 = (float)(1.0 - std::pow((double)beta2, (double)h->adam_t));
+    k_adam<<<grid1(h->npar), EW, 0, h->stream>>>(h->par, h->grad, h->m, h->v, h->npar, lr, beta1, beta2, eps, c1,
+                                                 c2, h->parb);
+    NOCHK(hipGetLastError());
+    return LBM_NO_OK;
+  });
 }
 
 int lbm_no_get(lbm_no* h, int32_t which, float* host_out) {
-  if (!h || !host_out || which < 0 || which > 1) return fail(LBM_NO_EINVAL, "bad argument");
-  NOCHK(hipMemcpyAsync(host_out, which == 0 ? h->par : h->grad, (size_t)h->npar * 4, hipMemcpyDeviceToHost,
-                       h->stream));
-  NOCHK(hipStreamSynchronize(h->stream));
-  return LBM_NO_OK;
+  return guarded([&]() -> int {
+    if (!h || !host_out || which < 0 || which > 1) return fail(LBM_NO_EINVAL, "bad argument");
+    NOCHK(hipMemcpyAsync(host_out, which == 0 ? h->par : h->grad, (size_t)h->npar * 4, hipMemcpyDeviceToHost,
+                         h->stream));
+    NOCHK(hipStreamSynchronize(h->stream));
+    return LBM_NO_OK;
+  });
 }
 
 int lbm_no_sync(lbm_no* h) {
