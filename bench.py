@@ -146,6 +146,60 @@ def sweep_batch(Lattice, n_inst, steps, stream):
                               (("running", 0), ("converged", 1), ("diverged", 2), ("stalled", 3))}}
 
 
+def sweep_to_steady(n_inst, cap, chunk=10_000, floor=3e-7):
+    """The batched sweep run toward res <= 1e-8 with autotuned launches, step
+    graphs and finished instances dropped from the launch after every chunk,
+    up to `cap` steps.  It starts in FP16 storage, whose rounding noise keeps
+    the residual near 1e-7 at a check interval of 1000, and converts the
+    whole batch to FP32 in place (precision handoff) once half of the running
+    instances are within 3x of that floor.  Counts of converged / stalled /
+    diverged instances, steps of the converged ones, node updates per second."""
+    import numpy as np
+    import torch
+
+    import lbm_inputs as li
+    from paper_1409_5929_amd import Lattice
+
+    cfgs = li.sweep(n_inst=n_inst, seed=1409)
+    sizes = np.array([c["nr"] * c["nz"] for c in cfgs], dtype=np.float64)
+    lat = Lattice(cfgs, storage="fp16", check_interval=1000, tol=1e-8, max_steps=cap)
+    lat.autotune(trial_steps=10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t = lat.info()["t"]
+    updates = 0.0
+    running = n_inst
+    t_handoff = None
+    while t < cap + 1000 and running > 0:
+        r = lat.residual()
+        alive = sizes[r["status"] == 0].sum()
+        if t_handoff is None and t > 0:
+            res_run = r["res"][r["status"] == 0]
+            if res_run.size and np.mean(res_run < floor) >= 0.5:
+                lat.set_storage("fp32")
+                lat.autotune(trial_steps=10)  # FP32 prefers other launch shapes; 150 real steps
+                t += 15 * 10
+                t_handoff = t
+                log(f"sweep to steady: FP16 -> FP32 at t={t}")
+        lat.step(chunk)
+        t += chunk
+        updates += alive * chunk  # upper bound within the chunk: instances that stop mid-chunk
+        running = lat.compact()
+        log(f"sweep to steady: t={t}, {running} of {n_inst} running, {time.perf_counter() - t0:.0f} s")
+    lat.sync()
+    wall = time.perf_counter() - t0
+    r = lat.residual()
+    steps = np.array([lat.info(i)["t"] for i in range(n_inst)])
+    lat.close()
+    st = r["status"]
+    conv = st == 1
+    return {"instances": n_inst, "cap": cap, "wall_s": round(wall, 1),
+            "converged": int(conv.sum()), "stalled": int((st == 3).sum()), "diverged": int((st == 2).sum()),
+            "running": int((st == 0).sum()), "handoff_step": t_handoff,
+            "steps_converged_median": float(np.median(steps[conv])) if conv.any() else None,
+            "node_updates_per_s_upper": round(updates / wall / 1e6, 1)}
+
+
 def time_to_steady(n_problems, cap):
     """Time to steady state (res <= 1e-8) of 128^2 annuli of the sweep
     distribution (held-out problems of the warm-start network's training
@@ -225,6 +279,8 @@ def main():
     ap.add_argument("--sweep-steps", type=int, default=1000)
     ap.add_argument("--steady-problems", type=int, default=32)
     ap.add_argument("--steady-max-steps", type=int, default=600_000)
+    ap.add_argument("--sweep-to-steady", type=int, default=0, metavar="CAP",
+                    help="only run the 1024-instance sweep toward res <= 1e-8 for up to CAP steps")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 2 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -241,6 +297,10 @@ def main():
     from paper_1409_5929_amd import Lattice
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.sweep_to_steady > 0:
+        print(json.dumps({"sweep_to_steady": sweep_to_steady(args.sweep_instances, args.sweep_to_steady)}),
+              flush=True)
+        return
     n = args.size
     log(f"porosity field {n}x{n} (seed 1409)")
     cfg, _ = li.variable_porosity_annulus(n=n)
