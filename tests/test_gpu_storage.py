@@ -159,3 +159,40 @@ def test_fp32_to_fp32_conversion_is_exact(L):
     for k in ("uz", "ur", "p", "T", "mask"):
         np.testing.assert_array_equal(a[k], b[k])
         np.testing.assert_array_equal(c[k], d[k])
+
+
+def test_fp16_beyond_4gib_uses_flat_addressing(L, oracle_mod):
+    """A 13000^2 annulus in FP16 storage: 4.7 GB of populations, beyond the
+    4 GiB reach of 32-bit buffer offsets, so the step kernels take the flat
+    (64-bit address) path.  Windows of the field after 4 steps against the
+    oracle on the same windows (every node farther than n + 2 from a window's
+    artificial sides depends only on the window), at the FP16 bound."""
+    from tests.test_gpu_parity import _window
+
+    size, n, w = 13000, 4, 28
+    cfg, _ = li.variable_porosity_annulus(n=size)
+    phi = li.porosity_grf(size, size, seed=1409)
+    lat = L.Lattice(cfg, phi=phi, storage="fp16", check_interval=0)
+    assert lat.info()["device_bytes"] > 14 * size * size * 2 > 4 * 2 ** 30
+    lat.step(n)
+    g = lat.fields()
+    lat.close()
+    margin = n + 2
+    tol = 6 * U16["fp16"]
+    for j0, k0 in [(0, 0), (size - w, size // 2), (size // 2, size - w)]:
+        c, ph = _window(cfg, phi, j0, k0, w)
+        c["side_z"] = "wall"
+        o = oracle_mod.Oracle(c, phi_field=ph)
+        o.step(n)
+        m = o.macros()
+        o.close()
+        jl = 0 if j0 == 0 else margin
+        jh = w if j0 + w == size else w - margin
+        kl = 0 if k0 == 0 else margin
+        kh = w if k0 + w == size else w - margin
+        sub = {k: g[k][k0 + kl:k0 + kh, j0 + jl:j0 + jh] for k in ("uz", "ur", "p", "T", "mask")}
+        ref = {k: m[k][kl:kh, jl:jh] for k in ("uz", "ur", "p", "T", "mask")}
+        np.testing.assert_array_equal(sub["mask"], ref["mask"])
+        e = rel_errors(sub, ref, u_floor=1e-3 * li.U_SCALE)
+        print(f"13000^2 FP16 window {(j0, k0)}: {e}", flush=True)
+        assert max(e.values()) <= tol, (j0, k0, e)
