@@ -296,7 +296,8 @@ def main():
     import lbm_inputs as li
     from paper_1409_5929_amd import Lattice
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if not torch.cuda.is_available():
+        sys.exit("bench.py needs a GPU")
     if args.sweep_to_steady > 0:
         print(json.dumps({"sweep_to_steady": sweep_to_steady(args.sweep_instances, args.sweep_to_steady)}),
               flush=True)

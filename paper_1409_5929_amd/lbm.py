@@ -173,6 +173,8 @@ class Lattice:
             phis = [None] * n
         if not inits:
             inits = [None] * n
+        if len(phis) != n or len(inits) != n:
+            raise ValueError("phi and init must be given per instance (or once for a single instance)")
         self.shapes = [(int(c["nz"]), int(c["nr"])) for c in cfgs]
         arr = (Params * n)()
         for i, c in enumerate(cfgs):
@@ -185,12 +187,14 @@ class Lattice:
             nz, nr = self.shapes[i]
             if phis[i] is not None:
                 a = np.ascontiguousarray(phis[i], dtype=np.float32)
-                assert a.shape == (nz, nr)
+                if a.shape != (nz, nr):
+                    raise ValueError(f"porosity field {i} has shape {a.shape}, expected {(nz, nr)}")
                 keep.append(a)
                 phi_ptrs[i] = a.ctypes.data_as(fp)
             if inits[i] is not None:
                 a = np.ascontiguousarray(inits[i], dtype=np.float32)
-                assert a.shape == (3, nz, nr)
+                if a.shape != (3, nz, nr):
+                    raise ValueError(f"start fields {i} have shape {a.shape}, expected {(3, nz, nr)}")
                 keep.append(a)
                 init_ptrs[i] = a.ctypes.data_as(fp)
         h = ctypes.c_void_p()

@@ -92,8 +92,11 @@ class WarmStartNet:
     def _tensor(self, t, channels):
         import torch
 
-        assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous(), "float32 contiguous device tensor"
-        assert t.dim() == 4 and t.shape[1:] == (channels, self.height, self.width), t.shape
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise ValueError("expected a float32 contiguous device tensor")
+        if t.dim() != 4 or tuple(t.shape[1:]) != (channels, self.height, self.width):
+            raise ValueError(f"tensor shape {tuple(t.shape)}, expected (batch, {channels}, "
+                             f"{self.height}, {self.width})")
         return ctypes.c_void_p(t.data_ptr())
 
     def forward(self, x):
