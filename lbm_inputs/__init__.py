@@ -12,8 +12,10 @@ A problem is a plain ``dict`` with these keys (lattice units, spacing 1):
   L                      characteristic length of Eq. (9)
   side_rmin, side_rmax   "wall" | "axis" (r_min only) | "periodic"
   side_z                 "wall" | "periodic"
-  therm_rmin, therm_rmax, therm_z   "fixed" | "adiabatic"
+  therm_rmin, therm_rmax, therm_z   "fixed" | "adiabatic" | "flux" (radial walls)
   T_rmin, T_rmax, T_zmin, T_zmax    wall temperatures of fixed walls
+  flux_rmin, flux_rmax   q'/k of flux walls (a temperature gradient)
+  flux_zlo, flux_zhi     heated window of flux walls, z = k (default: the whole wall)
   T_ref, T_init, delta_T reference temperature T_0 of Eq. (7), initial
                          temperature, temperature difference (0: T_rmin - T_rmax)
   phi, Da, F_phi         porosity (reference porosity with a field), Darcy
@@ -81,6 +83,32 @@ def annulus(nr: int = 256, nz: int = 256, Rstar: float = 2.0, phi: float = 0.6,
 def table2(Ra: float, nr: int = 100, nz: int = 200) -> dict:
     """Annulus without porous medium as in Sec. 4.2 / Table 2 (phi = 1, Da = 1e8)."""
     return annulus(nr=nr, nz=nz, Rstar=2.0, phi=1.0, Da=1e8, Ra=Ra, Pr=0.7, F_phi=0.0)
+
+
+def heater_annulus(Da: float, nr: int = 200, nz: int = 200, Ra: float = 1e7, Pr: float = 0.7,
+                   phi: float = 0.9, F_phi: float = 0.0, Rstar: float = 2.0,
+                   l_over_H: float = 0.4, h_over_H: float = 0.5, dT: float = 10.0,
+                   T_o: float = 1.0, Ma: float = 0.1) -> dict:
+    """Porous annulus with an isoflux heater on the inner wall (Sec. 4.4, Fig. 7).
+
+    Wall nodes lie on the walls: L = r_o - r_i = nr - 1, H = nz - 1,
+    r_i = L / (R* - 1).  The heater covers h - l/2 <= z <= h + l/2 of the
+    inner wall with q'/k = dT / L (so that q' L / k = dT); the rest of the
+    inner wall and both ends are adiabatic; the outer wall is held at T_o,
+    which is also T_0 and the start temperature.  The defaults are the
+    paper's: Ra = 1e7, Pr = 0.7, phi = 0.9, F_phi = 0, A = 1, R* = 2,
+    l/H = 0.4, h/H = 0.5, dT = 10, T_o = 1 on a 200 x 200 grid.
+    """
+    L = nr - 1.0
+    H = nz - 1.0
+    ri = L / (Rstar - 1.0)
+    return dict(nr=nr, nz=nz, r0=ri, L=L, side_rmin="wall", side_rmax="wall",
+                side_z="wall", therm_rmin="flux", therm_rmax="fixed", therm_z="adiabatic",
+                T_rmin=0.0, T_rmax=T_o, T_zmin=0.0, T_zmax=0.0, T_ref=T_o, T_init=T_o,
+                delta_T=dT, flux_rmin=dT / L, flux_rmax=0.0,
+                flux_zlo=(h_over_H - 0.5 * l_over_H) * H, flux_zhi=(h_over_H + 0.5 * l_over_H) * H,
+                phi=phi, Da=Da, F_phi=F_phi, Ra=Ra, Pr=Pr, J=1.0, lam=1.0, Ma=Ma, tau_nu=0.0,
+                accel_r=0.0, accel_z=0.0)
 
 
 def porosity_grf(nz: int, nr: int, seed: int = 1409, sigma: float = 8.0, mean: float = 0.6,

@@ -23,7 +23,7 @@ _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
 SIDE = {"wall": 0, "axis": 1, "periodic": 2}
-THERM = {"fixed": 0, "adiabatic": 1}
+THERM = {"fixed": 0, "adiabatic": 1, "flux": 2}
 
 
 class _Params(ctypes.Structure):
@@ -41,6 +41,8 @@ class _Params(ctypes.Structure):
         ("T_rmin", ctypes.c_double), ("T_rmax", ctypes.c_double),
         ("T_zmin", ctypes.c_double), ("T_zmax", ctypes.c_double),
         ("T_ref", ctypes.c_double), ("T_init", ctypes.c_double), ("delta_T", ctypes.c_double),
+        ("flux_rmin", ctypes.c_double), ("flux_rmax", ctypes.c_double),
+        ("flux_zlo", ctypes.c_double), ("flux_zhi", ctypes.c_double),
     ]
 
 
@@ -83,6 +85,8 @@ def _load():
     lib.orc_derived.argtypes = [ctypes.c_void_p, d]
     lib.orc_matrices.argtypes = [ctypes.c_void_p, d, d]
     lib.orc_node.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, d, d, d, d, d, d, d]
+    lib.orc_stream_function.restype = ctypes.c_double
+    lib.orc_stream_function.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, d, d]
     lib.orc_last_error.restype = ctypes.c_char_p
     lib.orc_threads.restype = ctypes.c_int
     _lib = lib
@@ -96,6 +100,7 @@ DEFAULTS = dict(
     tau_nu=0.0, accel_r=0.0, accel_z=0.0, s_e=1.1, s_eps=1.1, s_q=1.2, s_j=1.0, s_nu=0.0,
     src_printed=0,
     T_rmin=0.0, T_rmax=0.0, T_zmin=0.0, T_zmax=0.0, T_ref=0.0, T_init=0.0, delta_T=0.0,
+    flux_rmin=0.0, flux_rmax=0.0, flux_zlo=-np.inf, flux_zhi=np.inf,
 )
 
 
@@ -184,6 +189,8 @@ class Oracle:
         return dict(res_u=out[0], res_T=out[1], res=out[2])
 
     def nusselt(self):
+        """(Nu_i, Nu_o): Eq. (42) on fixed-temperature walls, the heater mean of
+        Eqs. (43)-(44) on flux walls."""
         a, b = ctypes.c_double(), ctypes.c_double()
         self._lib.orc_nusselt(self._h, ctypes.byref(a), ctypes.byref(b))
         return a.value, b.value
@@ -221,6 +228,16 @@ class Oracle:
                            _dptr(meq), _dptr(S), _dptr(fo), _dptr(go))
         return dict(rho=macro[0], ur=macro[1], uz=macro[2], T=macro[3], Ftr=macro[4],
                     Ftz=macro[5], a_r=macro[6], meq=meq, S=S, f_out=fo, g_out=go)
+
+
+def stream_function(uz, r0: float):
+    """Stokes stream function of a u_z field [nz, nr] with rows at r0 + j,
+    zero on row 0 (trapezoid rule); returns (psi, max |psi|)."""
+    uz = np.ascontiguousarray(uz, dtype=np.float64)
+    nz, nr = uz.shape
+    psi = np.empty_like(uz)
+    mx = _load().orc_stream_function(nr, nz, float(r0), _dptr(uz), _dptr(psi))
+    return psi, float(mx)
 
 
 def threads() -> int:

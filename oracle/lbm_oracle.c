@@ -59,6 +59,23 @@
  *      follow from the change of variables that leads to Eq. (15),
  *      f = f~ - (dt/2) S~, i.e. f = M^{-1} (m^eq - S/2).  Then Eqs. (26)-(28)
  *      return u0 itself (exactly when F_phi = 0).  g = g^eq(T0, u0).
+ *   R9 Isoflux walls (Sec. 4.4).  A radial wall of type THERM_FLUX carries the
+ *      heat flux q' = -k dT/dn (n pointing out of the fluid, so dT/dr at r_min)
+ *      on its nodes with flux_zlo <= z <= flux_zhi and is adiabatic elsewhere.
+ *      The given flux is q'/k, a temperature gradient.  A heated wall node
+ *      takes T_b = T_B + (q'/k) * 1, the one-sided difference to its fluid
+ *      neighbour B one spacing away (the adiabatic copy T_b = T_B is the case
+ *      q' = 0), and is then treated as in R2.  At a corner any
+ *      fixed-temperature wall wins over the flux.
+ *   R10 Heater Nusselt numbers (Eqs. 43-44).  Nu(z) = (q'/k) L / (T_h - T_0)
+ *      at each heated node, T_h its wall temperature and T_0 = T_ref (the
+ *      paper takes T_0 = T_o, the cold wall); the heater mean is the plain
+ *      average over the heated nodes, each standing for a unit length of
+ *      wall (midpoint rule of Eq. 43).
+ *   R11 Stream function (Table 3; not defined in the paper).  The Stokes
+ *      stream function of the axisymmetric flow, u_z = (1/r) dpsi/dr and
+ *      u_r = -(1/r) dpsi/dz, zero on the r_min wall:
+ *      psi(r, z) = integral from r_min to r of r' u_z(r', z) dr'.
  */
 #include <math.h>
 #include <stdint.h>
@@ -93,7 +110,7 @@ static const double MM[9][9] = {
     {0, 0, 0, 0, 0, 1, -1, 1, -1}};
 
 enum { SIDE_WALL = 0, SIDE_AXIS = 1, SIDE_PERIODIC = 2 };
-enum { THERM_FIXED = 0, THERM_ADIABATIC = 1 };
+enum { THERM_FIXED = 0, THERM_ADIABATIC = 1, THERM_FLUX = 2 };
 enum { MASK_RMIN = 1, MASK_RMAX = 2, MASK_ZMIN = 4, MASK_ZMAX = 8, MASK_AXISROW = 16 };
 
 typedef struct {
@@ -115,6 +132,8 @@ typedef struct {
   double T_ref;    /* T_0 of Eq. (7) */
   double T_init;   /* initial temperature where no field is given */
   double delta_T;  /* characteristic temperature difference; 0 = T_rmin - T_rmax */
+  double flux_rmin, flux_rmax; /* q'/k of THERM_FLUX radial walls (R9) */
+  double flux_zlo, flux_zhi;   /* heated window of a flux wall, z = k */
 } orc_params;
 
 typedef struct {
@@ -312,12 +331,25 @@ static void owner_of(const orc_params* p, uint8_t m, int j, int k, int* jb, int*
   (void)p;
 }
 
-/* Wall temperature (R2). */
-static double wall_temperature(const orc_params* p, uint8_t m, double T_owner) {
+/* Does wall node (mask m, column k) take the flux condition of R9?  *q gets q'/k. */
+static int flux_node(const orc_params* p, uint8_t m, int k, double* q) {
+  if ((m & MASK_RMIN) && p->therm_rmin == THERM_FIXED) return 0;
+  if ((m & MASK_RMAX) && p->therm_rmax == THERM_FIXED) return 0;
+  if ((m & (MASK_ZMIN | MASK_ZMAX)) && p->therm_z == THERM_FIXED) return 0;
+  if (!(p->flux_zlo <= k && k <= p->flux_zhi)) return 0;
+  if ((m & MASK_RMIN) && p->therm_rmin == THERM_FLUX) { *q = p->flux_rmin; return 1; }
+  if ((m & MASK_RMAX) && p->therm_rmax == THERM_FLUX) { *q = p->flux_rmax; return 1; }
+  return 0;
+}
+
+/* Wall temperature (R2, R9). */
+static double wall_temperature(const orc_params* p, uint8_t m, int k, double T_owner) {
+  double q;
   if ((m & MASK_RMIN) && p->therm_rmin == THERM_FIXED) return p->T_rmin;
   if ((m & MASK_RMAX) && p->therm_rmax == THERM_FIXED) return p->T_rmax;
   if ((m & MASK_ZMIN) && p->therm_z == THERM_FIXED) return p->T_zmin;
   if ((m & MASK_ZMAX) && p->therm_z == THERM_FIXED) return p->T_zmax;
+  if (flux_node(p, m, k, &q)) return T_owner + q * 1.0; /* q'/k times the spacing to B */
   return T_owner;
 }
 
@@ -385,6 +417,7 @@ orc_state* orc_create(const orc_params* p, const double* phi_field, const double
     g_err = "radial periodicity must be on both sides"; return NULL;
   }
   if (!(p->r0 > 0.0)) { g_err = "r0 must be positive"; return NULL; }
+  if (p->therm_z == THERM_FLUX) { g_err = "flux walls are radial only"; return NULL; }
   orc_state* s = (orc_state*)calloc(1, sizeof(orc_state));
   s->p = *p;
   if (derive(s) != 0) { free(s); return NULL; }
@@ -460,7 +493,7 @@ static void compute_all_macros(orc_state* s) {
       s->rho[idx] = s->rho[ib];
       s->ur[idx] = 0.0;
       s->uz[idx] = 0.0;
-      s->T[idx] = wall_temperature(&s->p, m, s->T[ib]);
+      s->T[idx] = wall_temperature(&s->p, m, k, s->T[ib]);
     }
 }
 
@@ -634,6 +667,42 @@ void orc_nusselt(const orc_state* s, double* nu_i, double* nu_o) {
   }
   *nu_i = -(s->r[0] / (H * dT)) * si;
   *nu_o = -(s->r[nr - 1] / (H * dT)) * so;
+  /* A flux wall reports the heater mean of Eqs. (43)-(44) instead (R10). */
+  for (int side = 0; side < 2; ++side) {
+    int therm = side ? p->therm_rmax : p->therm_rmin;
+    if (therm != THERM_FLUX) continue;
+    int j = side ? nr - 1 : 0;
+    double sum = 0.0, q = 0.0;
+    int cnt = 0;
+    for (int k = 0; k < nz; ++k) {
+      int idx = k * nr + j;
+      if (!is_boundary(s->mask[idx]) || !flux_node(p, s->mask[idx], k, &q)) continue;
+      sum += q * p->L / (s->T[idx] - p->T_ref); /* Eq. (44) */
+      cnt += 1;
+    }
+    double nu = cnt ? sum / cnt : NAN;          /* Eq. (43) */
+    if (side) *nu_o = nu; else *nu_i = nu;
+  }
+}
+
+/*
+ * Stokes stream function (R11) of a u_z field ([nz][nr], rows at r0 + j):
+ * psi[k][0] = 0 and psi[k][j] = psi[k][j-1] + (r_{j-1} u_{j-1} + r_j u_j) / 2
+ * (trapezoid rule of the integral of r u_z dr).  Returns max |psi|.
+ */
+double orc_stream_function(int nr, int nz, double r0, const double* uz, double* psi) {
+  double mx = 0.0;
+  for (int k = 0; k < nz; ++k) {
+    const double* u = uz + (long)k * nr;
+    double acc = 0.0;
+    if (psi) psi[(long)k * nr] = 0.0;
+    for (int j = 1; j < nr; ++j) {
+      acc += 0.5 * ((r0 + j - 1) * u[j - 1] + (r0 + j) * u[j]);
+      if (psi) psi[(long)k * nr + j] = acc;
+      if (fabs(acc) > mx) mx = fabs(acc);
+    }
+  }
+  return mx;
 }
 
 /* Raw populations, [nz][nr][9] and [nz][nr][5]. */
