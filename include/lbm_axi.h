@@ -68,7 +68,16 @@ enum lbm_axi_side {
   LBM_SIDE_PERIODIC = 2  /* periodic; along r only for tests (both r sides) */
 };
 
-enum lbm_axi_thermal { LBM_T_FIXED = 0, LBM_T_ADIABATIC = 1 };
+/*
+ * Thermal wall types.  LBM_T_FLUX (radial walls only) is the isoflux wall of
+ * Sec. 4.4: the nodes of the wall with flux_zlo <= z <= flux_zhi carry the
+ * heat flux q' = -k dT/dn into the fluid (n the outward normal of the fluid,
+ * so q' = -k dT/dr on an r_min wall) and the rest of the wall is adiabatic.
+ * A heated wall node takes T_b = T_B + q'/k, the one-sided difference to its
+ * fluid neighbour B one spacing away, and is then treated like any wall node;
+ * at a corner a fixed-temperature wall wins.
+ */
+enum lbm_axi_thermal { LBM_T_FIXED = 0, LBM_T_ADIABATIC = 1, LBM_T_FLUX = 2 };
 
 /* Storage of the populations.  Arithmetic is FP32 in every case. */
 enum lbm_axi_storage {
@@ -115,6 +124,8 @@ typedef struct lbm_axi_params {
   double delta_T;              /* temperature difference of Ra and Nu; 0: T_rmin - T_rmax */
   double tol;                  /* convergence threshold on the residual (0: only an exact 0) */
   int64_t max_steps;           /* stall after this many steps (0: never) */
+  double flux_rmin, flux_rmax; /* q'/k of LBM_T_FLUX walls (temperature per lattice unit) */
+  double flux_zlo, flux_zhi;   /* heated window of LBM_T_FLUX walls in z (default: all) */
 } lbm_axi_params;
 
 /* Fill *p with the paper's default rates and ratios; grid and physics zero. */
@@ -155,6 +166,20 @@ int lbm_axi_macros(lbm_axi* h, int32_t inst, float* uz, float* ur, float* p, flo
                    uint8_t* mask, int32_t dst_is_device);
 
 /*
+ * Stokes stream function of instance inst at its current time (the paper
+ * reports its largest magnitude in Table 3 without defining it):
+ * u_z = (1/r) dpsi/dr, u_r = -(1/r) dpsi/dz, psi = 0 on row 0, i.e.
+ * psi(r_j, z_k) = integral from r0 to r_j of r u_z dr by the trapezoid rule
+ * over the rows (FP64 sums of the FP32 velocity field), in lattice units
+ * (divide by nu L for the scale of the paper's table).  psi: NULL or [nz][nr]
+ * floats, device memory if dst_is_device (written on the handle's stream)
+ * else host memory.  psi_absmax: NULL or one host double, max |psi|.  The
+ * call allocates temporary device memory and waits for the stream.
+ */
+int lbm_axi_stream_function(lbm_axi* h, int32_t inst, float* psi, double* psi_absmax,
+                            int32_t dst_is_device);
+
+/*
  * Latest check of every instance (waits for the stream).  Each pointer may be
  * NULL; arrays have n_inst entries.  The paper defines no convergence
  * criterion; at step n (a multiple N of check_interval) res = max(R_u, R_T)
@@ -164,7 +189,10 @@ int lbm_axi_macros(lbm_axi* h, int32_t inst, float* uz, float* ur, float* p, flo
  * that rounding flicker of FP32 storage does not set a floor.  nu_i, nu_o =
  * Eq. (42) at step n on the r_min and r_max walls (second-order one-sided
  * dT/dr, trapezoid rule, H = nz - 1).  status = lbm_axi_run_state.  Before
- * the first check res = +inf.
+ * the first check res = +inf.  On an LBM_T_FLUX wall nu_i (nu_o) is instead
+ * the heater mean of Eqs. (43)-(44): Nu(z) = (q'/k) L / (T_h - T_ref) at each
+ * heated wall node (T_h its wall temperature; the paper takes T_0 = T_o, the
+ * cold-wall temperature), averaged over the heated nodes (NaN if none).
  */
 int lbm_axi_residual(lbm_axi* h, double* res, double* nu_i, double* nu_o, int32_t* status);
 

@@ -10,6 +10,7 @@
 //   k_init     start state
 //   k_convert  storage conversion (FP32 / FP16 / BF16) of one instance
 //   k_setclock device clock read by captured step graphs
+//   k_psi, k_absmax  Stokes stream function of one instance and its largest magnitude
 //   k_step<MODE_FIELDS>  macroscopic fields of one instance (no population writes)
 //
 // Launch geometry: blocks of 64 x 4 threads; lanes run along r (coalesced
@@ -259,13 +260,24 @@ __global__ __launch_bounds__(RB) void k_resid(const InstDev* __restrict__ descs,
         a[2] += dT * dT;
         a[3] += uz * uz + ur * ur;
       }
+      // Walls: the Eq. (42) integrand, or on an isoflux wall 1 / (T_h - T_0) of
+      // each heated node for the heater mean of Eqs. (43)-(44).
+      float q;
       if (j == 0 && D.nr >= 3) {
-        const double g = (-3.0 * cu[2 * pl + o] + 4.0 * cu[2 * pl + o + 1] - cu[2 * pl + o + 2]) * 0.5;
-        a[4] += ck * g;
+        if (D.therm_rmin != THERM_FLUX) {
+          const double g = (-3.0 * cu[2 * pl + o] + 4.0 * cu[2 * pl + o + 1] - cu[2 * pl + o + 2]) * 0.5;
+          a[4] += ck * g;
+        } else if (is_boundary(D, j, k) && flux_node(D, node_mask(D, j, k), k, q)) {
+          a[4] += 1.0 / ((double)cu[2 * pl + o] - (double)D.T_ref);
+        }
       }
       if (j == D.nr - 1 && D.nr >= 3) {
-        const double g = (3.0 * cu[2 * pl + o] - 4.0 * cu[2 * pl + o - 1] + cu[2 * pl + o - 2]) * 0.5;
-        a[5] += ck * g;
+        if (D.therm_rmax != THERM_FLUX) {
+          const double g = (3.0 * cu[2 * pl + o] - 4.0 * cu[2 * pl + o - 1] + cu[2 * pl + o - 2]) * 0.5;
+          a[5] += ck * g;
+        } else if (is_boundary(D, j, k) && flux_node(D, node_mask(D, j, k), k, q)) {
+          a[5] += 1.0 / ((double)cu[2 * pl + o] - (double)D.T_ref);
+        }
       }
     }
   }
@@ -338,6 +350,51 @@ __global__ __launch_bounds__(RB) void k_final(const int* __restrict__ first,
   out[inst] = r;
 }
 
+// Stokes stream function (zero on the r_min row) of a u_z field [nz][nr] with
+// rows at r0 + j: one wave per column k scans the trapezoid terms
+// (r_{j-1} u_{j-1} + r_j u_j) / 2 along r in FP64, 64 rows at a time, and
+// writes psi (if non-null) and colmax[k] = max_j |psi[k][j]|.
+__global__ __launch_bounds__(RB) void k_psi(const float* __restrict__ uz, int nr, int nz, double r0,
+                                            float* __restrict__ psi, double* __restrict__ colmax) {
+  const int lane = threadIdx.x & 63;
+  const int k = blockIdx.x * (RB / 64) + (threadIdx.x >> 6);
+  if (k >= nz) return;  // whole waves leave together
+  const float* u = uz + (int64_t)k * nr;
+  double carry = 0.0, mx = 0.0;
+  for (int j0 = 0; j0 < nr; j0 += 64) {
+    const int j = j0 + lane;
+    double t = 0.0;
+    if (j >= 1 && j < nr) t = 0.5 * ((r0 + (j - 1)) * (double)u[j - 1] + (r0 + j) * (double)u[j]);
+    for (int off = 1; off < 64; off <<= 1) {
+      const double y = __shfl_up(t, off, 64);
+      if (lane >= off) t += y;
+    }
+    const double v = carry + t;
+    if (j < nr) {
+      if (psi) psi[(int64_t)k * nr + j] = (float)v;
+      mx = fmax(mx, fabs(v));
+    }
+    carry = __shfl(v, 63, 64);
+  }
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  if (lane == 0) colmax[k] = mx;
+}
+
+// out[0] = max of colmax[0..n) (one block).
+__global__ __launch_bounds__(RB) void k_absmax(const double* __restrict__ colmax, int n,
+                                               double* __restrict__ out) {
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < n; i += RB) mx = fmax(mx, colmax[i]);
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  __shared__ double sh[RB / 64];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < RB / 64; ++i) mx = fmax(mx, sh[i]);
+    out[0] = fmax(mx, sh[0]);
+  }
+}
+
 // ---- host side ------------------------------------------------------------------
 
 namespace {
@@ -367,6 +424,12 @@ int validate(const lbm_axi_params& p, int i) {
   if (p.sigma != 1.0)
     return fail(LBM_AXI_EUNSUPPORTED, pre + "only a heat-capacity ratio of 1 is defined (Eq. 4)");
   if (p.storage < 0 || p.storage > 2) return fail(LBM_AXI_EINVAL, pre + "storage code out of range");
+  if (p.therm_rmin < 0 || p.therm_rmin > 2 || p.therm_rmax < 0 || p.therm_rmax > 2 || p.therm_z < 0 ||
+      p.therm_z > 1)
+    return fail(LBM_AXI_EINVAL, pre + "thermal code out of range (flux walls are radial only)");
+  if (!std::isfinite(p.flux_rmin) || !std::isfinite(p.flux_rmax) || std::isnan(p.flux_zlo) ||
+      std::isnan(p.flux_zhi))
+    return fail(LBM_AXI_EINVAL, pre + "flux values must be finite and the window not NaN");
   if (p.check_interval == 1 || p.check_interval < 0)
     return fail(LBM_AXI_EINVAL, pre + "check_interval must be 0 or >= 2");
   if (!(p.tau_nu > 0.0) && !(p.Ra > 0.0))
@@ -607,6 +670,8 @@ void lbm_axi_default_params(lbm_axi_params* p) {
   p->side_rmin = p->side_rmax = p->side_z = LBM_SIDE_WALL;
   p->therm_rmin = p->therm_rmax = LBM_T_FIXED;
   p->therm_z = LBM_T_ADIABATIC;
+  p->flux_zlo = -HUGE_VAL;
+  p->flux_zhi = HUGE_VAL;
   p->storage = LBM_STORE_FP32;
   p->storage_shift = 0;
   p->check_interval = 100;
@@ -776,6 +841,18 @@ int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* 
         nus[4 * i] = walls ? p[i].r0 / (H * dT) : 0.0;
         nus[4 * i + 1] = (p[i].side_rmax == SIDE_WALL && dT != 0.0 && H > 0)
                              ? (p[i].r0 + nr - 1) / (H * dT) : 0.0;
+        // Isoflux walls: Nu = (q'/k) L / n_heated * sum 1 / (T_h - T_0) (NaN if unheated).
+        for (int side = 0; side < 2; ++side) {
+          if ((side ? p[i].therm_rmax : p[i].therm_rmin) != LBM_T_FLUX) continue;
+          const InstDev& D = h->hdesc[i];
+          const int j = side ? nr - 1 : 0;
+          int cnt = 0;
+          float qf;
+          for (int k = 0; k < nz; ++k)
+            if (is_boundary(D, j, k) && flux_node(D, node_mask(D, j, k), k, qf)) ++cnt;
+          const double qv = side ? p[i].flux_rmax : p[i].flux_rmin;
+          nus[4 * i + side] = cnt ? -qv * p[i].L / cnt : NAN;
+        }
         // residual scales: 1 / (Ma c_s) and 1 / |dT|
         nus[4 * i + 2] = p[i].Ma > 0.0 ? 1.0 / (p[i].Ma * std::sqrt(1.0 / 3.0)) : 1.0;
         nus[4 * i + 3] = dT != 0.0 ? 1.0 / std::fabs(dT) : 1.0;
@@ -1149,6 +1226,56 @@ int lbm_axi_macros(lbm_axi* h, int32_t inst, float* uz, float* ur, float* p, flo
       if (e != hipSuccess) rc = fail(LBM_AXI_EDEVICE, std::string("field download: ") + hipGetErrorString(e));
     }
     for (void* x : tmp) (void)hipFree(x);
+    return rc;
+  });
+}
+
+int lbm_axi_stream_function(lbm_axi* h, int32_t inst, float* psi, double* psi_absmax,
+                            int32_t dst_is_device) {
+  return guarded([&]() -> int {
+    if (!h || inst < 0 || inst >= h->n_inst) return fail(LBM_AXI_EINVAL, "bad handle or instance");
+    int64_t info[4];
+    int rc = lbm_axi_info(h, inst, info);
+    if (rc) return rc;
+    const bool odd = (info[0] & 1) != 0;
+    const lbm_axi_params& q = h->prm[inst];
+    const size_t n = (size_t)q.nr * q.nz;
+    void *duz = nullptr, *dcol = nullptr, *dmax = nullptr, *dpsi = nullptr;
+    auto release_tmp = [&]() {
+      (void)hipStreamSynchronize(h->stream);
+      for (void* x : {duz, dcol, dmax}) (void)hipFree(x);
+      if (!dst_is_device) (void)hipFree(dpsi);
+    };
+    bool ok = hipMalloc(&duz, sizeof(float) * n) == hipSuccess &&
+              hipMalloc(&dcol, sizeof(double) * q.nz) == hipSuccess &&
+              hipMalloc(&dmax, sizeof(double)) == hipSuccess;
+    if (ok && psi) {
+      if (dst_is_device) dpsi = psi;
+      else ok = hipMalloc(&dpsi, sizeof(float) * n) == hipSuccess;
+    }
+    if (!ok) {
+      release_tmp();
+      return fail(LBM_AXI_ENOMEM, "stream function staging");
+    }
+    FieldOut fo{(float*)duz, nullptr, nullptr, nullptr, nullptr};
+    switch (h->storage) {
+      case LBM_STORE_FP32: rc = launch_fields<float>(h, inst, odd, fo); break;
+      case LBM_STORE_FP16: rc = launch_fields<__half>(h, inst, odd, fo); break;
+      default: rc = launch_fields<__hip_bfloat16>(h, inst, odd, fo); break;
+    }
+    if (!rc) {
+      k_psi<<<(q.nz + RB / 64 - 1) / (RB / 64), RB, 0, h->stream>>>((const float*)duz, q.nr, q.nz, q.r0,
+                                                                    (float*)dpsi, (double*)dcol);
+      k_absmax<<<1, RB, 0, h->stream>>>((const double*)dcol, q.nz, (double*)dmax);
+      hipError_t e = hipGetLastError();
+      if (e == hipSuccess && psi && !dst_is_device)
+        e = hipMemcpyAsync(psi, dpsi, sizeof(float) * n, hipMemcpyDeviceToHost, h->stream);
+      if (e == hipSuccess && psi_absmax)
+        e = hipMemcpyAsync(psi_absmax, dmax, sizeof(double), hipMemcpyDeviceToHost, h->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+      if (e != hipSuccess) rc = fail(LBM_AXI_EDEVICE, std::string("stream function: ") + hipGetErrorString(e));
+    }
+    release_tmp();
     return rc;
   });
 }

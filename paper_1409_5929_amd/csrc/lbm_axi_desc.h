@@ -87,6 +87,12 @@ inline int describe(const lbm_axi_params& q, bool field, InstDev& D, std::string
     D.C2 = (float)(1.75 * std::sqrt(kr / (150.0 * Kref)));
     D.C3 = (float)(q.F_phi * std::sqrt(kr / Kref));
   }
+  // Isoflux window: columns k with flux_zlo <= k <= flux_zhi (clamped to the grid).
+  D.q_rmin = (float)q.flux_rmin;
+  D.q_rmax = (float)q.flux_rmax;
+  const double klo = std::ceil(q.flux_zlo), khi = std::floor(q.flux_zhi);
+  D.qk_lo = klo <= 0.0 ? 0 : (klo >= q.nz ? q.nz : (int32_t)klo);
+  D.qk_hi = khi < 0.0 ? -1 : (khi >= q.nz - 1 ? q.nz - 1 : (int32_t)khi);
   int shift = q.storage_shift;
   if (q.storage == LBM_STORE_FP16 && shift == 0) shift = 10;
   D.st_scale = q.storage == LBM_STORE_FP32 ? 1.0f : std::ldexp(1.0f, shift);

@@ -48,7 +48,7 @@
 namespace lbmaxi {
 
 enum { SIDE_WALL = 0, SIDE_AXIS = 1, SIDE_PERIODIC = 2 };
-enum { THERM_FIXED = 0, THERM_ADIABATIC = 1 };
+enum { THERM_FIXED = 0, THERM_ADIABATIC = 1, THERM_FLUX = 2 };
 enum { RUN = 0, CONVERGED = 1, DIVERGED = 2, STALLED = 3 };
 enum { MODE_STEP = 0, MODE_STEP_MACRO = 1, MODE_FIELDS = 2 };
 enum { MASK_RMIN = 1, MASK_RMAX = 2, MASK_ZMIN = 4, MASK_ZMAX = 8, MASK_AXIS = 16 };
@@ -85,6 +85,8 @@ struct InstDev {
   float tau_T, omc;   // omc = 1 / (tau_T + 1/2)
   float T_rmin, T_rmax, T_zmin, T_zmax;
   float st_scale, st_inv;  // storage scale 2^shift and its inverse
+  float q_rmin, q_rmax;    // q'/k of isoflux radial walls
+  int32_t qk_lo, qk_hi;    // heated columns qk_lo..qk_hi of an isoflux wall
 };
 
 // Optional outputs of the field kernel ([nz][nr], unpadded).
@@ -323,6 +325,25 @@ __host__ __device__ inline uint8_t node_mask(const InstDev& D, int j, int k) {
   return m;
 }
 
+// Isoflux wall node (Sec. 4.4): true, with q = q'/k, when wall node (mask m,
+// column k) lies in the heated window of a flux wall and no fixed-temperature
+// wall meets there.
+__host__ __device__ inline bool flux_node(const InstDev& D, uint8_t m, int k, float& q) {
+  if ((m & MASK_RMIN) && D.therm_rmin == THERM_FIXED) return false;
+  if ((m & MASK_RMAX) && D.therm_rmax == THERM_FIXED) return false;
+  if ((m & (MASK_ZMIN | MASK_ZMAX)) && D.therm_z == THERM_FIXED) return false;
+  if (k < D.qk_lo || k > D.qk_hi) return false;
+  if ((m & MASK_RMIN) && D.therm_rmin == THERM_FLUX) {
+    q = D.q_rmin;
+    return true;
+  }
+  if ((m & MASK_RMAX) && D.therm_rmax == THERM_FLUX) {
+    q = D.q_rmax;
+    return true;
+  }
+  return false;
+}
+
 // Porosity, phi nu / K and phi F_phi / sqrt(K) at a node (Eqs. 6, 8).
 // From the porosity value of the node (phi_raw: the field value, or unused
 // when the porosity is uniform).
@@ -452,6 +473,11 @@ __host__ __device__ inline void wall_node(const InstDev& D, const A& P, const No
   else if ((m & MASK_RMAX) && D.therm_rmax == THERM_FIXED) Tb = D.T_rmax;
   else if ((m & MASK_ZMIN) && D.therm_z == THERM_FIXED) Tb = D.T_zmin;
   else if ((m & MASK_ZMAX) && D.therm_z == THERM_FIXED) Tb = D.T_zmax;
+  else {
+    // Isoflux: one-sided difference over the unit spacing to B gives -dT/dn = q'/k.
+    float q;
+    if (flux_node(D, m, kb, q)) Tb = B.T + q;
+  }
 
   if (MODE != MODE_FIELDS) {
     // Flow: m+(b) = m^eq(b) + (I - L)(r_B / r_b) n(B) + (I - L/2) S(b), all / r_b.

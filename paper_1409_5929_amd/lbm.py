@@ -8,7 +8,8 @@ the library is loaded so that both share one HIP runtime.
 
 The entry points mirror ``include/lbm_axi.h``:
   create -> Lattice(...), step -> Lattice.step, macros -> Lattice.fields,
-  residual -> Lattice.residual, info -> Lattice.info, destroy -> Lattice.close.
+  stream_function -> Lattice.stream_function, residual -> Lattice.residual,
+  info -> Lattice.info, destroy -> Lattice.close.
 """
 from __future__ import annotations
 
@@ -21,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm_axi.so")
 
 SIDE = {"wall": 0, "axis": 1, "periodic": 2}
-THERM = {"fixed": 0, "adiabatic": 1}
+THERM = {"fixed": 0, "adiabatic": 1, "flux": 2}
 STORAGE = {"fp32": 0, "fp16": 1, "bf16": 2}
 RUN_STATE = {0: "running", 1: "converged", 2: "diverged", 3: "stalled"}
 
@@ -45,6 +46,8 @@ class Params(ctypes.Structure):
         ("T_rmin", ctypes.c_double), ("T_rmax", ctypes.c_double), ("T_zmin", ctypes.c_double),
         ("T_zmax", ctypes.c_double), ("T_ref", ctypes.c_double), ("T_init", ctypes.c_double),
         ("delta_T", ctypes.c_double), ("tol", ctypes.c_double), ("max_steps", ctypes.c_int64),
+        ("flux_rmin", ctypes.c_double), ("flux_rmax", ctypes.c_double),
+        ("flux_zlo", ctypes.c_double), ("flux_zhi", ctypes.c_double),
     ]
 
 
@@ -108,6 +111,9 @@ def _load():
     lib.lbm_axi_residual.restype = ctypes.c_int
     lib.lbm_axi_info.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_int64)]
     lib.lbm_axi_info.restype = ctypes.c_int
+    lib.lbm_axi_stream_function.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                            P(ctypes.c_double), ctypes.c_int32]
+    lib.lbm_axi_stream_function.restype = ctypes.c_int
     lib.lbm_axi_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32]
     lib.lbm_axi_set_timing.restype = ctypes.c_int
     lib.lbm_axi_kernel_time.argtypes = [ctypes.c_void_p, P(ctypes.c_double), P(ctypes.c_int64)]
@@ -249,6 +255,17 @@ class Lattice:
                                         out["ur"].data_ptr(), out["p"].data_ptr(),
                                         out["T"].data_ptr(), None, 1))
         return out
+
+    def stream_function(self, inst: int = 0, field: bool = True):
+        """Stokes stream function of one instance (lattice units, zero on row 0)
+        as a host [nz, nr] float32 array (None with field=False) and max |psi|."""
+        nz, nr = self.shapes[inst]
+        psi = np.empty((nz, nr), dtype=np.float32) if field else None
+        mx = ctypes.c_double()
+        _check(self._lib.lbm_axi_stream_function(self._h, int(inst),
+                                                 psi.ctypes.data if field else None,
+                                                 ctypes.byref(mx), 0))
+        return psi, mx.value
 
     def residual(self) -> dict:
         n = self.n_inst
