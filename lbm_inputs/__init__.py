@@ -11,7 +11,8 @@ A problem is a plain ``dict`` with these keys (lattice units, spacing 1):
   r0                     radius of row j = 0 (rows sit at r0 + j)
   L                      characteristic length of Eq. (9)
   side_rmin, side_rmax   "wall" | "axis" (r_min only) | "periodic"
-  side_z                 "wall" | "periodic"
+  side_z                 "wall" | "periodic" | "flow" (inlet at z = 0, outlet at z = H)
+  u_in                   inlet axial velocity of side_z = "flow"
   therm_rmin, therm_rmax, therm_z   "fixed" | "adiabatic" | "flux" (radial walls)
   T_rmin, T_rmax, T_zmin, T_zmax    wall temperatures of fixed walls
   flux_rmin, flux_rmax   q'/k of flux walls (a temperature gradient)
@@ -83,6 +84,45 @@ def annulus(nr: int = 256, nz: int = 256, Rstar: float = 2.0, phi: float = 0.6,
 def table2(Ra: float, nr: int = 100, nz: int = 200) -> dict:
     """Annulus without porous medium as in Sec. 4.2 / Table 2 (phi = 1, Da = 1e8)."""
     return annulus(nr=nr, nz=nz, Rstar=2.0, phi=1.0, Da=1e8, Ra=Ra, Pr=0.7, F_phi=0.0)
+
+
+def developing_pipe(Da: float = 1e8, nr: int = 41, A: float = 16.0, Re: float = 100.0,
+                    Pr: float = 0.7, u_in: float = 0.005, phi: float = 1.0, F_phi: float = 0.0,
+                    T_in: float = 0.0, T_w: float = 1.0) -> dict:
+    """Thermally developing flow in a pipe filled with porous medium (Sec. 4.1, Fig. 1).
+
+    Rows are cell-centred about the axis (r0 = 1/2). The wall row nr-1 sits at
+    r_i = nr - 1/2, which is also the length L of Re = L u_in / nu. The paper's
+    "81 x 648" grid with A = H / r_i = 16 gives r_i = 40.5: nr = 41 rows here,
+    i.e. 81 cells across the diameter. The pipe spans H = A r_i with columns at
+    z = 0..H. Column 0 is the inlet (u_z = u_in, T = T_in) and column H the
+    outlet (zero axial gradient). The wall is held at T_w.
+
+    The paper gives no relaxation time for this problem. tau_nu follows from
+    Re and u_in, whose default of 0.005 keeps the Darcy pressure drop at
+    Da = 1e-3 near 1 % of the density. Ma = u_in / c_s makes the inlet
+    velocity the velocity scale of the steady-state residual. With Ra = 0 and
+    tau_nu given, Ma enters nothing else.
+    """
+    R = nr - 0.5
+    H = A * R
+    nz = int(round(H)) + 1
+    nu = u_in * R / Re
+    return dict(nr=nr, nz=nz, r0=0.5, L=R, side_rmin="axis", side_rmax="wall", side_z="flow",
+                therm_rmin="adiabatic", therm_rmax="fixed", therm_z="fixed", T_rmin=0.0,
+                T_rmax=T_w, T_zmin=T_in, T_zmax=0.0, T_ref=0.0, T_init=T_in,
+                delta_T=T_w - T_in, phi=phi, Da=Da, F_phi=F_phi, Ra=0.0, Pr=Pr, J=1.0, lam=1.0,
+                Ma=u_in * math.sqrt(3.0), tau_nu=0.5 + 3.0 * nu, accel_r=0.0, accel_z=0.0,
+                u_in=u_in)
+
+
+def plug_start(cfg: dict) -> np.ndarray:
+    """Start fields (u_z, u_r, T) of a pipe problem: plug flow at u_in, T_init."""
+    nz, nr = cfg["nz"], cfg["nr"]
+    out = np.zeros((3, nz, nr))
+    out[0] = cfg["u_in"]
+    out[2] = cfg["T_init"]
+    return out
 
 
 def heater_annulus(Da: float, nr: int = 200, nz: int = 200, Ra: float = 1e7, Pr: float = 0.7,

@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
-SIDE = {"wall": 0, "axis": 1, "periodic": 2}
+SIDE = {"wall": 0, "axis": 1, "periodic": 2, "flow": 3}
 THERM = {"fixed": 0, "adiabatic": 1, "flux": 2}
 
 
@@ -43,6 +43,7 @@ class _Params(ctypes.Structure):
         ("T_ref", ctypes.c_double), ("T_init", ctypes.c_double), ("delta_T", ctypes.c_double),
         ("flux_rmin", ctypes.c_double), ("flux_rmax", ctypes.c_double),
         ("flux_zlo", ctypes.c_double), ("flux_zhi", ctypes.c_double),
+        ("u_in", ctypes.c_double),
     ]
 
 
@@ -85,6 +86,8 @@ def _load():
     lib.orc_derived.argtypes = [ctypes.c_void_p, d]
     lib.orc_matrices.argtypes = [ctypes.c_void_p, d, d]
     lib.orc_node.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, d, d, d, d, d, d, d]
+    lib.orc_pipe_nusselt.restype = ctypes.c_int
+    lib.orc_pipe_nusselt.argtypes = [ctypes.c_void_p, ctypes.c_int, d, d]
     lib.orc_stream_function.restype = ctypes.c_double
     lib.orc_stream_function.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, d, d]
     lib.orc_last_error.restype = ctypes.c_char_p
@@ -100,7 +103,7 @@ DEFAULTS = dict(
     tau_nu=0.0, accel_r=0.0, accel_z=0.0, s_e=1.1, s_eps=1.1, s_q=1.2, s_j=1.0, s_nu=0.0,
     src_printed=0,
     T_rmin=0.0, T_rmax=0.0, T_zmin=0.0, T_zmax=0.0, T_ref=0.0, T_init=0.0, delta_T=0.0,
-    flux_rmin=0.0, flux_rmax=0.0, flux_zlo=-np.inf, flux_zhi=np.inf,
+    flux_rmin=0.0, flux_rmax=0.0, flux_zlo=-np.inf, flux_zhi=np.inf, u_in=0.0,
 )
 
 
@@ -194,6 +197,15 @@ class Oracle:
         a, b = ctypes.c_double(), ctypes.c_double()
         self._lib.orc_nusselt(self._h, ctypes.byref(a), ctypes.byref(b))
         return a.value, b.value
+
+    def pipe_nusselt(self, area: bool = False):
+        """Local Nusselt number (Eq. 40) and bulk temperature at every column of
+        a pipe (axis at r_min, wall at r_max): mixing-cup T_b, or with
+        area=True the area mean as Eq. (41) is printed."""
+        nu, tb = np.empty(self.nz), np.empty(self.nz)
+        if self._lib.orc_pipe_nusselt(self._h, 1 if area else 0, _dptr(nu), _dptr(tb)) != 0:
+            raise ValueError("pipe Nusselt numbers need an axis at r_min and a wall at r_max")
+        return nu, tb
 
     def populations(self):
         f = np.empty((self.nz, self.nr, 9))

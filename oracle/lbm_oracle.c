@@ -72,6 +72,25 @@
  *      paper takes T_0 = T_o, the cold wall); the heater mean is the plain
  *      average over the heated nodes, each standing for a unit length of
  *      wall (midpoint rule of Eq. 43).
+ *   R12 Inlet and outlet (Sec. 4.1).  With side_z = SIDE_FLOW, column 0 is a
+ *      velocity inlet and column nz-1 an outlet, both reconstructed as in R2
+ *      with their own macroscopic state: the inlet takes u = (0, u_in),
+ *      T = T_zmin (when therm_z is fixed; else B's T) and B's density; the
+ *      outlet takes B's velocity and temperature (zero axial gradient, as the
+ *      paper states) and rho = rho_0 = 1 (the paper leaves the pressure level
+ *      open; fixing it at the outlet is the usual choice).  Radial walls win
+ *      at the corners (no slip, and their temperature when fixed).
+ *   R13 Pipe Nusselt number (Eqs. 40-41) at each column: D (dT/dr)_w /
+ *      (T_w - T_b) with D = 2 r_w and the second-order one-sided gradient of
+ *      Eq. (42) on the r_max wall.  The paper calls T_b the bulk temperature,
+ *      and its clear-pipe value is the textbook 3.657, which holds for the
+ *      mixing-cup temperature T_b = int r u_z T dr / int r u_z dr.  The
+ *      printed Eq. (41) lacks the u_z weight: with it, the fully developed
+ *      clear pipe gives about 5.6 instead.  So T_b is the mixing-cup value by
+ *      default; the printed area mean int r T dr / int r dr is available as
+ *      the other weighting.  Both integrals run from the axis to the wall by
+ *      the trapezoid rule over the rows plus the point r = 0 (where the
+ *      integrand vanishes).
  *   R11 Stream function (Table 3; not defined in the paper).  The Stokes
  *      stream function of the axisymmetric flow, u_z = (1/r) dpsi/dr and
  *      u_r = -(1/r) dpsi/dz, zero on the r_min wall:
@@ -109,7 +128,7 @@ static const double MM[9][9] = {
     {0, 0, -2, 0, 2, 1, 1, -1, -1},      {0, 1, -1, 1, -1, 0, 0, 0, 0},
     {0, 0, 0, 0, 0, 1, -1, 1, -1}};
 
-enum { SIDE_WALL = 0, SIDE_AXIS = 1, SIDE_PERIODIC = 2 };
+enum { SIDE_WALL = 0, SIDE_AXIS = 1, SIDE_PERIODIC = 2, SIDE_FLOW = 3 };
 enum { THERM_FIXED = 0, THERM_ADIABATIC = 1, THERM_FLUX = 2 };
 enum { MASK_RMIN = 1, MASK_RMAX = 2, MASK_ZMIN = 4, MASK_ZMAX = 8, MASK_AXISROW = 16 };
 
@@ -134,6 +153,7 @@ typedef struct {
   double delta_T;  /* characteristic temperature difference; 0 = T_rmin - T_rmax */
   double flux_rmin, flux_rmax; /* q'/k of THERM_FLUX radial walls (R9) */
   double flux_zlo, flux_zhi;   /* heated window of a flux wall, z = k */
+  double u_in;                 /* inlet axial velocity of SIDE_FLOW (R12) */
 } orc_params;
 
 typedef struct {
@@ -316,8 +336,9 @@ static uint8_t node_mask(const orc_params* p, int j, int k) {
   uint8_t m = 0;
   if (p->side_rmin == SIDE_WALL && j == 0) m |= MASK_RMIN;
   if (p->side_rmax == SIDE_WALL && j == p->nr - 1) m |= MASK_RMAX;
-  if (p->side_z == SIDE_WALL && k == 0) m |= MASK_ZMIN;
-  if (p->side_z == SIDE_WALL && k == p->nz - 1) m |= MASK_ZMAX;
+  const int zb = p->side_z == SIDE_WALL || p->side_z == SIDE_FLOW;
+  if (zb && k == 0) m |= MASK_ZMIN;
+  if (zb && k == p->nz - 1) m |= MASK_ZMAX;
   if (p->side_rmin == SIDE_AXIS && j == 0) m |= MASK_AXISROW;
   return m;
 }
@@ -348,9 +369,18 @@ static double wall_temperature(const orc_params* p, uint8_t m, int k, double T_o
   if ((m & MASK_RMIN) && p->therm_rmin == THERM_FIXED) return p->T_rmin;
   if ((m & MASK_RMAX) && p->therm_rmax == THERM_FIXED) return p->T_rmax;
   if ((m & MASK_ZMIN) && p->therm_z == THERM_FIXED) return p->T_zmin;
-  if ((m & MASK_ZMAX) && p->therm_z == THERM_FIXED) return p->T_zmax;
+  if ((m & MASK_ZMAX) && p->therm_z == THERM_FIXED && p->side_z != SIDE_FLOW) return p->T_zmax;
   if (flux_node(p, m, k, &q)) return T_owner + q * 1.0; /* q'/k times the spacing to B */
-  return T_owner;
+  return T_owner;                                       /* adiabatic wall, outlet (R12) */
+}
+
+/* Density and velocity of a boundary node (R2, R12) from its owner's values. */
+static void boundary_flow(const orc_params* p, uint8_t m, double rho_B, double ur_B, double uz_B,
+                          double* rho, double* ur, double* uz) {
+  *rho = rho_B; *ur = 0.0; *uz = 0.0;  /* no-slip wall, and every corner with a radial wall */
+  if (p->side_z != SIDE_FLOW || (m & (MASK_RMIN | MASK_RMAX))) return;
+  if (m & MASK_ZMIN) { *uz = p->u_in; return; }         /* inlet */
+  *rho = 1.0; *ur = ur_B; *uz = uz_B;                   /* outlet */
 }
 
 /* ---- state ---------------------------------------------------------------- */
@@ -418,6 +448,10 @@ orc_state* orc_create(const orc_params* p, const double* phi_field, const double
   }
   if (!(p->r0 > 0.0)) { g_err = "r0 must be positive"; return NULL; }
   if (p->therm_z == THERM_FLUX) { g_err = "flux walls are radial only"; return NULL; }
+  if (p->side_rmin == SIDE_FLOW || p->side_rmax == SIDE_FLOW) {
+    g_err = "inlet and outlet are axial only"; return NULL;
+  }
+  if (p->side_z == SIDE_FLOW && nz < 3) { g_err = "inlet and outlet need nz >= 3"; return NULL; }
   orc_state* s = (orc_state*)calloc(1, sizeof(orc_state));
   s->p = *p;
   if (derive(s) != 0) { free(s); return NULL; }
@@ -490,9 +524,8 @@ static void compute_all_macros(orc_state* s) {
       int jb, kb;
       owner_of(&s->p, m, j, k, &jb, &kb);
       int ib = kb * nr + jb;
-      s->rho[idx] = s->rho[ib];
-      s->ur[idx] = 0.0;
-      s->uz[idx] = 0.0;
+      boundary_flow(&s->p, m, s->rho[ib], s->ur[ib], s->uz[ib], &s->rho[idx], &s->ur[idx],
+                    &s->uz[idx]);
       s->T[idx] = wall_temperature(&s->p, m, k, s->T[ib]);
     }
 }
@@ -519,20 +552,21 @@ static void collide_all(orc_state* s) {
       owner_of(&s->p, m, j, k, &jb, &kb);
       int ib = kb * nr + jb;
       double rB = s->r[jb];
-      double rho = s->rho[ib], Tb = s->T[idx];
+      /* boundary state (R2, R9, R12), set by compute_all_macros */
+      double rho = s->rho[idx], urb = s->ur[idx], uzb = s->uz[idx], Tb = s->T[idx];
       double meqb[9], feqb[9], meqB[9], feqB[9], fb[9], gb[5];
-      eq_moments(r, rho, 0.0, 0.0, phi, meqb);
+      eq_moments(r, rho, urb, uzb, phi, meqb);
       matvec9(s->Minv, meqb, feqb);
       eq_moments(rB, s->rho[ib], s->ur[ib], s->uz[ib], s->phi[ib], meqB);
       matvec9(s->Minv, meqB, feqB);
       for (int i = 0; i < 9; ++i) fb[i] = feqb[i] + (s->f[9 * ib + i] - feqB[i]);
       for (int i = 0; i < 5; ++i)
-        gb[i] = g_eq(i, Tb, 0.0, 0.0) +
+        gb[i] = g_eq(i, Tb, urb, uzb) +
                 (s->g[5 * ib + i] - g_eq(i, s->T[ib], s->ur[ib], s->uz[ib]));
       double Fr, Fz, ar;
-      total_force(s, r, phi, K, Fphi, 0.0, 0.0, Tb, &Fr, &Fz, &ar);
-      mrt_collide(s, r, phi, rho, 0.0, 0.0, Fr, Fz, ar, fb, s->fp + 9 * idx);
-      thermal_collide(s, r, Tb, 0.0, 0.0, gb, s->gp + 5 * idx);
+      total_force(s, r, phi, K, Fphi, urb, uzb, Tb, &Fr, &Fz, &ar);
+      mrt_collide(s, r, phi, rho, urb, uzb, Fr, Fz, ar, fb, s->fp + 9 * idx);
+      thermal_collide(s, r, Tb, urb, uzb, gb, s->gp + 5 * idx);
     }
 }
 
@@ -683,6 +717,35 @@ void orc_nusselt(const orc_state* s, double* nu_i, double* nu_o) {
     double nu = cnt ? sum / cnt : NAN;          /* Eq. (43) */
     if (side) *nu_o = nu; else *nu_i = nu;
   }
+}
+
+/*
+ * Local pipe Nusselt number and bulk temperature at every column (R13,
+ * Eqs. 40-41): area = 0 takes the mixing-cup T_b, area = 1 the area mean as
+ * printed.  Needs an axis at r_min and a wall at r_max; returns -1 otherwise.
+ */
+int orc_pipe_nusselt(const orc_state* s, int area, double* nu, double* Tb) {
+  const int nr = s->nr, nz = s->nz;
+  if (s->p.side_rmin != SIDE_AXIS || s->p.side_rmax != SIDE_WALL || nr < 3) return -1;
+  const double rw = s->r[nr - 1], D = 2.0 * rw;
+  for (int k = 0; k < nz; ++k) {
+    const double* T = s->T + (long)k * nr;
+    const double* u = s->uz + (long)k * nr;
+    double num = 0.0, den = 0.0;
+    for (int j = 0; j < nr; ++j) {
+      /* trapezoid weights over 0, r_0, ..., r_{nr-1}: the first interval
+         [0, r_0] adds r_0 / 2 to node 0, each later interval 1/2 to both ends */
+      double w = (j == 0 ? 0.5 * s->r[0] : 0.5) + (j < nr - 1 ? 0.5 : 0.0);
+      double wu = area ? w : w * u[j];
+      num += wu * s->r[j] * T[j];
+      den += wu * s->r[j];
+    }
+    double tb = num / den;                                          /* Eq. (41) */
+    double g = (3.0 * T[nr - 1] - 4.0 * T[nr - 2] + T[nr - 3]) / 2.0;
+    if (Tb) Tb[k] = tb;
+    if (nu) nu[k] = D * g / (T[nr - 1] - tb);                      /* Eq. (40) */
+  }
+  return 0;
 }
 
 /*
