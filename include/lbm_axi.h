@@ -62,10 +62,19 @@ enum lbm_axi_error {
   LBM_AXI_EUNSUPPORTED = -4  /* a parameter value the model does not define */
 };
 
+/*
+ * LBM_SIDE_FLOW (side_z only) makes column 0 a velocity inlet and column
+ * nz-1 an outlet (Sec. 4.1), both reconstructed like walls: the inlet node
+ * takes u = (u_r, u_z) = (0, u_in), T = T_zmin when therm_z is fixed (else its
+ * neighbour's T) and its neighbour's density; the outlet node takes its
+ * neighbour's u and T (zero axial gradient) and rho = rho_0 = 1, which fixes
+ * the pressure level the paper leaves open.  Radial walls win at corners.
+ */
 enum lbm_axi_side {
   LBM_SIDE_WALL = 0,     /* no-slip wall, nodes on the wall */
   LBM_SIDE_AXIS = 1,     /* axis of symmetry; r_min only */
-  LBM_SIDE_PERIODIC = 2  /* periodic; along r only for tests (both r sides) */
+  LBM_SIDE_PERIODIC = 2, /* periodic; along r only for tests (both r sides) */
+  LBM_SIDE_FLOW = 3      /* z only: inlet at z_min, outlet at z_max */
 };
 
 /*
@@ -126,6 +135,7 @@ typedef struct lbm_axi_params {
   int64_t max_steps;           /* stall after this many steps (0: never) */
   double flux_rmin, flux_rmax; /* q'/k of LBM_T_FLUX walls (temperature per lattice unit) */
   double flux_zlo, flux_zhi;   /* heated window of LBM_T_FLUX walls in z (default: all) */
+  double u_in;                 /* inlet axial velocity with side_z = LBM_SIDE_FLOW */
 } lbm_axi_params;
 
 /* Fill *p with the paper's default rates and ratios; grid and physics zero. */
@@ -178,6 +188,22 @@ int lbm_axi_macros(lbm_axi* h, int32_t inst, float* uz, float* ur, float* p, flo
  */
 int lbm_axi_stream_function(lbm_axi* h, int32_t inst, float* psi, double* psi_absmax,
                             int32_t dst_is_device);
+
+/*
+ * Local Nusselt number along the wall of a pipe (axis at r_min, wall at
+ * r_max), Sec. 4.1: at each column k, Nu = D (dT/dr)_w / (T_w - T_b) (Eq. 40)
+ * with D = 2 r_w and the second-order one-sided wall gradient.  T_b is the
+ * bulk temperature: with area = 0 the mixing-cup value
+ * int r u_z T dr / int r u_z dr (the bulk temperature of the textbook pipe
+ * Nusselt numbers the paper's Table 1 reproduces), with area = 1 the area
+ * mean int r T dr / int r dr as Eq. (41) is printed; the integrals run from
+ * the axis to the wall by the trapezoid rule over the rows plus the point
+ * r = 0.  FP64 sums of the FP32 fields at the instance's current time.  nu
+ * and T_b are host arrays of nz doubles (each may be NULL).  Allocates
+ * temporary device memory and waits for the stream.  LBM_AXI_EINVAL unless
+ * the instance is a pipe.
+ */
+int lbm_axi_pipe_nusselt(lbm_axi* h, int32_t inst, int32_t area, double* nu, double* T_b);
 
 /*
  * Latest check of every instance (waits for the stream).  Each pointer may be

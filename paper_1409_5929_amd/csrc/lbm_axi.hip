@@ -11,6 +11,7 @@
 //   k_convert  storage conversion (FP32 / FP16 / BF16) of one instance
 //   k_setclock device clock read by captured step graphs
 //   k_psi, k_absmax  Stokes stream function of one instance and its largest magnitude
+//   k_pipe_nu  local pipe Nusselt number and bulk temperature of one instance
 //   k_step<MODE_FIELDS>  macroscopic fields of one instance (no population writes)
 //
 // Launch geometry: blocks of 64 x 4 threads; lanes run along r (coalesced
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(BX* BY) void k_step(const InstDev* __restrict__ des
   if (j >= D.nr) return;
   if ((D.side_rmin == SIDE_WALL && j == 0) || (D.side_rmax == SIDE_WALL && j == D.nr - 1)) return;
   const RowC R = make_row(D, j);
-  const bool zwall = D.side_z == SIDE_WALL;
+  const bool zwall = z_bounded(D);
   // Fluid nodes of this thread's strip: k = kbeg, kbeg + BY, ... < kend.
   const int k0 = tl.z + (int)threadIdx.y;
   int kbeg = k0, kend = min(k0 + BY * kz, D.nz);
@@ -380,6 +381,43 @@ __global__ __launch_bounds__(RB) void k_psi(const float* __restrict__ uz, int nr
   if (lane == 0) colmax[k] = mx;
 }
 
+// Local pipe Nusselt number (Eq. 40) and bulk temperature of one column per
+// wave, in FP64 from the FP32 fields [nz][nr] (rows at r0 + j, wall row
+// nr-1): T_b = sum v_j r_j T_j / sum v_j r_j with v_j = w_j u_z,j (mixing cup)
+// or v_j = w_j (area mean, Eq. 41 as printed) and the trapezoid weights w_j
+// over the points 0, r_0, ..., r_{nr-1} (the integrands vanish on the axis);
+// Nu = 2 r_w (dT/dr)_w / (T_w - T_b) with the second-order one-sided wall
+// gradient.
+__global__ __launch_bounds__(RB) void k_pipe_nu(const float* __restrict__ T,
+                                                const float* __restrict__ U, int area, int nr,
+                                                int nz, double r0, double* __restrict__ nu,
+                                                double* __restrict__ tb) {
+  const int lane = threadIdx.x & 63;
+  const int k = blockIdx.x * (RB / 64) + (threadIdx.x >> 6);
+  if (k >= nz) return;  // whole waves leave together
+  const float* t = T + (int64_t)k * nr;
+  const float* u = U + (int64_t)k * nr;
+  double num = 0.0, den = 0.0;
+  for (int j = lane; j < nr; j += 64) {
+    const double r = r0 + j;
+    double w = (j == 0 ? 0.5 * r0 : 0.5) + (j < nr - 1 ? 0.5 : 0.0);
+    if (!area) w *= (double)u[j];
+    num += w * r * (double)t[j];
+    den += w * r;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    num += __shfl_xor(num, off, 64);
+    den += __shfl_xor(den, off, 64);
+  }
+  if (lane == 0) {
+    const double b = num / den;
+    const double tw = t[nr - 1];
+    const double g = (3.0 * tw - 4.0 * (double)t[nr - 2] + (double)t[nr - 3]) * 0.5;
+    tb[k] = b;
+    nu[k] = 2.0 * (r0 + (nr - 1)) * g / (tw - b);
+  }
+}
+
 // out[0] = max of colmax[0..n) (one block).
 __global__ __launch_bounds__(RB) void k_absmax(const double* __restrict__ colmax, int n,
                                                double* __restrict__ out) {
@@ -402,18 +440,17 @@ namespace {
 int validate(const lbm_axi_params& p, int i) {
   const std::string pre = "instance " + std::to_string(i) + ": ";
   if (p.side_rmin < 0 || p.side_rmin > 2 || p.side_rmax < 0 || p.side_rmax > 2 || p.side_z < 0 ||
-      p.side_z > 2)
-    return fail(LBM_AXI_EINVAL, pre + "side code out of range");
+      p.side_z > 3)
+    return fail(LBM_AXI_EINVAL, pre + "side code out of range (inlet/outlet along z only)");
   if (p.side_z == SIDE_AXIS) return fail(LBM_AXI_EINVAL, pre + "the z sides cannot be an axis");
   if (p.side_rmax == SIDE_AXIS) return fail(LBM_AXI_EINVAL, pre + "the axis can only be at r_min");
   if ((p.side_rmin == SIDE_PERIODIC) != (p.side_rmax == SIDE_PERIODIC))
     return fail(LBM_AXI_EINVAL, pre + "radial periodicity needs both r sides periodic");
   if (p.side_rmin == SIDE_AXIS && p.r0 != 0.5)
     return fail(LBM_AXI_EINVAL, pre + "an axis needs r0 = 1/2 (cell-centred rows)");
-  if (p.side_rmin == SIDE_AXIS && p.side_z == SIDE_WALL)
-    return fail(LBM_AXI_EUNSUPPORTED, pre + "axis together with axial walls is not supported");
-  if (p.nr < 3 || p.nz < 1 || (p.side_z == SIDE_WALL && p.nz < 3))
-    return fail(LBM_AXI_EINVAL, pre + "grid too small (nr >= 3, nz >= 3 with axial walls)");
+  if (p.nr < 3 || p.nz < 1 || ((p.side_z == SIDE_WALL || p.side_z == SIDE_FLOW) && p.nz < 3))
+    return fail(LBM_AXI_EINVAL, pre + "grid too small (nr >= 3, nz >= 3 with axial boundaries)");
+  if (!std::isfinite(p.u_in)) return fail(LBM_AXI_EINVAL, pre + "u_in must be finite");
   if ((int64_t)p.nr * p.nz > (int64_t)1 << 31)
     return fail(LBM_AXI_EINVAL, pre + "grid larger than 2^31 nodes");
   if (!(p.r0 > 0.0)) return fail(LBM_AXI_EINVAL, pre + "r0 must be positive");
@@ -1274,6 +1311,50 @@ int lbm_axi_stream_function(lbm_axi* h, int32_t inst, float* psi, double* psi_ab
         e = hipMemcpyAsync(psi_absmax, dmax, sizeof(double), hipMemcpyDeviceToHost, h->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
       if (e != hipSuccess) rc = fail(LBM_AXI_EDEVICE, std::string("stream function: ") + hipGetErrorString(e));
+    }
+    release_tmp();
+    return rc;
+  });
+}
+
+int lbm_axi_pipe_nusselt(lbm_axi* h, int32_t inst, int32_t area, double* nu, double* T_b) {
+  return guarded([&]() -> int {
+    if (!h || inst < 0 || inst >= h->n_inst) return fail(LBM_AXI_EINVAL, "bad handle or instance");
+    const lbm_axi_params& q = h->prm[inst];
+    if (q.side_rmin != LBM_SIDE_AXIS || q.side_rmax != LBM_SIDE_WALL)
+      return fail(LBM_AXI_EINVAL, "pipe Nusselt numbers need an axis at r_min and a wall at r_max");
+    int64_t info[4];
+    int rc = lbm_axi_info(h, inst, info);
+    if (rc) return rc;
+    const bool odd = (info[0] & 1) != 0;
+    const size_t n = (size_t)q.nr * q.nz;
+    void *dT = nullptr, *dU = nullptr, *dnu = nullptr, *dtb = nullptr;
+    auto release_tmp = [&]() {
+      (void)hipStreamSynchronize(h->stream);
+      for (void* x : {dT, dU, dnu, dtb}) (void)hipFree(x);
+    };
+    if (hipMalloc(&dT, sizeof(float) * n) != hipSuccess || hipMalloc(&dU, sizeof(float) * n) != hipSuccess ||
+        hipMalloc(&dnu, sizeof(double) * q.nz) != hipSuccess ||
+        hipMalloc(&dtb, sizeof(double) * q.nz) != hipSuccess) {
+      release_tmp();
+      return fail(LBM_AXI_ENOMEM, "pipe Nusselt staging");
+    }
+    FieldOut fo{(float*)dU, nullptr, nullptr, (float*)dT, nullptr};
+    switch (h->storage) {
+      case LBM_STORE_FP32: rc = launch_fields<float>(h, inst, odd, fo); break;
+      case LBM_STORE_FP16: rc = launch_fields<__half>(h, inst, odd, fo); break;
+      default: rc = launch_fields<__hip_bfloat16>(h, inst, odd, fo); break;
+    }
+    if (!rc) {
+      k_pipe_nu<<<(q.nz + RB / 64 - 1) / (RB / 64), RB, 0, h->stream>>>(
+          (const float*)dT, (const float*)dU, area ? 1 : 0, q.nr, q.nz, q.r0, (double*)dnu, (double*)dtb);
+      hipError_t e = hipGetLastError();
+      if (e == hipSuccess && nu)
+        e = hipMemcpyAsync(nu, dnu, sizeof(double) * q.nz, hipMemcpyDeviceToHost, h->stream);
+      if (e == hipSuccess && T_b)
+        e = hipMemcpyAsync(T_b, dtb, sizeof(double) * q.nz, hipMemcpyDeviceToHost, h->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+      if (e != hipSuccess) rc = fail(LBM_AXI_EDEVICE, std::string("pipe Nusselt: ") + hipGetErrorString(e));
     }
     release_tmp();
     return rc;

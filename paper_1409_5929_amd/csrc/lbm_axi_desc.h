@@ -93,6 +93,7 @@ inline int describe(const lbm_axi_params& q, bool field, InstDev& D, std::string
   const double klo = std::ceil(q.flux_zlo), khi = std::floor(q.flux_zhi);
   D.qk_lo = klo <= 0.0 ? 0 : (klo >= q.nz ? q.nz : (int32_t)klo);
   D.qk_hi = khi < 0.0 ? -1 : (khi >= q.nz - 1 ? q.nz - 1 : (int32_t)khi);
+  D.u_in = (float)q.u_in;
   int shift = q.storage_shift;
   if (q.storage == LBM_STORE_FP16 && shift == 0) shift = 10;
   D.st_scale = q.storage == LBM_STORE_FP32 ? 1.0f : std::ldexp(1.0f, shift);

@@ -47,7 +47,7 @@
 
 namespace lbmaxi {
 
-enum { SIDE_WALL = 0, SIDE_AXIS = 1, SIDE_PERIODIC = 2 };
+enum { SIDE_WALL = 0, SIDE_AXIS = 1, SIDE_PERIODIC = 2, SIDE_FLOW = 3 };
 enum { THERM_FIXED = 0, THERM_ADIABATIC = 1, THERM_FLUX = 2 };
 enum { RUN = 0, CONVERGED = 1, DIVERGED = 2, STALLED = 3 };
 enum { MODE_STEP = 0, MODE_STEP_MACRO = 1, MODE_FIELDS = 2 };
@@ -87,6 +87,7 @@ struct InstDev {
   float st_scale, st_inv;  // storage scale 2^shift and its inverse
   float q_rmin, q_rmax;    // q'/k of isoflux radial walls
   int32_t qk_lo, qk_hi;    // heated columns qk_lo..qk_hi of an isoflux wall
+  float u_in;              // inlet axial velocity with inlet/outlet columns
 };
 
 // Optional outputs of the field kernel ([nz][nr], unpadded).
@@ -310,17 +311,22 @@ __host__ __device__ inline RowC make_row(const InstDev& D, int j) {
   return R;
 }
 
+// Columns 0 and nz-1 are boundary nodes: no-slip walls, or inlet and outlet.
+__host__ __device__ inline bool z_bounded(const InstDev& D) {
+  return D.side_z == SIDE_WALL || D.side_z == SIDE_FLOW;
+}
+
 __host__ __device__ inline bool is_boundary(const InstDev& D, int j, int k) {
   return (D.side_rmin == SIDE_WALL && j == 0) || (D.side_rmax == SIDE_WALL && j == D.nr - 1) ||
-         (D.side_z == SIDE_WALL && (k == 0 || k == D.nz - 1));
+         (z_bounded(D) && (k == 0 || k == D.nz - 1));
 }
 
 __host__ __device__ inline uint8_t node_mask(const InstDev& D, int j, int k) {
   uint8_t m = 0;
   if (D.side_rmin == SIDE_WALL && j == 0) m |= MASK_RMIN;
   if (D.side_rmax == SIDE_WALL && j == D.nr - 1) m |= MASK_RMAX;
-  if (D.side_z == SIDE_WALL && k == 0) m |= MASK_ZMIN;
-  if (D.side_z == SIDE_WALL && k == D.nz - 1) m |= MASK_ZMAX;
+  if (z_bounded(D) && k == 0) m |= MASK_ZMIN;
+  if (z_bounded(D) && k == D.nz - 1) m |= MASK_ZMAX;
   if (D.side_rmin == SIDE_AXIS && j == 0) m |= MASK_AXIS;
   return m;
 }
@@ -437,27 +443,42 @@ __host__ __device__ inline void store_wall(const InstDev& D, const A& P, int jb,
   constexpr int EXr[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
   constexpr int EZr[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
   constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+  constexpr int MIR[9] = {0, 3, 2, 1, 4, 6, 5, 8, 7};  // e_r reversed
   const int64_t pl = D.plane;
+  // A population that leaves row 0 towards an axis lands in the mirror row,
+  // whose slot i is slot i* of row 0: the boundary nodes of row 0 feed the
+  // fluid nodes of row 0 through it.
   for (int i = 1; i < 9; ++i) {
-    int kd = kb + EZr[i];
-    if (!fluid_dest(D, jb + EXr[i], kd)) continue;
+    int jd = jb + EXr[i], kd = kb + EZr[i], slot = i;
+    if (jd < 0 && D.side_rmin == SIDE_AXIS) {
+      jd = 0;
+      slot = MIR[i];
+    }
+    if (!fluid_dest(D, jd, kd)) continue;
     if (ODD)
-      P.st(i * pl + (int64_t)kd * D.stride + jb + EXr[i], d[i], rn.next());
+      P.st(slot * pl + (int64_t)kd * D.stride + jd, d[i], rn.next());
     else
       P.st(OPP[i] * pl + (int64_t)kb * D.stride + jb, d[i], rn.next());
   }
   for (int i = 1; i < 5; ++i) {
-    int kd = kb + EZr[i];
-    if (!fluid_dest(D, jb + EXr[i], kd)) continue;
+    int jd = jb + EXr[i], kd = kb + EZr[i], slot = i;
+    if (jd < 0 && D.side_rmin == SIDE_AXIS) {
+      jd = 0;
+      slot = MIR[i];
+    }
+    if (!fluid_dest(D, jd, kd)) continue;
     if (ODD)
-      P.st((9 + i) * pl + (int64_t)kd * D.stride + jb + EXr[i], tg[i], rn.next());
+      P.st((9 + slot) * pl + (int64_t)kd * D.stride + jd, tg[i], rn.next());
     else
       P.st((9 + OPP[i]) * pl + (int64_t)kb * D.stride + jb, tg[i], rn.next());
   }
 }
 
-// Wall node b = x + (dr, dz) owned by fluid node x (non-equilibrium
-// extrapolation, Sec. 4): imposed rho_B, u = 0, wall temperature.
+// Boundary node b = x + (dr, dz) owned by fluid node x (non-equilibrium
+// extrapolation, Sec. 4) with its own macroscopic state: no-slip walls take
+// rho_B, u = 0 and the wall temperature; with inlet/outlet columns (Sec. 4.1)
+// the inlet takes rho_B, u = (0, u_in) and the inlet temperature, the outlet
+// rho = 1 and B's u and T.  Radial walls win at corners.
 template <typename S, bool ODD, int MODE, typename A>
 __host__ __device__ inline void wall_node(const InstDev& D, const A& P, const NodeState& B, float rB,
                                           int j, int k, int dr, int dz, int mac_slot,
@@ -466,13 +487,25 @@ __host__ __device__ inline void wall_node(const InstDev& D, const A& P, const No
   const float rb = rB + (float)dr;
   const float inv_rb = 1.0f / rb;
   const int64_t ob = (int64_t)kb * D.stride + jb;
-  const float phib = D.phi_mode == 0 ? D.phiu : D.phi[ob];
+  float phib, cDb, cFb;
+  porosity_of(D, D.phi_mode == 0 ? 0.0f : D.phi[ob], phib, cDb, cFb);
   const uint8_t m = node_mask(D, jb, kb);
+  float drho = B.drho, urb = 0.0f, uzb = 0.0f;
+  if (D.side_z == SIDE_FLOW && !(m & (MASK_RMIN | MASK_RMAX))) {
+    if (m & MASK_ZMIN) {
+      uzb = D.u_in;
+    } else {
+      drho = 0.0f;  // outlet: rho = rho_0 = 1
+      urb = B.ur;
+      uzb = B.uz;
+    }
+  }
+  const float rhob = 1.0f + drho;
   float Tb = B.T;
   if ((m & MASK_RMIN) && D.therm_rmin == THERM_FIXED) Tb = D.T_rmin;
   else if ((m & MASK_RMAX) && D.therm_rmax == THERM_FIXED) Tb = D.T_rmax;
   else if ((m & MASK_ZMIN) && D.therm_z == THERM_FIXED) Tb = D.T_zmin;
-  else if ((m & MASK_ZMAX) && D.therm_z == THERM_FIXED) Tb = D.T_zmax;
+  else if ((m & MASK_ZMAX) && D.therm_z == THERM_FIXED && D.side_z != SIDE_FLOW) Tb = D.T_zmax;
   else {
     // Isoflux: one-sided difference over the unit spacing to B gives -dT/dn = q'/k.
     float q;
@@ -480,48 +513,62 @@ __host__ __device__ inline void wall_node(const InstDev& D, const A& P, const No
   }
 
   if (MODE != MODE_FIELDS) {
-    // Flow: m+(b) = m^eq(b) + (I - L)(r_B / r_b) n(B) + (I - L/2) S(b), all / r_b.
+    // Flow: m+(b) = m^eq(b) + (I - L)(r_B / r_b) n(B) + (I - L/2) S(b), all / r_b,
+    // as deviations from the quiescent post-collision moments
+    // (1, -2, 1, c_s^2 / (2 r_b), -c_s^2 / (2 r_b), 0, 0, 0, 0).
+    const float iphib = 1.0f / phib;
     const float Gz = D.gbeta * (Tb - D.T_ref) + D.accel_z;
-    const float Frb = phib * D.accel_r, Fzb = phib * Gz;
-    const float S3 = B.rho * (Frb + CS2 * inv_rb), S5 = B.rho * Fzb;
+    const float drag = cDb + cFb * sqrtf(urb * urb + uzb * uzb);
+    const float Frb = phib * D.accel_r - drag * urb, Fzb = phib * Gz - drag * uzb;
+    const float arb = CS2 * inv_rb - 2.0f * D.c_tau * urb * inv_rb * inv_rb;  // Eq. (25)
+    float S1, S7, S8;
+    source(D.src_printed != 0, rhob, urb, uzb, iphib, Frb, Fzb, arb, S1, S7, S8);
+    const float S3 = rhob * (Frb + arb), S5 = rhob * Fzb;
+    const float ru2 = 3.0f * rhob * (urb * urb + uzb * uzb) * iphib;
     const float q = rB * inv_rb;
-    const float hb = 0.5f * CS2 * inv_rb;  // quiescent reference: moment 3 +hb, moment 4 -hb
+    const float hb = 0.5f * CS2 * inv_rb;
     float d[9];
-    d[0] = W0 * B.drho;
-    d[1] = d[2] = d[3] = d[4] = W1 * B.drho;
-    d[5] = d[6] = d[7] = d[8] = W5 * B.drho;
-    back_transform(d, (1.0f - D.s_e) * q * B.n1, (1.0f - D.s_eps) * q * B.n2,
-                   (1.0f - D.s_j) * q * B.n3 + (1.0f - 0.5f * D.s_j) * S3 - hb,
-                   (1.0f - D.s_q) * q * B.n4 - (1.0f - 0.5f * D.s_q) * S3 + hb,
-                   (1.0f - D.s_j) * q * B.n5 + (1.0f - 0.5f * D.s_j) * S5,
-                   (1.0f - D.s_q) * q * B.n6 - (1.0f - 0.5f * D.s_q) * S5,
-                   (1.0f - D.s_nu) * q * B.n7, (1.0f - D.s_nu) * q * B.n8);
-    // Temperature: g+(b) = g^eq(T_b, 0) + (1 - omega_i(r_b)) g^neq(B).
+    d[0] = W0 * drho;
+    d[1] = d[2] = d[3] = d[4] = W1 * drho;
+    d[5] = d[6] = d[7] = d[8] = W5 * drho;
+    back_transform(d, ru2 + (1.0f - D.s_e) * q * B.n1 + (1.0f - 0.5f * D.s_e) * S1,
+                   -ru2 + (1.0f - D.s_eps) * q * B.n2 - (1.0f - 0.5f * D.s_eps) * S1,
+                   rhob * urb + (1.0f - D.s_j) * q * B.n3 + (1.0f - 0.5f * D.s_j) * S3 - hb,
+                   -rhob * urb + (1.0f - D.s_q) * q * B.n4 - (1.0f - 0.5f * D.s_q) * S3 + hb,
+                   rhob * uzb + (1.0f - D.s_j) * q * B.n5 + (1.0f - 0.5f * D.s_j) * S5,
+                   -rhob * uzb + (1.0f - D.s_q) * q * B.n6 - (1.0f - 0.5f * D.s_q) * S5,
+                   rhob * (urb * urb - uzb * uzb) * iphib + (1.0f - D.s_nu) * q * B.n7 +
+                       (1.0f - 0.5f * D.s_nu) * S7,
+                   rhob * urb * uzb * iphib + (1.0f - D.s_nu) * q * B.n8 + (1.0f - 0.5f * D.s_nu) * S8);
+    // Temperature: g+(b) = g^eq(T_b, u_b) + (1 - omega_i(r_b)) g^neq(B) + psi_i(b).
     const float eu[5] = {0.0f, B.ur, B.uz, -B.ur, -B.uz};
+    const float eb[5] = {0.0f, urb, uzb, -urb, -uzb};
     const float wt[5] = {WT0, WT1, WT1, WT1, WT1};
     const float tb1 = D.tau_T * inv_rb;
     const float om[5] = {D.omc, D.omc * (1.0f + tb1), D.omc, D.omc * (1.0f - tb1), D.omc};
+    const float psib = -urb * inv_rb;
     float tg[5];
     float qn[5];
     for (int i = 1; i < 5; ++i) qn[i] = B.t[i] - wt[i] * B.theta;
     qn[0] = -((qn[1] + qn[3]) + (qn[2] + qn[4]));
     for (int i = 0; i < 5; ++i) {
       const float gneq = qn[i] - 5.0f * wt[i] * B.T * eu[i];
-      tg[i] = wt[i] * (Tb - D.T_s) + (1.0f - om[i]) * gneq;
+      const float geqm = wt[i] * Tb * 5.0f * eb[i];  // velocity part of g^eq(T_b, u_b)
+      tg[i] = wt[i] * (Tb - D.T_s) + geqm + (1.0f - om[i]) * gneq + psib * (wt[i] * Tb + geqm);
     }
     store_wall<S, ODD>(D, P, jb, kb, d, tg, rn);
   }
   if (MODE == MODE_STEP_MACRO) {
     float* mac = mac_slot ? D.mac[1] : D.mac[0];  // select, not index: keeps D out of scratch
-    mac[ob] = 0.0f;
-    mac[D.plane + ob] = 0.0f;
+    mac[ob] = uzb;
+    mac[D.plane + ob] = urb;
     mac[2 * D.plane + ob] = Tb;
   }
   if (MODE == MODE_FIELDS) {
     const int64_t o = (int64_t)kb * D.nr + jb;
-    if (fo.uz) fo.uz[o] = 0.0f;
-    if (fo.ur) fo.ur[o] = 0.0f;
-    if (fo.p) fo.p[o] = B.rho * CS2 / phib;
+    if (fo.uz) fo.uz[o] = uzb;
+    if (fo.ur) fo.ur[o] = urb;
+    if (fo.p) fo.p[o] = rhob * CS2 / phib;
     if (fo.T) fo.T[o] = Tb;
     if (fo.mask) fo.mask[o] = m;
   }
@@ -746,8 +793,8 @@ __host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC&
   // ---- wall nodes owned by this node ---------------------------------------
   const bool own_rm = D.side_rmin == SIDE_WALL && j == 1;
   const bool own_rp = D.side_rmax == SIDE_WALL && j == D.nr - 2;
-  const bool own_zm = D.side_z == SIDE_WALL && k == 1;
-  const bool own_zp = D.side_z == SIDE_WALL && k == D.nz - 2;
+  const bool own_zm = z_bounded(D) && k == 1;
+  const bool own_zp = z_bounded(D) && k == D.nz - 2;
   if (own_rm || own_rp || own_zm || own_zp) {
     for (int dr = -1; dr <= 1; ++dr) {
       if ((dr == -1 && !own_rm) || (dr == 1 && !own_rp)) continue;

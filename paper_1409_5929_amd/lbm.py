@@ -8,7 +8,8 @@ the library is loaded so that both share one HIP runtime.
 
 The entry points mirror ``include/lbm_axi.h``:
   create -> Lattice(...), step -> Lattice.step, macros -> Lattice.fields,
-  stream_function -> Lattice.stream_function, residual -> Lattice.residual,
+  stream_function -> Lattice.stream_function, pipe_nusselt -> Lattice.pipe_nusselt,
+  residual -> Lattice.residual,
   info -> Lattice.info, destroy -> Lattice.close.
 """
 from __future__ import annotations
@@ -21,7 +22,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm_axi.so")
 
-SIDE = {"wall": 0, "axis": 1, "periodic": 2}
+SIDE = {"wall": 0, "axis": 1, "periodic": 2, "flow": 3}
 THERM = {"fixed": 0, "adiabatic": 1, "flux": 2}
 STORAGE = {"fp32": 0, "fp16": 1, "bf16": 2}
 RUN_STATE = {0: "running", 1: "converged", 2: "diverged", 3: "stalled"}
@@ -48,6 +49,7 @@ class Params(ctypes.Structure):
         ("delta_T", ctypes.c_double), ("tol", ctypes.c_double), ("max_steps", ctypes.c_int64),
         ("flux_rmin", ctypes.c_double), ("flux_rmax", ctypes.c_double),
         ("flux_zlo", ctypes.c_double), ("flux_zhi", ctypes.c_double),
+        ("u_in", ctypes.c_double),
     ]
 
 
@@ -114,6 +116,9 @@ def _load():
     lib.lbm_axi_stream_function.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                             P(ctypes.c_double), ctypes.c_int32]
     lib.lbm_axi_stream_function.restype = ctypes.c_int
+    lib.lbm_axi_pipe_nusselt.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_void_p, ctypes.c_void_p]
+    lib.lbm_axi_pipe_nusselt.restype = ctypes.c_int
     lib.lbm_axi_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32]
     lib.lbm_axi_set_timing.restype = ctypes.c_int
     lib.lbm_axi_kernel_time.argtypes = [ctypes.c_void_p, P(ctypes.c_double), P(ctypes.c_int64)]
@@ -266,6 +271,16 @@ class Lattice:
                                                  psi.ctypes.data if field else None,
                                                  ctypes.byref(mx), 0))
         return psi, mx.value
+
+    def pipe_nusselt(self, inst: int = 0, area: bool = False):
+        """Local Nusselt number (Eq. 40) and bulk temperature at every column of
+        a pipe instance, as two float64 arrays of length nz: mixing-cup T_b, or
+        with area=True the area mean as Eq. (41) is printed."""
+        nz, _ = self.shapes[inst]
+        nu, tb = np.empty(nz), np.empty(nz)
+        _check(self._lib.lbm_axi_pipe_nusselt(self._h, int(inst), 1 if area else 0,
+                                              nu.ctypes.data, tb.ctypes.data))
+        return nu, tb
 
     def residual(self) -> dict:
         n = self.n_inst

@@ -65,7 +65,10 @@ def test_default_params_are_the_papers_rates():
     (dict(side_rmin="periodic"), -1),              # one-sided radial periodicity
     (dict(phi=1.5), -1),                           # porosity out of range
     (dict(tau_nu=0.0, Ra=0.0), -1),                # no way to set tau_nu
-    (dict(side_rmin="axis", r0=0.5, side_z="wall"), -4),  # axis with axial walls
+    (dict(side_rmin="flow"), -1),                  # inlet/outlet only along z
+    (dict(side_z="flow", nz=2), -1),               # inlet and outlet need three columns
+    (dict(therm_z="flux"), -1),                    # flux walls are radial only
+    (dict(side_z="flow", u_in=float("nan")), -1),
     (dict(storage=7), -1),
 ])
 def test_invalid_problems_are_refused_without_a_device(bad, code):
