@@ -151,6 +151,19 @@ def heater_annulus(Da: float, nr: int = 200, nz: int = 200, Ra: float = 1e7, Pr:
                 accel_r=0.0, accel_z=0.0)
 
 
+def porous_annulus_43(Ra_star: float, nr: int = 300, nz: int = 300, F_phi: float = ERGUN) -> dict:
+    """Natural convection in a vertical annulus filled with porous medium (Sec. 4.3).
+
+    R* = 5.338, A = 1, Pr = 1, phi = 0.3698, Da = 1.66e-6 and the Darcy-Rayleigh
+    number Ra* = Ra Da, so Ra = Ra* / Da; hot inner wall, cold outer wall,
+    adiabatic ends, on the paper's 300 x 300 grid by default.  The section does
+    not set F_phi (Secs. 4.1 and 4.4 set it to 0 explicitly), so Eq. (8)'s Ergun
+    value of the porosity applies.
+    """
+    return annulus(nr=nr, nz=nz, Rstar=5.338, phi=0.3698, Da=1.66e-6, Ra=Ra_star / 1.66e-6,
+                   Pr=1.0, F_phi=F_phi)
+
+
 def porosity_grf(nz: int, nr: int, seed: int = 1409, sigma: float = 8.0, mean: float = 0.6,
                  std: float = 0.15, lo: float = 0.3, hi: float = 0.95) -> np.ndarray:
     """Seeded Gaussian random porosity field, [nz, nr] float64.

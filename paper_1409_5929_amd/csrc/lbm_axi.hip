@@ -474,14 +474,16 @@ int validate(const lbm_axi_params& p, int i) {
   return LBM_AXI_OK;
 }
 
-// Default nodes per thread along z: the largest of 4 (FP32) or 16 (16-bit
+// Default nodes per thread along z: the largest of 2 (FP32) or 8 (16-bit
 // storage), halving down to 1, that still gives the launch at least 512
 // blocks.  Small grids are latency-bound: each thread's nodes run one after
 // another, so fewer nodes per thread shorten the critical path (measured on
 // 100 x 200 and 256^2: kz = 1 steps in 6.3 us against 15 us at kz = 4); large
-// grids are bandwidth-bound and prefer the longer strips (kz = 4 / 16 at 8192^2).
+// grids are bandwidth-bound and prefer the longer strips (at 8192^2 the FP32
+// step takes 1.49 ms at kz = 2 against 1.71 ms at kz = 4, the FP16 step
+// 0.96 ms at kz = 8 against 0.99 ms at kz = 16).
 int default_kz(const lbm_axi* h) {
-  const int kmax = h->storage == LBM_STORE_FP32 ? 4 : 16;
+  const int kmax = h->storage == LBM_STORE_FP32 ? 2 : 8;
   for (int kz = kmax; kz > 1; kz /= 2) {
     long long blocks = 0;
     for (const lbm_axi_params& q : h->prm)

@@ -3,10 +3,11 @@
   python -m paper_1409_5929_amd.studies table1     # Sec. 4.1, thermally developing porous pipe
   python -m paper_1409_5929_amd.studies table2     # Sec. 4.2, annulus without porous medium
   python -m paper_1409_5929_amd.studies table3     # Sec. 4.4, porous annulus with a heater
+  python -m paper_1409_5929_amd.studies sec43      # Sec. 4.3, porous annulus, Ra* = 200, 500, 2000
 
 Every case of a table runs as one instance of a single batched handle: for
-Tables 2 and 3 until its residual reaches the tolerance (or the step cap), for
-Table 1 for a fixed number of flow-through times. Progress lines are printed
+Tables 2 and 3 and Sec. 4.3 until its residual reaches the tolerance (or the
+step cap), for Table 1 for a fixed number of flow-through times. Progress lines are printed
 as the run goes, followed by a table of the measured and printed values.
 
 For Table 1, each case runs on the paper's grid spacing (r_i = 40.5) and at
@@ -17,6 +18,10 @@ shorter than the clear pipe's thermal entry length at this Re (about
 0.05 Re_D Pr D = 7 D = 0.9 H), so the default pipe is twice as long. The
 inlet velocity 0.0025 keeps the Darcy pressure drop, and the spurious T div u
 sink it causes in the temperature equation, small at Da = 1e-3.
+
+Sec. 4.3 prints no numbers (its results are the curves of Figs. 5-6): the
+study reports the mean Nusselt numbers of both walls and the temperature
+profiles T(r) at z / H = 0.25, 0.5, 0.75 and 1.
 
 For Table 3, max |psi| is reported in units of alpha_e L. Here
 alpha_e = c_sT^2 tau_T is the effective thermal diffusivity (text after Eq. 38),
@@ -54,9 +59,10 @@ def alpha_e(cfg: dict) -> float:
 
 
 def run_to_steady(cfgs, tol=1e-10, max_steps=40_000_000, check=2000, chunk=1_000_000,
-                  log=print):
+                  log=print, temperature=False):
     """Run all problems in one handle until none is running. Returns, per case,
-    the state, step count, residual, Nu_i, Nu_o and max |psi| (lattice units)."""
+    the state, step count, residual, Nu_i, Nu_o, max |psi| (lattice units) and,
+    with temperature=True, the temperature field."""
     lat = Lattice(cfgs, check_interval=check, tol=tol, max_steps=max_steps)
     t0 = time.time()
     try:
@@ -71,7 +77,8 @@ def run_to_steady(cfgs, tol=1e-10, max_steps=40_000_000, check=2000, chunk=1_000
                 break
         return [dict(status=info[i]["status"], t=info[i]["t"], res=float(r["res"][i]),
                      nu_i=float(r["nu_i"][i]), nu_o=float(r["nu_o"][i]),
-                     psi_max=lat.stream_function(i, field=False)[1])
+                     psi_max=lat.stream_function(i, field=False)[1],
+                     T=lat.fields(i)["T"] if temperature else None)
                 for i in range(len(cfgs))]
     finally:
         lat.close()
@@ -134,9 +141,32 @@ def table3(nr=200, nz=200, log=print):
     return out
 
 
+def sec43(nr=300, nz=300, ra_stars=(200.0, 500.0, 2000.0), tol=1e-9, max_steps=30_000_000,
+          log=print):
+    """Sec. 4.3 annulus at the given Darcy-Rayleigh numbers: steady mean Nusselt
+    numbers (Eq. 42) and the temperature profiles theta = (T - T_o) / (T_i - T_o)
+    across the gap at z / H = 0.25, 0.5, 0.75 and 1 (the curves of Fig. 6)."""
+    cfgs = [li.porous_annulus_43(ra, nr=nr, nz=nz) for ra in ra_stars]
+    out = run_to_steady(cfgs, tol=tol, max_steps=max_steps, log=log, temperature=True)
+    log("Ra*     Nu_i     Nu_o     steps      state")
+    for ra, o in zip(ra_stars, out):
+        log(f"{ra:<7g} {o['nu_i']:.4f}  {o['nu_o']:.4f}  {o['t']:<10d} {o['status']}")
+    xs = [0.0, 0.05, 0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0]
+    log("theta at (r - r_i) / L = " + " ".join(f"{x:5.2f}" for x in xs))
+    for ra, c, o in zip(ra_stars, cfgs, out):
+        theta = (o["T"] - c["T_rmax"]) / (c["T_rmin"] - c["T_rmax"])
+        o["theta"] = {}
+        for zh in (0.25, 0.5, 0.75, 1.0):
+            k = int(round(zh * (nz - 1)))
+            row = [float(theta[k, int(round(x * (nr - 1)))]) for x in xs]
+            o["theta"][zh] = row
+            log(f"Ra*={ra:<6g} z/H={zh:<4g} " + " ".join(f"{v:5.3f}" for v in row))
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("table", choices=["table1", "table2", "table3"])
+    ap.add_argument("table", choices=["table1", "table2", "table3", "sec43"])
     ap.add_argument("--grid", type=int, default=200, help="table3: nr = nz (paper: 200)")
     ap.add_argument("--A", type=float, default=32.0, help="table1: pipe length over r_i (paper: 16)")
     a = ap.parse_args(argv)
@@ -145,6 +175,8 @@ def main(argv=None):
         table1(A=a.A, log=log)
     elif a.table == "table2":
         table2(log)
+    elif a.table == "sec43":
+        sec43(log=log)
     else:
         table3(a.grid, a.grid, log)
 

@@ -249,3 +249,12 @@ def test_full_size_sampled_windows(L, oracle_mod):
         worst = max(worst, *e.values())
         assert max(e.values()) <= TOL_FP32, (j0, k0, e)
     print(f"8192^2 windows: worst rel L2 {worst:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("ra_star", [200.0, 2000.0])
+def test_porous_annulus_sec43_parity(L, oracle_mod, ra_star):
+    """Sec. 4.3 parameters (R* = 5.338, phi = 0.3698, Da = 1.66e-6, Ergun F_phi,
+    Ra* = Ra Da) on a ragged 75 x 70 grid: fields after 300 steps."""
+    cfg = li.porous_annulus_43(ra_star, nr=75, nz=70)
+    assert_parity(gpu_fields(L, cfg, 300), orc_fields(oracle_mod, cfg, 300),
+                  label=f"sec. 4.3 Ra*={ra_star:g}", u_floor=U_FLOOR)
