@@ -28,10 +28,14 @@
  *     temperature) plus the neighbour's non-equilibrium part, unscaled, and
  *     collides with those values.  The neighbour is the normal one, the
  *     diagonal one at corners.  Adiabatic walls copy the neighbour's
- *     temperature; at a corner a fixed-temperature radial wall wins.
+ *     temperature; isoflux walls (LBM_T_FLUX) add q'/k to it; at a corner a
+ *     fixed-temperature radial wall wins.  Inlet and outlet columns
+ *     (LBM_SIDE_FLOW, Sec. 4.1) are reconstructed the same way with their own
+ *     velocity, density and temperature (see lbm_axi_side).
  *   - Axis (LBM_SIDE_AXIS at r_min, r0 must be 1/2): a mirror row at r = -1/2
  *     with f_i(-r) = -f_i*(r) for the r-weighted populations (i* reverses
- *     e_r) and g_i(-r) = g_i*(r).
+ *     e_r) and g_i(-r) = g_i*(r).  It may be combined with axial walls or an
+ *     inlet and outlet (pipes, closed cylinders).
  *   - Source moments: with src_printed = 0 the axisymmetric correction a_r of
  *     Eq. (25) enters the second-order moments of Eq. (24) without the 1/phi
  *     factor that the porous-medium force F carries; src_printed = 1 divides

@@ -5,7 +5,8 @@
 //   k_step     fused D2Q9-MRT + D2Q5 collide-stream, AA pattern, in place
 //              (lbm_axi_dev.h); optionally writes u_z, u_r, T for the check
 //   k_resid    FP64 partial sums of the residual and of the Eq. (42) wall
-//              integrals (wave shuffles, then LDS across the block's waves)
+//              integrals, or of the heater sums of Eqs. (43)-(44) on an
+//              isoflux wall (wave shuffles, then LDS across the block's waves)
 //   k_final    per-instance reduction of the partials, run-state update
 //   k_init     start state
 //   k_convert  storage conversion (FP32 / FP16 / BF16) of one instance

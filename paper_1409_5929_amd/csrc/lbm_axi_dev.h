@@ -30,12 +30,14 @@
 // the plain copy fhat_i(-r) = fhat_i*(r), so the alias needs no arithmetic;
 // the reader's rescaling with r_src = -1/2 restores the sign.
 //
-// Walls.  Wall nodes (rows 0 / nr-1, columns 0 / nz-1) are reconstructed by
-// non-equilibrium extrapolation (Sec. 4) from a fluid neighbour B that owns
-// them (normal neighbour; diagonal one for corners).  B's thread computes the
-// wall node's post-collision populations from its own registers and writes
-// the ones that stream into fluid nodes to the AA slots the wall node would
-// have written.
+// Walls.  Boundary nodes (rows 0 / nr-1, columns 0 / nz-1: no-slip walls,
+// or an inlet and an outlet column) are reconstructed by non-equilibrium
+// extrapolation (Sec. 4) from a fluid neighbour B that owns them (normal
+// neighbour; diagonal one for corners), each with its own density, velocity
+// and temperature.  B's thread computes the boundary node's post-collision
+// populations from its own registers and writes the ones that stream into
+// fluid nodes, also through the axis mirror, to the AA slots the boundary
+// node would have written.
 #pragma once
 
 #include <hip/hip_bf16.h>
@@ -491,7 +493,8 @@ __host__ __device__ inline void wall_node(const InstDev& D, const A& P, const No
   porosity_of(D, D.phi_mode == 0 ? 0.0f : D.phi[ob], phib, cDb, cFb);
   const uint8_t m = node_mask(D, jb, kb);
   float drho = B.drho, urb = 0.0f, uzb = 0.0f;
-  if (D.side_z == SIDE_FLOW && !(m & (MASK_RMIN | MASK_RMAX))) {
+  const bool moving = D.side_z == SIDE_FLOW && !(m & (MASK_RMIN | MASK_RMAX));  // inlet or outlet
+  if (moving) {
     if (m & MASK_ZMIN) {
       uzb = D.u_in;
     } else {
@@ -516,45 +519,62 @@ __host__ __device__ inline void wall_node(const InstDev& D, const A& P, const No
     // Flow: m+(b) = m^eq(b) + (I - L)(r_B / r_b) n(B) + (I - L/2) S(b), all / r_b,
     // as deviations from the quiescent post-collision moments
     // (1, -2, 1, c_s^2 / (2 r_b), -c_s^2 / (2 r_b), 0, 0, 0, 0).
-    const float iphib = 1.0f / phib;
-    const float Gz = D.gbeta * (Tb - D.T_ref) + D.accel_z;
-    const float drag = cDb + cFb * sqrtf(urb * urb + uzb * uzb);
-    const float Frb = phib * D.accel_r - drag * urb, Fzb = phib * Gz - drag * uzb;
-    const float arb = CS2 * inv_rb - 2.0f * D.c_tau * urb * inv_rb * inv_rb;  // Eq. (25)
-    float S1, S7, S8;
-    source(D.src_printed != 0, rhob, urb, uzb, iphib, Frb, Fzb, arb, S1, S7, S8);
-    const float S3 = rhob * (Frb + arb), S5 = rhob * Fzb;
-    const float ru2 = 3.0f * rhob * (urb * urb + uzb * uzb) * iphib;
+    // Temperature: g+(b) = g^eq(T_b, u_b) + (1 - omega_i(r_b)) g^neq(B) + psi_i(b).
+    // No-slip walls (u_b = 0) take a short path: the velocity terms vanish.
+    // At one wave per SIMD (small grids) the wall work sits on the critical
+    // path of the owner's wave, so it is kept as short as the case allows.
     const float q = rB * inv_rb;
     const float hb = 0.5f * CS2 * inv_rb;
-    float d[9];
-    d[0] = W0 * drho;
-    d[1] = d[2] = d[3] = d[4] = W1 * drho;
-    d[5] = d[6] = d[7] = d[8] = W5 * drho;
-    back_transform(d, ru2 + (1.0f - D.s_e) * q * B.n1 + (1.0f - 0.5f * D.s_e) * S1,
-                   -ru2 + (1.0f - D.s_eps) * q * B.n2 - (1.0f - 0.5f * D.s_eps) * S1,
-                   rhob * urb + (1.0f - D.s_j) * q * B.n3 + (1.0f - 0.5f * D.s_j) * S3 - hb,
-                   -rhob * urb + (1.0f - D.s_q) * q * B.n4 - (1.0f - 0.5f * D.s_q) * S3 + hb,
-                   rhob * uzb + (1.0f - D.s_j) * q * B.n5 + (1.0f - 0.5f * D.s_j) * S5,
-                   -rhob * uzb + (1.0f - D.s_q) * q * B.n6 - (1.0f - 0.5f * D.s_q) * S5,
-                   rhob * (urb * urb - uzb * uzb) * iphib + (1.0f - D.s_nu) * q * B.n7 +
-                       (1.0f - 0.5f * D.s_nu) * S7,
-                   rhob * urb * uzb * iphib + (1.0f - D.s_nu) * q * B.n8 + (1.0f - 0.5f * D.s_nu) * S8);
-    // Temperature: g+(b) = g^eq(T_b, u_b) + (1 - omega_i(r_b)) g^neq(B) + psi_i(b).
+    const float Gz = D.gbeta * (Tb - D.T_ref) + D.accel_z;
     const float eu[5] = {0.0f, B.ur, B.uz, -B.ur, -B.uz};
-    const float eb[5] = {0.0f, urb, uzb, -urb, -uzb};
     const float wt[5] = {WT0, WT1, WT1, WT1, WT1};
     const float tb1 = D.tau_T * inv_rb;
     const float om[5] = {D.omc, D.omc * (1.0f + tb1), D.omc, D.omc * (1.0f - tb1), D.omc};
-    const float psib = -urb * inv_rb;
-    float tg[5];
     float qn[5];
     for (int i = 1; i < 5; ++i) qn[i] = B.t[i] - wt[i] * B.theta;
     qn[0] = -((qn[1] + qn[3]) + (qn[2] + qn[4]));
-    for (int i = 0; i < 5; ++i) {
-      const float gneq = qn[i] - 5.0f * wt[i] * B.T * eu[i];
-      const float geqm = wt[i] * Tb * 5.0f * eb[i];  // velocity part of g^eq(T_b, u_b)
-      tg[i] = wt[i] * (Tb - D.T_s) + geqm + (1.0f - om[i]) * gneq + psib * (wt[i] * Tb + geqm);
+    float d[9], tg[5];
+    d[0] = W0 * drho;
+    d[1] = d[2] = d[3] = d[4] = W1 * drho;
+    d[5] = d[6] = d[7] = d[8] = W5 * drho;
+    if (!moving) {
+      const float S3 = rhob * (phib * D.accel_r + CS2 * inv_rb), S5 = rhob * phib * Gz;
+      back_transform(d, (1.0f - D.s_e) * q * B.n1, (1.0f - D.s_eps) * q * B.n2,
+                     (1.0f - D.s_j) * q * B.n3 + (1.0f - 0.5f * D.s_j) * S3 - hb,
+                     (1.0f - D.s_q) * q * B.n4 - (1.0f - 0.5f * D.s_q) * S3 + hb,
+                     (1.0f - D.s_j) * q * B.n5 + (1.0f - 0.5f * D.s_j) * S5,
+                     (1.0f - D.s_q) * q * B.n6 - (1.0f - 0.5f * D.s_q) * S5,
+                     (1.0f - D.s_nu) * q * B.n7, (1.0f - D.s_nu) * q * B.n8);
+      for (int i = 0; i < 5; ++i) {
+        const float gneq = qn[i] - 5.0f * wt[i] * B.T * eu[i];
+        tg[i] = wt[i] * (Tb - D.T_s) + (1.0f - om[i]) * gneq;
+      }
+    } else {
+      const float iphib = 1.0f / phib;
+      const float drag = cDb + cFb * sqrtf(urb * urb + uzb * uzb);
+      const float Frb = phib * D.accel_r - drag * urb, Fzb = phib * Gz - drag * uzb;
+      const float arb = CS2 * inv_rb - 2.0f * D.c_tau * urb * inv_rb * inv_rb;  // Eq. (25)
+      float S1, S7, S8;
+      source(D.src_printed != 0, rhob, urb, uzb, iphib, Frb, Fzb, arb, S1, S7, S8);
+      const float S3 = rhob * (Frb + arb), S5 = rhob * Fzb;
+      const float ru2 = 3.0f * rhob * (urb * urb + uzb * uzb) * iphib;
+      back_transform(d, ru2 + (1.0f - D.s_e) * q * B.n1 + (1.0f - 0.5f * D.s_e) * S1,
+                     -ru2 + (1.0f - D.s_eps) * q * B.n2 - (1.0f - 0.5f * D.s_eps) * S1,
+                     rhob * urb + (1.0f - D.s_j) * q * B.n3 + (1.0f - 0.5f * D.s_j) * S3 - hb,
+                     -rhob * urb + (1.0f - D.s_q) * q * B.n4 - (1.0f - 0.5f * D.s_q) * S3 + hb,
+                     rhob * uzb + (1.0f - D.s_j) * q * B.n5 + (1.0f - 0.5f * D.s_j) * S5,
+                     -rhob * uzb + (1.0f - D.s_q) * q * B.n6 - (1.0f - 0.5f * D.s_q) * S5,
+                     rhob * (urb * urb - uzb * uzb) * iphib + (1.0f - D.s_nu) * q * B.n7 +
+                         (1.0f - 0.5f * D.s_nu) * S7,
+                     rhob * urb * uzb * iphib + (1.0f - D.s_nu) * q * B.n8 +
+                         (1.0f - 0.5f * D.s_nu) * S8);
+      const float eb[5] = {0.0f, urb, uzb, -urb, -uzb};
+      const float psib = -urb * inv_rb;
+      for (int i = 0; i < 5; ++i) {
+        const float gneq = qn[i] - 5.0f * wt[i] * B.T * eu[i];
+        const float geqm = wt[i] * Tb * 5.0f * eb[i];  // velocity part of g^eq(T_b, u_b)
+        tg[i] = wt[i] * (Tb - D.T_s) + geqm + (1.0f - om[i]) * gneq + psib * (wt[i] * Tb + geqm);
+      }
     }
     store_wall<S, ODD>(D, P, jb, kb, d, tg, rn);
   }
@@ -795,6 +815,9 @@ __host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC&
   const bool own_rp = D.side_rmax == SIDE_WALL && j == D.nr - 2;
   const bool own_zm = z_bounded(D) && k == 1;
   const bool own_zp = z_bounded(D) && k == D.nz - 2;
+  // Each (dr, dz) below is a separate inlined copy with constant offsets: on
+  // annuli, where corner owners take three wall nodes, these specialised
+  // passes run faster than one generic pass walked per lane.
   if (own_rm || own_rp || own_zm || own_zp) {
     for (int dr = -1; dr <= 1; ++dr) {
       if ((dr == -1 && !own_rm) || (dr == 1 && !own_rp)) continue;
