@@ -203,9 +203,10 @@ int lbm_axi_stream_function(lbm_axi* h, int32_t inst, float* psi, double* psi_ab
  * mean int r T dr / int r dr as Eq. (41) is printed; the integrals run from
  * the axis to the wall by the trapezoid rule over the rows plus the point
  * r = 0.  FP64 sums of the FP32 fields at the instance's current time.  nu
- * and T_b are host arrays of nz doubles (each may be NULL).  Allocates
- * temporary device memory and waits for the stream.  LBM_AXI_EINVAL unless
- * the instance is a pipe.
+ * and T_b are host arrays of nz doubles (each may be NULL).  A column that
+ * carries no net axial flux (a closed cylinder) has no mixing-cup T_b: its
+ * entries then divide by a vanishing flux and carry no meaning (use area = 1).  Allocates temporary device memory and waits
+ * for the stream.  LBM_AXI_EINVAL unless the instance is a pipe.
  */
 int lbm_axi_pipe_nusselt(lbm_axi* h, int32_t inst, int32_t area, double* nu, double* T_b);
 

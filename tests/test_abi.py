@@ -93,6 +93,8 @@ def test_null_handles_are_refused():
     assert lib.lbm_axi_set_graph(None, 32) == -1
     assert lib.lbm_axi_compact(None, None) == -1
     assert lib.lbm_axi_autotune(None, 1, None, None, None) == -1
+    assert lib.lbm_axi_stream_function(None, 0, None, None, 0) == -1
+    assert lib.lbm_axi_pipe_nusselt(None, 0, 0, None, None) == -1
     lib.lbm_axi_destroy(None)  # allowed
 
 
