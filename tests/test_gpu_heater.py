@@ -117,3 +117,24 @@ def test_table3_heater(L, Da, nu_paper, psi_paper):
     assert abs(r["nu_i"][0] - nu_paper) <= 0.02 * nu_paper
     assert abs(psi - psi_paper) <= 0.03 * psi_paper
     assert abs(r["nu_o"][0] - balance) <= 0.02 * balance
+
+
+def test_stream_function_into_device_memory(L):
+    """lbm_axi_stream_function with a device destination (written on the
+    handle's stream) equals the host-destination result."""
+    import ctypes
+
+    import torch
+
+    cfg = li.heater_annulus(Da=1e-2, nr=48, nz=40, Ra=1e5)
+    lat = L.Lattice(cfg, check_interval=0)
+    lat.step(300)
+    psi_h, mx_h = lat.stream_function()
+    dev = torch.empty((cfg["nz"], cfg["nr"]), dtype=torch.float32, device="cuda")
+    mx = ctypes.c_double()
+    rc = lat._lib.lbm_axi_stream_function(lat._h, 0, dev.data_ptr(), ctypes.byref(mx), 1)
+    assert rc == 0
+    lat.sync()
+    np.testing.assert_array_equal(dev.cpu().numpy(), psi_h)
+    assert mx.value == mx_h
+    lat.close()
