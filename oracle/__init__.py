@@ -89,7 +89,8 @@ def _load():
     lib.orc_pipe_nusselt.restype = ctypes.c_int
     lib.orc_pipe_nusselt.argtypes = [ctypes.c_void_p, ctypes.c_int, d, d]
     lib.orc_stream_function.restype = ctypes.c_double
-    lib.orc_stream_function.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, d, d]
+    lib.orc_stream_function.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                        d, d]
     lib.orc_last_error.restype = ctypes.c_char_p
     lib.orc_threads.restype = ctypes.c_int
     _lib = lib
@@ -242,13 +243,14 @@ class Oracle:
                     Ftz=macro[5], a_r=macro[6], meq=meq, S=S, f_out=fo, g_out=go)
 
 
-def stream_function(uz, r0: float):
-    """Stokes stream function of a u_z field [nz, nr] with rows at r0 + j,
-    zero on row 0 (trapezoid rule); returns (psi, max |psi|)."""
+def stream_function(uz, r0: float, axis: bool = False):
+    """Stokes stream function of a u_z field [nz, nr] with rows at r0 + j, zero
+    on row 0 (an r_min wall) or, with axis=True, on the axis r = 0 (trapezoid
+    rule); returns (psi, max |psi|)."""
     uz = np.ascontiguousarray(uz, dtype=np.float64)
     nz, nr = uz.shape
     psi = np.empty_like(uz)
-    mx = _load().orc_stream_function(nr, nz, float(r0), _dptr(uz), _dptr(psi))
+    mx = _load().orc_stream_function(nr, nz, float(r0), 1 if axis else 0, _dptr(uz), _dptr(psi))
     return psi, float(mx)
 
 

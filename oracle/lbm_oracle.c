@@ -93,8 +93,8 @@
  *      integrand vanishes).
  *   R11 Stream function (Table 3; not defined in the paper).  The Stokes
  *      stream function of the axisymmetric flow, u_z = (1/r) dpsi/dr and
- *      u_r = -(1/r) dpsi/dz, zero on the r_min wall:
- *      psi(r, z) = integral from r_min to r of r' u_z(r', z) dr'.
+ *      u_r = -(1/r) dpsi/dz, zero on the r_min wall (or on the axis r = 0):
+ *      psi(r, z) = integral from r_min (or 0) to r of r' u_z(r', z) dr'.
  */
 #include <math.h>
 #include <stdint.h>
@@ -750,15 +750,18 @@ int orc_pipe_nusselt(const orc_state* s, int area, double* nu, double* Tb) {
 
 /*
  * Stokes stream function (R11) of a u_z field ([nz][nr], rows at r0 + j):
- * psi[k][0] = 0 and psi[k][j] = psi[k][j-1] + (r_{j-1} u_{j-1} + r_j u_j) / 2
- * (trapezoid rule of the integral of r u_z dr).  Returns max |psi|.
+ * psi[k][j] = psi[k][j-1] + (r_{j-1} u_{j-1} + r_j u_j) / 2 (trapezoid rule of
+ * the integral of r u_z dr), starting from psi[k][0] = 0 on an r_min wall, or,
+ * with axis = 1, from psi[k][0] = r0 (r0 u_0) / 2 (the interval [0, r0], where
+ * r u_z vanishes on the axis).  Returns max |psi|.
  */
-double orc_stream_function(int nr, int nz, double r0, const double* uz, double* psi) {
+double orc_stream_function(int nr, int nz, double r0, int axis, const double* uz, double* psi) {
   double mx = 0.0;
   for (int k = 0; k < nz; ++k) {
     const double* u = uz + (long)k * nr;
-    double acc = 0.0;
-    if (psi) psi[(long)k * nr] = 0.0;
+    double acc = axis ? 0.5 * r0 * (r0 * u[0]) : 0.0;
+    if (psi) psi[(long)k * nr] = acc;
+    if (fabs(acc) > mx) mx = fabs(acc);
     for (int j = 1; j < nr; ++j) {
       acc += 0.5 * ((r0 + j - 1) * u[j - 1] + (r0 + j) * u[j]);
       if (psi) psi[(long)k * nr + j] = acc;

@@ -123,6 +123,20 @@ def test_stream_function_linear_integrand_exact(oracle_mod):
     assert np.all(psi[:, 0] == 0.0)
 
 
+def test_stream_function_from_the_axis_exact(oracle_mod):
+    """In a pipe psi vanishes on the axis r = 0, half a row below row 0: plug
+    flow u_z = a has psi = a r^2 / 2, which the trapezoid rule (r u_z linear)
+    gives exactly, row 0 included."""
+    rng = np.random.default_rng(8)
+    nz, nr = 4, 29
+    r = 0.5 + np.arange(nr)
+    a = rng.normal(size=(nz, 1))
+    psi, mx = oracle_mod.stream_function(np.broadcast_to(a, (nz, nr)), 0.5, axis=True)
+    exact = a * (r * r)[None, :] / 2.0
+    np.testing.assert_allclose(psi, exact, rtol=1e-13, atol=1e-15)
+    assert mx == pytest.approx(np.abs(exact).max(), rel=1e-13)
+
+
 def test_stream_function_closes_on_outer_wall(oracle_mod):
     """Steady convection carries no net mass through a horizontal section, so
     psi returns to about zero on the outer wall (trapezoid and wall errors)."""
