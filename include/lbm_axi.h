@@ -182,9 +182,11 @@ int lbm_axi_macros(lbm_axi* h, int32_t inst, float* uz, float* ur, float* p, flo
 /*
  * Stokes stream function of instance inst at its current time (the paper
  * reports its largest magnitude in Table 3 without defining it):
- * u_z = (1/r) dpsi/dr, u_r = -(1/r) dpsi/dz, psi = 0 on row 0, i.e.
+ * u_z = (1/r) dpsi/dr, u_r = -(1/r) dpsi/dz, psi = 0 on the r_min wall, i.e.
  * psi(r_j, z_k) = integral from r0 to r_j of r u_z dr by the trapezoid rule
- * over the rows (FP64 sums of the FP32 velocity field), in lattice units
+ * over the rows (FP64 sums of the FP32 velocity field); with an axis at r_min
+ * psi = 0 on the axis and the integral starts at r = 0 (row 0 holds
+ * r0 (r0 u_z) / 2, the trapezoid over [0, r0]).  In lattice units
  * (divide by nu L for the scale of the paper's table).  psi: NULL or [nz][nr]
  * floats, device memory if dst_is_device (written on the handle's stream)
  * else host memory.  psi_absmax: NULL or one host double, max |psi|.  The

@@ -352,17 +352,19 @@ __global__ __launch_bounds__(RB) void k_final(const int* __restrict__ first,
   out[inst] = r;
 }
 
-// Stokes stream function (zero on the r_min row) of a u_z field [nz][nr] with
-// rows at r0 + j: one wave per column k scans the trapezoid terms
-// (r_{j-1} u_{j-1} + r_j u_j) / 2 along r in FP64, 64 rows at a time, and
-// writes psi (if non-null) and colmax[k] = max_j |psi[k][j]|.
+// Stokes stream function of a u_z field [nz][nr] with rows at r0 + j, zero
+// on the r_min wall, or with axis = 1 on the axis r = 0 (row 0 then holds
+// r0 (r0 u_0) / 2, the trapezoid over [0, r0]): one wave per column k scans the
+// trapezoid terms (r_{j-1} u_{j-1} + r_j u_j) / 2 along r in FP64, 64 rows at a
+// time, and writes psi (if non-null) and colmax[k] = max_j |psi[k][j]|.
 __global__ __launch_bounds__(RB) void k_psi(const float* __restrict__ uz, int nr, int nz, double r0,
-                                            float* __restrict__ psi, double* __restrict__ colmax) {
+                                            int axis, float* __restrict__ psi,
+                                            double* __restrict__ colmax) {
   const int lane = threadIdx.x & 63;
   const int k = blockIdx.x * (RB / 64) + (threadIdx.x >> 6);
   if (k >= nz) return;  // whole waves leave together
   const float* u = uz + (int64_t)k * nr;
-  double carry = 0.0, mx = 0.0;
+  double carry = axis ? 0.5 * r0 * (r0 * (double)u[0]) : 0.0, mx = 0.0;
   for (int j0 = 0; j0 < nr; j0 += 64) {
     const int j = j0 + lane;
     double t = 0.0;
@@ -1304,8 +1306,9 @@ int lbm_axi_stream_function(lbm_axi* h, int32_t inst, float* psi, double* psi_ab
       default: rc = launch_fields<__hip_bfloat16>(h, inst, odd, fo); break;
     }
     if (!rc) {
-      k_psi<<<(q.nz + RB / 64 - 1) / (RB / 64), RB, 0, h->stream>>>((const float*)duz, q.nr, q.nz, q.r0,
-                                                                    (float*)dpsi, (double*)dcol);
+      k_psi<<<(q.nz + RB / 64 - 1) / (RB / 64), RB, 0, h->stream>>>(
+          (const float*)duz, q.nr, q.nz, q.r0, q.side_rmin == LBM_SIDE_AXIS ? 1 : 0, (float*)dpsi,
+          (double*)dcol);
       k_absmax<<<1, RB, 0, h->stream>>>((const double*)dcol, q.nz, (double*)dmax);
       hipError_t e = hipGetLastError();
       if (e == hipSuccess && psi && !dst_is_device)

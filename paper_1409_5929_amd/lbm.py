@@ -262,8 +262,9 @@ class Lattice:
         return out
 
     def stream_function(self, inst: int = 0, field: bool = True):
-        """Stokes stream function of one instance (lattice units, zero on row 0)
-        as a host [nz, nr] float32 array (None with field=False) and max |psi|."""
+        """Stokes stream function of one instance (lattice units, zero on the r_min
+        wall or on the axis) as a host [nz, nr] float32 array (None with
+        field=False) and max |psi|."""
         nz, nr = self.shapes[inst]
         psi = np.empty((nz, nr), dtype=np.float32) if field else None
         mx = ctypes.c_double()

@@ -51,6 +51,7 @@ def test_pipe_fields_parity(L, oracle_mod, case, n):
     # a closed cylinder carries no net axial flux: only the area mean is defined
     weights = [True] if cfg["side_z"] != "flow" else [False, True]
     gpu_nu = [lat.pipe_nusselt(area=a) for a in weights]
+    gpu_psi, gpu_mx = lat.stream_function()
     lat.close()
     o = oracle_mod.Oracle(cfg, phi_field=phi, init=init)
     o.step(n)
@@ -58,6 +59,11 @@ def test_pipe_fields_parity(L, oracle_mod, case, n):
     orc_nu = [o.pipe_nusselt(area=a) for a in weights]
     o.close()
     assert_parity(g, m, label=f"{name} n={n}", u_floor=U_FLOOR)
+    # stream function from the axis
+    psi_o, mx_o = oracle_mod.stream_function(m["uz"], cfg["r0"], axis=True)
+    scale = max(mx_o, U_FLOOR * cfg["nr"] ** 2)
+    assert np.abs(gpu_psi - psi_o).max() <= 1e-5 * scale, name
+    assert abs(gpu_mx - mx_o) <= 1e-5 * scale
     for (nu_g, tb_g), (nu_o, tb_o) in zip(gpu_nu, orc_nu):
         # T_b is a weighted mean of T: the FP32 rounding of T and u bounds its error
         assert np.abs(tb_g - tb_o).max() <= 1e-5 * max(1.0, np.abs(tb_o).max())
