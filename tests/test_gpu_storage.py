@@ -233,3 +233,34 @@ def test_storage_error_with_flux_inlet_outlet_and_axis_walls(L, oracle_mod, stor
           flush=True)
     for k, v in e.items():
         assert v <= tol, (storage, name, k, v)
+
+
+def test_fp16_handoff_heater_steady_nusselt(L):
+    """Table 3 heater (Da = 1e-2, 200 x 200): 1.5 million steps in FP16
+    storage (of about 2.5 million to a residual of 1e-10), then handed over to
+    FP32 in place and run to 1e-10.  At the handoff the FP16 run's heater
+    Nusselt number is within 2e-3 of an FP32 run's at the same step; at the
+    end the two agree within 1e-3 and lie within 2 % of the paper's 17.09."""
+    cfg = li.heater_annulus(Da=1e-2)
+    switch = 1_500_000
+
+    def run(storage):
+        lat = L.Lattice(cfg, storage=storage, check_interval=2000, tol=1e-10, max_steps=8_000_000)
+        lat.step(switch + 1)  # the check at level `switch` runs in the step after it
+        nu_mid = lat.residual()["nu_i"][0]
+        if storage != "fp32":
+            lat.set_storage("fp32")
+        while lat.info()["status"] == "running":
+            lat.step(100_000)
+        out = (nu_mid, lat.residual()["nu_i"][0], lat.info())
+        lat.close()
+        return out
+
+    m32, nu32, i32 = run("fp32")
+    m16, nu16, i16 = run("fp16")
+    print(f"heater Da=1e-2 at {switch} steps: FP32 Nu {m32:.5f}, FP16 Nu {m16:.5f}; final: FP32 "
+          f"{nu32:.5f} ({i32['t']} steps), FP16 then FP32 {nu16:.5f} ({i16['t']} steps)", flush=True)
+    assert i32["status"] == "converged" and i16["status"] == "converged"
+    assert abs(m16 - m32) <= 2e-3 * m32
+    assert abs(nu16 - nu32) <= 1e-3 * nu32
+    assert abs(nu16 - 17.09) <= 0.02 * 17.09
