@@ -248,11 +248,13 @@ int lbm_axi_kernel_time(lbm_axi* h, double* total_ms, int64_t* launches);
 /*
  * Launch shape of the step kernel: blocks of 64 lanes along r by 4 waves,
  * each thread updating kz nodes along z (1 <= kz <= 64), and at most
- * blocks_per_cu blocks resident per compute unit (0: no cap; 1..64).  The
- * default kz is the largest of 2 (FP32) or 8 (16-bit storage), halving down
- * to 1, that gives the launch at least 512 blocks (short strips for small,
- * latency-bound grids); a storage conversion re-applies the default unless
- * this call or lbm_axi_autotune chose the shape.
+ * blocks_per_cu blocks resident per compute unit (0: no cap; 1..64).  This
+ * call sets the same kz for both parities of the AA step.  By default each
+ * parity has its own: the largest of 1 (FP32 even steps), 2 (FP32 odd steps)
+ * or 8 (16-bit storage), halving down to 1, that gives the launch at least
+ * 512 blocks (short strips for small, latency-bound grids); a storage
+ * conversion re-applies the default unless this call or lbm_axi_autotune
+ * chose the shape.
  * Waits for the stream and rebuilds the tile lists; results do not depend
  * on it.
  */

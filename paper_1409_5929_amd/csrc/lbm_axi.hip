@@ -87,8 +87,11 @@ struct lbm_axi {
   std::vector<InstDev> hdesc;
   InstDev* ddesc = nullptr;
   std::vector<void*> allocs;
-  int4* dtiles = nullptr;       // XCD-ordered tiles of all instances (own allocation)
+  int4* dtiles = nullptr;       // XCD-ordered tiles of all instances, even steps (own allocation)
   int ntiles_launch = 0;
+  int4* dtiles_odd = nullptr;   // the same for odd steps, strips of kz_odd nodes (own allocation)
+  int ntiles_odd = 0;
+  int kz_odd = 1;
   int4* dtiles_plain = nullptr; // tiles in instance order (own allocation)
   std::vector<int> tile_first, tile_count;
   ResTile* drt = nullptr;
@@ -477,16 +480,17 @@ int validate(const lbm_axi_params& p, int i) {
   return LBM_AXI_OK;
 }
 
-// Default nodes per thread along z: the largest of 2 (FP32) or 8 (16-bit
-// storage), halving down to 1, that still gives the launch at least 512
-// blocks.  Small grids are latency-bound: each thread's nodes run one after
-// another, so fewer nodes per thread shorten the critical path (measured on
-// 100 x 200 and 256^2: kz = 1 steps in 6.3 us against 15 us at kz = 4); large
-// grids are bandwidth-bound and prefer the longer strips (at 8192^2 the FP32
-// step takes 1.49 ms at kz = 2 against 1.71 ms at kz = 4, the FP16 step
-// 0.96 ms at kz = 8 against 0.99 ms at kz = 16).
-int default_kz(const lbm_axi* h) {
-  const int kmax = h->storage == LBM_STORE_FP32 ? 2 : 8;
+// Default nodes per thread along z, per parity of the AA step: the largest of
+// 1 (FP32 even steps), 2 (FP32 odd steps) or 8 (16-bit storage), halving down
+// to 1, that still gives the launch at least 512 blocks.  Small grids are
+// latency-bound: each thread's nodes run one after another, so fewer nodes
+// per thread shorten the critical path (measured on 100 x 200 and 256^2:
+// kz = 1 steps in 6.3 us against 15 us at kz = 4); large grids are
+// bandwidth-bound, and at 8192^2 the FP32 even step is fastest at kz = 1
+// (1.41 ms; 1.46 at kz = 2), the odd step at kz = 2 (1.55 ms; 1.87 at
+// kz = 1), both 16-bit steps at kz = 8 (0.95 / 0.98 ms).
+int default_kz(const lbm_axi* h, bool odd = false) {
+  const int kmax = h->storage == LBM_STORE_FP32 ? (odd ? 2 : 1) : 8;
   for (int kz = kmax; kz > 1; kz /= 2) {
     long long blocks = 0;
     for (const lbm_axi_params& q : h->prm)
@@ -526,9 +530,9 @@ int launch_step_b(lbm_axi* h, bool odd, int mode, int slot, uint32_t seed, hipSt
       k_step<S, false, MODE_STEP_MACRO, BUF><<<h->ntiles_launch, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo, seed, clk, off);
   } else {
     if (mode == MODE_STEP)
-      k_step<S, true, MODE_STEP, BUF><<<h->ntiles_launch, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo, seed, clk, off);
+      k_step<S, true, MODE_STEP, BUF><<<h->ntiles_odd, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles_odd, h->dstatus, h->kz_odd, slot, fo, seed, clk, off);
     else
-      k_step<S, true, MODE_STEP_MACRO, BUF><<<h->ntiles_launch, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo, seed, clk, off);
+      k_step<S, true, MODE_STEP_MACRO, BUF><<<h->ntiles_odd, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles_odd, h->dstatus, h->kz_odd, slot, fo, seed, clk, off);
   }
   HIPCHK(hipGetLastError());
   return LBM_AXI_OK;
@@ -577,48 +581,65 @@ int launch_init(lbm_axi* h, int inst, const float* dinit, float T_init) {
 // of tiles (neighbouring rows share that XCD's L2).
 // Only instances flagged in h->active (all when it is empty) enter the launch
 // list; the per-instance list (field output) always holds every instance.
-int build_tiles(lbm_axi* h, int kz) {
-  std::vector<int4> tiles, live;
+int build_tiles(lbm_axi* h, int kz, int kz_odd) {
+  // Per-instance list in instance order (field and start kernels, strips of kz)
+  // and, for each parity, the XCD-ordered list of the running instances.
+  std::vector<int4> tiles;
   std::vector<int> first, count;
-  const int tile_h = BY * kz;
   for (int i = 0; i < h->n_inst; ++i) {
     const lbm_axi_params& q = h->prm[i];
-    const bool on = h->active.empty() || h->active[i];
     first.push_back((int)tiles.size());
-    for (int k0 = 0; k0 < q.nz; k0 += tile_h)
-      for (int j0 = 0; j0 < q.nr; j0 += BX) {
-        tiles.push_back(make_int4(i, j0, k0, 0));
-        if (on) live.push_back(tiles.back());
-      }
+    for (int k0 = 0; k0 < q.nz; k0 += BY * kz)
+      for (int j0 = 0; j0 < q.nr; j0 += BX) tiles.push_back(make_int4(i, j0, k0, 0));
     count.push_back((int)tiles.size() - first.back());
   }
-  const int T = (int)live.size();
-  const int per = T > 0 ? (T + 7) / 8 : 1;
-  std::vector<int4> order((size_t)per * 8, make_int4(-1, 0, 0, 0));
-  for (int b = 0; b < per * 8; ++b) {
-    const int t = (b % 8) * per + b / 8;
-    if (t < T) order[b] = live[t];
-  }
-  int4 *dt = nullptr, *dp = nullptr;
-  if (hipMalloc(&dt, sizeof(int4) * order.size()) != hipSuccess ||
+  auto ordered = [&](int kzp) {
+    std::vector<int4> live;
+    for (int i = 0; i < h->n_inst; ++i) {
+      if (!(h->active.empty() || h->active[i])) continue;
+      const lbm_axi_params& q = h->prm[i];
+      for (int k0 = 0; k0 < q.nz; k0 += BY * kzp)
+        for (int j0 = 0; j0 < q.nr; j0 += BX) live.push_back(make_int4(i, j0, k0, 0));
+    }
+    const int T = (int)live.size();
+    const int per = T > 0 ? (T + 7) / 8 : 1;
+    std::vector<int4> order((size_t)per * 8, make_int4(-1, 0, 0, 0));
+    for (int b = 0; b < per * 8; ++b) {
+      const int t = (b % 8) * per + b / 8;
+      if (t < T) order[b] = live[t];
+    }
+    return order;
+  };
+  const std::vector<int4> even = ordered(kz), odd = ordered(kz_odd);
+  int4 *dt = nullptr, *dto = nullptr, *dp = nullptr;
+  auto free_new = [&]() {
+    for (int4* x : {dt, dto, dp})
+      if (x) (void)hipFree(x);
+  };
+  if (hipMalloc(&dt, sizeof(int4) * even.size()) != hipSuccess ||
+      hipMalloc(&dto, sizeof(int4) * odd.size()) != hipSuccess ||
       hipMalloc(&dp, sizeof(int4) * tiles.size()) != hipSuccess) {
-    if (dt) (void)hipFree(dt);
+    free_new();
     return fail(LBM_AXI_ENOMEM, "tile lists");
   }
-  if (hipMemcpy(dt, order.data(), sizeof(int4) * order.size(), hipMemcpyHostToDevice) != hipSuccess ||
+  if (hipMemcpy(dt, even.data(), sizeof(int4) * even.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dto, odd.data(), sizeof(int4) * odd.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(dp, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipFree(dt);
-    (void)hipFree(dp);
+    free_new();
     return fail(LBM_AXI_EDEVICE, "tile list upload");
   }
   if (h->dtiles) (void)hipFree(h->dtiles);
+  if (h->dtiles_odd) (void)hipFree(h->dtiles_odd);
   if (h->dtiles_plain) (void)hipFree(h->dtiles_plain);
   h->dtiles = dt;
+  h->dtiles_odd = dto;
   h->dtiles_plain = dp;
-  h->ntiles_launch = per * 8;
+  h->ntiles_launch = (int)even.size();
+  h->ntiles_odd = (int)odd.size();
   h->tile_first = first;
   h->tile_count = count;
   h->kz = kz;
+  h->kz_odd = kz_odd;
   return LBM_AXI_OK;
 }
 
@@ -742,6 +763,7 @@ void lbm_axi_destroy(lbm_axi* h) {
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   for (void* p : h->allocs) (void)hipFree(p);
   if (h->dtiles) (void)hipFree(h->dtiles);
+  if (h->dtiles_odd) (void)hipFree(h->dtiles_odd);
   if (h->dtiles_plain) (void)hipFree(h->dtiles_plain);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
@@ -774,6 +796,7 @@ int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* 
     h->check = p[0].check_interval;
     h->prm.assign(p, p + n_inst);
     h->kz = default_kz(h);  // needs the problem sizes
+    h->kz_odd = default_kz(h, true);
     auto bail = [&](int rc) {
       lbm_axi_destroy(h);
       return rc;
@@ -841,7 +864,7 @@ int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* 
       }
     }
     {
-      const int rc = build_tiles(h, h->kz);
+      const int rc = build_tiles(h, h->kz, h->kz_odd);
       if (rc) return bail(rc);
     }
     h->ddesc = (InstDev*)dalloc(h, sizeof(InstDev) * n_inst, &err);
@@ -1038,7 +1061,7 @@ int lbm_axi_compact(lbm_axi* h, int32_t* n_running) {
     if (act == h->active || (h->active.empty() && nr == h->n_inst)) return LBM_AXI_OK;
     h->active = act;
     drop_graph(h);
-    return build_tiles(h, h->kz);
+    return build_tiles(h, h->kz, h->kz_odd);
   });
 }
 
@@ -1150,8 +1173,8 @@ int lbm_axi_set_storage(lbm_axi* h, int32_t storage, int32_t storage_shift) {
     h->storage = storage;
     h->buf = all_buffer_addressable(h);
     HIPCHK(hipMemcpy(h->ddesc, h->hdesc.data(), sizeof(InstDev) * h->n_inst, hipMemcpyHostToDevice));
-    if (!h->tiles_set && default_kz(h) != h->kz) {
-      const int rc = build_tiles(h, default_kz(h));
+    if (!h->tiles_set && (default_kz(h) != h->kz || default_kz(h, true) != h->kz_odd)) {
+      const int rc = build_tiles(h, default_kz(h), default_kz(h, true));
       if (rc) return rc;
     }
     // Converged or stalled runs continue in the new storage; diverged ones stay.
@@ -1176,7 +1199,7 @@ int lbm_axi_set_tiles(lbm_axi* h, int32_t kz, int32_t blocks_per_cu) {
     h->lds_bytes = lds < h->lds_per_block ? lds : h->lds_per_block;
     drop_graph(h);
     h->tiles_set = true;
-    return build_tiles(h, kz);
+    return build_tiles(h, kz, kz);
   });
 }
 
