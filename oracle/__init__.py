@@ -1,6 +1,6 @@
 """FP64 CPU oracle of the axisymmetric MRT lattice Boltzmann model (arXiv:1409.5929).
 
-TEST INFRASTRUCTURE ONLY.  This package is the independent judge of the GPU
+TEST INFRASTRUCTURE ONLY.  This package is the independent reference for the GPU
 library: only the test suite, the package smoke check and the benchmark's
 CPU-baseline leg may import it.  It shares no code with the GPU library, and
 the GPU library never imports it.

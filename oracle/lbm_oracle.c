@@ -2,7 +2,7 @@
  * FP64 CPU oracle of the axisymmetric MRT lattice Boltzmann model for thermal
  * flow in porous media of Liu, He and Li (arXiv:1409.5929).
  *
- * TEST INFRASTRUCTURE ONLY.  This file is the independent judge of the GPU
+ * TEST INFRASTRUCTURE ONLY.  This file is the independent reference for the GPU
  * library.  Only the test suite, the package smoke check and the benchmark's
  * CPU-baseline leg may load it.  It shares no code, header, table or constant
  * with the GPU library, and the GPU library never calls it.
