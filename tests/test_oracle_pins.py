@@ -325,6 +325,46 @@ def test_annular_conduction_log_profile(oracle_mod):
         assert abs(a - exact_nu) / abs(b - exact_nu) > 1.6
 
 
+def test_pipe_conduction_mode_decays_through_the_axis(oracle_mod):
+    """No flow in a pipe with its wall held at T = 0: the slowest conduction mode
+    T = J0(lam r / R), lam the first zero of J0, keeps its shape and decays at
+    alpha lam^2 / R^2 (Eq. 12 with u = 0 in cylindrical coordinates; alpha =
+    c_sT^2 tau_T).  A slab of the same half-width would decay at alpha (pi/2)^2 / R^2,
+    less than half as fast, so the rate checks the 1/r terms of the temperature
+    lattice and the axis rows together.  The rate is taken between half and one
+    and a half decay times, after the start transient, on R = 10.5, 20.5 and 40.5;
+    its error must fall by more than 2.5 per grid doubling."""
+    from scipy.special import j0
+
+    lam = 2.404825557695773
+    errs = []
+    for nr in (11, 21, 41):
+        cfg = li.pipe(nr=nr, nz=3, phi=1.0, Da=1e8, Re=0.0, tau_nu=0.8, Pr=1.0, F_phi=0.0, T_wall=0.0)
+        cfg["accel_z"] = 0.0
+        R = nr - 0.5
+        r = 0.5 + np.arange(nr)
+        mode = j0(lam * r[:-1] / R)
+        init = np.zeros((3, 3, nr))
+        init[2] = j0(lam * r / R)[None, :]
+        o = oracle_mod.Oracle(cfg, init=init)
+        alpha = 0.2 * o.derived()["tau_T"]
+        rate = alpha * lam * lam / (R * R)
+        t1, t2 = int(0.5 / rate), int(1.5 / rate)
+        amps = []
+        for n in (t1, t2 - t1):
+            o.step(n)
+            m = o.macros()
+            T = m["T"][1, :-1]
+            a = (T * mode).sum() / (mode * mode).sum()
+            assert np.abs(T - a * mode).max() <= 0.02 * a  # the shape is kept
+            assert np.abs(m["uz"]).max() <= 1e-15 and np.abs(m["ur"]).max() <= 1e-15
+            amps.append(a)
+        o.close()
+        errs.append(abs(math.log(amps[0] / amps[1]) / (t2 - t1) / rate - 1.0))
+    assert errs[0] <= 0.05 and errs[2] <= 0.006
+    assert errs[0] / errs[1] > 2.5 and errs[1] / errs[2] > 2.5
+
+
 def test_derived_constants_eq39(oracle_mod):
     """Eq. (39) relaxation times and g beta dT = U^2 / L for the Table 2 cases."""
     for Ra, tn, tt in ((1e3, 0.9537, 1.080), (1e4, 0.6435, 0.342), (1e5, 0.5454, 0.108)):
