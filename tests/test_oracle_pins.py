@@ -325,6 +325,38 @@ def test_annular_conduction_log_profile(oracle_mod):
         assert abs(a - exact_nu) / abs(b - exact_nu) > 1.6
 
 
+@pytest.mark.parametrize("phi, G", [(0.45, 0.055), (0.75, 0.005)])
+def test_uniform_porous_flow_obeys_ergun(oracle_mod, phi, G):
+    """A body force G drives a uniform flow through a packed bed whose porosity
+    phi differs from the reference porosity phi_ref = 0.6 (porosity field, Ergun
+    F_phi).  At steady state Eq. (2) loses every gradient, so the drag of
+    Eq. (6) must balance G; written in Ergun's own form with superficial velocity
+    U and particle diameter d (fixed by K(phi_ref) = Da L^2), that is
+    G = 150 nu (1 - phi)^2 U / (phi^3 d^2) + 1.75 (1 - phi) U^2 / (phi^3 d).
+    This checks K(phi) and F_phi(phi) of Eq. (8) against the Ergun equation
+    itself.  The Forchheimer part carries 18 % and 42 % of the drag here.
+    A large r0 makes the radial wrap of the fully periodic lattice negligible."""
+    phi_ref, L, Da = 0.6, 10.0, 1e-2
+    cfg = dict(nr=3, nz=3, r0=1e6, L=L, side_rmin="periodic", side_rmax="periodic",
+               side_z="periodic", phi=phi_ref, Da=Da, F_phi=-1.0, tau_nu=0.8, Ra=0.0, Pr=1.0,
+               accel_z=G, T_rmin=0.0, T_rmax=0.0, T_ref=0.0, T_init=0.0)
+    o = oracle_mod.Oracle(cfg, phi_field=np.full((3, 3), phi))
+    nu = o.derived()["nu"]
+    o.step(3000)
+    U0 = o.macros()["uz"]
+    o.step(100)
+    m = o.macros()
+    o.close()
+    U = m["uz"].mean()
+    assert np.abs(m["uz"] - U0).max() <= 1e-14 and np.ptp(m["uz"]) <= 1e-14
+    assert 0.09 < U < 0.16
+    d = math.sqrt(150.0 * (1.0 - phi_ref) ** 2 * Da * L * L / phi_ref ** 3)
+    darcy = 150.0 * nu * (1.0 - phi) ** 2 * U / (phi ** 3 * d * d)
+    forch = 1.75 * (1.0 - phi) * U * U / (phi ** 3 * d)
+    assert forch > 0.15 * (darcy + forch)
+    assert abs((darcy + forch) / G - 1.0) <= 1e-8
+
+
 def test_pipe_conduction_mode_decays_through_the_axis(oracle_mod):
     """No flow in a pipe with its wall held at T = 0: the slowest conduction mode
     T = J0(lam r / R), lam the first zero of J0, keeps its shape and decays at
