@@ -308,8 +308,13 @@ def main():
     phi = li.porosity_grf(n, n, seed=1409)
     log("create lattice")
     stream = torch.cuda.Stream()  # the library launches on this stream; events are recorded on it
-    lat = Lattice(cfg, phi=phi.astype(np.float32), storage=args.storage,
+    phi32 = phi.astype(np.float32)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter()
+    lat = Lattice(cfg, phi=phi32, storage=args.storage,
                   check_interval=args.check_interval, stream=stream.cuda_stream)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t_create
     log(f"warmup {args.warmup} steps")
     lat.step(args.warmup)
     torch.cuda.synchronize()
@@ -335,6 +340,10 @@ def main():
     lat.set_timing(False)
     res = lat.residual()
     info = lat.info()
+    t_read = time.perf_counter()
+    host_fields = lat.fields()  # u_z, u_r, p, T and node classes into host memory
+    t_read = time.perf_counter() - t_read
+    del host_fields
     lat.close()
     copy_gbs = device_copy_gbs(torch, stream)
     variants = sweep = steady = None
@@ -393,6 +402,13 @@ def main():
             "launches": launches,
             "copy_gbs": round(copy_gbs, 1),
             "frac_of_copy": round(achieved / copy_gbs, 4),
+        },
+        # the same job with its host hand-overs: create (allocation, porosity
+        # upload, start state) before and the field read-back after the steps
+        "with_host_io": {
+            "create_s": round(t_create, 3),
+            "readback_s": round(t_read, 3),
+            "mlups": round(n * n * args.steps / (t_create + total_ms * 1e-3 + t_read) / 1e6, 1),
         },
         "storage_variants": variants,
         "sweep": sweep,
