@@ -19,6 +19,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -238,16 +239,13 @@ def time_to_steady(n_problems, cap):
     return c
 
 
-def cpu_baseline(cfg, phi, seconds: float):
-    """The FP64 oracle on a 1024 x 1024 corner of the same problem (inner
-    wall, bottom wall), stepped until `seconds` of work are done."""
+def oracle_rate(cfg: dict, phi, seconds: float):
+    """Steps of the FP64 oracle on (cfg, phi) until `seconds` of work are done:
+    (steps, seconds, threads used)."""
     import oracle
 
     oracle.build(force=False)
-    w = 1024
-    c = dict(cfg)
-    c.update(nr=w, nz=w, side_rmax="wall", therm_rmax="adiabatic")
-    o = oracle.Oracle(c, phi_field=phi[:w, :w])
+    o = oracle.Oracle(cfg, phi_field=phi)
     o.step(1)
     t0 = time.perf_counter()
     n = 0
@@ -258,9 +256,59 @@ def cpu_baseline(cfg, phi, seconds: float):
         if dt >= seconds and n >= 2:
             break
     o.close()
-    return dict(value=w * w * n / dt / 1e6, unit="MLUPS", cores=oracle.threads(), kind="oracle",
-                sample=f"{w}x{w} corner window of the {cfg['nr']}x{cfg['nz']} problem "
-                       f"(same physics and porosity field), {n} steps in {dt:.1f} s, FP64")
+    return n, dt, oracle.threads()
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, phi, seconds: float):
+    """The FP64 oracle on a 1024 x 1024 corner of the same problem (inner
+    wall, bottom wall), stepped until `seconds` of work are done, with all the
+    host threads OpenMP is given; then the same window on one thread, in a
+    child process (the oracle's thread count is fixed once it is loaded)."""
+    import tempfile
+
+    import numpy as np
+
+    w = 1024
+    c = dict(cfg)
+    c.update(nr=w, nz=w, side_rmax="wall", therm_rmax="adiabatic")
+    win = np.ascontiguousarray(phi[:w, :w])
+    n, dt, threads = oracle_rate(c, win, seconds)
+    out = dict(value=w * w * n / dt / 1e6, unit="MLUPS", cores=threads, kind="oracle",
+               sample=f"{w}x{w} corner window of the {cfg['nr']}x{cfg['nz']} problem "
+                      f"(same physics and porosity field), {n} steps in {dt:.1f} s, FP64",
+               cpu_model=cpu_model(), host_cpus=os.cpu_count())
+    one_s = max(2.0, seconds / 3)
+    with tempfile.TemporaryDirectory() as d:
+        np.save(os.path.join(d, "phi.npy"), win)
+        with open(os.path.join(d, "cfg.json"), "w") as f:
+            json.dump(c, f)
+        code = ("import json, os, sys, numpy as np, bench\n"
+                "d = sys.argv[1]\n"
+                "c = json.load(open(os.path.join(d, 'cfg.json')))\n"
+                "n, dt, t = bench.oracle_rate(c, np.load(os.path.join(d, 'phi.npy')), float(sys.argv[2]))\n"
+                "print(json.dumps([n, dt, t]))\n")
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, "-c", code, d, str(one_s)], cwd=os.path.dirname(os.path.abspath(__file__)),
+                           env=env, capture_output=True, text=True, timeout=300)
+    if r.returncode == 0:
+        n1, dt1, t1 = json.loads(r.stdout.strip().splitlines()[-1])
+        out["single_thread"] = dict(value=w * w * n1 / dt1 / 1e6, threads=t1,
+                                    sample=f"same window, {n1} steps in {dt1:.1f} s")
+    else:
+        out["single_thread"] = None
+        log(f"single-thread oracle run failed: {r.stderr.strip()[-300:]}")
+    return out
 
 
 def main():
