@@ -226,6 +226,15 @@ def time_to_steady(n_problems, cap):
     c.update(problems=n_problems, grid=ws.GRID, tol=1e-8, max_steps=cap,
              converged_cold=int((cold["status"] == 1).sum()), converged_warm=int((warm["status"] == 1).sum()),
              predict_s=round(t_pred, 3), wall_warm_s=round(warm["wall"] + t_pred, 3))
+    # Non-learned control: fluid at rest with the radial conduction profile
+    # ln(r_o / r) / ln R* of T, over the problems that converge from all three starts.
+    cond = ws.solve(cfgs, init=[ws.conduction_start(cf) for cf in cfgs], max_steps=cap, fields=False)
+    ok3 = ok & (cond["status"] == 1)
+    cc, cw = ws.compare(cold, cond, ok3), ws.compare(cold, warm, ok3)
+    c["conduction_control"] = dict(n=cc["n"], converged=int((cond["status"] == 1).sum()),
+                                   steps_ratio_total=cc.get("steps_ratio_total"),
+                                   warm_steps_ratio_total_same_set=cw.get("steps_ratio_total"),
+                                   wall_s=round(cond["wall"], 3))
     # The batch wall times above run until the slowest problem stops (the cap
     # for those that do not converge); the same comparison restricted to the
     # problems that converge from both starts:
