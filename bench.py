@@ -308,8 +308,12 @@ def cpu_baseline(cfg, phi, seconds: float):
                 "n, dt, t = bench.oracle_rate(c, np.load(os.path.join(d, 'phi.npy')), float(sys.argv[2]))\n"
                 "print(json.dumps([n, dt, t]))\n")
         env = dict(os.environ, OMP_NUM_THREADS="1")
-        r = subprocess.run([sys.executable, "-c", code, d, str(one_s)], cwd=os.path.dirname(os.path.abspath(__file__)),
-                           env=env, capture_output=True, text=True, timeout=300)
+        try:
+            r = subprocess.run([sys.executable, "-c", code, d, str(one_s)],
+                               cwd=os.path.dirname(os.path.abspath(__file__)), env=env,
+                               capture_output=True, text=True, timeout=300)
+        except subprocess.TimeoutExpired:
+            r = subprocess.CompletedProcess([], 1, "", "timed out after 300 s")
     if r.returncode == 0:
         n1, dt1, t1 = json.loads(r.stdout.strip().splitlines()[-1])
         out["single_thread"] = dict(value=w * w * n1 / dt1 / 1e6, threads=t1,
