@@ -264,3 +264,60 @@ def test_fp16_handoff_heater_steady_nusselt(L):
     assert abs(m16 - m32) <= 2e-3 * m32
     assert abs(nu16 - nu32) <= 1e-3 * nu32
     assert abs(nu16 - 17.09) <= 0.02 * 17.09
+
+
+def _window(cfg, phi, j0, k0, w):
+    """w x w sub-problem: real walls where the window touches them, walls
+    elsewhere (which contaminate only a margin)."""
+    c = dict(cfg)
+    c.update(nr=w, nz=w, r0=cfg["r0"] + j0, side_z="wall")
+    if j0 > 0:
+        c.update(side_rmin="wall", therm_rmin="adiabatic")
+    if j0 + w < cfg["nr"]:
+        c.update(side_rmax="wall", therm_rmax="adiabatic")
+    return c, phi[k0:k0 + w, j0:j0 + w]
+
+
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_full_size_16bit_sampled_windows(L, oracle_mod, storage):
+    """8192^2 throughput problem in 16-bit storage, in the benchmark's launch
+    configuration: after n steps a node farther than n + 2 from a window's
+    artificial sides depends only on the window, so the oracle run on the
+    window gives it up to the storage rounding; the bound is the 512^2 one,
+    6 u16 in relative L2 (velocity measured against a floor near rest).  Where
+    the oracle's temperature is identically zero (cold outer wall, before the
+    heat arrives) T is checked absolutely, against 6 u16 dT."""
+    from tests.parity import U_FLOOR
+
+    size, n, w = 8192, 32, 100
+    cfg, _ = li.variable_porosity_annulus(n=size)
+    phi = li.porosity_grf(size, size, seed=1409)
+    lat = L.Lattice(cfg, phi=phi, storage=storage, check_interval=100)
+    lat.step(n)
+    g = lat.fields()
+    lat.close()
+    tol = 6 * U16[storage]
+    margin = n + 2
+    worst = 0.0
+    for j0, k0 in [(0, 0), (0, size // 2), (0, size - w), (size - w, size - w), (size - w, 1234)]:
+        c, ph = _window(cfg, phi, j0, k0, w)
+        o = oracle_mod.Oracle(c, phi_field=ph)
+        o.step(n)
+        m = o.macros()
+        o.close()
+        jl = 0 if j0 == 0 else margin
+        jh = w if j0 + w == size else w - margin
+        kl = 0 if k0 == 0 else margin
+        kh = w if k0 + w == size else w - margin
+        sub = {k: g[k][k0 + kl:k0 + kh, j0 + jl:j0 + jh] for k in ("uz", "ur", "p", "T", "mask")}
+        ref = {k: m[k][kl:kh, jl:jh] for k in ("uz", "ur", "p", "T", "mask")}
+        np.testing.assert_array_equal(sub["mask"], ref["mask"])
+        e = rel_errors(sub, ref, u_floor=U_FLOOR)
+        if not np.any(ref["T"]):
+            e["T"] = float(np.abs(sub["T"]).max() / cfg["delta_T"])
+        print(f"{storage} 8192^2 window ({j0}, {k0}) n={n}: u {e['u']:.2e} p {e['p']:.2e} "
+              f"T {e['T']:.2e} (tol {tol:.1e})", flush=True)
+        worst = max(worst, *e.values())
+        for k, v in e.items():
+            assert v <= tol, (storage, j0, k0, k, v)
+    print(f"{storage} 8192^2 windows: worst {worst:.2e}", flush=True)
