@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import lbm_inputs as li
-from tests.parity import TOL_FP32, assert_parity
+from tests.parity import TOL_FP32, assert_parity, rel_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -103,3 +103,37 @@ def test_sweep_batch_against_oracle(L, oracle_mod):
         o.step(200)
         assert_parity(got[i], o.macros(), tol=TOL_FP32, label=f"sweep instance {i}")
         o.close()
+
+
+def test_full_sweep_fp16_against_oracle(L, oracle_mod):
+    """The benchmark's sweep: 1024 instances, grids 32-512, FP16 storage, the
+    autotuner's launch shape and step graphs.  The smallest, the largest, the
+    widest and the tallest instance are compared with the oracle after the
+    same number of steps, to the 16-bit storage bound (6 u16 = 2.9e-3 in
+    relative L2, velocity against a floor near rest)."""
+    from tests.parity import U_FLOOR
+
+    cfgs = li.sweep(n_inst=1024, seed=1409)
+    lat = L.Lattice(cfgs, storage="fp16", check_interval=1000, tol=1e-8, max_steps=2_000_000)
+    tune = lat.autotune(trial_steps=10)
+    target = lat.info()["t"] + 90  # the autotuner's trial steps are real steps
+    lat.step(90)
+    nodes = np.array([c["nr"] * c["nz"] for c in cfgs])
+    aspect = np.array([c["nr"] / c["nz"] for c in cfgs])
+    picks = sorted({int(nodes.argmin()), int(nodes.argmax()), int(aspect.argmax()), int(aspect.argmin())})
+    got = {i: lat.fields(i) for i in picks}
+    steps = {i: lat.info(i)["t"] for i in picks}
+    lat.close()
+    tol = 6 * 2.0 ** -11
+    for i in picks:
+        assert steps[i] == target
+        o = oracle_mod.Oracle(cfgs[i])
+        o.step(target)
+        m = o.macros()
+        o.close()
+        np.testing.assert_array_equal(got[i]["mask"], m["mask"])
+        e = rel_errors(got[i], m, u_floor=U_FLOOR)
+        print(f"sweep instance {i} ({cfgs[i]['nr']}x{cfgs[i]['nz']}, kz {tune['kz']}): "
+              f"u {e['u']:.2e} p {e['p']:.2e} T {e['T']:.2e} (tol {tol:.1e})", flush=True)
+        for k, v in e.items():
+            assert v <= tol, (i, k, v)
