@@ -6,6 +6,7 @@ conservation laws, and closed-form solutions of the macroscopic equations the
 model is built to recover (Eqs. 1-5).
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -395,6 +396,25 @@ def test_pipe_conduction_mode_decays_through_the_axis(oracle_mod):
         errs.append(abs(math.log(amps[0] / amps[1]) / (t2 - t1) / rate - 1.0))
     assert errs[0] <= 0.05 and errs[2] <= 0.006
     assert errs[0] / errs[1] > 2.5 and errs[1] / errs[2] > 2.5
+
+
+def test_oracle_steady_annulus_matches_table2():
+    """The oracle's steady Nusselt numbers for the Sec. 4.2 annulus (R* = 2,
+    A = 2, Pr = 0.7, no porous medium), stored in tests/golden/table2_nu_oracle.txt
+    by make_nusselt_golden.py (which calls only the oracle), against the
+    "Present" column of Table 2: within 0.3 % (0.23, 0.10, 0.04 % at Ra = 1e3,
+    1e4, 1e5).  At steady state the heat entering at the inner wall leaves at
+    the outer one, Nu_i = Nu_o (Eq. 42), up to the first-order wall error
+    (1.3, 0.3, 0.5 % here; bound 1.5 %)."""
+    printed = {1e3: 1.710, 1e4: 3.211, 1e5: 5.768}
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "table2_nu_oracle.txt")
+    rows = [line.split() for line in open(path) if line.strip() and not line.startswith("#")]
+    assert sorted(float(r[0]) for r in rows) == sorted(printed)
+    for ra, _, res, nu_i, nu_o in rows:
+        ra, res, nu_i, nu_o = float(ra), float(res), float(nu_i), float(nu_o)
+        assert res <= 1e-10
+        assert abs(nu_i - printed[ra]) <= 0.003 * printed[ra], (ra, nu_i)
+        assert abs(nu_i - nu_o) <= 0.015 * nu_i, (ra, nu_i, nu_o)
 
 
 def test_derived_constants_eq39(oracle_mod):
