@@ -186,10 +186,12 @@ int lbm_axi_macros(lbm_axi* h, int32_t inst, float* uz, float* ur, float* p, flo
  * psi(r_j, z_k) = integral from r0 to r_j of r u_z dr by the trapezoid rule
  * over the rows (FP64 sums of the FP32 velocity field); with an axis at r_min
  * psi = 0 on the axis and the integral starts at r = 0 (row 0 holds
- * r0 (r0 u_z) / 2, the trapezoid over [0, r0]).  In lattice units
- * (divide by nu L for the scale of the paper's table).  psi: NULL or [nz][nr]
- * floats, device memory if dst_is_device (written on the handle's stream)
- * else host memory.  psi_absmax: NULL or one host double, max |psi|.  The
+ * r0 (r0 u_z) / 2, the trapezoid over [0, r0]).  In lattice units; divide
+ * by alpha_e L, alpha_e = c_sT^2 tau_T the effective thermal diffusivity
+ * (text after Eq. 38), for the scale of Table 3 (the paper does not state
+ * it; this one matches its values at Da = 1e-4 and 1e-2, nu L does not).
+ * psi: NULL or [nz][nr] floats, device memory if dst_is_device (written on
+ * the handle's stream) else host memory.  psi_absmax: NULL or one host double, max |psi|.  The
  * call allocates temporary device memory and waits for the stream.
  */
 int lbm_axi_stream_function(lbm_axi* h, int32_t inst, float* psi, double* psi_absmax,
