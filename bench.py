@@ -11,7 +11,12 @@ before the timed region starts.
 Prints one JSON line: MLUPS (million node updates per second, one node = both
 lattices), the HBM roofline of the step kernel (algorithmic bytes per launch
 over its average duration from HIP events on the library's stream) and the
-FP64 CPU oracle timed on a bounded sample of the same problem.
+FP64 CPU oracle timed on a bounded sample of the same problem (all host
+threads and one).  Also on the line: the same job with its host hand-overs
+(create, field read-back), the FP16 and BF16 storage variants, the
+1024-instance batched sweep, and the time to steady state of 32 held-out
+128^2 problems from a cold start, from the learned warm start and from the
+conduction-profile start.
 """
 from __future__ import annotations
 
