@@ -347,6 +347,8 @@ def main():
     ap.add_argument("--steady-max-steps", type=int, default=600_000)
     ap.add_argument("--sweep-to-steady", type=int, default=0, metavar="CAP",
                     help="only run the 1024-instance sweep toward res <= 1e-8 for up to CAP steps")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="only run the batched sweep (the --sweep-instances / --sweep-steps line)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 2 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -364,6 +366,11 @@ def main():
 
     if not torch.cuda.is_available():
         sys.exit("bench.py needs a GPU")
+    if args.sweep_only:
+        stream = torch.cuda.Stream()
+        print(json.dumps({"sweep": sweep_batch(Lattice, args.sweep_instances, args.sweep_steps, stream)}),
+              flush=True)
+        return
     if args.sweep_to_steady > 0:
         print(json.dumps({"sweep_to_steady": sweep_to_steady(args.sweep_instances, args.sweep_to_steady)}),
               flush=True)
