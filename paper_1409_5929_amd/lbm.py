@@ -211,6 +211,7 @@ class Lattice:
         h = ctypes.c_void_p()
         st = ctypes.c_void_p(stream) if stream is not None else _current_stream()
         _check(lib.lbm_axi_create(arr, n, phi_ptrs, init_ptrs, st, ctypes.byref(h)))
+        self._stream = st.value or 0
         self._h = h
         self._lib = lib
         self.n_inst = n
@@ -250,7 +251,11 @@ class Lattice:
         return out
 
     def fields_device(self, inst: int = 0) -> dict:
-        """u_z, u_r, p, T as torch device tensors written on the handle's stream."""
+        """u_z, u_r, p, T as torch device tensors, written on the handle's
+        stream.  The tensors belong to torch's current stream: unless the
+        handle runs on that very stream, this waits for the handle's stream
+        before returning, so that neither a reader nor torch's allocator sees
+        them before they are written."""
         import torch
 
         nz, nr = self.shapes[inst]
@@ -259,6 +264,9 @@ class Lattice:
         _check(self._lib.lbm_axi_macros(self._h, int(inst), out["uz"].data_ptr(),
                                         out["ur"].data_ptr(), out["p"].data_ptr(),
                                         out["T"].data_ptr(), None, 1))
+        # A zero stream value means the library created its own stream.
+        if self._stream == 0 or self._stream != (torch.cuda.current_stream().cuda_stream or 0):
+            self.sync()
         return out
 
     def stream_function(self, inst: int = 0, field: bool = True):

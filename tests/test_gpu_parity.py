@@ -181,6 +181,25 @@ def test_device_fields_equal_host_fields(L):
     lat.close()
 
 
+@pytest.mark.parametrize("own_stream", [False, True])
+def test_device_fields_from_a_handle_on_another_stream(L, own_stream):
+    """A handle on a stream other than torch's current one (a torch side
+    stream, or the library's own when given the null stream): the device
+    fields are read on torch's stream with no synchronisation by the caller."""
+    import torch
+
+    cfg = li.annulus(nr=300, nz=200, Ra=1e5, Da=1e-3)
+    side = torch.cuda.Stream()
+    lat = L.Lattice(cfg, stream=0 if own_stream else side.cuda_stream)
+    lat.step(41)
+    dev = lat.fields_device()
+    got = {k: dev[k].cpu().numpy() for k in ("uz", "ur", "p", "T")}
+    host = lat.fields()
+    lat.close()
+    for k in ("uz", "ur", "p", "T"):
+        np.testing.assert_array_equal(got[k], host[k])
+
+
 @pytest.mark.parametrize("Ra, nu_paper", [(1e3, 1.710), (1e4, 3.211), (1e5, 5.768)])
 def test_table2_mean_nusselt(L, Ra, nu_paper):
     """Sec. 4.2 / Table 2: annulus without porous medium, 100 x 200 grid,
