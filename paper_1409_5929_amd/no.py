@@ -99,17 +99,34 @@ class WarmStartNet:
                              f"{self.height}, {self.width})")
         return ctypes.c_void_p(t.data_ptr())
 
+    def _ordered(self, call):
+        """Run call() with the handle's stream ordered after torch's current
+        stream (which wrote the inputs) and the current stream after the
+        handle's (which writes the outputs) when the two differ."""
+        import torch
+
+        cur = torch.cuda.current_stream()
+        if (cur.cuda_stream or 0) == (self.stream or 0):
+            return call()
+        own = torch.cuda.ExternalStream(self.stream)
+        own.wait_stream(cur)
+        out = call()
+        cur.wait_stream(own)
+        return out
+
     def forward(self, x):
         import torch
 
         y = torch.empty((x.shape[0], 3, self.height, self.width), dtype=torch.float32, device=x.device)
-        _check(self._lib.lbm_no_forward(self._h, self._tensor(x, 6), int(x.shape[0]), self._tensor(y, 3)))
+        self._ordered(lambda: _check(self._lib.lbm_no_forward(self._h, self._tensor(x, 6), int(x.shape[0]),
+                                                               self._tensor(y, 3))))
         return y
 
     def gradients(self, x, target) -> float:
         loss = ctypes.c_double()
-        _check(self._lib.lbm_no_gradients(self._h, self._tensor(x, 6), self._tensor(target, 3), int(x.shape[0]),
-                                          ctypes.byref(loss)))
+        self._ordered(lambda: _check(self._lib.lbm_no_gradients(self._h, self._tensor(x, 6),
+                                                                 self._tensor(target, 3), int(x.shape[0]),
+                                                                 ctypes.byref(loss))))
         return loss.value
 
     def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):

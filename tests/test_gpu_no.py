@@ -122,3 +122,29 @@ def test_invalid_arguments_are_refused(torch):
     with pytest.raises(NoError):
         net.forward(torch.zeros((3, 6, 32, 40), device="cuda"))  # batch above max_batch
     net.close()
+
+
+def test_network_on_another_stream_is_ordered(torch):
+    """A network created on a side stream and called under torch's current
+    stream: its inputs, written by torch on the current stream just before,
+    are read only after they are written, and its outputs are read there only
+    after they are written.  Results are bit-identical to a network on the
+    current stream."""
+    from paper_1409_5929_amd.no import WarmStartNet
+
+    params, x, t = problem(seed=11, B=4)
+    side = torch.cuda.Stream()
+    a = WarmStartNet(WIDTHS, 32, 40, 4, params)
+    b = WarmStartNet(WIDTHS, 32, 40, 4, params, stream=side.cuda_stream)
+    xs = torch.from_numpy(x).cuda()
+    ts = torch.from_numpy(t).cuda()
+    ya = a.forward(xs * 2.0 - 1.0).cpu().numpy()
+    yb = b.forward(xs * 2.0 - 1.0).cpu().numpy()
+    la = a.gradients(xs * 0.5, ts + 0.25)
+    lb = b.gradients(xs * 0.5, ts + 0.25)
+    ga, gb = a.grads(), b.grads()
+    a.close()
+    b.close()
+    np.testing.assert_array_equal(ya, yb)
+    assert la == lb
+    np.testing.assert_array_equal(ga, gb)
