@@ -49,3 +49,42 @@ def test_table2_annulus_is_sec_4_2():
     assert (c["phi"], c["Da"], c["Pr"]) == (1.0, 1e8, 0.7)
     assert math.isclose((c["r0"] + c["L"]) / c["r0"], 2.0)
     assert c["T_ref"] == 0.5 * (c["T_rmin"] + c["T_rmax"])
+
+
+def test_porosity_field_recipe():
+    """Seeded, reproducible; mean 0.6 and standard deviation 0.15 before the
+    clip to [0.3, 0.95]; spatially correlated over about sigma = 8 cells."""
+    a = li.porosity_grf(512, 512, seed=1409)
+    b = li.porosity_grf(512, 512, seed=1409)
+    c = li.porosity_grf(512, 512, seed=1410)
+    np.testing.assert_array_equal(a, b)
+    assert not np.array_equal(a, c)
+    assert a.min() >= 0.3 and a.max() <= 0.95
+    assert abs(a.mean() - 0.6) < 0.01 and abs(a.std() - 0.15) < 0.01
+    d = a - a.mean()
+    corr = lambda s: float((d[:, s:] * d[:, :-s]).mean() / d.var())  # noqa: E731
+    assert corr(1) > 0.95 and corr(8) > 0.5 and corr(64) < 0.1
+
+
+def test_sweep_distribution():
+    """1024 annuli: grid sides uniform on {32, ..., 512}; Ra, Da and R*
+    log-uniform on their ranges; phi uniform on [0.3, 0.95]; Pr from
+    {0.71, 1, 7}; Ergun Forchheimer coefficient; reproducible from the seed."""
+    cfgs = li.sweep(n_inst=1024, seed=1409)
+    assert cfgs == li.sweep(n_inst=1024, seed=1409)
+    nr = np.array([c["nr"] for c in cfgs])
+    nz = np.array([c["nz"] for c in cfgs])
+    sizes = set(range(32, 513, 32))
+    assert set(nr) == sizes and set(nz) == sizes
+    ra = np.log10([c["Ra"] for c in cfgs])
+    da = np.log10([c["Da"] for c in cfgs])
+    rs = np.log([(c["r0"] + c["L"]) / c["r0"] for c in cfgs])
+    phi = np.array([c["phi"] for c in cfgs])
+    assert 3.0 <= ra.min() and ra.max() <= 6.0 and abs(ra.mean() - 4.5) < 0.1
+    assert -6.0 <= da.min() and da.max() <= -2.0 and abs(da.mean() + 4.0) < 0.15
+    assert np.log(1.2) - 1e-12 <= rs.min() and rs.max() <= np.log(10.0) + 1e-12
+    assert abs(rs.mean() - 0.5 * (np.log(1.2) + np.log(10.0))) < 0.05
+    assert 0.3 <= phi.min() and phi.max() <= 0.95 and abs(phi.mean() - 0.625) < 0.02
+    assert {c["Pr"] for c in cfgs} == {0.71, 1.0, 7.0}
+    assert all(c["F_phi"] < 0 for c in cfgs)
+    assert all(c["L"] == c["nr"] - 1 for c in cfgs)
