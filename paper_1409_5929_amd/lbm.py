@@ -6,11 +6,11 @@ and a HIP stream to the library and unpacks what it returns.  PyTorch, when
 present, only supplies the stream and device buffers; it is imported before
 the library is loaded so that both share one HIP runtime.
 
-The entry points mirror ``include/lbm_axi.h``:
-  create -> Lattice(...), step -> Lattice.step, macros -> Lattice.fields,
-  stream_function -> Lattice.stream_function, pipe_nusselt -> Lattice.pipe_nusselt,
-  residual -> Lattice.residual,
-  info -> Lattice.info, destroy -> Lattice.close.
+The entry points mirror ``include/lbm_axi.h``: lbm_axi_create is
+Lattice(...), lbm_axi_default_params fills every parameter a problem
+dictionary leaves out, and every other lbm_axi_<name> is Lattice.<name>
+(macros is also available as fields, destroy as close; macros with device
+outputs is fields_device).
 """
 from __future__ import annotations
 
@@ -221,6 +221,8 @@ class Lattice:
             self._lib.lbm_axi_destroy(self._h)
             self._h = ctypes.c_void_p()
 
+    destroy = close
+
     def __del__(self):
         try:
             self.close()
@@ -249,6 +251,8 @@ class Lattice:
                                         out["T"].ctypes.data, mask.ctypes.data, 0))
         out["mask"] = mask
         return out
+
+    macros = fields
 
     def fields_device(self, inst: int = 0) -> dict:
         """u_z, u_r, p, T as torch device tensors, written on the handle's

@@ -5,6 +5,11 @@ all run in ``liblbm_no.so`` (HIP, gfx950).  Tensors are torch device tensors
 (float32, contiguous, [batch][channel][height][width]); torch provides device
 memory and streams.  Importing works without a GPU; creating a network needs
 the built library and raises if it is missing.
+
+The entry points mirror ``include/lbm_no.h``: lbm_no_create is
+WarmStartNet(...), lbm_no_param_count is param_count, and every other
+lbm_no_<name> is WarmStartNet.<name> (get(which) also as params() and
+grads(), destroy also as close()).
 """
 from __future__ import annotations
 
@@ -133,13 +138,15 @@ class WarmStartNet:
         _check(self._lib.lbm_no_adam(self._h, float(lr), float(beta1), float(beta2), float(eps)))
 
     def params(self) -> np.ndarray:
-        out = np.empty(param_count(self.widths), dtype=np.float32)
-        _check(self._lib.lbm_no_get(self._h, 0, _fptr(out)))
-        return out
+        return self.get(0)
 
     def grads(self) -> np.ndarray:
+        return self.get(1)
+
+    def get(self, which: int) -> np.ndarray:
+        """Parameters (which = 0) or the last gradients (which = 1), host float32."""
         out = np.empty(param_count(self.widths), dtype=np.float32)
-        _check(self._lib.lbm_no_get(self._h, 1, _fptr(out)))
+        _check(self._lib.lbm_no_get(self._h, int(which), _fptr(out)))
         return out
 
     def set_params(self, params):
@@ -153,6 +160,8 @@ class WarmStartNet:
         if getattr(self, "_h", None):
             self._lib.lbm_no_destroy(self._h)
             self._h = None
+
+    destroy = close
 
     def __del__(self):
         try:

@@ -118,3 +118,27 @@ def test_network_library_exports_and_counts_parameters():
     assert lib.lbm_no_forward(None, None, 1, None) == -1
     assert lib.lbm_no_adam(None, 1e-3, 0.9, 0.999, 1e-8) == -1
     lib.lbm_no_destroy(None)
+
+
+def test_binding_has_every_entry_point_by_name():
+    """Every lbm_axi_<name> of the header is Lattice.<name> (create is the
+    constructor; default_params fills problem dictionaries; last_error is read
+    by the error path)."""
+    from paper_1409_5929_amd.lbm import Lattice
+
+    text = open(HEADER).read()
+    names = sorted(set(re.findall(r"\blbm_axi_([a-z_]+)\s*\(", text)))
+    special = {"create", "default_params", "last_error"}
+    missing = [n for n in names if n not in special and not callable(getattr(Lattice, n, None))]
+    assert not missing, missing
+
+
+def test_network_binding_has_every_entry_point_by_name():
+    from paper_1409_5929_amd import no
+
+    text = open(os.path.join(ROOT, "include", "lbm_no.h")).read()
+    names = sorted(set(re.findall(r"\blbm_no_([a-z_]+)\s*\(", text)))
+    special = {"create", "param_count", "last_error"}
+    missing = [n for n in names if n not in special and not callable(getattr(no.WarmStartNet, n, None))]
+    assert not missing, missing
+    assert callable(no.param_count)
