@@ -198,6 +198,43 @@ def test_fp16_beyond_4gib_uses_flat_addressing(L, oracle_mod):
         assert max(e.values()) <= tol, (j0, k0, e)
 
 
+
+def test_fp32_beyond_2g_elements(L, oracle_mod):
+    """The same 13000^2 annulus in FP32: 14 planes of 169M nodes are 2.37G
+    elements (9.5 GB), so element offsets pass 2^31 and the FP32 steps,
+    whose odd step has its own load pipeline, must index in 64 bits.
+    Windows after 5 steps (both parities and a second even step) against the
+    oracle at the FP32 bound."""
+    from tests.parity import TOL_FP32
+    from tests.test_gpu_parity import _window
+
+    size, n, w = 13000, 5, 30
+    cfg, _ = li.variable_porosity_annulus(n=size)
+    phi = li.porosity_grf(size, size, seed=1409)
+    lat = L.Lattice(cfg, phi=phi, storage="fp32", check_interval=0)
+    assert lat.info()["device_bytes"] > 14 * size * size * 4 > 8 * 2 ** 30
+    lat.step(n)
+    g = lat.fields()
+    lat.close()
+    margin = n + 2
+    for j0, k0 in [(0, 0), (size - w, size // 2), (size // 2, size - w), (size - w, size - w)]:
+        c, ph = _window(cfg, phi, j0, k0, w)
+        c["side_z"] = "wall"
+        o = oracle_mod.Oracle(c, phi_field=ph)
+        o.step(n)
+        m = o.macros()
+        o.close()
+        jl = 0 if j0 == 0 else margin
+        jh = w if j0 + w == size else w - margin
+        kl = 0 if k0 == 0 else margin
+        kh = w if k0 + w == size else w - margin
+        sub = {k: g[k][k0 + kl:k0 + kh, j0 + jl:j0 + jh] for k in ("uz", "ur", "p", "T", "mask")}
+        ref = {k: m[k][kl:kh, jl:jh] for k in ("uz", "ur", "p", "T", "mask")}
+        np.testing.assert_array_equal(sub["mask"], ref["mask"])
+        e = rel_errors(sub, ref)
+        print(f"13000^2 FP32 window {(j0, k0)}: {e}", flush=True)
+        assert max(e.values()) <= TOL_FP32, (j0, k0, e)
+
 def _boundary_cases():
     heater = li.heater_annulus(Da=1e-2, nr=48, nz=40, Ra=1e5)
     pipe = li.developing_pipe(Da=1e-2, nr=21, A=2.0, u_in=0.02)
