@@ -180,6 +180,17 @@ int lbm_axi_macros(lbm_axi* h, int32_t inst, float* uz, float* ur, float* p, flo
                    uint8_t* mask, int32_t dst_is_device);
 
 /*
+ * Density deviation rho - 1 of instance inst at its current time (Eq. 26;
+ * the rest density is 1), into drho ([nz][nr] floats).  The library keeps
+ * populations as deviations from the rest state, so this value carries FP32's
+ * relative precision even where rho is within 1e-6 of 1, which the total
+ * p = rho c_s^2 / phi of lbm_axi_macros cannot resolve.  Wall nodes report the
+ * density they are built from (lbm_axi_macros).  dst_is_device as in
+ * lbm_axi_macros.  LBM_AXI_EINVAL if drho is NULL.
+ */
+int lbm_axi_density_deviation(lbm_axi* h, int32_t inst, float* drho, int32_t dst_is_device);
+
+/*
  * Stokes stream function of instance inst at its current time (the paper
  * reports its largest magnitude in Table 3 without defining it):
  * u_z = (1/r) dpsi/dr, u_r = -(1/r) dpsi/dz, psi = 0 on the r_min wall, i.e.
@@ -232,9 +243,12 @@ int lbm_axi_pipe_nusselt(lbm_axi* h, int32_t inst, int32_t area, double* nu, dou
 int lbm_axi_residual(lbm_axi* h, double* res, double* nu_i, double* nu_o, int32_t* status);
 
 /*
- * Details of instance inst (waits for the stream): out[0] = its time step,
- * out[1] = step of the latest check, out[2] = run state, out[3] = bytes of
- * device memory the handle holds.  out has 4 entries.
+ * Details of instance inst (waits for the stream): out[0] = its own time
+ * level (the steps it has taken: the handle's level while it runs, the level
+ * at which it stopped once it has stopped, less the handle steps it sat out
+ * before a restart by lbm_axi_set_storage), out[1] = handle level of its
+ * latest check, out[2] = run state, out[3] = bytes of device memory the
+ * handle holds.  out has 4 entries.
  */
 int lbm_axi_info(lbm_axi* h, int32_t inst, int64_t* out);
 
@@ -272,8 +286,14 @@ int lbm_axi_set_tiles(lbm_axi* h, int32_t kz, int32_t blocks_per_cu);
  * noise, then finish in FP32.
  * Waits for the stream; allocates the new arrays before freeing the old ones,
  * so on LBM_AXI_ENOMEM the handle is unchanged.  Step count, the last check
- * and the check buffers carry over; converged and stalled instances are set
- * running again (diverged ones stay diverged).
+ * and the check buffers carry over.  Converged instances are set running
+ * again from the state at which they stopped: one whose stopping level and
+ * the handle's current level differ in parity first takes one step on its
+ * own, so that its in-place (AA) layout matches the handle's; the handle steps
+ * it sat out do not count as its steps (lbm_axi_info), and its first check
+ * after the restart records the Nusselt numbers only (residual +inf), since
+ * a residual needs a full check interval of its own steps.  Stalled and
+ * diverged instances stay stopped.
  */
 int lbm_axi_set_storage(lbm_axi* h, int32_t storage, int32_t storage_shift);
 

@@ -63,7 +63,10 @@ int fail(int code, const std::string& msg) {
 
 struct DevResult {
   double res, res_u, res_T, nu_i, nu_o, u_rms;
-  long long t_check, t_stop;
+  long long t_check, t_stop;  // handle time levels (t_stop: level at which the run stopped)
+  long long t_off;  // handle steps the instance sat out while stopped (even); its own
+                    // time level is the handle's minus t_off
+  long long t_arm;  // first check whose comparison spans steps the instance took
 };
 
 struct ResTile {
@@ -244,8 +247,10 @@ __device__ inline double wave_sum(double v) {
 // |du|^2, node count, dT^2, |u|^2, and the Eq. (42) integrands on both walls.
 __global__ __launch_bounds__(RB) void k_resid(const InstDev* __restrict__ descs,
                                               const ResTile* __restrict__ rts, int cur,
+                                              const int* __restrict__ status,
                                               double* __restrict__ part) {
   const ResTile rt = rts[blockIdx.x];
+  if (status[rt.inst] != RUN) return;  // k_final skips stopped instances
   const InstDev D = descs[rt.inst];
   const float* cu = cur ? D.mac[1] : D.mac[0];
   const float* pv = cur ? D.mac[0] : D.mac[1];
@@ -300,10 +305,13 @@ __global__ __launch_bounds__(RB) void k_resid(const InstDev* __restrict__ descs,
   }
 }
 
-// Per instance (one block each): sum its partials in a fixed order, form the
-// residual (root-mean-square change of u and T over the fluid nodes since the
-// previous check, per step, scaled by Ma c_s and dT) and the Nusselt numbers,
-// update the run state.
+// Per running instance (one block each): sum its partials in a fixed order,
+// form the residual (root-mean-square change of u and T over the fluid nodes
+// since the previous check, per step, scaled by Ma c_s and dT) and the
+// Nusselt numbers, update the run state.  A stopped instance keeps the
+// results of the check at which it stopped.  A check before t_arm (the first
+// one after a restart) compares with a check buffer the instance did not
+// write one interval earlier: it records the Nusselt numbers only.
 __global__ __launch_bounds__(RB) void k_final(const int* __restrict__ first,
                                               const double* __restrict__ part, long long t,
                                               double per_step, const double* __restrict__ tol,
@@ -312,6 +320,7 @@ __global__ __launch_bounds__(RB) void k_final(const int* __restrict__ first,
                                               int* __restrict__ status,
                                               DevResult* __restrict__ out) {
   const int inst = blockIdx.x;
+  if (status[inst] != RUN) return;  // uniform across the block
   double a[6] = {0, 0, 0, 0, 0, 0};
   const int b0 = first[2 * inst], nb = first[2 * inst + 1];
   for (int b = b0 + (int)threadIdx.x; b < b0 + nb; b += RB)
@@ -342,15 +351,18 @@ __global__ __launch_bounds__(RB) void k_final(const int* __restrict__ first,
   r.nu_o = -nu_scale[4 * inst + 1] * a[5];
   r.u_rms = sqrt(a[3] / nf);
   r.t_check = t;
-  int st = status[inst];
-  if (st == RUN) {
-    if (!isfinite(res)) st = DIVERGED;
-    else if (res <= tol[inst]) st = CONVERGED;
-    else if (max_steps[inst] > 0 && t + 1 >= max_steps[inst]) st = STALLED;
-    if (st != RUN) {
-      r.t_stop = t + 1;
-      status[inst] = st;
-    }
+  if (t < r.t_arm) {
+    r.res = r.res_u = r.res_T = HUGE_VAL;
+    out[inst] = r;
+    return;
+  }
+  int st = RUN;
+  if (!isfinite(res)) st = DIVERGED;
+  else if (res <= tol[inst]) st = CONVERGED;
+  else if (max_steps[inst] > 0 && t + 1 - r.t_off >= max_steps[inst]) st = STALLED;
+  if (st != RUN) {
+    r.t_stop = t + 1;
+    status[inst] = st;
   }
   out[inst] = r;
 }
@@ -522,7 +534,7 @@ template <typename S, bool BUF>
 int launch_step_b(lbm_axi* h, bool odd, int mode, int slot, uint32_t seed, hipStream_t st,
                 const long long* clk, int off) {
   const dim3 blk(BX, BY);
-  const FieldOut fo{nullptr, nullptr, nullptr, nullptr, nullptr};
+  const FieldOut fo{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   if (!odd) {
     if (mode == MODE_STEP)
       k_step<S, false, MODE_STEP, BUF><<<h->ntiles_launch, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo, seed, clk, off);
@@ -710,6 +722,74 @@ void release(lbm_axi* h, void* p, size_t bytes) {
     }
 }
 
+// One step of instance inst alone, in the AA layout of parity `odd` (plain
+// tile list, flat addressing).
+template <typename S>
+int launch_inst_step(lbm_axi* h, int inst, bool odd, uint32_t seed) {
+  const dim3 blk(BX, BY);
+  const FieldOut fo{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  const int4* tl = h->dtiles_plain + h->tile_first[inst];
+  if (!odd)
+    k_step<S, false, MODE_STEP, false><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->dstatus, h->kz, 0, fo, seed, nullptr, 0);
+  else
+    k_step<S, true, MODE_STEP, false><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->dstatus, h->kz, 0, fo, seed, nullptr, 0);
+  HIPCHK(hipGetLastError());
+  return LBM_AXI_OK;
+}
+
+// Sets converged instances running again (after a storage conversion).  A
+// stopped instance's populations sit at the handle level t_stop at which it
+// stopped, in that level's AA layout, while the handle has moved on to h->t.
+// If the two levels differ in parity the instance first takes one step on its
+// own, so that its layout is the one the handle's next step expects.  The
+// handle steps it sat out are added to t_off (an even number), so that its
+// own time level stays continuous, and its first check after the restart only
+// records (its other check buffer is stale).  Stalled and diverged instances
+// stay stopped.
+int resume_converged(lbm_axi* h) {
+  const int n = h->n_inst;
+  std::vector<int> st(n);
+  std::vector<DevResult> rr(n);
+  HIPCHK(hipMemcpy(st.data(), h->dstatus, sizeof(int) * n, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(rr.data(), h->dres, sizeof(DevResult) * n, hipMemcpyDeviceToHost));
+  std::vector<int> resumed;
+  for (int i = 0; i < n; ++i)
+    if (st[i] == CONVERGED && rr[i].t_stop >= 0 && rr[i].t_stop <= h->t) {
+      st[i] = RUN;
+      resumed.push_back(i);
+    }
+  if (resumed.empty()) return LBM_AXI_OK;
+  HIPCHK(hipMemcpy(h->dstatus, st.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+  const long long N = h->check > 0 ? h->check : 1;
+  for (int i : resumed) {
+    DevResult& r = rr[i];
+    const long long gap = h->t - r.t_stop;
+    if (gap & 1) {
+      const bool odd = (r.t_stop & 1) != 0;
+      const uint32_t seed = step_seed(r.t_stop - r.t_off);
+      int rc;
+      switch (h->storage) {
+        case LBM_STORE_FP32: rc = launch_inst_step<float>(h, i, odd, seed); break;
+        case LBM_STORE_FP16: rc = launch_inst_step<__half>(h, i, odd, seed); break;
+        default: rc = launch_inst_step<__hip_bfloat16>(h, i, odd, seed); break;
+      }
+      if (rc) return rc;
+    }
+    r.t_off += gap - (gap & 1);
+    r.t_arm = (h->t + N - 1) / N * N + N;
+    r.t_stop = -1;
+    r.res = r.res_u = r.res_T = HUGE_VAL;
+  }
+  HIPCHK(hipMemcpyAsync(h->dres, rr.data(), sizeof(DevResult) * n, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (!h->active.empty()) {
+    for (int i : resumed) h->active[i] = 1;
+    drop_graph(h);
+    return build_tiles(h, h->kz, h->kz_odd);
+  }
+  return LBM_AXI_OK;
+}
+
 // Host-side failures (allocation) become error codes: nothing may unwind
 // through the C ABI.
 template <typename F>
@@ -883,6 +963,8 @@ int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* 
         r.nu_i = r.nu_o = r.u_rms = 0.0;
         r.t_check = -1;
         r.t_stop = -1;
+        r.t_off = 0;
+        r.t_arm = h->check;  // the check at level 0 only fills a buffer
       }
       HIPBAIL(hipMemcpy(h->dres, r0.data(), sizeof(DevResult) * n_inst, hipMemcpyHostToDevice));
     }
@@ -1022,7 +1104,7 @@ int lbm_axi_step(lbm_axi* h, int32_t nsteps) {
         }
       }
       if (check) {
-        k_resid<<<h->nrt, RB, 0, h->stream>>>(h->ddesc, h->drt, slot, h->dpart);
+        k_resid<<<h->nrt, RB, 0, h->stream>>>(h->ddesc, h->drt, slot, h->dstatus, h->dpart);
         HIPCHK(hipGetLastError());
         k_final<<<h->n_inst, RB, 0, h->stream>>>(h->dfirst, h->dpart, n, 1.0 / h->check, h->dtol,
                                                   h->dmx, h->dnus, h->dstatus, h->dres);
@@ -1177,13 +1259,7 @@ int lbm_axi_set_storage(lbm_axi* h, int32_t storage, int32_t storage_shift) {
       const int rc = build_tiles(h, default_kz(h), default_kz(h, true));
       if (rc) return rc;
     }
-    // Converged or stalled runs continue in the new storage; diverged ones stay.
-    std::vector<int> st(h->n_inst);
-    HIPCHK(hipMemcpy(st.data(), h->dstatus, sizeof(int) * h->n_inst, hipMemcpyDeviceToHost));
-    for (int& v : st)
-      if (v == CONVERGED || v == STALLED) v = RUN;
-    HIPCHK(hipMemcpy(h->dstatus, st.data(), sizeof(int) * h->n_inst, hipMemcpyHostToDevice));
-    return LBM_AXI_OK;
+    return resume_converged(h);
   });
 }
 
@@ -1234,15 +1310,21 @@ int lbm_axi_info(lbm_axi* h, int32_t inst, int64_t* out) {
   HIPCHK(hipMemcpyAsync(&r, h->dres + inst, sizeof(DevResult), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipMemcpyAsync(&st, h->dstatus + inst, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
-  out[0] = st == RUN ? h->t : r.t_stop;
+  out[0] = (st == RUN ? h->t : r.t_stop) - r.t_off;
   out[1] = r.t_check;
   out[2] = st;
   out[3] = (int64_t)h->bytes;
   return LBM_AXI_OK;
 }
 
-int lbm_axi_macros(lbm_axi* h, int32_t inst, float* uz, float* ur, float* p, float* T,
-                   uint8_t* mask, int32_t dst_is_device) {
+}  // extern "C"
+
+namespace {
+
+// Field output of instance inst into the buffers of `out` (each may be null):
+// written directly when they are device memory, else through device staging
+// buffers and copied to the host (waits).
+int fields_to(lbm_axi* h, int inst, const FieldOut& out, int dst_is_device) {
   return guarded([&]() -> int {
     if (!h || inst < 0 || inst >= h->n_inst) return fail(LBM_AXI_EINVAL, "bad handle or instance");
     int64_t info[4];
@@ -1251,10 +1333,12 @@ int lbm_axi_macros(lbm_axi* h, int32_t inst, float* uz, float* ur, float* p, flo
     const bool odd = (info[0] & 1) != 0;
     const lbm_axi_params& q = h->prm[inst];
     const size_t n = (size_t)q.nr * q.nz;
-    FieldOut fo{uz, ur, p, T, mask};
+    FieldOut fo = out;
+    float *uz = out.uz, *ur = out.ur, *p = out.p, *T = out.T, *dr = out.drho;
+    uint8_t* mask = out.mask;
     std::vector<void*> tmp;
     if (!dst_is_device) {
-      float** fp[4] = {&fo.uz, &fo.ur, &fo.p, &fo.T};
+      float** fp[5] = {&fo.uz, &fo.ur, &fo.p, &fo.T, &fo.drho};
       for (float** f : fp)
         if (*f) {
           void* d = nullptr;
@@ -1287,12 +1371,27 @@ int lbm_axi_macros(lbm_axi* h, int32_t inst, float* uz, float* ur, float* p, flo
       if (p && e == hipSuccess) e = hipMemcpyAsync(p, fo.p, sizeof(float) * n, hipMemcpyDeviceToHost, h->stream);
       if (T && e == hipSuccess) e = hipMemcpyAsync(T, fo.T, sizeof(float) * n, hipMemcpyDeviceToHost, h->stream);
       if (mask && e == hipSuccess) e = hipMemcpyAsync(mask, fo.mask, n, hipMemcpyDeviceToHost, h->stream);
+      if (dr && e == hipSuccess) e = hipMemcpyAsync(dr, fo.drho, sizeof(float) * n, hipMemcpyDeviceToHost, h->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
       if (e != hipSuccess) rc = fail(LBM_AXI_EDEVICE, std::string("field download: ") + hipGetErrorString(e));
     }
     for (void* x : tmp) (void)hipFree(x);
     return rc;
   });
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_axi_macros(lbm_axi* h, int32_t inst, float* uz, float* ur, float* p, float* T,
+                   uint8_t* mask, int32_t dst_is_device) {
+  return fields_to(h, inst, FieldOut{uz, ur, p, T, mask, nullptr}, dst_is_device);
+}
+
+int lbm_axi_density_deviation(lbm_axi* h, int32_t inst, float* drho, int32_t dst_is_device) {
+  if (!drho) return fail(LBM_AXI_EINVAL, "null output");
+  return fields_to(h, inst, FieldOut{nullptr, nullptr, nullptr, nullptr, nullptr, drho}, dst_is_device);
 }
 
 int lbm_axi_stream_function(lbm_axi* h, int32_t inst, float* psi, double* psi_absmax,
@@ -1322,7 +1421,7 @@ int lbm_axi_stream_function(lbm_axi* h, int32_t inst, float* psi, double* psi_ab
       release_tmp();
       return fail(LBM_AXI_ENOMEM, "stream function staging");
     }
-    FieldOut fo{(float*)duz, nullptr, nullptr, nullptr, nullptr};
+    FieldOut fo{(float*)duz, nullptr, nullptr, nullptr, nullptr, nullptr};
     switch (h->storage) {
       case LBM_STORE_FP32: rc = launch_fields<float>(h, inst, odd, fo); break;
       case LBM_STORE_FP16: rc = launch_fields<__half>(h, inst, odd, fo); break;
@@ -1368,7 +1467,7 @@ int lbm_axi_pipe_nusselt(lbm_axi* h, int32_t inst, int32_t area, double* nu, dou
       release_tmp();
       return fail(LBM_AXI_ENOMEM, "pipe Nusselt staging");
     }
-    FieldOut fo{(float*)dU, nullptr, nullptr, (float*)dT, nullptr};
+    FieldOut fo{(float*)dU, nullptr, nullptr, (float*)dT, nullptr, nullptr};
     switch (h->storage) {
       case LBM_STORE_FP32: rc = launch_fields<float>(h, inst, odd, fo); break;
       case LBM_STORE_FP16: rc = launch_fields<__half>(h, inst, odd, fo); break;

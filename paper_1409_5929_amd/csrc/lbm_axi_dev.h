@@ -96,6 +96,7 @@ struct InstDev {
 struct FieldOut {
   float *uz, *ur, *p, *T;
   uint8_t* mask;
+  float* drho;  // rho - 1
 };
 
 // ---- storage types --------------------------------------------------------
@@ -180,7 +181,9 @@ __host__ __device__ inline uint32_t mix32(uint32_t x) {
 // lane).  PopAcc<S, true>: buffer addressing, one descriptor in scalar
 // registers per instance and 32-bit byte offsets per lane (half the address
 // registers; the hardware also drops accesses outside the array), usable when
-// the population array is below 4 GiB.
+// the population array is below 4 GiB.  The hardware takes the record count
+// and the offsets as unsigned 32-bit values; the builtins declare them int,
+// so values of 2^31 and above pass as their bit patterns.
 template <typename S, bool BUF>
 struct PopAcc;
 template <typename S>
@@ -199,16 +202,16 @@ struct PopAcc<S, true> {
   float inv, sc;
   __host__ __device__ explicit PopAcc(const InstDev& D) : inv(D.st_inv), sc(D.st_scale) {
 #if defined(__HIP_DEVICE_COMPILE__)
-    rs = __builtin_amdgcn_make_buffer_rsrc(D.pop, (short)0, (int)D.pop_bytes, 0x00020000);
+    rs = __builtin_amdgcn_make_buffer_rsrc(D.pop, (short)0, (int)(uint32_t)D.pop_bytes, 0x00020000);
 #endif
   }
   __host__ __device__ float ld(int64_t i) const {
 #if defined(__HIP_DEVICE_COMPILE__)
-    const int off = (int)((uint32_t)i * (uint32_t)sizeof(S));
+    const uint32_t off = (uint32_t)i * (uint32_t)sizeof(S);
     if constexpr (std::is_same<S, float>::value) {
-      return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+      return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
     } else {
-      const uint16_t b = (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0);
+      const uint16_t b = (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(rs, (int)off, 0, 0);
       if constexpr (std::is_same<S, __half>::value)
         return __half2float(__builtin_bit_cast(__half, b)) * inv;
       else
@@ -221,16 +224,16 @@ struct PopAcc<S, true> {
   }
   __host__ __device__ void st(int64_t i, float v, uint32_t r) const {
 #if defined(__HIP_DEVICE_COMPILE__)
-    const int off = (int)((uint32_t)i * (uint32_t)sizeof(S));
+    const uint32_t off = (uint32_t)i * (uint32_t)sizeof(S);
     if constexpr (std::is_same<S, float>::value) {
       (void)r;
-      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, off, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, (int)off, 0, 0);
     } else if constexpr (std::is_same<S, __half>::value) {
       const lbm_h2 h = __builtin_amdgcn_cvt_sr_f16_f32(lbm_h2{0, 0}, v * sc, r, false);
-      __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h[0]), rs, off, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h[0]), rs, (int)off, 0, 0);
     } else {
       const lbm_b2 h = __builtin_amdgcn_cvt_sr_bf16_f32(lbm_b2{0, 0}, v * sc, r, false);
-      __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h[0]), rs, off, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h[0]), rs, (int)off, 0, 0);
     }
 #else
     (void)i;
@@ -591,6 +594,7 @@ __host__ __device__ inline void wall_node(const InstDev& D, const A& P, const No
     if (fo.p) fo.p[o] = rhob * CS2 / phib;
     if (fo.T) fo.T[o] = Tb;
     if (fo.mask) fo.mask[o] = m;
+    if (fo.drho) fo.drho[o] = drho;
   }
 }
 
@@ -708,6 +712,7 @@ __host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC&
     if (fo.p) fo.p[oo] = rho * CS2 / phi;
     if (fo.T) fo.T[oo] = B.T;
     if (fo.mask) fo.mask[oo] = node_mask(D, j, k);
+    if (fo.drho) fo.drho[oo] = B.drho;
   }
 
   // ---- forces (Eq. 6) and the axisymmetric correction (Eq. 25) -----------

@@ -108,6 +108,9 @@ def _load():
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_int32]
     lib.lbm_axi_macros.restype = ctypes.c_int
+    lib.lbm_axi_density_deviation.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                              ctypes.c_int32]
+    lib.lbm_axi_density_deviation.restype = ctypes.c_int
     lib.lbm_axi_residual.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p]
     lib.lbm_axi_residual.restype = ctypes.c_int
@@ -241,8 +244,9 @@ class Lattice:
     def sync(self):
         _check(self._lib.lbm_axi_sync(self._h))
 
-    def fields(self, inst: int = 0) -> dict:
-        """Host copies of u_z, u_r, p, T (float32) and the node classes (uint8)."""
+    def fields(self, inst: int = 0, drho: bool = True) -> dict:
+        """Host copies of u_z, u_r, p, T (float32), the node classes (uint8) and,
+        with drho=True, the density deviation rho - 1 (float32, "drho")."""
         nz, nr = self.shapes[inst]
         out = {k: np.empty((nz, nr), dtype=np.float32) for k in ("uz", "ur", "p", "T")}
         mask = np.empty((nz, nr), dtype=np.uint8)
@@ -250,6 +254,15 @@ class Lattice:
                                         out["ur"].ctypes.data, out["p"].ctypes.data,
                                         out["T"].ctypes.data, mask.ctypes.data, 0))
         out["mask"] = mask
+        if drho:
+            out["drho"] = self.density_deviation(inst)
+        return out
+
+    def density_deviation(self, inst: int = 0) -> np.ndarray:
+        """rho - 1 at every node as a host [nz, nr] float32 array."""
+        nz, nr = self.shapes[inst]
+        out = np.empty((nz, nr), dtype=np.float32)
+        _check(self._lib.lbm_axi_density_deviation(self._h, int(inst), out.ctypes.data, 0))
         return out
 
     macros = fields

@@ -95,6 +95,7 @@ def test_null_handles_are_refused():
     assert lib.lbm_axi_autotune(None, 1, None, None, None) == -1
     assert lib.lbm_axi_stream_function(None, 0, None, None, 0) == -1
     assert lib.lbm_axi_pipe_nusselt(None, 0, 0, None, None) == -1
+    assert lib.lbm_axi_density_deviation(None, 0, None, 0) == -1
     lib.lbm_axi_destroy(None)  # allowed
 
 

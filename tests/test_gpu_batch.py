@@ -6,11 +6,11 @@ import numpy as np
 import pytest
 
 import lbm_inputs as li
-from tests.parity import TOL_FP32, assert_parity, rel_errors
+from tests.parity import RHO_FLOOR_16, TOL_FP32, assert_parity, rel_errors
 
 pytestmark = pytest.mark.gpu
 
-KEYS = ("uz", "ur", "p", "T", "mask")
+KEYS = ("uz", "ur", "p", "T", "mask", "drho")
 
 
 @pytest.fixture(scope="module")
@@ -132,7 +132,8 @@ def test_full_sweep_fp16_against_oracle(L, oracle_mod):
         m = o.macros()
         o.close()
         np.testing.assert_array_equal(got[i]["mask"], m["mask"])
-        e = rel_errors(got[i], m, u_floor=U_FLOOR)
+        e = rel_errors(got[i], m, u_floor=U_FLOOR, t_floor=abs(cfgs[i]["delta_T"]),
+                       rho_floor=RHO_FLOOR_16)
         print(f"sweep instance {i} ({cfgs[i]['nr']}x{cfgs[i]['nz']}, kz {tune['kz']}): "
               f"u {e['u']:.2e} p {e['p']:.2e} T {e['T']:.2e} (tol {tol:.1e})", flush=True)
         for k, v in e.items():

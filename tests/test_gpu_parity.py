@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import lbm_inputs as li
-from tests.parity import TOL_FP32, U_FLOOR, assert_parity, rel_errors
+from tests.parity import TOL_FP32, U_FLOOR, assert_parity, rel_errors, window
 
 pytestmark = pytest.mark.gpu
 
@@ -127,7 +127,7 @@ def test_batched_instances_match_single_runs(L, oracle_mod):
     lat.close()
     for i, c in enumerate(cfgs):
         single = gpu_fields(L, c, n, check_interval=10)
-        for k in ("uz", "ur", "p", "T", "mask"):
+        for k in ("uz", "ur", "p", "T", "mask", "drho"):
             np.testing.assert_array_equal(batched[i][k], single[k])
     assert_parity(batched[1], orc_fields(oracle_mod, cfgs[1], n), label="batched instance 1")
 
@@ -261,8 +261,8 @@ def test_full_size_sampled_windows(L, oracle_mod):
         jh = w if j0 + w == size else w - margin
         kl = 0 if k0 == 0 else margin
         kh = w if k0 + w == size else w - margin
-        sub = {k: g[k][k0 + kl:k0 + kh, j0 + jl:j0 + jh] for k in ("uz", "ur", "p", "T", "mask")}
-        ref = {k: o[k][kl:kh, jl:jh] for k in ("uz", "ur", "p", "T", "mask")}
+        sub = window(g, slice(k0 + kl, k0 + kh), slice(j0 + jl, j0 + jh))
+        ref = window(o, slice(kl, kh), slice(jl, jh))
         np.testing.assert_array_equal(sub["mask"], ref["mask"])
         e = rel_errors(sub, ref)
         worst = max(worst, *e.values())

@@ -17,7 +17,7 @@ import lbm_inputs as li
 
 pytestmark = pytest.mark.gpu
 
-KEYS = ("uz", "ur", "p", "T", "mask")
+KEYS = ("uz", "ur", "p", "T", "mask", "drho")
 
 
 @pytest.fixture(scope="module")
