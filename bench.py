@@ -23,6 +23,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import subprocess
 import sys
@@ -253,6 +254,18 @@ def time_to_steady(n_problems, cap):
     return c
 
 
+def check_summary(res, info, interval):
+    """The last residual / Nusselt check of the main run: its step, residual and
+    Nu_i, or a note when no check fell in the run (a check compares two check
+    steps, the first at level 0, so the first one runs at level `interval`)."""
+    t_check = int(info["t_check"])
+    if t_check < 0 or not math.isfinite(float(res["res"][0])):
+        return {"t_check": None, "residual": None, "nu_i": None,
+                "note": f"no check in this run (checks at multiples of {interval} steps from "
+                        f"level {interval} on; run ended at level {int(info['t'])})"}
+    return {"t_check": t_check, "residual": float(res["res"][0]), "nu_i": float(res["nu_i"][0])}
+
+
 def oracle_rate(cfg: dict, phi, seconds: float):
     """Steps of the FP64 oracle on (cfg, phi) until `seconds` of work are done:
     (steps, seconds, threads used)."""
@@ -423,9 +436,11 @@ def main():
     if not args.no_variants and args.storage == "fp32":
         variants = []
         for st in ("fp16", "bf16"):
+            # at least 100 warm-up and 200 timed steps, whatever the main leg's counts
             log(f"storage variant {st}")
-            variants.append(storage_variant(Lattice, cfg, phi.astype(np.float32), st, args.steps // 2,
-                                            args.warmup, args.check_interval, stream))
+            variants.append(storage_variant(Lattice, cfg, phi.astype(np.float32), st,
+                                            max(args.steps // 2, 200), max(args.warmup, 100),
+                                            args.check_interval, stream))
         log(f"batched sweep: {args.sweep_instances} instances")
         sweep = sweep_batch(Lattice, args.sweep_instances, args.sweep_steps, stream)
         log(f"time to steady: {args.steady_problems} problems, cold vs warm start")
@@ -486,8 +501,7 @@ def main():
         "storage_variants": variants,
         "sweep": sweep,
         "time_to_steady": steady,
-        "residual": float(res["res"][0]),
-        "nu_i": float(res["nu_i"][0]),
+        "check": check_summary(res, info, args.check_interval),
         "t": int(info["t"]),
     }
     if not args.no_cpu_baseline:

@@ -253,6 +253,16 @@ int lbm_axi_residual(lbm_axi* h, double* res, double* nu_i, double* nu_o, int32_
 int lbm_axi_info(lbm_axi* h, int32_t inst, int64_t* out);
 
 /*
+ * Constants the library derives from a problem statement (FP64, on the host;
+ * needs no device and no handle): out[0] = tau_nu and out[1] = tau_T of
+ * Eq. (39) (tau_nu as given when p->tau_nu > 0), out[2] = nu_e (Eq. 31),
+ * out[3] = nu = nu_e / J and out[4] = K = Da L^2 (Eq. 9), out[5] = g beta =
+ * (Ma c_s)^2 / (L dT) (0 without buoyancy), out[6] = alpha_e = c_sT^2 tau_T
+ * (text after Eq. 38).  out has 7 entries.  LBM_AXI_EINVAL on NULL.
+ */
+int lbm_axi_derived(const lbm_axi_params* p, double* out);
+
+/*
  * Kernel timing: with on = 1 every later step-kernel launch is bracketed by
  * HIP events on the handle's stream; lbm_axi_kernel_time returns the summed
  * milliseconds and the number of launches since timing was switched on

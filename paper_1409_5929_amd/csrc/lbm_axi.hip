@@ -1389,6 +1389,14 @@ int lbm_axi_macros(lbm_axi* h, int32_t inst, float* uz, float* ur, float* p, flo
   return fields_to(h, inst, FieldOut{uz, ur, p, T, mask, nullptr}, dst_is_device);
 }
 
+int lbm_axi_derived(const lbm_axi_params* p, double* out) {
+  if (!p || !out) return fail(LBM_AXI_EINVAL, "null argument");
+  const Derived d = derive(*p);
+  const double v[7] = {d.tau_nu, d.tau_T, d.nu_e, d.nu, d.K_ref, d.gbeta, d.alpha_e};
+  for (int i = 0; i < 7; ++i) out[i] = v[i];
+  return LBM_AXI_OK;
+}
+
 int lbm_axi_density_deviation(lbm_axi* h, int32_t inst, float* drho, int32_t dst_is_device) {
   if (!drho) return fail(LBM_AXI_EINVAL, "null output");
   return fields_to(h, inst, FieldOut{nullptr, nullptr, nullptr, nullptr, nullptr, drho}, dst_is_device);

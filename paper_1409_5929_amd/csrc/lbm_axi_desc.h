@@ -15,6 +15,30 @@ namespace lbmaxi {
 
 inline double kappa(double ph) { return ph * ph * ph / ((1.0 - ph) * (1.0 - ph)); }
 
+// Constants of one instance derived from its problem statement, in FP64:
+// tau_nu and tau_T (Eq. 39), the effective viscosity nu_e (Eq. 31), the
+// fluid viscosity nu = nu_e / J and the reference permeability K = Da L^2
+// (Eq. 9), g beta = (Ma c_s)^2 / (L dT) (0 without buoyancy) and the
+// effective thermal diffusivity alpha_e = c_sT^2 tau_T (text after Eq. 38).
+struct Derived {
+  double tau_nu, tau_T, nu_e, nu, K_ref, gbeta, alpha_e;
+};
+
+inline Derived derive(const lbm_axi_params& q) {
+  Derived d;
+  const double cs = std::sqrt(1.0 / 3.0);
+  d.tau_nu = q.tau_nu > 0.0 ? q.tau_nu
+                            : 0.5 + q.Ma * q.J * q.L * std::sqrt(q.Pr) / (cs * std::sqrt(q.Ra));  // Eq. (39)
+  d.tau_T = (1.0 / 3.0) * q.lambda * (d.tau_nu - 0.5) / (0.2 * q.J * q.Pr);                // Eq. (39)
+  d.nu_e = (1.0 / 3.0) * (d.tau_nu - 0.5);                                                  // Eq. (31)
+  d.nu = d.nu_e / q.J;  // J = nu_e / nu
+  d.K_ref = q.Da * q.L * q.L;  // Da = K / L^2
+  const double dT = q.delta_T != 0.0 ? q.delta_T : q.T_rmin - q.T_rmax;
+  d.gbeta = (q.Ra > 0.0 && dT != 0.0) ? (q.Ma * cs) * (q.Ma * cs) / q.L / dT : 0.0;  // U = sqrt(g beta dT L)
+  d.alpha_e = 0.2 * d.tau_T;
+  return d;
+}
+
 // Returns LBM_AXI_OK or an error code with a message in err.
 inline int describe(const lbm_axi_params& q, bool field, InstDev& D, std::string& err) {
   std::memset(&D, 0, sizeof(D));
@@ -29,25 +53,16 @@ inline int describe(const lbm_axi_params& q, bool field, InstDev& D, std::string
   D.therm_rmax = q.therm_rmax;
   D.therm_z = q.therm_z;
   D.src_printed = q.src_printed ? 1 : 0;
-  const double cs = std::sqrt(1.0 / 3.0);
-  const double tau = q.tau_nu > 0.0
-                         ? q.tau_nu
-                         : 0.5 + q.Ma * q.J * q.L * std::sqrt(q.Pr) / (cs * std::sqrt(q.Ra));  // Eq. (39)
+  const Derived dv = derive(q);
+  const double tau = dv.tau_nu, tauT = dv.tau_T, nu = dv.nu, Kref = dv.K_ref, gbeta = dv.gbeta;
   if (!(tau > 0.5)) {
     err = "tau_nu must exceed 1/2";
     return LBM_AXI_EINVAL;
   }
-  const double tauT = (1.0 / 3.0) * q.lambda * (tau - 0.5) / (0.2 * q.J * q.Pr);  // Eq. (39)
-  const double nu = (1.0 / 3.0) * (tau - 0.5) / q.J;  // Eq. (31) and J = nu_e / nu
-  const double Kref = q.Da * q.L * q.L;                // Da = K / L^2
   const double dT = q.delta_T != 0.0 ? q.delta_T : q.T_rmin - q.T_rmax;
-  double gbeta = 0.0;
-  if (q.Ra > 0.0) {
-    if (dT == 0.0) {
-      err = "buoyancy needs a nonzero temperature difference";
-      return LBM_AXI_EINVAL;
-    }
-    gbeta = (q.Ma * cs) * (q.Ma * cs) / q.L / dT;  // U = Ma c_s = sqrt(g beta dT L)
+  if (q.Ra > 0.0 && dT == 0.0) {
+    err = "buoyancy needs a nonzero temperature difference";
+    return LBM_AXI_EINVAL;
   }
   D.r0 = (float)q.r0;
   D.T_ref = (float)q.T_ref;

@@ -79,6 +79,16 @@ def make_params(cfg: dict, storage: str = "fp32", check_interval: int = 100, tol
     return p
 
 
+def derived(cfg: dict) -> dict:
+    """tau_nu, tau_T (Eq. 39), nu_e (Eq. 31), nu, K (Eq. 9), g beta and
+    alpha_e = c_sT^2 tau_T of a problem, as the library derives them (no device
+    needed)."""
+    p = make_params(cfg)
+    out = (ctypes.c_double * 7)()
+    _check(_load().lbm_axi_derived(ctypes.byref(p), out))
+    return dict(zip(("tau_nu", "tau_T", "nu_e", "nu", "K_ref", "gbeta", "alpha_e"), list(out)))
+
+
 _lib = None
 
 
@@ -108,6 +118,8 @@ def _load():
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_int32]
     lib.lbm_axi_macros.restype = ctypes.c_int
+    lib.lbm_axi_derived.argtypes = [P(Params), P(ctypes.c_double)]
+    lib.lbm_axi_derived.restype = ctypes.c_int
     lib.lbm_axi_density_deviation.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                               ctypes.c_int32]
     lib.lbm_axi_density_deviation.restype = ctypes.c_int
@@ -190,6 +202,7 @@ class Lattice:
         if len(phis) != n or len(inits) != n:
             raise ValueError("phi and init must be given per instance (or once for a single instance)")
         self.shapes = [(int(c["nz"]), int(c["nr"])) for c in cfgs]
+        self.cfgs = cfgs
         arr = (Params * n)()
         for i, c in enumerate(cfgs):
             arr[i] = make_params(c, storage, check_interval, tol, max_steps, storage_shift)
@@ -320,6 +333,10 @@ class Lattice:
         out = (ctypes.c_int64 * 4)()
         _check(self._lib.lbm_axi_info(self._h, int(inst), out))
         return dict(t=out[0], t_check=out[1], status=RUN_STATE[out[2]], device_bytes=out[3])
+
+    def derived(self, inst: int = 0) -> dict:
+        """derived(cfg) of one instance's problem."""
+        return derived(self.cfgs[inst])
 
     def set_tiles(self, kz: int, blocks_per_cu: int = 0):
         """Launch shape of the step kernel: nodes per thread along z and a cap

@@ -423,3 +423,39 @@ def test_derived_constants_eq39(oracle_mod):
         d = oracle_mod.Oracle(li.table2(Ra)).derived()
         assert abs(d["tau_nu"] - tn) < 1e-4 and abs(d["tau_T"] - tt) < 1e-3
         assert abs(d["gbeta"] - 0.01 / 3 / 99) < 1e-12
+
+
+# --- steady-state residual ----------------------------------------------------
+
+@pytest.mark.parametrize("du, dT", [((3e-4, -4e-4), 0.0), ((0.0, 0.0), 2e-3), ((1e-4, 0.0), 5e-4)])
+def test_residual_of_a_uniform_change_is_its_rate(oracle_mod, du, dT):
+    """The residual is the rms change per step since the snapshot, scaled by
+    U = Ma c_s and dT.  Between the snapshot and a state n steps later whose
+    fluid-node velocity differs by a constant vector du and temperature by a
+    constant dT (a field changing linearly in time), it is exactly
+    |du| / (n U) and |dT| / (n dT_ref), and res is the larger of the two.  The
+    two states are start states (reading R8), whose fluid nodes return the
+    given u and T (exactly with F_phi = 0)."""
+    cfg = li.annulus(nr=12, nz=9, Ra=1e4, Da=1e-2, F_phi=0.0)
+    nz, nr = cfg["nz"], cfg["nr"]
+    rng = np.random.default_rng(7)
+    a = np.stack([rng.normal(0, 0.01, (nz, nr)), rng.normal(0, 0.01, (nz, nr)), rng.uniform(0, 1, (nz, nr))])
+    b = a.copy()
+    b[0] += du[1]  # u_z
+    b[1] += du[0]  # u_r
+    b[2] += dT
+    n = 37
+    o = oracle_mod.Oracle(cfg, init=a)
+    o.snapshot()
+    o.step(n)
+    ob = oracle_mod.Oracle(cfg, init=b)
+    o.set_populations(*ob.populations())
+    ob.close()
+    r = o.residual()
+    o.close()
+    U = cfg["Ma"] * math.sqrt(CS2)
+    want_u = math.hypot(*du) / (n * U)
+    want_T = abs(dT) / (n * abs(cfg["delta_T"]))
+    assert r["res_u"] == pytest.approx(want_u, rel=1e-9, abs=1e-15)
+    assert r["res_T"] == pytest.approx(want_T, rel=1e-9, abs=1e-15)
+    assert r["res"] == max(r["res_u"], r["res_T"])
