@@ -103,12 +103,30 @@ def storage_variant(Lattice, cfg, phi, storage, steps, warmup, check, stream):
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
     kern_ms, launches = lat.kernel_time()
+    lat.set_timing(False)
+    pat = pattern_ceiling(lat)
     lat.close()
     bpn = 26 * 2 + 2 * 4 + 4
-    return {"storage": storage, "mlups": round(n * n * steps / (total_ms * 1e-3) / 1e6, 1),
+    achieved = (n - 2) ** 2 * bpn / (kern_ms / launches * 1e-3) / 1e9
+    return {"storage": storage, "steps": steps, "warmup": warmup,
+            "mlups": round(n * n * steps / (total_ms * 1e-3) / 1e6, 1),
             "ms_per_step": round(total_ms / steps, 5), "avg_launch_ms": round(kern_ms / launches, 5),
-            "bytes_per_node": bpn,
-            "achieved_gbs": round((n - 2) ** 2 * bpn / (kern_ms / launches * 1e-3) / 1e9, 1)}
+            "bytes_per_node": bpn, "achieved_gbs": round(achieved, 1),
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            # against the 56 + 2 bytes per node of 16-bit populations and a 16-bit
+            # porosity, which this layout exceeds (FP32 g_0 and porosity planes)
+            "frac_at_58_bytes": round(achieved * 58 / bpn / HBM_PEAK_GBS, 4),
+            "pattern_ceiling_gbs": pat, "frac_of_pattern": round(achieved / pat["pair"], 4)}
+
+
+def pattern_ceiling(lat, reps: int = 20) -> dict:
+    """The step's own access pattern without arithmetic on the same handle
+    (lbm_axi_pattern_bandwidth): even and odd parity, their pair (harmonic mean:
+    a step pair moves the same bytes in each), and a plain read+write stream."""
+    r = lat.pattern_bandwidth(reps=reps)
+    pair = 2.0 / (1.0 / r["even_gbs"] + 1.0 / r["odd_gbs"])
+    return {"even": round(r["even_gbs"], 1), "odd": round(r["odd_gbs"], 1), "pair": round(pair, 1),
+            "stream_rw": round(r["stream_gbs"], 1), "reps": reps}
 
 
 def sweep_batch(Lattice, n_inst, steps, stream):
@@ -426,6 +444,8 @@ def main():
     lat.set_timing(False)
     res = lat.residual()
     info = lat.info()
+    log("pattern ceiling probe")
+    pattern = pattern_ceiling(lat)
     t_read = time.perf_counter()
     host_fields = lat.fields()  # u_z, u_r, p, T and node classes into host memory
     t_read = time.perf_counter() - t_read
@@ -490,6 +510,9 @@ def main():
             "launches": launches,
             "copy_gbs": round(copy_gbs, 1),
             "frac_of_copy": round(achieved / copy_gbs, 4),
+            # the step's exact access pattern with no arithmetic, on the same handle
+            "pattern_ceiling_gbs": pattern,
+            "frac_of_pattern": round(achieved / pattern["pair"], 4),
         },
         # the same job with its host hand-overs: create (allocation, porosity
         # upload, start state) before and the field read-back after the steps

@@ -263,6 +263,23 @@ int lbm_axi_info(lbm_axi* h, int32_t inst, int64_t* out);
 int lbm_axi_derived(const lbm_axi_params* p, double* out);
 
 /*
+ * Streaming ceiling of the step's memory access pattern, measured on the
+ * handle's own arrays and launch shapes (waits for the stream): probe kernels
+ * that make exactly the step kernel's loads and stores for each parity of the
+ * in-place (AA) layout, with no arithmetic (every value is stored back where
+ * it was read, so the state is unchanged), and a plain in-place read+write
+ * stream over the population arrays.  Each is launched reps times after one
+ * untimed launch and timed with HIP events on the handle's stream.
+ * out[0] = even-step pattern, out[1] = odd-step pattern, out[2] = plain
+ * stream, in GB/s (bytes read plus written per second; the patterns count the
+ * step's algorithmic bytes: per fluid node of the running instances, 13
+ * populations of the storage type and the FP32 g_0 read and written, and the
+ * porosity read where it is a field), out[3] = those algorithmic bytes of one
+ * step launch.  out has 4 entries; 1 <= reps <= 100000.
+ */
+int lbm_axi_pattern_bandwidth(lbm_axi* h, int32_t reps, double* out);
+
+/*
  * Kernel timing: with on = 1 every later step-kernel launch is bracketed by
  * HIP events on the handle's stream; lbm_axi_kernel_time returns the summed
  * milliseconds and the number of launches since timing was switched on

@@ -27,6 +27,7 @@
 // launched one by one.  Both give identical results.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -173,6 +174,50 @@ __global__ __launch_bounds__(BX* BY) void k_step(const InstDev* __restrict__ des
 #pragma unroll
     for (int q = 0; q < 5; ++q) t[q] = tn[q];
     ph = phn;
+  }
+}
+
+// Streaming-ceiling probe of the step: the step's launch (tiles, strips of
+// kz nodes, addressing) and its loads and stores, with no arithmetic
+// (pattern_store); two nodes of a strip are in flight at a time.
+template <typename S, bool ODD, bool BUF>
+__global__ __launch_bounds__(BX* BY) void k_pattern(const InstDev* __restrict__ descs,
+                                                    const int4* __restrict__ tiles,
+                                                    const int* __restrict__ status, int kz,
+                                                    uint32_t key) {
+  const int4 tl = tiles[blockIdx.x];
+  if (tl.x < 0 || status[tl.x] != RUN) return;
+  const InstDev D = descs[tl.x];
+  const int j = tl.y + (int)threadIdx.x;
+  if (j >= D.nr) return;
+  if ((D.side_rmin == SIDE_WALL && j == 0) || (D.side_rmax == SIDE_WALL && j == D.nr - 1)) return;
+  const RowC R = make_row(D, j);
+  const int k0 = tl.z + (int)threadIdx.y;
+  int kbeg = k0, kend = min(k0 + BY * kz, D.nz);
+  if (z_bounded(D)) {
+    if (kbeg == 0) kbeg += BY;
+    if (kend == D.nz && (D.nz - 1 - k0) % BY == 0) kend = D.nz - 1;
+  }
+  for (int k = kbeg; k < kend; k += 2 * BY) {
+    float s[9], t[5], ph, s2[9], t2[5], ph2 = 0.0f;
+    const bool two = k + BY < kend;
+    node_load<S, ODD, BUF>(D, R, j, k, s, t, ph);
+    if (two) node_load<S, ODD, BUF>(D, R, j, k + BY, s2, t2, ph2);
+    pattern_store<S, ODD, BUF>(D, R, j, k, s, t, ph, key);
+    if (two) pattern_store<S, ODD, BUF>(D, R, j, k + BY, s2, t2, ph2, key);
+  }
+}
+
+// Plain in-place read+write stream over n 16-byte words (bits XORed with key).
+__global__ __launch_bounds__(RB) void k_stream_rw(uint4* __restrict__ p, int64_t n, uint32_t key) {
+  const int64_t stride = (int64_t)gridDim.x * RB;
+  for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += stride) {
+    uint4 v = p[i];
+    v.x ^= key;
+    v.y ^= key;
+    v.z ^= key;
+    v.w ^= key;
+    p[i] = v;
   }
 }
 
@@ -573,6 +618,25 @@ int launch_fields(lbm_axi* h, int inst, bool odd, const FieldOut& fo) {
     k_step<S, true, MODE_FIELDS, false><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->dstatus, h->kz, 0, fo, 0u, nullptr, 0);
   HIPCHK(hipGetLastError());
   return LBM_AXI_OK;
+}
+
+template <typename S, bool BUF>
+void launch_pattern_b(lbm_axi* h, bool odd, uint32_t key) {
+  const dim3 blk(BX, BY);
+  if (!odd)
+    k_pattern<S, false, BUF><<<h->ntiles_launch, blk, h->lds_bytes, h->stream>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, key);
+  else
+    k_pattern<S, true, BUF><<<h->ntiles_odd, blk, h->lds_bytes, h->stream>>>(h->ddesc, h->dtiles_odd, h->dstatus, h->kz_odd, key);
+}
+
+// The probe takes the step's addressing: buffer addressing for 16-bit
+// storage when every array is below 4 GiB, flat otherwise.
+template <typename S>
+void launch_pattern(lbm_axi* h, bool odd, uint32_t key) {
+  if constexpr (sizeof(S) == 2) {
+    if (h->buf) return launch_pattern_b<S, true>(h, odd, key);
+  }
+  launch_pattern_b<S, false>(h, odd, key);
 }
 
 template <typename S>
@@ -1494,6 +1558,82 @@ int lbm_axi_pipe_nusselt(lbm_axi* h, int32_t inst, int32_t area, double* nu, dou
     }
     release_tmp();
     return rc;
+  });
+}
+
+int lbm_axi_pattern_bandwidth(lbm_axi* h, int32_t reps, double* out) {
+  return guarded([&]() -> int {
+    if (!h || !out || reps < 1 || reps > 100000)
+      return fail(LBM_AXI_EINVAL, "bad handle, output or reps out of [1, 100000]");
+    HIPCHK(hipStreamSynchronize(h->stream));
+    std::vector<int> st(h->n_inst);
+    HIPCHK(hipMemcpy(st.data(), h->dstatus, sizeof(int) * h->n_inst, hipMemcpyDeviceToHost));
+    // Algorithmic bytes of one step launch: per fluid node of the running
+    // instances in the launch, 13 populations of the storage type and the
+    // FP32 g_0 read and written, and the porosity read where it is a field.
+    const double esz = h->storage == LBM_STORE_FP32 ? 4.0 : 2.0;
+    double bytes = 0.0, arr = 0.0;
+    for (int i = 0; i < h->n_inst; ++i) {
+      const lbm_axi_params& q = h->prm[i];
+      const InstDev& D = h->hdesc[i];
+      arr += 14.0 * D.plane * esz + (h->storage == LBM_STORE_FP32 ? 0.0 : 4.0 * D.plane);
+      if (st[i] != RUN || !(h->active.empty() || h->active[i])) continue;
+      const double nrf = q.nr - (q.side_rmin == SIDE_WALL) - (q.side_rmax == SIDE_WALL);
+      const double nzf = q.nz - (z_bounded(D) ? 2 : 0);
+      bytes += nrf * nzf * (26.0 * esz + 8.0 + (D.phi ? 4.0 : 0.0));
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    auto timed = [&](auto&& launch, double& ms) -> int {
+      launch();  // untimed first launch
+      HIPCHK(hipEventRecord(e0, h->stream));
+      for (int r = 0; r < reps; ++r) launch();
+      HIPCHK(hipEventRecord(e1, h->stream));
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipEventSynchronize(e1));
+      float f = 0.0f;
+      HIPCHK(hipEventElapsedTime(&f, e0, e1));
+      ms = f / reps;
+      return LBM_AXI_OK;
+    };
+    double ms[3] = {0, 0, 0};
+    int rc = LBM_AXI_OK;
+    for (int par = 0; par < 2 && rc == LBM_AXI_OK; ++par) {
+      const bool odd = par == 1;
+      auto go = [&]() {
+        switch (h->storage) {
+          case LBM_STORE_FP32: launch_pattern<float>(h, odd, 0u); break;
+          case LBM_STORE_FP16: launch_pattern<__half>(h, odd, 0u); break;
+          default: launch_pattern<__hip_bfloat16>(h, odd, 0u); break;
+        }
+      };
+      rc = timed(go, ms[par]);
+    }
+    // plain stream: every instance's population array (and separate g_0 plane)
+    // read and written in place, 16-byte words
+    if (rc == LBM_AXI_OK) {
+      auto go = [&]() {
+        for (int i = 0; i < h->n_inst; ++i) {
+          const InstDev& D = h->hdesc[i];
+          const int64_t nw = 14 * D.plane * (int64_t)esz / 16;
+          const unsigned nb = (unsigned)std::min<int64_t>((nw + RB - 1) / RB, 8192);
+          k_stream_rw<<<nb, RB, 0, h->stream>>>((uint4*)D.pop, nw, 0u);
+          if (h->storage != LBM_STORE_FP32)
+            k_stream_rw<<<(unsigned)std::min<int64_t>((D.plane / 4 + RB - 1) / RB, 8192), RB, 0,
+                          h->stream>>>((uint4*)D.g0, D.plane / 4, 0u);
+        }
+      };
+      rc = timed(go, ms[2]);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    out[0] = bytes / (ms[0] * 1e-3) / 1e9;
+    out[1] = bytes / (ms[1] * 1e-3) / 1e9;
+    out[2] = 2.0 * arr / (ms[2] * 1e-3) / 1e9;
+    out[3] = bytes;
+    return LBM_AXI_OK;
   });
 }
 

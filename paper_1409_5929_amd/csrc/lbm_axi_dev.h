@@ -641,6 +641,72 @@ __host__ __device__ inline void node_load(const InstDev& D, const RowC& R, int j
   phi_raw = D.phi_mode == 0 ? 0.0f : D.phi[o];
 }
 
+// Slots of the populations arriving at fluid node (j, k) in the AA layout of
+// the step's parity, as node_load reads them: a[0..8] hold f_0..f_8,
+// a[9..12] g_1..g_4 (indices into the 14-plane array); o is the node's own
+// offset (g_0 plane, porosity).  The step writes its post-collision f_i into
+// the slot it read f_opposite(i) from, so these are also the slots it
+// writes.  Used by the streaming-ceiling probe, whose identity update (every
+// value stored back where node_load found it) leaves the state unchanged only
+// if this map is node_load's.
+template <bool ODD>
+__host__ __device__ inline void node_slots(const InstDev& D, const RowC& R, int j, int k,
+                                           int64_t a[13], int64_t& o) {
+  const int64_t pl = D.plane;
+  const int st = D.stride;
+  int km = k - 1, kp = k + 1;
+  if (D.side_z == SIDE_PERIODIC) {
+    if (km < 0) km += D.nz;
+    if (kp >= D.nz) kp -= D.nz;
+  }
+  o = (int64_t)k * st + j;
+  const int64_t rowm = (int64_t)km * st, row0 = (int64_t)k * st, rowp = (int64_t)kp * st;
+  if (!ODD) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) a[q] = q * pl + o;
+#pragma unroll
+    for (int q = 1; q < 5; ++q) a[8 + q] = (9 + q) * pl + o;
+  } else {
+    const int64_t cm = R.cm, cp = R.cp;
+    a[0] = o;
+    a[1] = (R.mir ? 1 : 3) * pl + row0 + cm;
+    a[2] = 4 * pl + rowm + j;
+    a[3] = 1 * pl + row0 + cp;
+    a[4] = 2 * pl + rowp + j;
+    a[5] = (R.mir ? 8 : 7) * pl + rowm + cm;
+    a[6] = 8 * pl + rowm + cp;
+    a[7] = 5 * pl + rowp + cp;
+    a[8] = (R.mir ? 5 : 6) * pl + rowp + cm;
+    a[9] = (R.mir ? 10 : 12) * pl + row0 + cm;
+    a[10] = 13 * pl + rowm + j;
+    a[11] = 10 * pl + row0 + cp;
+    a[12] = 11 * pl + rowp + j;
+  }
+}
+
+// Streaming-ceiling probe: the stores of fluid node (j, k) with the step's
+// memory traffic and no arithmetic.  After the step's loads (node_load) each
+// value goes back, as the step orders its stores (f_i^+ into the slot of
+// f_opposite(i), then g), into the slot it came from, its bits XORed with
+// key: key = 0 leaves the state as it was, and the compiler cannot drop the
+// stores.  The porosity value is folded into the g_0 store the same way.
+template <typename S, bool ODD, bool BUF>
+__device__ inline void pattern_store(const InstDev& D, const RowC& R, int j, int k, const float s[9],
+                                     const float t[5], float ph, uint32_t key) {
+  constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+  const PopAcc<S, BUF> P(D);
+  int64_t a[13], o;
+  node_slots<ODD>(D, R, j, k, a, o);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) P.st(a[OPP[i]], __uint_as_float(__float_as_uint(s[OPP[i]]) ^ key), 0u);
+  D.g0[o] = __uint_as_float(__float_as_uint(t[0]) ^ (key & __float_as_uint(ph)));
+#pragma unroll
+  for (int i = 1; i < 5; ++i) {
+    const int q = i <= 2 ? i + 2 : i - 2;  // opposite of i in D2Q5
+    P.st(a[8 + q], __uint_as_float(__float_as_uint(t[q]) ^ key), 0u);
+  }
+}
+
 // One fluid node (j, k) at one time step, from its loaded populations s, t
 // and porosity value.  seed: random bits of this step for stochastic
 // rounding of 16-bit storage.

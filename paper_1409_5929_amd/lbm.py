@@ -118,6 +118,8 @@ def _load():
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_int32]
     lib.lbm_axi_macros.restype = ctypes.c_int
+    lib.lbm_axi_pattern_bandwidth.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_double)]
+    lib.lbm_axi_pattern_bandwidth.restype = ctypes.c_int
     lib.lbm_axi_derived.argtypes = [P(Params), P(ctypes.c_double)]
     lib.lbm_axi_derived.restype = ctypes.c_int
     lib.lbm_axi_density_deviation.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
@@ -366,6 +368,14 @@ class Lattice:
         _check(self._lib.lbm_axi_autotune(self._h, int(trial_steps), ctypes.byref(kz),
                                           ctypes.byref(bpc), ctypes.byref(ms)))
         return dict(kz=kz.value, blocks_per_cu=bpc.value, ms=ms.value)
+
+    def pattern_bandwidth(self, reps: int = 20) -> dict:
+        """Streaming ceiling of the step's access pattern on this handle's arrays
+        (GB/s of the even-step and odd-step patterns without arithmetic, of a
+        plain read+write stream, and the algorithmic bytes of one step launch)."""
+        out = (ctypes.c_double * 4)()
+        _check(self._lib.lbm_axi_pattern_bandwidth(self._h, int(reps), out))
+        return dict(even_gbs=out[0], odd_gbs=out[1], stream_gbs=out[2], bytes_per_launch=out[3])
 
     def set_timing(self, on: bool):
         _check(self._lib.lbm_axi_set_timing(self._h, 1 if on else 0))

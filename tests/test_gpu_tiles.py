@@ -75,3 +75,36 @@ def test_launch_shape_does_not_change_results(L, storage):
                 np.testing.assert_array_equal(a[k], b[k], err_msg=f"{storage} {shape} instance {i}: {k}")
         for k in ("res", "nu_i", "nu_o", "status"):
             np.testing.assert_array_equal(ref["res"][k], got["res"][k], err_msg=f"{storage} {shape}: {k}")
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("case", ["annulus field", "pipe axis periodic", "closed cylinder"])
+def test_pattern_probe_leaves_the_state_unchanged(L, storage, case):
+    """The streaming-ceiling probe makes the step's loads and stores and puts
+    every value back where node_load read it; afterwards the run continues
+    bit for bit as if the probe had not run, at either parity.  This also shows
+    that the probe's slot map (node_slots) is node_load's, slot for slot."""
+    if case == "annulus field":
+        cfg = li.annulus(nr=150, nz=70, Ra=1e5, Da=1e-3)
+        phi = li.porosity_grf(70, 150, seed=2, sigma=3.0)
+    elif case == "pipe axis periodic":
+        cfg, phi = li.pipe(nr=70, nz=12), None
+    else:
+        cfg = li.pipe(nr=33, nz=40)
+        cfg.update(side_z="wall", therm_z="fixed", T_zmin=1.0, T_zmax=0.0)
+        phi = None
+    got = []
+    for probe in (False, True):
+        lat = L.Lattice(cfg, phi=phi, storage=storage, check_interval=0)
+        lat.step(7)
+        if probe:
+            r = lat.pattern_bandwidth(reps=3)
+            assert r["even_gbs"] > 0 and r["odd_gbs"] > 0 and r["stream_gbs"] > 0
+        lat.step(4)
+        if probe:
+            lat.pattern_bandwidth(reps=2)
+        lat.step(3)
+        got.append(lat.fields())
+        lat.close()
+    for k in KEYS:
+        np.testing.assert_array_equal(got[0][k], got[1][k], err_msg=k)
