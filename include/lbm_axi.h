@@ -209,6 +209,23 @@ int lbm_axi_stream_function(lbm_axi* h, int32_t inst, float* psi, double* psi_ab
                             int32_t dst_is_device);
 
 /*
+ * lbm_axi_stream_function for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same result without any allocation.  psi: NULL or device
+ * memory for [nz][nr] floats; psi_absmax: NULL or device memory for one
+ * double (max |psi|).  Both are written on the handle's stream and not waited
+ * for.  Its scratch (the u_z field and the per-column maxima) is a static
+ * array of the library on each device, held until the process ends, of at
+ * most 2^23 nodes and 2^16 columns: a larger instance gets LBM_AXI_EINVAL.
+ * All handles on one device share that array and each call leaves its
+ * contents behind, so calls that overlap on one device (handles on different
+ * streams, threads) race; calls ordered on one stream do not.  The call reads
+ * the instance's run state and time level from the device (a small copy to
+ * the host, as lbm_axi_info).
+ */
+int lbm_axi_stream_function_static(lbm_axi* h, int32_t inst, float* psi, double* psi_absmax);
+
+/*
  * Local Nusselt number along the wall of a pipe (axis at r_min, wall at
  * r_max), Sec. 4.1: at each column k, Nu = D (dT/dr)_w / (T_w - T_b) (Eq. 40)
  * with D = 2 r_w and the second-order one-sided wall gradient.  T_b is the

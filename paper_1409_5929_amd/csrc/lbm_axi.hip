@@ -31,6 +31,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -74,9 +75,24 @@ struct ResTile {
   int inst, k0, k1, pad;
 };
 
+// Scratch of lbm_axi_stream_function_static, for callers that cannot
+// allocate: the u_z field of one instance (at most SCRATCH_NODES floats) and
+// its per-column maxima (at most SCRATCH_COLS doubles).  Each device holds its
+// own copy for the life of the process; host code must use the per-device
+// address from hipGetSymbolAddress (scratch_address), never the array's name.
+constexpr int64_t SCRATCH_NODES = int64_t(1) << 23;
+constexpr int64_t SCRATCH_COLS = int64_t(1) << 16;
+constexpr int MAX_DEVICES = 64;
+__device__ __align__(256) unsigned char scratch[SCRATCH_NODES * 4 + SCRATCH_COLS * 8];
+
+std::mutex g_scratch_mu;
+void* g_scratch[MAX_DEVICES] = {};
+
 }  // namespace
 
 struct lbm_axi {
+  int device = 0;               // HIP device the handle was created on
+  void* scratch = nullptr;      // that device's copy of the static scratch array
   int n_inst = 0;
   int storage = 0;
   int check = 0;
@@ -959,6 +975,19 @@ int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* 
         return bail(fail(LBM_AXI_EDEVICE, "device query failed"));
       h->lds_per_cu = lds;
       h->lds_per_block = ldsb;
+      h->device = dev;
+      // Device address of the static scratch array, resolved once per device
+      // with that device current (it is the current one here).
+      if (dev < 0 || dev >= MAX_DEVICES) return bail(fail(LBM_AXI_EDEVICE, "device index out of range"));
+      std::lock_guard<std::mutex> lock(g_scratch_mu);
+      if (!g_scratch[dev]) {
+        void* sp = nullptr;
+        const hipError_t se = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+        if (se != hipSuccess || !sp)
+          return bail(fail(LBM_AXI_EDEVICE, std::string("scratch address: ") + hipGetErrorString(se)));
+        g_scratch[dev] = sp;
+      }
+      h->scratch = g_scratch[dev];
     }
     if (hip_stream) {
       h->stream = (hipStream_t)hip_stream;
@@ -1514,6 +1543,34 @@ int lbm_axi_stream_function(lbm_axi* h, int32_t inst, float* psi, double* psi_ab
     }
     release_tmp();
     return rc;
+  });
+}
+
+int lbm_axi_stream_function_static(lbm_axi* h, int32_t inst, float* psi, double* psi_absmax) {
+  return guarded([&]() -> int {
+    if (!h || inst < 0 || inst >= h->n_inst) return fail(LBM_AXI_EINVAL, "bad handle or instance");
+    const lbm_axi_params& q = h->prm[inst];
+    if ((int64_t)q.nr * q.nz > SCRATCH_NODES || q.nz > SCRATCH_COLS)
+      return fail(LBM_AXI_EINVAL, "instance larger than the static scratch (2^23 nodes, 2^16 columns)");
+    if (!h->scratch) return fail(LBM_AXI_EDEVICE, "no scratch address for this device");
+    int64_t info[4];
+    int rc = lbm_axi_info(h, inst, info);  // run state and time level: a copy to the host, no allocation
+    if (rc) return rc;
+    const bool odd = (info[0] & 1) != 0;
+    float* duz = (float*)h->scratch;
+    double* dcol = (double*)((unsigned char*)h->scratch + SCRATCH_NODES * 4);
+    FieldOut fo{duz, nullptr, nullptr, nullptr, nullptr, nullptr};
+    switch (h->storage) {
+      case LBM_STORE_FP32: rc = launch_fields<float>(h, inst, odd, fo); break;
+      case LBM_STORE_FP16: rc = launch_fields<__half>(h, inst, odd, fo); break;
+      default: rc = launch_fields<__hip_bfloat16>(h, inst, odd, fo); break;
+    }
+    if (rc) return rc;
+    k_psi<<<(q.nz + RB / 64 - 1) / (RB / 64), RB, 0, h->stream>>>(
+        duz, q.nr, q.nz, q.r0, q.side_rmin == LBM_SIDE_AXIS ? 1 : 0, psi, dcol);
+    if (psi_absmax) k_absmax<<<1, RB, 0, h->stream>>>(dcol, q.nz, psi_absmax);
+    HIPCHK(hipGetLastError());
+    return LBM_AXI_OK;
   });
 }
 

@@ -118,6 +118,9 @@ def _load():
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_int32]
     lib.lbm_axi_macros.restype = ctypes.c_int
+    lib.lbm_axi_stream_function_static.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                                   ctypes.c_void_p]
+    lib.lbm_axi_stream_function_static.restype = ctypes.c_int
     lib.lbm_axi_pattern_bandwidth.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_double)]
     lib.lbm_axi_pattern_bandwidth.restype = ctypes.c_int
     lib.lbm_axi_derived.argtypes = [P(Params), P(ctypes.c_double)]
@@ -312,6 +315,15 @@ class Lattice:
                                                  psi.ctypes.data if field else None,
                                                  ctypes.byref(mx), 0))
         return psi, mx.value
+
+    def stream_function_static(self, inst: int = 0, psi=None, psi_absmax=None):
+        """The stream function written into caller device memory without any
+        allocation: psi a float32 [nz, nr] device tensor (or None), psi_absmax a
+        float64 device tensor of one element (or None); written on the
+        handle's stream."""
+        _check(self._lib.lbm_axi_stream_function_static(
+            self._h, int(inst), None if psi is None else psi.data_ptr(),
+            None if psi_absmax is None else psi_absmax.data_ptr()))
 
     def pipe_nusselt(self, inst: int = 0, area: bool = False):
         """Local Nusselt number (Eq. 40) and bulk temperature at every column of

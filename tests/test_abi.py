@@ -97,6 +97,7 @@ def test_null_handles_are_refused():
     assert lib.lbm_axi_pipe_nusselt(None, 0, 0, None, None) == -1
     assert lib.lbm_axi_density_deviation(None, 0, None, 0) == -1
     assert lib.lbm_axi_pattern_bandwidth(None, 1, None) == -1
+    assert lib.lbm_axi_stream_function_static(None, 0, None, None) == -1
     assert lib.lbm_axi_derived(None, None) == -1
     lib.lbm_axi_destroy(None)  # allowed
 
