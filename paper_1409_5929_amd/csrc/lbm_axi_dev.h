@@ -262,6 +262,9 @@ struct Dither {
   }
 };
 
+// Offset of row k in a plane (64-bit: planes of large grids pass 2^31).
+__host__ __device__ inline int64_t row_off(int k, int stride) { return (int64_t)k * stride; }
+
 // ---- per-column constants (r is fixed along a thread's z loop) -------------
 struct RowC {
   float r, inv_r;
@@ -276,43 +279,53 @@ struct RowC {
 };
 
 __host__ __device__ inline RowC make_row(const InstDev& D, int j) {
+  // Row j sits at r = r0 + j, exact in FP64.  The streaming rescale factors
+  // r_src / r and the wrap offsets carry every arriving population, and mass
+  // is conserved only if they match the radii the neighbouring rows use, so
+  // they are FP64 quotients rounded once.  The other constants take FP32 from
+  // the correctly rounded 1 / r: their rounding is one more FP32 rounding of
+  // the update (measured against the oracle: no change beyond 1e-7).
   RowC R;
-  const double r = (double)D.r0 + j;
-  const double inv = 1.0 / r;
+  const double rd = (double)D.r0 + j;
   const bool rper = D.side_rmin == SIDE_PERIODIC;
+  const bool wrap_p = j == 0 && rper, wrap_m = j == D.nr - 1 && rper;
   R.cm = j - 1;
   R.cp = j + 1;
   R.mir = false;
-  double src_p = r - 1.0, src_m = r + 1.0;
-  if (j == 0) {
-    if (D.side_rmin == SIDE_AXIS) {
-      R.cm = 0;
-      R.mir = true;  // source radius r - 1 = -1/2 is the mirror row itself
-    } else if (rper) {
-      R.cm = D.nr - 1;
-      src_p = (double)D.r0 + (D.nr - 1);
-    }
+  if (j == 0 && D.side_rmin == SIDE_AXIS) {
+    R.cm = 0;
+    R.mir = true;  // source radius r - 1 = -1/2 is the mirror row itself
   }
-  if (j == D.nr - 1 && rper) {
-    R.cp = 0;
-    src_m = (double)D.r0;
-  }
-  R.r = (float)r;
-  R.inv_r = (float)inv;
+  if (wrap_p) R.cm = D.nr - 1;
+  if (wrap_m) R.cp = 0;
+  const double src_p = wrap_p ? (double)D.r0 + (D.nr - 1) : rd - 1.0;
+  const double src_m = wrap_m ? (double)D.r0 : rd + 1.0;
   // d = (r_src / r) s + w (r_src - r + e_r) / r: the offset is zero unless
   // the source sits across a radial wrap (r_src != r - e_r).
-  R.rp = (float)(src_p * inv);
-  R.op1 = (float)((1.0 / 9.0) * (src_p - r + 1.0) * inv);
-  R.op5 = (float)((1.0 / 36.0) * (src_p - r + 1.0) * inv);
-  R.rm = (float)(src_m * inv);
-  R.om1 = (float)((1.0 / 9.0) * (src_m - r - 1.0) * inv);
-  R.om5 = (float)((1.0 / 36.0) * (src_m - r - 1.0) * inv);
-  R.lr0b = (float)(0.5 * (1.0 + (double)D.c_tau * inv * inv));
-  R.hcs2r = (float)(0.5 / 3.0 * inv);
-  R.ar0 = (float)(inv / 3.0);
-  R.ar1 = (float)(2.0 * (double)D.c_tau * inv * inv);
-  R.omT1 = (float)((double)D.omc * (1.0 + (double)D.tau_T * inv));
-  R.omT3 = (float)((double)D.omc * (1.0 - (double)D.tau_T * inv));
+  const double invd = 1.0 / rd;
+  R.rp = (float)(src_p * invd);
+  R.rm = (float)(src_m * invd);
+  R.op1 = R.op5 = R.om1 = R.om5 = 0.0f;
+  if (wrap_p) {
+    const double gp = (src_p - rd + 1.0) * invd;
+    R.op1 = (float)((1.0 / 9.0) * gp);
+    R.op5 = (float)((1.0 / 36.0) * gp);
+  }
+  if (wrap_m) {
+    const double gm = (src_m - rd - 1.0) * invd;
+    R.om1 = (float)((1.0 / 9.0) * gm);
+    R.om5 = (float)((1.0 / 36.0) * gm);
+  }
+  const float r = (float)rd;
+  const float inv = (float)invd;
+  R.r = r;
+  R.inv_r = inv;
+  R.lr0b = 0.5f * (1.0f + D.c_tau * inv * inv);
+  R.hcs2r = (float)(0.5 / 3.0) * inv;
+  R.ar0 = inv * (float)(1.0 / 3.0);
+  R.ar1 = 2.0f * D.c_tau * inv * inv;
+  R.omT1 = D.omc * (1.0f + D.tau_T * inv);
+  R.omT3 = D.omc * (1.0f - D.tau_T * inv);
   return R;
 }
 
@@ -355,6 +368,35 @@ __host__ __device__ inline bool flux_node(const InstDev& D, uint8_t m, int k, fl
   return false;
 }
 
+// Reciprocal and square root from gfx950's single instructions (v_rcp_f32,
+// v_sqrt_f32, about 1 ulp) with one Newton correction each, rather than the
+// correctly rounded sequences that '/' and sqrtf compile to (about ten
+// instructions each, with scaling and special-case handling that the step's
+// finite, normal operands never need): a node update takes six reciprocals
+// and four square roots, and the 16-bit step is bound by its vector-ALU
+// instructions.  Without the corrections the 1-ulp errors are biased and
+// accumulate over a run (measured: 5e-5 in rho - 1 after 300 steps of the
+// Sec. 4.3 annulus); with them the results stay within the FP32 parity bound.
+// Host code (descriptors only) divides exactly.
+__host__ __device__ inline float frcp(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const float r = __builtin_amdgcn_rcpf(x);
+  return __builtin_fmaf(__builtin_fmaf(-x, r, 1.0f), r, r);  // r (2 - x r)
+#else
+  return 1.0f / x;
+#endif
+}
+__host__ __device__ inline float fsqrt(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const float y = __builtin_amdgcn_sqrtf(x);
+  const float h = 0.5f * __builtin_amdgcn_rcpf(y);  // y = 0 gives h = inf and a NaN below
+  const float c = __builtin_fmaf(__builtin_fmaf(-y, y, x), h, y);  // y + (x - y^2) / (2 y)
+  return y > 0.0f ? c : y;
+#else
+  return sqrtf(x);
+#endif
+}
+
 // Porosity, phi nu / K and phi F_phi / sqrt(K) at a node (Eqs. 6, 8).
 // From the porosity value of the node (phi_raw: the field value, or unused
 // when the porosity is uniform).
@@ -366,9 +408,10 @@ __host__ __device__ inline void porosity_of(const InstDev& D, float phi_raw, flo
     cF = D.cF;
   } else {
     phi = phi_raw;
-    const float q = (1.0f - phi) / phi;
+    const float iph = frcp(phi);
+    const float q = (1.0f - phi) * iph;
     cD = D.C1 * q * q;
-    cF = D.phi_mode == 1 ? D.C2 * q / phi : D.C3 * (1.0f - phi) / sqrtf(phi);
+    cF = D.phi_mode == 1 ? D.C2 * q * iph : D.C3 * (1.0f - phi) * frcp(fsqrt(phi));
   }
 }
 __host__ __device__ inline void porosity(const InstDev& D, int64_t o, float& phi, float& cD,
@@ -379,9 +422,10 @@ __host__ __device__ inline void porosity(const InstDev& D, int64_t o, float& phi
     cF = D.cF;
   } else {
     phi = D.phi[o];
-    const float q = (1.0f - phi) / phi;
+    const float iph = frcp(phi);
+    const float q = (1.0f - phi) * iph;
     cD = D.C1 * q * q;
-    cF = D.phi_mode == 1 ? D.C2 * q / phi : D.C3 * (1.0f - phi) / sqrtf(phi);
+    cF = D.phi_mode == 1 ? D.C2 * q * iph : D.C3 * (1.0f - phi) * frcp(fsqrt(phi));
   }
 }
 
@@ -461,9 +505,9 @@ __host__ __device__ inline void store_wall(const InstDev& D, const A& P, int jb,
     }
     if (!fluid_dest(D, jd, kd)) continue;
     if (ODD)
-      P.st(slot * pl + (int64_t)kd * D.stride + jd, d[i], rn.next());
+      P.st(slot * pl + row_off(kd, D.stride) + jd, d[i], rn.next());
     else
-      P.st(OPP[i] * pl + (int64_t)kb * D.stride + jb, d[i], rn.next());
+      P.st(OPP[i] * pl + row_off(kb, D.stride) + jb, d[i], rn.next());
   }
   for (int i = 1; i < 5; ++i) {
     int jd = jb + EXr[i], kd = kb + EZr[i], slot = i;
@@ -473,9 +517,9 @@ __host__ __device__ inline void store_wall(const InstDev& D, const A& P, int jb,
     }
     if (!fluid_dest(D, jd, kd)) continue;
     if (ODD)
-      P.st((9 + slot) * pl + (int64_t)kd * D.stride + jd, tg[i], rn.next());
+      P.st((9 + slot) * pl + row_off(kd, D.stride) + jd, tg[i], rn.next());
     else
-      P.st((9 + OPP[i]) * pl + (int64_t)kb * D.stride + jb, tg[i], rn.next());
+      P.st((9 + OPP[i]) * pl + row_off(kb, D.stride) + jb, tg[i], rn.next());
   }
 }
 
@@ -490,8 +534,8 @@ __host__ __device__ inline void wall_node(const InstDev& D, const A& P, const No
                                           const FieldOut& fo, Dither& rn) {
   const int jb = j + dr, kb = k + dz;
   const float rb = rB + (float)dr;
-  const float inv_rb = 1.0f / rb;
-  const int64_t ob = (int64_t)kb * D.stride + jb;
+  const float inv_rb = frcp(rb);
+  const int64_t ob = row_off(kb, D.stride) + jb;
   float phib, cDb, cFb;
   porosity_of(D, D.phi_mode == 0 ? 0.0f : D.phi[ob], phib, cDb, cFb);
   const uint8_t m = node_mask(D, jb, kb);
@@ -553,8 +597,8 @@ __host__ __device__ inline void wall_node(const InstDev& D, const A& P, const No
         tg[i] = wt[i] * (Tb - D.T_s) + (1.0f - om[i]) * gneq;
       }
     } else {
-      const float iphib = 1.0f / phib;
-      const float drag = cDb + cFb * sqrtf(urb * urb + uzb * uzb);
+      const float iphib = frcp(phib);
+      const float drag = cDb + cFb * fsqrt(urb * urb + uzb * uzb);
       const float Frb = phib * D.accel_r - drag * urb, Fzb = phib * Gz - drag * uzb;
       const float arb = CS2 * inv_rb - 2.0f * D.c_tau * urb * inv_rb * inv_rb;  // Eq. (25)
       float S1, S7, S8;
@@ -613,8 +657,8 @@ __host__ __device__ inline void node_load(const InstDev& D, const RowC& R, int j
     if (km < 0) km += D.nz;
     if (kp >= D.nz) kp -= D.nz;
   }
-  const int64_t o = (int64_t)k * st + j;
-  const int64_t rowm = (int64_t)km * st, row0 = (int64_t)k * st, rowp = (int64_t)kp * st;
+  const int64_t rowm = row_off(km, st), row0 = row_off(k, st), rowp = row_off(kp, st);
+  const int64_t o = row0 + j;
   if (!ODD) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) s[q] = P.ld(q * pl + o);
@@ -659,8 +703,8 @@ __host__ __device__ inline void node_slots(const InstDev& D, const RowC& R, int 
     if (km < 0) km += D.nz;
     if (kp >= D.nz) kp -= D.nz;
   }
-  o = (int64_t)k * st + j;
-  const int64_t rowm = (int64_t)km * st, row0 = (int64_t)k * st, rowp = (int64_t)kp * st;
+  const int64_t rowm = row_off(km, st), row0 = row_off(k, st), rowp = row_off(kp, st);
+  o = row0 + j;
   if (!ODD) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) a[q] = q * pl + o;
@@ -723,9 +767,9 @@ __host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC&
     if (km < 0) km += D.nz;
     if (kp >= D.nz) kp -= D.nz;
   }
-  const int64_t o = (int64_t)k * st + j;
+  const int64_t rowm = row_off(km, st), row0 = row_off(k, st), rowp = row_off(kp, st);
+  const int64_t o = row0 + j;
   Dither rn(mix32(seed ^ (uint32_t)o));
-  const int64_t rowm = (int64_t)km * st, row0 = (int64_t)k * st, rowp = (int64_t)kp * st;
   float t[5] = {t_in[0], t_in[1], t_in[2], t_in[3], t_in[4]};
   float phi, cD, cF;
   porosity_of(D, phi_raw, phi, cD, cF);
@@ -747,7 +791,7 @@ __host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC&
   const float sa = d[1] + d[2] + d[3] + d[4], sd = d[5] + d[6] + d[7] + d[8];
   B.drho = d[0] + sa + sd;                                  // rho - 1, Eq. (26)
   B.rho = 1.0f + B.drho;
-  const float inv_rho = 1.0f / B.rho;
+  const float inv_rho = frcp(B.rho);
   // sum e_r f / r = Jr - c_s^2 / (2 r); sum e_z f / r = Jz
   const float Jr = d[1] - d[3] + d[5] - d[6] - d[7] + d[8];
   const float Jz = d[2] - d[4] + d[5] + d[6] - d[7] - d[8];
@@ -760,9 +804,9 @@ __host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC&
   const float lr0 = R.lr0b + 0.25f * cD;                    // Eq. (30) / r
   const float lz0 = 0.5f + 0.25f * cD;
   const float l1 = 0.5f * cF;
-  const float vm = sqrtf(vr * vr + vz * vz);
-  B.ur = vr / (lr0 + sqrtf(lr0 * lr0 + l1 * vm));           // Eq. (28)
-  B.uz = vz / (lz0 + sqrtf(lz0 * lz0 + l1 * vm));
+  const float vm = fsqrt(vr * vr + vz * vz);
+  B.ur = vr * frcp(lr0 + fsqrt(lr0 * lr0 + l1 * vm));       // Eq. (28)
+  B.uz = vz * frcp(lz0 + fsqrt(lz0 * lz0 + l1 * vm));
   const float ur = B.ur, uz = B.uz, rho = B.rho;
 
   if (MODE == MODE_STEP_MACRO) {
@@ -782,14 +826,14 @@ __host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC&
   }
 
   // ---- forces (Eq. 6) and the axisymmetric correction (Eq. 25) -----------
-  const float um = sqrtf(ur * ur + uz * uz);
+  const float um = fsqrt(ur * ur + uz * uz);
   const float drag = cD + cF * um;
   const float Fr = phi * Gr - drag * ur;
   const float Fz = phi * Gz - drag * uz;
   const float ar = R.ar0 - R.ar1 * ur;
 
   // ---- moments of d and the non-equilibrium part (Eqs. 16-20) -----------
-  const float iphi = 1.0f / phi;
+  const float iphi = frcp(phi);
   const float ru2 = rho * (ur * ur + uz * uz) * iphi;
   B.n1 = (-4.0f * d[0] - sa + 2.0f * sd) + 2.0f * B.drho - 3.0f * ru2;
   B.n2 = (4.0f * d[0] - 2.0f * sa + sd) - B.drho + 3.0f * ru2;
