@@ -140,6 +140,7 @@ typedef struct lbm_axi_params {
   double flux_rmin, flux_rmax; /* q'/k of LBM_T_FLUX walls (temperature per lattice unit) */
   double flux_zlo, flux_zhi;   /* heated window of LBM_T_FLUX walls in z (default: all) */
   double u_in;                 /* inlet axial velocity with side_z = LBM_SIDE_FLOW */
+  double tail_tol;             /* > 0: convergence also needs the extrapolated tail (below) <= tail_tol */
 } lbm_axi_params;
 
 /* Fill *p with the paper's default rates and ratios; grid and physics zero. */
@@ -256,6 +257,16 @@ int lbm_axi_pipe_nusselt(lbm_axi* h, int32_t inst, int32_t area, double* nu, dou
  * the heater mean of Eqs. (43)-(44): Nu(z) = (q'/k) L / (T_h - T_ref) at each
  * heated wall node (T_h its wall temperature; the paper takes T_0 = T_o, the
  * cold-wall temperature), averaged over the heated nodes (NaN if none).
+ * Convergence: res <= tol.  A residual measures the rate of change, and an
+ * instance that relaxes slowly (time constant tau steps) stops at res = tol
+ * still about tau * tol away from its steady state.  With tail_tol > 0 it
+ * must also bring the changes still to come, extrapolated geometrically from
+ * its last checks, to at most tail_tol, each of: R_u N rho / (1 - rho) and
+ * R_T N rho / (1 - rho) (rho the ratio of the part's last two values,
+ * infinite while rho >= 1; units of res times steps, i.e. a distance to the
+ * steady state relative to U and dT), and for Nu_i and Nu_o the change over
+ * the last interval times rho / (1 - rho), relative to Nu (rho the ratio of
+ * the last two interval changes; a change below 1e-7 Nu counts as none).
  */
 int lbm_axi_residual(lbm_axi* h, double* res, double* nu_i, double* nu_o, int32_t* status);
 

@@ -263,15 +263,29 @@ def conduction_T(cfg: dict) -> np.ndarray:
 T_SCALE = 4.0  # departures of T from conduction are ~4x smaller than u / U
 
 
+def velocity_scale(cfg: dict) -> float:
+    """Expected size of the buoyant velocity of an annulus problem (lattice
+    units).  In a porous layer the velocity is the Darcy velocity
+    u_D = K g beta dT / nu; with K = Da L^2 (Eq. 9), g beta dT = U^2 / L and
+    nu = U L sqrt(Pr / Ra) (Eq. 39 with J = 1) that is q U, q = Da sqrt(Ra / Pr),
+    which spans six decades over the sweep distribution.  Where the medium
+    barely resists (q large) the velocity stays near U = Ma c_s, hence
+    U q / (1 + q)."""
+    q = cfg["Da"] * math.sqrt(cfg["Ra"] / cfg["Pr"])
+    return U_SCALE * q / (1.0 + q)
+
+
 def no_targets(fields: dict, cfg: dict) -> np.ndarray:
-    """Network targets of a field dict, float32 [3, nz, nr]: u_z / U, u_r / U
-    and T_SCALE times the departure of T from radial conduction (so that a
-    zero output is the conduction start)."""
-    return np.stack([fields["uz"] / U_SCALE, fields["ur"] / U_SCALE,
+    """Network targets of a field dict, float32 [3, nz, nr]: u_z and u_r over
+    the problem's velocity_scale, and T_SCALE times the departure of T from
+    radial conduction (so that a zero output is the conduction start)."""
+    us = velocity_scale(cfg)
+    return np.stack([fields["uz"] / us, fields["ur"] / us,
                      T_SCALE * (fields["T"] - conduction_T(cfg))]).astype(np.float32)
 
 
 def no_fields(pred: np.ndarray, cfg: dict) -> np.ndarray:
     """Inverse of no_targets: start fields (u_z, u_r, T) [3, nz, nr] from a prediction."""
-    return np.stack([pred[0] * U_SCALE, pred[1] * U_SCALE,
+    us = velocity_scale(cfg)
+    return np.stack([pred[0] * us, pred[1] * us,
                      pred[2] / T_SCALE + conduction_T(cfg)]).astype(np.float32)

@@ -69,6 +69,9 @@ struct DevResult {
   long long t_off;  // handle steps the instance sat out while stopped (even); its own
                     // time level is the handle's minus t_off
   long long t_arm;  // first check whose comparison spans steps the instance took
+  // previous check, for the tail extrapolation: residual parts, Nusselt
+  // numbers and their change over the interval before it
+  double ru_prev, rT_prev, nu_i_prev, nu_o_prev, dnu_i_prev, dnu_o_prev;
 };
 
 struct ResTile {
@@ -118,6 +121,7 @@ struct lbm_axi {
   int nrt = 0;
   double* dpart = nullptr;      // [nrt][6]
   double* dtol = nullptr;       // per-instance tolerance
+  double* dtail = nullptr;      // per-instance tail tolerance (0: none)
   double* dnus = nullptr;       // per instance: r_w / (H dT) of both walls, 1 / (Ma c_s), 1 / dT
   long long* dmx = nullptr;     // per-instance max_steps
   int* dstatus = nullptr;
@@ -376,6 +380,7 @@ __global__ __launch_bounds__(RB) void k_resid(const InstDev* __restrict__ descs,
 __global__ __launch_bounds__(RB) void k_final(const int* __restrict__ first,
                                               const double* __restrict__ part, long long t,
                                               double per_step, const double* __restrict__ tol,
+                                              const double* __restrict__ tail_tol,
                                               const long long* __restrict__ max_steps,
                                               const double* __restrict__ nu_scale,
                                               int* __restrict__ status,
@@ -412,14 +417,41 @@ __global__ __launch_bounds__(RB) void k_final(const int* __restrict__ first,
   r.nu_o = -nu_scale[4 * inst + 1] * a[5];
   r.u_rms = sqrt(a[3] / nf);
   r.t_check = t;
+  const double nu_i_old = r.nu_i_prev, nu_o_old = r.nu_o_prev;
+  r.nu_i_prev = r.nu_i;
+  r.nu_o_prev = r.nu_o;
   if (t < r.t_arm) {
-    r.res = r.res_u = r.res_T = HUGE_VAL;
+    r.res = r.res_u = r.res_T = r.ru_prev = r.rT_prev = HUGE_VAL;
+    r.dnu_i_prev = r.dnu_o_prev = HUGE_VAL;
     out[inst] = r;
     return;
   }
+  // Geometric tail of the changes still to come (when asked for), for each
+  // of u, T (rates: the sum of the future interval changes is
+  // rate rho / (1 - rho) / per_step with rho the ratio of successive rates)
+  // and the two wall Nusselt numbers (relative change over the interval;
+  // changes below 1e-7 of Nu, its resolution from FP32 fields, count as 0).
+  bool tail_ok = true;
+  const double dni = fabs(r.nu_i - nu_i_old), dno = fabs(r.nu_o - nu_o_old);
+  if (tail_tol[inst] > 0.0) {
+    const double tt = tail_tol[inst];
+    auto tail = [](double now, double before) {  // unknown before (+inf): no estimate yet
+      const double rho = before > 0.0 && before < HUGE_VAL ? now / before : HUGE_VAL;
+      return rho < 1.0 ? now * rho / (1.0 - rho) : HUGE_VAL;
+    };
+    tail_ok = tail(ru, r.ru_prev) / per_step <= tt || ru == 0.0;
+    tail_ok = tail_ok && (tail(rT, r.rT_prev) / per_step <= tt || rT == 0.0);
+    const double ni = fabs(r.nu_i), no = fabs(r.nu_o);
+    if (isfinite(r.nu_i) && ni > 0.0 && dni > 1e-7 * ni) tail_ok = tail_ok && tail(dni, r.dnu_i_prev) <= tt * ni;
+    if (isfinite(r.nu_o) && no > 0.0 && dno > 1e-7 * no) tail_ok = tail_ok && tail(dno, r.dnu_o_prev) <= tt * no;
+  }
+  r.ru_prev = ru;
+  r.rT_prev = rT;
+  r.dnu_i_prev = dni;
+  r.dnu_o_prev = dno;
   int st = RUN;
   if (!isfinite(res)) st = DIVERGED;
-  else if (res <= tol[inst]) st = CONVERGED;
+  else if (res == 0.0 || (res <= tol[inst] && tail_ok)) st = CONVERGED;
   else if (max_steps[inst] > 0 && t + 1 - r.t_off >= max_steps[inst]) st = STALLED;
   if (st != RUN) {
     r.t_stop = t + 1;
@@ -530,6 +562,7 @@ int validate(const lbm_axi_params& p, int i) {
   if (p.nr < 3 || p.nz < 1 || ((p.side_z == SIDE_WALL || p.side_z == SIDE_FLOW) && p.nz < 3))
     return fail(LBM_AXI_EINVAL, pre + "grid too small (nr >= 3, nz >= 3 with axial boundaries)");
   if (!std::isfinite(p.u_in)) return fail(LBM_AXI_EINVAL, pre + "u_in must be finite");
+  if (!(p.tail_tol >= 0.0)) return fail(LBM_AXI_EINVAL, pre + "tail_tol must be 0 or positive");
   if ((int64_t)p.nr * p.nz > (int64_t)1 << 31)
     return fail(LBM_AXI_EINVAL, pre + "grid larger than 2^31 nodes");
   if (!(p.r0 > 0.0)) return fail(LBM_AXI_EINVAL, pre + "r0 must be positive");
@@ -858,7 +891,8 @@ int resume_converged(lbm_axi* h) {
     r.t_off += gap - (gap & 1);
     r.t_arm = (h->t + N - 1) / N * N + N;
     r.t_stop = -1;
-    r.res = r.res_u = r.res_T = HUGE_VAL;
+    r.res = r.res_u = r.res_T = r.ru_prev = r.rT_prev = HUGE_VAL;
+    r.dnu_i_prev = r.dnu_o_prev = HUGE_VAL;
   }
   HIPCHK(hipMemcpyAsync(h->dres, rr.data(), sizeof(DevResult) * n, hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -1058,6 +1092,8 @@ int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* 
         r.t_stop = -1;
         r.t_off = 0;
         r.t_arm = h->check;  // the check at level 0 only fills a buffer
+        r.ru_prev = r.rT_prev = r.dnu_i_prev = r.dnu_o_prev = HUGE_VAL;
+        r.nu_i_prev = r.nu_o_prev = 0.0;
       }
       HIPBAIL(hipMemcpy(h->dres, r0.data(), sizeof(DevResult) * n_inst, hipMemcpyHostToDevice));
     }
@@ -1065,7 +1101,7 @@ int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* 
     if (h->check > 0) {
       std::vector<ResTile> rts;
       std::vector<int> first(2 * n_inst);
-      std::vector<double> tol(n_inst), nus(4 * n_inst);
+      std::vector<double> tol(n_inst), tail(n_inst), nus(4 * n_inst);
       std::vector<long long> mx(n_inst);
       for (int i = 0; i < n_inst; ++i) {
         const int nz = p[i].nz, nr = p[i].nr;
@@ -1074,6 +1110,7 @@ int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* 
         for (int k0 = 0; k0 < nz; k0 += rz) rts.push_back(ResTile{i, k0, std::min(nz, k0 + rz), 0});
         first[2 * i + 1] = (int)rts.size() - first[2 * i];
         tol[i] = p[i].tol;
+        tail[i] = p[i].tail_tol;
         mx[i] = p[i].max_steps;
         const double dT = p[i].delta_T != 0.0 ? p[i].delta_T : p[i].T_rmin - p[i].T_rmax;
         const double H = nz - 1;
@@ -1102,13 +1139,15 @@ int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* 
       h->dpart = (double*)dalloc(h, sizeof(double) * 6 * rts.size(), &err);
       h->dfirst = (int*)dalloc(h, sizeof(int) * first.size(), &err);
       h->dtol = (double*)dalloc(h, sizeof(double) * n_inst, &err);
+      h->dtail = (double*)dalloc(h, sizeof(double) * n_inst, &err);
       h->dnus = (double*)dalloc(h, sizeof(double) * 4 * n_inst, &err);
       h->dmx = (long long*)dalloc(h, sizeof(long long) * n_inst, &err);
-      if (!h->drt || !h->dpart || !h->dfirst || !h->dtol || !h->dnus || !h->dmx)
+      if (!h->drt || !h->dpart || !h->dfirst || !h->dtol || !h->dtail || !h->dnus || !h->dmx)
         return bail(fail(LBM_AXI_ENOMEM, "reduction arrays"));
       HIPBAIL(hipMemcpy(h->drt, rts.data(), sizeof(ResTile) * rts.size(), hipMemcpyHostToDevice));
       HIPBAIL(hipMemcpy(h->dfirst, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice));
       HIPBAIL(hipMemcpy(h->dtol, tol.data(), sizeof(double) * n_inst, hipMemcpyHostToDevice));
+      HIPBAIL(hipMemcpy(h->dtail, tail.data(), sizeof(double) * n_inst, hipMemcpyHostToDevice));
       HIPBAIL(hipMemcpy(h->dnus, nus.data(), sizeof(double) * 4 * n_inst, hipMemcpyHostToDevice));
       HIPBAIL(hipMemcpy(h->dmx, mx.data(), sizeof(long long) * n_inst, hipMemcpyHostToDevice));
     }
@@ -1200,7 +1239,7 @@ int lbm_axi_step(lbm_axi* h, int32_t nsteps) {
         k_resid<<<h->nrt, RB, 0, h->stream>>>(h->ddesc, h->drt, slot, h->dstatus, h->dpart);
         HIPCHK(hipGetLastError());
         k_final<<<h->n_inst, RB, 0, h->stream>>>(h->dfirst, h->dpart, n, 1.0 / h->check, h->dtol,
-                                                  h->dmx, h->dnus, h->dstatus, h->dres);
+                                                  h->dtail, h->dmx, h->dnus, h->dstatus, h->dres);
         HIPCHK(hipGetLastError());
       }
       h->t = n + 1;

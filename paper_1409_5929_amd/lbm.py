@@ -49,7 +49,7 @@ class Params(ctypes.Structure):
         ("delta_T", ctypes.c_double), ("tol", ctypes.c_double), ("max_steps", ctypes.c_int64),
         ("flux_rmin", ctypes.c_double), ("flux_rmax", ctypes.c_double),
         ("flux_zlo", ctypes.c_double), ("flux_zhi", ctypes.c_double),
-        ("u_in", ctypes.c_double),
+        ("u_in", ctypes.c_double), ("tail_tol", ctypes.c_double),
     ]
 
 
@@ -57,7 +57,7 @@ _ALIASES = {"lam": "lambda_", "lambda": "lambda_"}
 
 
 def make_params(cfg: dict, storage: str = "fp32", check_interval: int = 100, tol: float = 0.0,
-                max_steps: int = 0, storage_shift: int = 0) -> Params:
+                max_steps: int = 0, storage_shift: int = 0, tail_tol: float = 0.0) -> Params:
     """Pack a problem dictionary (see ``lbm_inputs``) into ``lbm_axi_params``."""
     p = Params()
     lib = _load()
@@ -76,6 +76,7 @@ def make_params(cfg: dict, storage: str = "fp32", check_interval: int = 100, tol
     p.check_interval = int(check_interval)
     p.tol = float(cfg.get("tol", tol))  # a problem may carry its own stopping rule
     p.max_steps = int(cfg.get("max_steps", max_steps))
+    p.tail_tol = float(cfg.get("tail_tol", tail_tol))
     return p
 
 
@@ -194,7 +195,7 @@ class Lattice:
     """
 
     def __init__(self, cfg, phi=None, init=None, storage="fp32", check_interval=100,
-                 tol=0.0, max_steps=0, storage_shift=0, stream=None):
+                 tol=0.0, max_steps=0, storage_shift=0, stream=None, tail_tol=0.0):
         lib = _load()
         cfgs = list(cfg) if isinstance(cfg, (list, tuple)) else [cfg]
         n = len(cfgs)
@@ -210,7 +211,7 @@ class Lattice:
         self.cfgs = cfgs
         arr = (Params * n)()
         for i, c in enumerate(cfgs):
-            arr[i] = make_params(c, storage, check_interval, tol, max_steps, storage_shift)
+            arr[i] = make_params(c, storage, check_interval, tol, max_steps, storage_shift, tail_tol)
         keep = []
         fp = ctypes.POINTER(ctypes.c_float)
         phi_ptrs = (fp * n)()

@@ -33,7 +33,7 @@ def test_trained_network_matches_oracle(ws):
     from paper_1409_5929_amd.no import WarmStartNet
 
     params = ws.load_weights(ws.WEIGHTS)
-    cfg = ws.problems(2048 + 128, 1409)[2048 + 40]
+    cfg = ws.held_out(41)[40]
     x = li.no_features(cfg)[None]
     net = WarmStartNet(ws.WIDTHS, ws.GRID, ws.GRID, 1, params)
     y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
@@ -48,25 +48,29 @@ def test_trained_network_matches_oracle(ws):
     assert eT <= 3e-2 and eu <= 3e-2
 
 
-def test_warm_start_reaches_the_same_steady_state_in_fewer_steps(ws):
-    """16 held-out problems: every problem that converges from the cold start
-    converges from the prediction too, in fewer steps in total (at most 60 %
-    of the cold steps), to the same state: Nu_i agrees to the level that
-    stopping at res = 1e-8 allows (median 2e-3; runs approaching the steady
-    state from different sides stop at different distances from it)."""
+def test_learned_start_beats_the_conduction_start(ws):
+    """24 held-out problems from the cold start, the network's start and the
+    non-learned conduction-profile start, each to the warm-start stopping rule
+    (res <= 1e-8 and extrapolated remaining change <= 1e-4).  Over the
+    problems that converge from all three: the learned start takes fewer
+    steps in total than the conduction start (and than the cold start), and
+    every problem's Nu_i lies within 1e-3 of the cold start's, from both."""
     from paper_1409_5929_amd.no import WarmStartNet
 
-    cfgs = ws.problems(2048 + 128, 1409)[2048:2048 + 16]
+    cfgs = ws.held_out(24)
     net = WarmStartNet(ws.WIDTHS, ws.GRID, ws.GRID, 32, ws.load_weights(ws.WEIGHTS))
     pred = ws.predict(net, cfgs)
     net.close()
     assert np.isfinite(pred).all()
     cold = ws.solve(cfgs, max_steps=600_000, fields=False)
     warm = ws.solve(cfgs, init=list(pred), max_steps=600_000, fields=False)
-    ok = cold["status"] == 1
-    assert ok.sum() >= 8
-    assert (warm["status"][ok] == 1).all()
-    c = ws.compare(cold, warm, ok)
-    print(f"warm vs cold: {c}", flush=True)
-    assert c["steps_ratio_total"] <= 0.6
-    assert c["nu_rel_diff_median"] <= 2e-3
+    cond = ws.solve(cfgs, init=[ws.conduction_start(c) for c in cfgs], max_steps=600_000, fields=False)
+    ok = (cold["status"] == 1) & (warm["status"] == 1) & (cond["status"] == 1)
+    wc, dc, wd = ws.compare(cold, warm, ok), ws.compare(cold, cond, ok), ws.compare(cond, warm, ok)
+    print(f"converged cold/warm/conduction {int((cold['status'] == 1).sum())}/"
+          f"{int((warm['status'] == 1).sum())}/{int((cond['status'] == 1).sum())} of {len(cfgs)}; "
+          f"warm vs cold {wc}; conduction vs cold {dc}; warm vs conduction {wd}", flush=True)
+    assert ok.sum() >= 12
+    assert wd["steps_ratio_total"] < 1.0
+    assert wc["steps_ratio_total"] < 1.0
+    assert wc["nu_rel_diff_max"] <= 1e-3 and dc["nu_rel_diff_max"] <= 1e-3
