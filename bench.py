@@ -14,7 +14,7 @@ over its average duration from HIP events on the library's stream) and the
 FP64 CPU oracle timed on a bounded sample of the same problem (all host
 threads and one).  Also on the line: the same job with its host hand-overs
 (create, field read-back), the FP16 and BF16 storage variants, the
-1024-instance batched sweep, and the time to steady state of 32 held-out
+1024-instance batched sweep, and the time to steady state of 64 held-out
 128^2 problems from a cold start, from the learned warm start and from the
 conduction-profile start.
 """
@@ -359,7 +359,7 @@ def main():
                     help="skip the FP16/BF16 storage runs and the batched sweep")
     ap.add_argument("--sweep-instances", type=int, default=1024)
     ap.add_argument("--sweep-steps", type=int, default=1000)
-    ap.add_argument("--steady-problems", type=int, default=32)
+    ap.add_argument("--steady-problems", type=int, default=64)
     ap.add_argument("--steady-max-steps", type=int, default=600_000)
     ap.add_argument("--sweep-to-steady", type=int, default=0, metavar="CAP",
                     help="only run the 1024-instance sweep toward res <= 1e-8 for up to CAP steps")
