@@ -269,6 +269,17 @@ def time_to_steady(n_problems, cap):
     return out
 
 
+def check_summary(res, info, interval):
+    """The last residual / Nusselt check of the main run: its step, residual and
+    Nu_i, or a note when no check fell in the run (a check compares two check
+    steps, the first at level 0, so the first one runs at level `interval`)."""
+    t_check = int(info["t_check"])
+    if t_check < 0 or not math.isfinite(float(res["res"][0])):
+        return {"t_check": None, "residual": None, "nu_i": None,
+                "note": f"no check in this run (checks at multiples of {interval} steps from "
+                        f"level {interval} on; run ended at level {int(info['t'])})"}
+    return {"t_check": t_check, "residual": float(res["res"][0]), "nu_i": float(res["nu_i"][0])}
+
 def oracle_rate(cfg: dict, phi, seconds: float):
     """Steps of the FP64 oracle on (cfg, phi) until `seconds` of work are done:
     (steps, seconds, threads used)."""
