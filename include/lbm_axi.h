@@ -332,6 +332,24 @@ int lbm_axi_kernel_time(lbm_axi* h, double* total_ms, int64_t* launches);
 int lbm_axi_set_tiles(lbm_axi* h, int32_t kz, int32_t blocks_per_cu);
 
 /*
+ * Which lanes compute the radial no-slip wall nodes beside fluid rows
+ * (non-equilibrium extrapolation, Sec. 4).  With wall lanes (mode 1) each
+ * such wall node's own lane, idle otherwise, loads its owner's populations
+ * with the owner's wave and writes the wall populations that stream into
+ * fluid nodes; without (mode 0) the owner writes them after its own update,
+ * which costs a wave about twice an interior wave but keeps the kernel's
+ * register count lower.  mode -1 restores the default, chosen once from the
+ * instances: wall lanes when more than 5 % of the step's waves (64-column
+ * groups, weighted by nz) hold a wall lane, as for batches of grids a few
+ * hundred columns wide, not for one 8192^2 grid.  The two variants give the
+ * same results up to FP32 rounding of the wall populations (and different
+ * random bits for their 16-bit stores), so a run is bit-reproducible only
+ * within one setting.  *on (nullable) receives the setting in force (0/1).
+ * Waits for the stream and drops a captured step graph.
+ */
+int lbm_axi_set_wall_lanes(lbm_axi* h, int32_t mode, int32_t* on);
+
+/*
  * Change the storage type of every instance's populations (LBM_STORE_*),
  * keeping the state: each slot keeps its value, converted to the new type
  * (rounded to nearest), with temperature slots moved to the new type's shift.

@@ -45,7 +45,7 @@ using namespace lbmaxi;
 
 namespace {
 
-constexpr int BX = 64;   // lanes along r
+constexpr int BX = LANES_R;  // lanes along r
 constexpr int BY = 4;    // waves per block, interleaved along z
 constexpr int RB = 256;  // threads of the reduction kernels
 
@@ -135,6 +135,7 @@ struct lbm_axi {
   long long timed_launches = 0;
   std::vector<char> active;     // instances in the launch list (empty: all)
   bool buf = false;             // step kernels use buffer addressing (all arrays below 4 GiB)
+  bool wall_lanes = false;      // step kernels compute radial wall nodes on their own lanes
   long long* dclk = nullptr;    // device clock of captured step graphs
   int graph_steps = 32;         // steps per captured graph (0: no graphs)
   hipStream_t cap_stream = nullptr;
@@ -145,7 +146,7 @@ struct lbm_axi {
 // ---- kernels ------------------------------------------------------------------
 
 
-template <typename S, bool ODD, int MODE, bool BUF>
+template <typename S, bool ODD, int MODE, bool BUF, bool WL = false>
 __global__ __launch_bounds__(BX* BY) void k_step(const InstDev* __restrict__ descs,
                                                  const int4* __restrict__ tiles,
                                                  const int* __restrict__ status, int kz,
@@ -158,9 +159,20 @@ __global__ __launch_bounds__(BX* BY) void k_step(const InstDev* __restrict__ des
   if (tl.x < 0) return;
   if (MODE != MODE_FIELDS && status[tl.x] != RUN) return;
   const InstDev D = descs[tl.x];
-  const int j = tl.y + (int)threadIdx.x;
-  if (j >= D.nr) return;
-  if ((D.side_rmin == SIDE_WALL && j == 0) || (D.side_rmax == SIDE_WALL && j == D.nr - 1)) return;
+  const int jt = tl.y + (int)threadIdx.x;
+  if (jt >= D.nr) return;
+  // With wall lanes (WL) a radial wall lane (column 0 or nr - 1 of a no-slip
+  // side) works on its owner's column j and writes its own wall node
+  // (radial_wall) when it shares the owner's wave; otherwise, and without
+  // wall lanes, the owner computes the wall node and the wall lane idles.
+  int wl = 0;
+  if constexpr (WL && MODE != MODE_FIELDS) {
+    wl = (D.side_rmin == SIDE_WALL && jt == 0) ? 1 : (D.side_rmax == SIDE_WALL && jt == D.nr - 1) ? -1 : 0;
+    if (wl < 0 && !wall_lane_rmax(D)) return;
+  } else {
+    if ((D.side_rmin == SIDE_WALL && jt == 0) || (D.side_rmax == SIDE_WALL && jt == D.nr - 1)) return;
+  }
+  const int j = jt + wl;
   const RowC R = make_row(D, j);
   const bool zwall = z_bounded(D);
   // Fluid nodes of this thread's strip: k = kbeg, kbeg + BY, ... < kend.
@@ -174,7 +186,7 @@ __global__ __launch_bounds__(BX* BY) void k_step(const InstDev* __restrict__ des
   // the loads are scattered over three rows and the registers allow it (even
   // steps would exceed 256 VGPRs; 16-bit steps would lose a wave per SIMD).
   if (MODE == MODE_FIELDS || !ODD || sizeof(S) != 4) {
-    for (int k = kbeg; k < kend; k += BY) node_update<S, ODD, MODE, BUF>(D, R, j, k, mac_slot, fo, seed);
+    for (int k = kbeg; k < kend; k += BY) node_update<S, ODD, MODE, BUF, WL>(D, R, j, k, mac_slot, fo, seed, wl);
     return;
   }
   if (kbeg >= kend) return;
@@ -187,7 +199,7 @@ __global__ __launch_bounds__(BX* BY) void k_step(const InstDev* __restrict__ des
     float sn[9], tn[5], phn = 0.0f;
     const bool more = k + BY < kend;
     if (more) node_load<S, ODD, BUF>(D, R, j, k + BY, sn, tn, phn);
-    node_update_loaded<S, ODD, MODE, BUF>(D, R, j, k, mac_slot, fo, seed, s, t, ph);
+    node_update_loaded<S, ODD, MODE, BUF, WL>(D, R, j, k, mac_slot, fo, seed, s, t, ph, wl);
     if (!more) break;
 #pragma unroll
     for (int q = 0; q < 9; ++q) s[q] = sn[q];
@@ -606,6 +618,31 @@ int default_kz(const lbm_axi* h, bool odd = false) {
   return 1;
 }
 
+// Share of the step's waves (column groups of BX lanes, weighted by nz) that
+// hold a radial wall lane, over every instance of the handle.  Without wall
+// lanes such a wave runs its owner's wall node after the owner's update
+// (measured: about 2.1 times an interior wave); with them the wall lanes run
+// a short tail of their own (about 1.5 times), but every wave of the kernel
+// carries about 20 more VGPRs (FP32 even steps drop from 4 to 3 waves per
+// SIMD, 3 % slower at 8192^2).  Wall lanes therefore pay above a few per
+// cent: measured 1.20 against 1.44 ms per step for the 1024-instance sweep
+// (42 % of waves), 0.935 against 0.922 ms at 8192^2 in FP16 (1.6 %).  The
+// choice depends on the instances only, so compaction and launch shapes keep
+// results bit-identical.
+double wall_wave_share(const lbm_axi* h) {
+  double all = 0.0, wall = 0.0;
+  for (const InstDev& D : h->hdesc) {
+    const int ncol = (D.nr + BX - 1) / BX;
+    const bool lo = D.side_rmin == SIDE_WALL;
+    const bool hi = D.side_rmax == SIDE_WALL && wall_lane_rmax(D);
+    const int walls = (lo ? 1 : 0) + (hi && !(lo && (D.nr - 1) / BX == 0) ? 1 : 0);
+    all += (double)ncol * D.nz;
+    wall += (double)walls * D.nz;
+  }
+  return all > 0.0 ? wall / all : 0.0;
+}
+bool default_wall_lanes(const lbm_axi* h) { return wall_wave_share(h) > 0.05; }
+
 // Byte size for buffer addressing (32-bit offsets), 0 when 4 GiB or more.
 uint32_t pop_bytes32(size_t bytes) { return bytes < 0xFFFFFFFFull ? (uint32_t)bytes : 0u; }
 
@@ -624,24 +661,31 @@ void* dalloc(lbm_axi* h, size_t bytes, hipError_t* err) {
   return p;
 }
 
-template <typename S, bool BUF>
-int launch_step_b(lbm_axi* h, bool odd, int mode, int slot, uint32_t seed, hipStream_t st,
-                const long long* clk, int off) {
+template <typename S, bool BUF, bool WL>
+int launch_step_w(lbm_axi* h, bool odd, int mode, int slot, uint32_t seed, hipStream_t st,
+                  const long long* clk, int off) {
   const dim3 blk(BX, BY);
   const FieldOut fo{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   if (!odd) {
     if (mode == MODE_STEP)
-      k_step<S, false, MODE_STEP, BUF><<<h->ntiles_launch, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo, seed, clk, off);
+      k_step<S, false, MODE_STEP, BUF, WL><<<h->ntiles_launch, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo, seed, clk, off);
     else
-      k_step<S, false, MODE_STEP_MACRO, BUF><<<h->ntiles_launch, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo, seed, clk, off);
+      k_step<S, false, MODE_STEP_MACRO, BUF, WL><<<h->ntiles_launch, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo, seed, clk, off);
   } else {
     if (mode == MODE_STEP)
-      k_step<S, true, MODE_STEP, BUF><<<h->ntiles_odd, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles_odd, h->dstatus, h->kz_odd, slot, fo, seed, clk, off);
+      k_step<S, true, MODE_STEP, BUF, WL><<<h->ntiles_odd, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles_odd, h->dstatus, h->kz_odd, slot, fo, seed, clk, off);
     else
-      k_step<S, true, MODE_STEP_MACRO, BUF><<<h->ntiles_odd, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles_odd, h->dstatus, h->kz_odd, slot, fo, seed, clk, off);
+      k_step<S, true, MODE_STEP_MACRO, BUF, WL><<<h->ntiles_odd, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles_odd, h->dstatus, h->kz_odd, slot, fo, seed, clk, off);
   }
   HIPCHK(hipGetLastError());
   return LBM_AXI_OK;
+}
+
+template <typename S, bool BUF>
+int launch_step_b(lbm_axi* h, bool odd, int mode, int slot, uint32_t seed, hipStream_t st,
+                  const long long* clk, int off) {
+  if (h->wall_lanes) return launch_step_w<S, BUF, true>(h, odd, mode, slot, seed, st, clk, off);
+  return launch_step_w<S, BUF, false>(h, odd, mode, slot, seed, st, clk, off);
 }
 
 // 16-bit storage: buffer addressing when every instance's population array
@@ -836,18 +880,23 @@ void release(lbm_axi* h, void* p, size_t bytes) {
 }
 
 // One step of instance inst alone, in the AA layout of parity `odd` (plain
-// tile list, flat addressing).
-template <typename S>
-int launch_inst_step(lbm_axi* h, int inst, bool odd, uint32_t seed) {
+// tile list, flat addressing, the handle's wall-lane variant).
+template <typename S, bool WL>
+int launch_inst_step_w(lbm_axi* h, int inst, bool odd, uint32_t seed) {
   const dim3 blk(BX, BY);
   const FieldOut fo{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   const int4* tl = h->dtiles_plain + h->tile_first[inst];
   if (!odd)
-    k_step<S, false, MODE_STEP, false><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->dstatus, h->kz, 0, fo, seed, nullptr, 0);
+    k_step<S, false, MODE_STEP, false, WL><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->dstatus, h->kz, 0, fo, seed, nullptr, 0);
   else
-    k_step<S, true, MODE_STEP, false><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->dstatus, h->kz, 0, fo, seed, nullptr, 0);
+    k_step<S, true, MODE_STEP, false, WL><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->dstatus, h->kz, 0, fo, seed, nullptr, 0);
   HIPCHK(hipGetLastError());
   return LBM_AXI_OK;
+}
+template <typename S>
+int launch_inst_step(lbm_axi* h, int inst, bool odd, uint32_t seed) {
+  return h->wall_lanes ? launch_inst_step_w<S, true>(h, inst, odd, seed)
+                       : launch_inst_step_w<S, false>(h, inst, odd, seed);
 }
 
 // Sets converged instances running again (after a storage conversion).  A
@@ -1082,6 +1131,7 @@ int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* 
       return bail(fail(LBM_AXI_ENOMEM, "descriptor arrays"));
     HIPBAIL(hipMemcpy(h->ddesc, h->hdesc.data(), sizeof(InstDev) * n_inst, hipMemcpyHostToDevice));
     h->buf = all_buffer_addressable(h);
+    h->wall_lanes = default_wall_lanes(h);
     HIPBAIL(hipMemset(h->dstatus, 0, sizeof(int) * n_inst));
     {
       std::vector<DevResult> r0(n_inst);
@@ -1408,6 +1458,18 @@ int lbm_axi_set_tiles(lbm_axi* h, int32_t kz, int32_t blocks_per_cu) {
     drop_graph(h);
     h->tiles_set = true;
     return build_tiles(h, kz, kz);
+  });
+}
+
+int lbm_axi_set_wall_lanes(lbm_axi* h, int32_t mode, int32_t* on) {
+  return guarded([&]() -> int {
+    if (!h || mode < -1 || mode > 1) return fail(LBM_AXI_EINVAL, "bad handle or mode not in {-1, 0, 1}");
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const bool want = mode < 0 ? default_wall_lanes(h) : mode == 1;
+    if (want != h->wall_lanes) drop_graph(h);  // captured graphs hold the other kernels
+    h->wall_lanes = want;
+    if (on) *on = want ? 1 : 0;
+    return LBM_AXI_OK;
   });
 }
 

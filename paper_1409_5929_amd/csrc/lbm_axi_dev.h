@@ -55,6 +55,10 @@ enum { RUN = 0, CONVERGED = 1, DIVERGED = 2, STALLED = 3 };
 enum { MODE_STEP = 0, MODE_STEP_MACRO = 1, MODE_FIELDS = 2 };
 enum { MASK_RMIN = 1, MASK_RMAX = 2, MASK_ZMIN = 4, MASK_ZMAX = 8, MASK_AXIS = 16 };
 
+// Lanes of a step wave along r: the step's tiles start at multiples of it,
+// so columns c and c' share a wave when c / LANES_R == c' / LANES_R.
+constexpr int LANES_R = 64;
+
 // c_s^2 of D2Q9 (text after Eq. 25); weights of Eq. (32); D2Q5 weights of
 // Eq. (36) with wt_0 = 3/5 and c_sT^2 = 1/5.
 constexpr float CS2 = (float)(1.0 / 3.0);
@@ -337,6 +341,16 @@ __host__ __device__ inline bool z_bounded(const InstDev& D) {
 __host__ __device__ inline bool is_boundary(const InstDev& D, int j, int k) {
   return (D.side_rmin == SIDE_WALL && j == 0) || (D.side_rmax == SIDE_WALL && j == D.nr - 1) ||
          (z_bounded(D) && (k == 0 || k == D.nz - 1));
+}
+
+// Radial wall nodes beside fluid rows can be computed in the step by their
+// own lanes (radial_wall, step kernels with wall lanes), which load their
+// owner's populations.  That is safe only in the owner's wave, where the
+// loads precede the owner's in-place stores: always at r_min (columns 0 and
+// 1), at r_max unless column nr - 1 starts a new wave; otherwise the owner
+// computes the wall node (wall_node).
+__host__ __device__ inline bool wall_lane_rmax(const InstDev& D) {
+  return (D.nr - 1) % LANES_R != 0;
 }
 
 __host__ __device__ inline uint8_t node_mask(const InstDev& D, int j, int k) {
@@ -642,6 +656,84 @@ __host__ __device__ inline void wall_node(const InstDev& D, const A& P, const No
   }
 }
 
+// Radial wall node b = (jB - sg, k) beside fluid row k, computed by its own
+// lane from the state B of its owner (jB, k) (non-equilibrium extrapolation,
+// Sec. 4; no-slip, so u_b = 0): sg = +1 for the wall at r_min (owner j = 1),
+// -1 for the wall at r_max (owner j = nr - 2).  It is wall_node's no-slip
+// case for (dr, dz) = (-sg, 0), reduced to what streams into fluid nodes: the
+// three populations with e_r = sg (towards jB at rows k, k + 1, k - 1) and
+// the D2Q5 one with e_r = sg.  The lane loads its owner's populations and
+// forms B with the same instructions as its wave's fluid lanes, so a wave
+// with a wall lane runs this short tail once instead of the owner running a
+// full wall_node after its own update.
+template <typename S, bool ODD, int MODE, typename A>
+__host__ __device__ inline void radial_wall(const InstDev& D, const A& P, const NodeState& B,
+                                            const float t[5], float rB, int jB, int k, int sg,
+                                            int64_t rowm, int64_t row0, int64_t rowp,
+                                            int mac_slot, uint32_t seed) {
+  const bool lo = sg > 0;
+  const float fs = (float)sg;
+  const int jb = jB - sg;
+  const float rb = rB - fs;
+  const float inv_rb = frcp(rb);
+  const int64_t ob = row0 + jb;
+  const float phib = D.phi_mode == 0 ? D.phiu : D.phi[ob];
+  float Tb = B.T;
+  const int th = lo ? D.therm_rmin : D.therm_rmax;
+  if (th == THERM_FIXED) Tb = lo ? D.T_rmin : D.T_rmax;
+  else if (th == THERM_FLUX && k >= D.qk_lo && k <= D.qk_hi) Tb = B.T + (lo ? D.q_rmin : D.q_rmax);
+
+  if (MODE == MODE_STEP_MACRO) {
+    float* mac = mac_slot ? D.mac[1] : D.mac[0];
+    mac[ob] = 0.0f;
+    mac[D.plane + ob] = 0.0f;
+    mac[2 * D.plane + ob] = Tb;
+  }
+  // m+(b) = m^eq(rho_B, 0) + (I - L)(r_B / r_b) n(B) + (I - L/2) S(b), all / r_b,
+  // as deviations from the quiescent post-collision moments; only the rows of
+  // M^{-1} for the three outgoing directions are applied (back_transform).
+  const float drho = B.drho, rhob = 1.0f + drho;
+  const float q = rB * inv_rb;
+  const float hb = 0.5f * CS2 * inv_rb;
+  const float Gz = D.gbeta * (Tb - D.T_ref) + D.accel_z;
+  const float S3 = rhob * (phib * D.accel_r + CS2 * inv_rb), S5 = rhob * phib * Gz;
+  const float a1 = ((1.0f - D.s_e) * q * B.n1) * (float)(1.0 / 36.0);
+  const float a2 = ((1.0f - D.s_eps) * q * B.n2) * (float)(1.0 / 36.0);
+  const float a3 = ((1.0f - D.s_j) * q * B.n3 + (1.0f - 0.5f * D.s_j) * S3 - hb) * (float)(1.0 / 6.0);
+  const float a4 = ((1.0f - D.s_q) * q * B.n4 - (1.0f - 0.5f * D.s_q) * S3 + hb) * (float)(1.0 / 12.0);
+  const float a5 = ((1.0f - D.s_j) * q * B.n5 + (1.0f - 0.5f * D.s_j) * S5) * (float)(1.0 / 6.0);
+  const float a6 = ((1.0f - D.s_q) * q * B.n6 - (1.0f - 0.5f * D.s_q) * S5) * (float)(1.0 / 12.0);
+  const float a7 = ((1.0f - D.s_nu) * q * B.n7) * 0.25f;
+  const float a8 = ((1.0f - D.s_nu) * q * B.n8) * 0.25f;
+  const float e = -a1 - 2.0f * a2, c = 2.0f * a1 + a2;
+  const float pr = fs * (a3 + a4), pz = a5 + a6, s8 = fs * a8;
+  const float fa = W1 * drho + (e + fs * a3 - 2.0f * fs * a4 + a7);  // e_z = 0
+  const float fu = W5 * drho + (c + pr + pz + s8);                    // e_z = +1
+  const float fd = W5 * drho + (c + pr - pz - s8);                    // e_z = -1
+  // g+(b) = wt (T_b - T_s) + (1 - omega(r_b)) g^neq(B) along e_r = sg, u_b = 0
+  const float om = D.omc * (1.0f + fs * D.tau_T * inv_rb);
+  const float tB = lo ? t[1] : t[3];
+  const float ga = WT1 * (Tb - D.T_s) + (1.0f - om) * (tB - WT1 * B.theta - 5.0f * WT1 * B.T * fs * B.ur);
+
+  const int64_t pl = D.plane;
+  const bool up = !(z_bounded(D) && k + 1 == D.nz - 1), dn = !(z_bounded(D) && k - 1 == 0);
+  Dither rn(mix32(seed ^ (uint32_t)ob));
+  const uint32_t r0 = rn.next(), r1 = rn.next(), r2 = rn.next(), r3 = rn.next();
+  if (ODD) {
+    // slot i of the destination node jB (rows k, k + 1, k - 1)
+    P.st((lo ? 1 : 3) * pl + row0 + jB, fa, r0);
+    if (up) P.st((lo ? 5 : 6) * pl + rowp + jB, fu, r1);
+    if (dn) P.st((lo ? 8 : 7) * pl + rowm + jB, fd, r2);
+    P.st((lo ? 10 : 12) * pl + row0 + jB, ga, r3);
+  } else {
+    // slot opposite(i) of the wall node itself
+    P.st((lo ? 3 : 1) * pl + ob, fa, r0);
+    if (up) P.st((lo ? 7 : 8) * pl + ob, fu, r1);
+    if (dn) P.st((lo ? 6 : 5) * pl + ob, fd, r2);
+    P.st((lo ? 12 : 10) * pl + ob, ga, r3);
+  }
+}
+
 // The populations arriving at fluid node (j, k) (as stored, unscaled to
 // FP32) and its porosity value.  Each slot is read and written by one node
 // only in a step, so these loads may be issued before earlier nodes of the
@@ -754,11 +846,11 @@ __device__ inline void pattern_store(const InstDev& D, const RowC& R, int j, int
 // One fluid node (j, k) at one time step, from its loaded populations s, t
 // and porosity value.  seed: random bits of this step for stochastic
 // rounding of 16-bit storage.
-template <typename S, bool ODD, int MODE, bool BUF = false>
+template <typename S, bool ODD, int MODE, bool BUF = false, bool WL = false>
 __host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC& R, int j, int k,
                                                    int mac_slot, const FieldOut& fo, uint32_t seed,
                                                    const float s[9], const float t_in[5],
-                                                   float phi_raw) {
+                                                   float phi_raw, int wl = 0) {
   const PopAcc<S, BUF> P(D);
   const int64_t pl = D.plane;
   const int st = D.stride;
@@ -845,7 +937,9 @@ __host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC&
   B.n7 = (d[1] - d[2] + d[3] - d[4]) - rho * (ur * ur - uz * uz) * iphi;
   B.n8 = (d[5] - d[6] + d[7] - d[8]) - rho * ur * uz * iphi;
 
-  if (MODE != MODE_FIELDS) {
+  // A radial wall lane (WL kernels, wl = +-1, node (j, k) being its owner)
+  // skips the fluid node's collision and stores and takes its wall node below.
+  if (MODE != MODE_FIELDS && (!WL || wl == 0)) {
     // ---- source (Eq. 24) and relaxation (Eq. 21) --------------------------
     float S1, S7, S8;
     source(D.src_printed != 0, rho, ur, uz, iphi, Fr, Fz, ar, S1, S7, S8);
@@ -926,18 +1020,31 @@ __host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC&
   }
 
   // ---- wall nodes owned by this node ---------------------------------------
+  // (after the fluid node's stores: only B stays live across them)
+  if constexpr (WL && MODE != MODE_FIELDS) {
+    if (wl != 0) {
+      radial_wall<S, ODD, MODE>(D, P, B, B.t, R.r, j, k, wl, rowm, row0, rowp, mac_slot, seed);
+      return;
+    }
+  }
   const bool own_rm = D.side_rmin == SIDE_WALL && j == 1;
   const bool own_rp = D.side_rmax == SIDE_WALL && j == D.nr - 2;
   const bool own_zm = z_bounded(D) && k == 1;
   const bool own_zp = z_bounded(D) && k == D.nz - 2;
+  // In the step kernels with wall lanes the radial wall nodes beside fluid
+  // rows are their own lanes' (radial_wall, where wall_lane_rmax allows);
+  // owners keep the rest: the z-wall nodes and the corners.
+  const bool rad_m = MODE == MODE_FIELDS || !WL;
+  const bool rad_p = MODE == MODE_FIELDS || !WL || !wall_lane_rmax(D);
   // Each (dr, dz) below is a separate inlined copy with constant offsets: on
   // annuli, where corner owners take three wall nodes, these specialised
   // passes run faster than one generic pass walked per lane.
-  if (own_rm || own_rp || own_zm || own_zp) {
+  if ((rad_m && own_rm) || (rad_p && own_rp) || own_zm || own_zp) {
     for (int dr = -1; dr <= 1; ++dr) {
       if ((dr == -1 && !own_rm) || (dr == 1 && !own_rp)) continue;
       for (int dz = -1; dz <= 1; ++dz) {
         if (dr == 0 && dz == 0) continue;
+        if (dz == 0 && ((dr == -1 && !rad_m) || (dr == 1 && !rad_p))) continue;
         if ((dz == -1 && !own_zm) || (dz == 1 && !own_zp)) continue;
         wall_node<S, ODD, MODE>(D, P, B, R.r, j, k, dr, dz, mac_slot, fo, rn);
       }
@@ -946,12 +1053,13 @@ __host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC&
 }
 
 // One fluid node (j, k) at one time step (load, then update).
-template <typename S, bool ODD, int MODE, bool BUF = false>
+template <typename S, bool ODD, int MODE, bool BUF = false, bool WL = false>
 __host__ __device__ inline void node_update(const InstDev& D, const RowC& R, int j, int k,
-                                            int mac_slot, const FieldOut& fo, uint32_t seed) {
+                                            int mac_slot, const FieldOut& fo, uint32_t seed,
+                                            int wl = 0) {
   float s[9], t[5], ph;
   node_load<S, ODD, BUF>(D, R, j, k, s, t, ph);
-  node_update_loaded<S, ODD, MODE, BUF>(D, R, j, k, mac_slot, fo, seed, s, t, ph);
+  node_update_loaded<S, ODD, MODE, BUF, WL>(D, R, j, k, mac_slot, fo, seed, s, t, ph, wl);
 }
 
 // Start state of node (j, k) (reading: f = f^eq - S~/2, g = g^eq), written

@@ -146,6 +146,8 @@ def _load():
     lib.lbm_axi_kernel_time.restype = ctypes.c_int
     lib.lbm_axi_set_tiles.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]
     lib.lbm_axi_set_tiles.restype = ctypes.c_int
+    lib.lbm_axi_set_wall_lanes.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.lbm_axi_set_wall_lanes.restype = ctypes.c_int
     lib.lbm_axi_set_storage.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]
     lib.lbm_axi_set_storage.restype = ctypes.c_int
     lib.lbm_axi_set_graph.argtypes = [ctypes.c_void_p, ctypes.c_int32]
@@ -357,6 +359,15 @@ class Lattice:
         """Launch shape of the step kernel: nodes per thread along z and a cap
         on resident blocks per compute unit (0: none).  Results do not change."""
         _check(self._lib.lbm_axi_set_tiles(self._h, int(kz), int(blocks_per_cu)))
+
+    def set_wall_lanes(self, mode: int = -1) -> bool:
+        """Radial wall nodes computed by their own lanes (1) or by their owners
+        after the owner's update (0); -1 restores the default chosen from the
+        instances.  Returns the setting in force.  The variants agree up to
+        FP32 rounding of the wall populations."""
+        on = ctypes.c_int32(0)
+        _check(self._lib.lbm_axi_set_wall_lanes(self._h, int(mode), ctypes.byref(on)))
+        return bool(on.value)
 
     def set_storage(self, storage: str, storage_shift: int = 0):
         """Convert the populations to another storage type ("fp32", "fp16",
