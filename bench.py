@@ -36,7 +36,8 @@ METRIC = "MLUPS (fused D2Q9+D2Q5) & % HBM roofline; time-to-steady warm vs cold 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic_8192.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1409_5929_amd", "csrc", f)
-                  for f in ("lbm_axi.hip", "lbm_axi_dev.h", "lbm_axi_desc.h")]
+                  for f in ("lbm_axi.hip", "lbm_axi_s16.hip", "lbm_axi_kernels.h", "lbm_axi_dev.h",
+                            "lbm_axi_desc.h")]
 
 
 def log(msg):

@@ -13,7 +13,8 @@ import sys
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 LIBS = {  # target -> sources
-    os.path.join(_HERE, "liblbm_axi.so"): [os.path.join(_HERE, "csrc", "lbm_axi.hip")],
+    os.path.join(_HERE, "liblbm_axi.so"): [os.path.join(_HERE, "csrc", "lbm_axi.hip"),
+                                           os.path.join(_HERE, "csrc", "lbm_axi_s16.hip")],
     os.path.join(_HERE, "liblbm_no.so"): [os.path.join(_HERE, "csrc", "lbm_no.hip")],
 }
 TARGET = os.path.join(_HERE, "liblbm_axi.so")

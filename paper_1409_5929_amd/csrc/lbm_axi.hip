@@ -40,13 +40,12 @@
 #include "../../include/lbm_axi.h"
 #include "lbm_axi_desc.h"
 #include "lbm_axi_dev.h"
+#include "lbm_axi_kernels.h"
 
 using namespace lbmaxi;
 
 namespace {
 
-constexpr int BX = LANES_R;  // lanes along r
-constexpr int BY = 4;    // waves per block, interleaved along z
 constexpr int RB = 256;  // threads of the reduction kernels
 
 thread_local std::string g_err;
@@ -146,100 +145,6 @@ struct lbm_axi {
 // ---- kernels ------------------------------------------------------------------
 
 
-template <typename S, bool ODD, int MODE, bool BUF, bool WL = false>
-__global__ __launch_bounds__(BX* BY) void k_step(const InstDev* __restrict__ descs,
-                                                 const int4* __restrict__ tiles,
-                                                 const int* __restrict__ status, int kz,
-                                                 int mac_slot, FieldOut fo, uint32_t seed,
-                                                 const long long* __restrict__ clk, int off) {
-  // Inside a captured step graph the time level comes from the device clock
-  // (set before every replay) plus the step's offset in the graph.
-  if (clk) seed = step_seed(*clk + off);
-  const int4 tl = tiles[blockIdx.x];
-  if (tl.x < 0) return;
-  if (MODE != MODE_FIELDS && status[tl.x] != RUN) return;
-  const InstDev D = descs[tl.x];
-  const int jt = tl.y + (int)threadIdx.x;
-  if (jt >= D.nr) return;
-  // With wall lanes (WL) a radial wall lane (column 0 or nr - 1 of a no-slip
-  // side) works on its owner's column j and writes its own wall node
-  // (radial_wall) when it shares the owner's wave; otherwise, and without
-  // wall lanes, the owner computes the wall node and the wall lane idles.
-  int wl = 0;
-  if constexpr (WL && MODE != MODE_FIELDS) {
-    wl = (D.side_rmin == SIDE_WALL && jt == 0) ? 1 : (D.side_rmax == SIDE_WALL && jt == D.nr - 1) ? -1 : 0;
-    if (wl < 0 && !wall_lane_rmax(D)) return;
-  } else {
-    if ((D.side_rmin == SIDE_WALL && jt == 0) || (D.side_rmax == SIDE_WALL && jt == D.nr - 1)) return;
-  }
-  const int j = jt + wl;
-  const RowC R = make_row(D, j);
-  const bool zwall = z_bounded(D);
-  // Fluid nodes of this thread's strip: k = kbeg, kbeg + BY, ... < kend.
-  const int k0 = tl.z + (int)threadIdx.y;
-  int kbeg = k0, kend = min(k0 + BY * kz, D.nz);
-  if (zwall) {
-    if (kbeg == 0) kbeg += BY;
-    if (kend == D.nz && (D.nz - 1 - k0) % BY == 0) kend = D.nz - 1;  // top wall row in this strip
-  }
-  // The two-stage pipeline below pays off only for the FP32 odd step: there
-  // the loads are scattered over three rows and the registers allow it (even
-  // steps would exceed 256 VGPRs; 16-bit steps would lose a wave per SIMD).
-  if (MODE == MODE_FIELDS || !ODD || sizeof(S) != 4) {
-    for (int k = kbeg; k < kend; k += BY) node_update<S, ODD, MODE, BUF, WL>(D, R, j, k, mac_slot, fo, seed, wl);
-    return;
-  }
-  if (kbeg >= kend) return;
-  // Two-stage pipeline: the next node's loads are in flight while this node
-  // is updated (each slot belongs to one node of the step, so the order of
-  // one thread's loads and stores across its nodes does not matter).
-  float s[9], t[5], ph;
-  node_load<S, ODD, BUF>(D, R, j, kbeg, s, t, ph);
-  for (int k = kbeg; k < kend; k += BY) {
-    float sn[9], tn[5], phn = 0.0f;
-    const bool more = k + BY < kend;
-    if (more) node_load<S, ODD, BUF>(D, R, j, k + BY, sn, tn, phn);
-    node_update_loaded<S, ODD, MODE, BUF, WL>(D, R, j, k, mac_slot, fo, seed, s, t, ph, wl);
-    if (!more) break;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) s[q] = sn[q];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) t[q] = tn[q];
-    ph = phn;
-  }
-}
-
-// Streaming-ceiling probe of the step: the step's launch (tiles, strips of
-// kz nodes, addressing) and its loads and stores, with no arithmetic
-// (pattern_store); two nodes of a strip are in flight at a time.
-template <typename S, bool ODD, bool BUF>
-__global__ __launch_bounds__(BX* BY) void k_pattern(const InstDev* __restrict__ descs,
-                                                    const int4* __restrict__ tiles,
-                                                    const int* __restrict__ status, int kz,
-                                                    uint32_t key) {
-  const int4 tl = tiles[blockIdx.x];
-  if (tl.x < 0 || status[tl.x] != RUN) return;
-  const InstDev D = descs[tl.x];
-  const int j = tl.y + (int)threadIdx.x;
-  if (j >= D.nr) return;
-  if ((D.side_rmin == SIDE_WALL && j == 0) || (D.side_rmax == SIDE_WALL && j == D.nr - 1)) return;
-  const RowC R = make_row(D, j);
-  const int k0 = tl.z + (int)threadIdx.y;
-  int kbeg = k0, kend = min(k0 + BY * kz, D.nz);
-  if (z_bounded(D)) {
-    if (kbeg == 0) kbeg += BY;
-    if (kend == D.nz && (D.nz - 1 - k0) % BY == 0) kend = D.nz - 1;
-  }
-  for (int k = kbeg; k < kend; k += 2 * BY) {
-    float s[9], t[5], ph, s2[9], t2[5], ph2 = 0.0f;
-    const bool two = k + BY < kend;
-    node_load<S, ODD, BUF>(D, R, j, k, s, t, ph);
-    if (two) node_load<S, ODD, BUF>(D, R, j, k + BY, s2, t2, ph2);
-    pattern_store<S, ODD, BUF>(D, R, j, k, s, t, ph, key);
-    if (two) pattern_store<S, ODD, BUF>(D, R, j, k + BY, s2, t2, ph2, key);
-  }
-}
-
 // Plain in-place read+write stream over n 16-byte words (bits XORed with key).
 __global__ __launch_bounds__(RB) void k_stream_rw(uint4* __restrict__ p, int64_t n, uint32_t key) {
   const int64_t stride = (int64_t)gridDim.x * RB;
@@ -258,41 +163,6 @@ __global__ void k_setclock(long long* clk, long long t) {
   if (threadIdx.x == 0) *clk = t;
 }
 
-template <typename S>
-__global__ __launch_bounds__(BX* BY) void k_init(const InstDev* __restrict__ descs,
-                                                 const int4* __restrict__ tiles, int kz,
-                                                 const float* __restrict__ init, int inst) {
-  const int4 tl = tiles[blockIdx.x];
-  if (tl.x != inst) return;
-  const InstDev D = descs[inst];
-  const int j = tl.y + (int)threadIdx.x;
-  if (j >= D.nr) return;
-  const int64_t n = (int64_t)D.nr * D.nz;
-  for (int i = 0; i < kz; ++i) {
-    const int k = tl.z + (int)threadIdx.y + BY * i;
-    if (k >= D.nz) break;
-    const int64_t o = (int64_t)k * D.nr + j;
-    init_node<S>(D, j, k, init[o], init[n + o], init[2 * n + o]);
-  }
-}
-
-// Start state without an init field: rest, uniform T_init.
-template <typename S>
-__global__ __launch_bounds__(BX* BY) void k_init_uniform(const InstDev* __restrict__ descs,
-                                                         const int4* __restrict__ tiles, int kz,
-                                                         float T_init, int inst) {
-  const int4 tl = tiles[blockIdx.x];
-  if (tl.x != inst) return;
-  const InstDev D = descs[inst];
-  const int j = tl.y + (int)threadIdx.x;
-  if (j >= D.nr) return;
-  for (int i = 0; i < kz; ++i) {
-    const int k = tl.z + (int)threadIdx.y + BY * i;
-    if (k >= D.nz) break;
-    init_node<S>(D, j, k, 0.0f, 0.0f, T_init);
-  }
-}
-
 // Storage conversion of one instance: every slot keeps its deviation; the
 // temperature slots move from the shift T_s of the source storage to that of
 // the target (g_i - wt_i T_s).  Walls' slots are converted like any other.
@@ -306,12 +176,13 @@ __global__ __launch_bounds__(RB) void k_convert(const InstDev Di, const InstDev 
   const float dT = Di.T_s - Do.T_s;
 #pragma unroll
   for (int q = 0; q < 9; ++q)
-    Store<So>::st(Q, q * pl + o, Store<Si>::ld(P, q * pl + o, Di.st_inv), Do.st_scale);
+    Store<So>::st(Q, slot_elem<So>(q, o, pl), Store<Si>::ld(P, slot_elem<Si>(q, o, pl), Di.st_inv),
+                  Do.st_scale);
   const float g0 = Di.g0[o] + WT0 * dT;
 #pragma unroll
   for (int q = 1; q < 5; ++q)
-    Store<So>::st(Q, (9 + q) * pl + o, Store<Si>::ld(P, (9 + q) * pl + o, Di.st_inv) + WT1 * dT,
-                  Do.st_scale);
+    Store<So>::st(Q, slot_elem<So>(9 + q, o, pl),
+                  Store<Si>::ld(P, slot_elem<Si>(9 + q, o, pl), Di.st_inv) + WT1 * dT, Do.st_scale);
   Do.g0[o] = g0;  // after the loads: in FP32 both g_0 planes may be plane 9 of one array
 }
 
@@ -661,87 +532,57 @@ void* dalloc(lbm_axi* h, size_t bytes, hipError_t* err) {
   return p;
 }
 
-template <typename S, bool BUF, bool WL>
-int launch_step_w(lbm_axi* h, bool odd, int mode, int slot, uint32_t seed, hipStream_t st,
-                  const long long* clk, int off) {
-  const dim3 blk(BX, BY);
-  const FieldOut fo{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  if (!odd) {
-    if (mode == MODE_STEP)
-      k_step<S, false, MODE_STEP, BUF, WL><<<h->ntiles_launch, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo, seed, clk, off);
-    else
-      k_step<S, false, MODE_STEP_MACRO, BUF, WL><<<h->ntiles_launch, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, slot, fo, seed, clk, off);
-  } else {
-    if (mode == MODE_STEP)
-      k_step<S, true, MODE_STEP, BUF, WL><<<h->ntiles_odd, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles_odd, h->dstatus, h->kz_odd, slot, fo, seed, clk, off);
-    else
-      k_step<S, true, MODE_STEP_MACRO, BUF, WL><<<h->ntiles_odd, blk, h->lds_bytes, st>>>(h->ddesc, h->dtiles_odd, h->dstatus, h->kz_odd, slot, fo, seed, clk, off);
-  }
-  HIPCHK(hipGetLastError());
+// Launch description of the step over the handle's tile list of one parity
+// (on stream st), and over one instance's plain tile list.
+StepLaunch step_launch(const lbm_axi* h, bool odd, hipStream_t st) {
+  return StepLaunch{h->ddesc, odd ? h->dtiles_odd : h->dtiles, h->dstatus,
+                    odd ? h->ntiles_odd : h->ntiles_launch, odd ? h->kz_odd : h->kz, h->lds_bytes, st};
+}
+StepLaunch inst_launch(const lbm_axi* h, int inst) {
+  return StepLaunch{h->ddesc, h->dtiles_plain + h->tile_first[inst], h->dstatus, h->tile_count[inst],
+                    h->kz, 0, h->stream};
+}
+
+int launch_result(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(LBM_AXI_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
   return LBM_AXI_OK;
 }
 
-template <typename S, bool BUF>
-int launch_step_b(lbm_axi* h, bool odd, int mode, int slot, uint32_t seed, hipStream_t st,
-                  const long long* clk, int off) {
-  if (h->wall_lanes) return launch_step_w<S, BUF, true>(h, odd, mode, slot, seed, st, clk, off);
-  return launch_step_w<S, BUF, false>(h, odd, mode, slot, seed, st, clk, off);
-}
-
-// 16-bit storage: buffer addressing when every instance's population array
-// is below 4 GiB (measured 12 % faster at 8192^2).  FP32 keeps flat
-// addressing: there the buffer form, though lighter on registers, measured
-// 15 % slower.
-template <typename S>
-int launch_step(lbm_axi* h, bool odd, int mode, int slot, uint32_t seed, hipStream_t st,
+// One step launch in the handle's storage type.  16-bit storage takes buffer
+// addressing when buf (every instance's population array below 4 GiB;
+// measured 12 % faster at 8192^2); FP32 keeps flat addressing: there the
+// buffer form, though lighter on registers, measured 15 % slower.
+int launch_step(lbm_axi* h, bool buf, bool odd, int mode, const StepLaunch& L, int slot, uint32_t seed,
                 const long long* clk, int off) {
-  if constexpr (sizeof(S) == 2) {
-    if (h->buf) return launch_step_b<S, true>(h, odd, mode, slot, seed, st, clk, off);
-  }
-  return launch_step_b<S, false>(h, odd, mode, slot, seed, st, clk, off);
+  hipError_t e;
+  if (h->storage == LBM_STORE_FP32)
+    e = launch_step_b<float, false>(h->wall_lanes, odd, mode, L, slot, seed, clk, off);
+  else
+    e = launch_step_s16(h->storage, buf, h->wall_lanes, odd, mode, L, slot, seed, clk, off);
+  return launch_result(e, "step kernel launch");
 }
 
-template <typename S>
 int launch_fields(lbm_axi* h, int inst, bool odd, const FieldOut& fo) {
-  const dim3 blk(BX, BY);
-  const int4* tl = h->dtiles_plain + h->tile_first[inst];
-  if (!odd)
-    k_step<S, false, MODE_FIELDS, false><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->dstatus, h->kz, 0, fo, 0u, nullptr, 0);
-  else
-    k_step<S, true, MODE_FIELDS, false><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->dstatus, h->kz, 0, fo, 0u, nullptr, 0);
-  HIPCHK(hipGetLastError());
-  return LBM_AXI_OK;
-}
-
-template <typename S, bool BUF>
-void launch_pattern_b(lbm_axi* h, bool odd, uint32_t key) {
-  const dim3 blk(BX, BY);
-  if (!odd)
-    k_pattern<S, false, BUF><<<h->ntiles_launch, blk, h->lds_bytes, h->stream>>>(h->ddesc, h->dtiles, h->dstatus, h->kz, key);
-  else
-    k_pattern<S, true, BUF><<<h->ntiles_odd, blk, h->lds_bytes, h->stream>>>(h->ddesc, h->dtiles_odd, h->dstatus, h->kz_odd, key);
+  const StepLaunch L = inst_launch(h, inst);
+  return launch_result(h->storage == LBM_STORE_FP32 ? launch_fields_t<float>(odd, L, fo)
+                                                    : launch_fields_s16(h->storage, odd, L, fo),
+                       "field kernel launch");
 }
 
 // The probe takes the step's addressing: buffer addressing for 16-bit
 // storage when every array is below 4 GiB, flat otherwise.
-template <typename S>
-void launch_pattern(lbm_axi* h, bool odd, uint32_t key) {
-  if constexpr (sizeof(S) == 2) {
-    if (h->buf) return launch_pattern_b<S, true>(h, odd, key);
-  }
-  launch_pattern_b<S, false>(h, odd, key);
+int launch_pattern(lbm_axi* h, bool odd, uint32_t key) {
+  const StepLaunch L = step_launch(h, odd, h->stream);
+  return launch_result(h->storage == LBM_STORE_FP32 ? launch_pattern_t<float, false>(odd, L, key)
+                                                    : launch_pattern_s16(h->storage, h->buf, odd, L, key),
+                       "pattern kernel launch");
 }
 
-template <typename S>
 int launch_init(lbm_axi* h, int inst, const float* dinit, float T_init) {
-  const dim3 blk(BX, BY);
-  const int4* tl = h->dtiles_plain + h->tile_first[inst];
-  if (dinit)
-    k_init<S><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->kz, dinit, inst);
-  else
-    k_init_uniform<S><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->kz, T_init, inst);
-  HIPCHK(hipGetLastError());
-  return LBM_AXI_OK;
+  const StepLaunch L = inst_launch(h, inst);
+  return launch_result(h->storage == LBM_STORE_FP32 ? launch_init_t<float>(L, dinit, T_init, inst)
+                                                    : launch_init_s16(h->storage, L, dinit, T_init, inst),
+                       "start kernel launch");
 }
 
 // Tiles of BX lanes along r by BY * kz rows along z, for every instance.
@@ -815,11 +656,7 @@ int build_tiles(lbm_axi* h, int kz, int kz_odd) {
 int dispatch_step(lbm_axi* h, bool odd, int mode, int slot, uint32_t seed,
                   hipStream_t st = nullptr, const long long* clk = nullptr, int off = 0) {
   if (!st) st = h->stream;
-  switch (h->storage) {
-    case LBM_STORE_FP32: return launch_step<float>(h, odd, mode, slot, seed, st, clk, off);
-    case LBM_STORE_FP16: return launch_step<__half>(h, odd, mode, slot, seed, st, clk, off);
-    default: return launch_step<__hip_bfloat16>(h, odd, mode, slot, seed, st, clk, off);
-  }
+  return launch_step(h, h->buf, odd, mode, step_launch(h, odd, st), slot, seed, clk, off);
 }
 
 void drop_graph(lbm_axi* h) {
@@ -881,22 +718,8 @@ void release(lbm_axi* h, void* p, size_t bytes) {
 
 // One step of instance inst alone, in the AA layout of parity `odd` (plain
 // tile list, flat addressing, the handle's wall-lane variant).
-template <typename S, bool WL>
-int launch_inst_step_w(lbm_axi* h, int inst, bool odd, uint32_t seed) {
-  const dim3 blk(BX, BY);
-  const FieldOut fo{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  const int4* tl = h->dtiles_plain + h->tile_first[inst];
-  if (!odd)
-    k_step<S, false, MODE_STEP, false, WL><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->dstatus, h->kz, 0, fo, seed, nullptr, 0);
-  else
-    k_step<S, true, MODE_STEP, false, WL><<<h->tile_count[inst], blk, 0, h->stream>>>(h->ddesc, tl, h->dstatus, h->kz, 0, fo, seed, nullptr, 0);
-  HIPCHK(hipGetLastError());
-  return LBM_AXI_OK;
-}
-template <typename S>
 int launch_inst_step(lbm_axi* h, int inst, bool odd, uint32_t seed) {
-  return h->wall_lanes ? launch_inst_step_w<S, true>(h, inst, odd, seed)
-                       : launch_inst_step_w<S, false>(h, inst, odd, seed);
+  return launch_step(h, false, odd, MODE_STEP, inst_launch(h, inst), 0, seed, nullptr, 0);
 }
 
 // Sets converged instances running again (after a storage conversion).  A
@@ -929,12 +752,7 @@ int resume_converged(lbm_axi* h) {
     if (gap & 1) {
       const bool odd = (r.t_stop & 1) != 0;
       const uint32_t seed = step_seed(r.t_stop - r.t_off);
-      int rc;
-      switch (h->storage) {
-        case LBM_STORE_FP32: rc = launch_inst_step<float>(h, i, odd, seed); break;
-        case LBM_STORE_FP16: rc = launch_inst_step<__half>(h, i, odd, seed); break;
-        default: rc = launch_inst_step<__hip_bfloat16>(h, i, odd, seed); break;
-      }
+      const int rc = launch_inst_step(h, i, odd, seed);
       if (rc) return rc;
     }
     r.t_off += gap - (gap & 1);
@@ -1214,11 +1032,7 @@ int lbm_axi_create(const lbm_axi_params* p, int32_t n_inst, const float* const* 
         }
       }
       int rc;
-      switch (h->storage) {
-        case LBM_STORE_FP32: rc = launch_init<float>(h, i, dinit, (float)p[i].T_init); break;
-        case LBM_STORE_FP16: rc = launch_init<__half>(h, i, dinit, (float)p[i].T_init); break;
-        default: rc = launch_init<__hip_bfloat16>(h, i, dinit, (float)p[i].T_init); break;
-      }
+      rc = launch_init(h, i, dinit, (float)p[i].T_init);
       if (dinit) {
         hipError_t e = hipStreamSynchronize(h->stream);
         (void)hipFree(dinit);
@@ -1553,11 +1367,7 @@ int fields_to(lbm_axi* h, int inst, const FieldOut& out, int dst_is_device) {
         fo.mask = (uint8_t*)d;
       }
     }
-    switch (h->storage) {
-      case LBM_STORE_FP32: rc = launch_fields<float>(h, inst, odd, fo); break;
-      case LBM_STORE_FP16: rc = launch_fields<__half>(h, inst, odd, fo); break;
-      default: rc = launch_fields<__hip_bfloat16>(h, inst, odd, fo); break;
-    }
+    rc = launch_fields(h, inst, odd, fo);
     if (!rc && !dst_is_device) {
       hipError_t e = hipSuccess;
       if (uz && e == hipSuccess) e = hipMemcpyAsync(uz, fo.uz, sizeof(float) * n, hipMemcpyDeviceToHost, h->stream);
@@ -1624,11 +1434,7 @@ int lbm_axi_stream_function(lbm_axi* h, int32_t inst, float* psi, double* psi_ab
       return fail(LBM_AXI_ENOMEM, "stream function staging");
     }
     FieldOut fo{(float*)duz, nullptr, nullptr, nullptr, nullptr, nullptr};
-    switch (h->storage) {
-      case LBM_STORE_FP32: rc = launch_fields<float>(h, inst, odd, fo); break;
-      case LBM_STORE_FP16: rc = launch_fields<__half>(h, inst, odd, fo); break;
-      default: rc = launch_fields<__hip_bfloat16>(h, inst, odd, fo); break;
-    }
+    rc = launch_fields(h, inst, odd, fo);
     if (!rc) {
       k_psi<<<(q.nz + RB / 64 - 1) / (RB / 64), RB, 0, h->stream>>>(
           (const float*)duz, q.nr, q.nz, q.r0, q.side_rmin == LBM_SIDE_AXIS ? 1 : 0, (float*)dpsi,
@@ -1661,11 +1467,7 @@ int lbm_axi_stream_function_static(lbm_axi* h, int32_t inst, float* psi, double*
     float* duz = (float*)h->scratch;
     double* dcol = (double*)((unsigned char*)h->scratch + SCRATCH_NODES * 4);
     FieldOut fo{duz, nullptr, nullptr, nullptr, nullptr, nullptr};
-    switch (h->storage) {
-      case LBM_STORE_FP32: rc = launch_fields<float>(h, inst, odd, fo); break;
-      case LBM_STORE_FP16: rc = launch_fields<__half>(h, inst, odd, fo); break;
-      default: rc = launch_fields<__hip_bfloat16>(h, inst, odd, fo); break;
-    }
+    rc = launch_fields(h, inst, odd, fo);
     if (rc) return rc;
     k_psi<<<(q.nz + RB / 64 - 1) / (RB / 64), RB, 0, h->stream>>>(
         duz, q.nr, q.nz, q.r0, q.side_rmin == LBM_SIDE_AXIS ? 1 : 0, psi, dcol);
@@ -1698,11 +1500,7 @@ int lbm_axi_pipe_nusselt(lbm_axi* h, int32_t inst, int32_t area, double* nu, dou
       return fail(LBM_AXI_ENOMEM, "pipe Nusselt staging");
     }
     FieldOut fo{(float*)dU, nullptr, nullptr, (float*)dT, nullptr, nullptr};
-    switch (h->storage) {
-      case LBM_STORE_FP32: rc = launch_fields<float>(h, inst, odd, fo); break;
-      case LBM_STORE_FP16: rc = launch_fields<__half>(h, inst, odd, fo); break;
-      default: rc = launch_fields<__hip_bfloat16>(h, inst, odd, fo); break;
-    }
+    rc = launch_fields(h, inst, odd, fo);
     if (!rc) {
       k_pipe_nu<<<(q.nz + RB / 64 - 1) / (RB / 64), RB, 0, h->stream>>>(
           (const float*)dT, (const float*)dU, area ? 1 : 0, q.nr, q.nz, q.r0, (double*)dnu, (double*)dtb);
@@ -1759,13 +1557,7 @@ int lbm_axi_pattern_bandwidth(lbm_axi* h, int32_t reps, double* out) {
     int rc = LBM_AXI_OK;
     for (int par = 0; par < 2 && rc == LBM_AXI_OK; ++par) {
       const bool odd = par == 1;
-      auto go = [&]() {
-        switch (h->storage) {
-          case LBM_STORE_FP32: launch_pattern<float>(h, odd, 0u); break;
-          case LBM_STORE_FP16: launch_pattern<__half>(h, odd, 0u); break;
-          default: launch_pattern<__hip_bfloat16>(h, odd, 0u); break;
-        }
-      };
+      auto go = [&]() { (void)launch_pattern(h, odd, 0u); };
       rc = timed(go, ms[par]);
     }
     // plain stream: every instance's population array (and separate g_0 plane)

@@ -180,6 +180,28 @@ __host__ __device__ inline uint32_t mix32(uint32_t x) {
   x ^= x >> 16;
   return x;
 }
+// Population layout of node offset o (a multiple-of-64 row stride times z,
+// planes of pl elements).  Slots 0..8 hold f_0..f_8, slots 10..13 g_1..g_4;
+// g_0 is slot 9 in FP32 storage and an FP32 plane of its own otherwise.
+// FP32: slot q at element q pl + o.  16-bit storage: the axial D2Q9 slot
+// q = 1..4 and the D2Q5 slot q + 9 share a 32-bit word (low and high half):
+// the AA step reads and writes these two at the same node in both parities,
+// so one 32-bit access moves both.  Word o of pair plane a = q - 1 sits at
+// elements (5 + 2a) pl + 2o; slots 0, 5, 6, 7, 8 keep 16-bit planes 0..4.
+// (Measured: an in-place stream moves 3.0 TB/s with 2-byte lanes against
+// 4.7-5.0 TB/s with 4-byte lanes; the memory pipeline is bound by
+// instructions, not bytes, at 2 bytes per lane.)
+template <typename S>
+__host__ __device__ inline int64_t slot_elem(int q, int64_t o, int64_t pl) {
+  if constexpr (sizeof(S) == 4) {
+    return q * pl + o;
+  } else {
+    if (q >= 1 && q <= 4) return (3 + 2 * q) * pl + 2 * o;
+    if (q >= 10) return (2 * q - 15) * pl + 2 * o + 1;
+    return (q == 0 ? 0 : q - 4) * pl + o;
+  }
+}
+
 // ---- population access --------------------------------------------------
 // PopAcc<S, false>: flat addressing through a pointer (64-bit addresses per
 // lane).  PopAcc<S, true>: buffer addressing, one descriptor in scalar
@@ -188,30 +210,82 @@ __host__ __device__ inline uint32_t mix32(uint32_t x) {
 // the population array is below 4 GiB.  The hardware takes the record count
 // and the offsets as unsigned 32-bit values; the builtins declare them int,
 // so values of 2^31 and above pass as their bit patterns.
+// ld / st: slot q of node o.  ld_pair / st_pair: slots a + 1 and a + 10 of
+// node o (a = 0..3), one 32-bit access in 16-bit storage; the two stochastic
+// roundings fill the low and the high half of the stored word.
+template <typename S>
+__device__ inline uint32_t pack_sr(float f, float g, uint32_t rf, uint32_t rg) {
+  if constexpr (std::is_same<S, __half>::value) {
+    lbm_h2 h = __builtin_amdgcn_cvt_sr_f16_f32(lbm_h2{0, 0}, f, rf, false);
+    h = __builtin_amdgcn_cvt_sr_f16_f32(h, g, rg, true);
+    return __builtin_bit_cast(uint32_t, h);
+  } else {
+    lbm_b2 h = __builtin_amdgcn_cvt_sr_bf16_f32(lbm_b2{0, 0}, f, rf, false);
+    h = __builtin_amdgcn_cvt_sr_bf16_f32(h, g, rg, true);
+    return __builtin_bit_cast(uint32_t, h);
+  }
+}
+template <typename S>
+__device__ inline void unpack(uint32_t w, float inv, float& f, float& g) {
+  if constexpr (std::is_same<S, __half>::value) {
+    const lbm_h2 h = __builtin_bit_cast(lbm_h2, w);
+    f = (float)h[0] * inv;
+    g = (float)h[1] * inv;
+  } else {
+    f = __uint_as_float(w << 16) * inv;
+    g = __uint_as_float(w & 0xFFFF0000u) * inv;
+  }
+}
+
 template <typename S, bool BUF>
 struct PopAcc;
 template <typename S>
 struct PopAcc<S, false> {
   S* P;
+  int64_t pl;
   float inv, sc;
-  __host__ __device__ explicit PopAcc(const InstDev& D) : P((S*)D.pop), inv(D.st_inv), sc(D.st_scale) {}
-  __host__ __device__ float ld(int64_t i) const { return Store<S>::ld(P, i, inv); }
-  __host__ __device__ void st(int64_t i, float v, uint32_t r) const { Store<S>::st_sr(P, i, v, sc, r); }
+  __host__ __device__ explicit PopAcc(const InstDev& D)
+      : P((S*)D.pop), pl(D.plane), inv(D.st_inv), sc(D.st_scale) {}
+  __host__ __device__ float ld(int q, int64_t o) const { return Store<S>::ld(P, slot_elem<S>(q, o, pl), inv); }
+  __host__ __device__ void st(int q, int64_t o, float v, uint32_t r) const {
+    Store<S>::st_sr(P, slot_elem<S>(q, o, pl), v, sc, r);
+  }
+  __host__ __device__ void ld_pair(int a, int64_t o, float& f, float& g) const {
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (sizeof(S) == 2) {
+      unpack<S>(((const uint32_t*)P)[(int64_t)(5 + 2 * a) * (pl >> 1) + o], inv, f, g);
+      return;
+    }
+#endif
+    f = ld(a + 1, o);
+    g = ld(a + 10, o);
+  }
+  __host__ __device__ void st_pair(int a, int64_t o, float f, float g, uint32_t rf, uint32_t rg) const {
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (sizeof(S) == 2) {
+      ((uint32_t*)P)[(int64_t)(5 + 2 * a) * (pl >> 1) + o] = pack_sr<S>(f * sc, g * sc, rf, rg);
+      return;
+    }
+#endif
+    st(a + 1, o, f, rf);
+    st(a + 10, o, g, rg);
+  }
 };
 template <typename S>
 struct PopAcc<S, true> {
 #if defined(__HIP_DEVICE_COMPILE__)
   __amdgpu_buffer_rsrc_t rs;
 #endif
+  int64_t pl;
   float inv, sc;
-  __host__ __device__ explicit PopAcc(const InstDev& D) : inv(D.st_inv), sc(D.st_scale) {
+  __host__ __device__ explicit PopAcc(const InstDev& D) : pl(D.plane), inv(D.st_inv), sc(D.st_scale) {
 #if defined(__HIP_DEVICE_COMPILE__)
     rs = __builtin_amdgcn_make_buffer_rsrc(D.pop, (short)0, (int)(uint32_t)D.pop_bytes, 0x00020000);
 #endif
   }
-  __host__ __device__ float ld(int64_t i) const {
+  __host__ __device__ float ld(int q, int64_t o) const {
 #if defined(__HIP_DEVICE_COMPILE__)
-    const uint32_t off = (uint32_t)i * (uint32_t)sizeof(S);
+    const uint32_t off = (uint32_t)slot_elem<S>(q, o, pl) * (uint32_t)sizeof(S);
     if constexpr (std::is_same<S, float>::value) {
       return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
     } else {
@@ -222,13 +296,14 @@ struct PopAcc<S, true> {
         return __uint_as_float((uint32_t)b << 16) * inv;
     }
 #else
-    (void)i;
+    (void)q;
+    (void)o;
     return 0.0f;
 #endif
   }
-  __host__ __device__ void st(int64_t i, float v, uint32_t r) const {
+  __host__ __device__ void st(int q, int64_t o, float v, uint32_t r) const {
 #if defined(__HIP_DEVICE_COMPILE__)
-    const uint32_t off = (uint32_t)i * (uint32_t)sizeof(S);
+    const uint32_t off = (uint32_t)slot_elem<S>(q, o, pl) * (uint32_t)sizeof(S);
     if constexpr (std::is_same<S, float>::value) {
       (void)r;
       __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, (int)off, 0, 0);
@@ -240,10 +315,33 @@ struct PopAcc<S, true> {
       __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h[0]), rs, (int)off, 0, 0);
     }
 #else
-    (void)i;
+    (void)q;
+    (void)o;
     (void)v;
     (void)r;
 #endif
+  }
+  __host__ __device__ void ld_pair(int a, int64_t o, float& f, float& g) const {
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (sizeof(S) == 2) {
+      const uint32_t off = (uint32_t)((int64_t)(5 + 2 * a) * pl + 2 * o) * 2u;
+      unpack<S>((uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0), inv, f, g);
+      return;
+    }
+#endif
+    f = ld(a + 1, o);
+    g = ld(a + 10, o);
+  }
+  __host__ __device__ void st_pair(int a, int64_t o, float f, float g, uint32_t rf, uint32_t rg) const {
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (sizeof(S) == 2) {
+      const uint32_t off = (uint32_t)((int64_t)(5 + 2 * a) * pl + 2 * o) * 2u;
+      __builtin_amdgcn_raw_buffer_store_b32(pack_sr<S>(f * sc, g * sc, rf, rg), rs, (int)off, 0, 0);
+      return;
+    }
+#endif
+    st(a + 1, o, f, rf);
+    st(a + 10, o, g, rg);
   }
 };
 
@@ -507,7 +605,6 @@ __host__ __device__ inline void store_wall(const InstDev& D, const A& P, int jb,
   constexpr int EZr[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
   constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
   constexpr int MIR[9] = {0, 3, 2, 1, 4, 6, 5, 8, 7};  // e_r reversed
-  const int64_t pl = D.plane;
   // A population that leaves row 0 towards an axis lands in the mirror row,
   // whose slot i is slot i* of row 0: the boundary nodes of row 0 feed the
   // fluid nodes of row 0 through it.
@@ -519,9 +616,9 @@ __host__ __device__ inline void store_wall(const InstDev& D, const A& P, int jb,
     }
     if (!fluid_dest(D, jd, kd)) continue;
     if (ODD)
-      P.st(slot * pl + row_off(kd, D.stride) + jd, d[i], rn.next());
+      P.st(slot, row_off(kd, D.stride) + jd, d[i], rn.next());
     else
-      P.st(OPP[i] * pl + row_off(kb, D.stride) + jb, d[i], rn.next());
+      P.st(OPP[i], row_off(kb, D.stride) + jb, d[i], rn.next());
   }
   for (int i = 1; i < 5; ++i) {
     int jd = jb + EXr[i], kd = kb + EZr[i], slot = i;
@@ -531,9 +628,9 @@ __host__ __device__ inline void store_wall(const InstDev& D, const A& P, int jb,
     }
     if (!fluid_dest(D, jd, kd)) continue;
     if (ODD)
-      P.st((9 + slot) * pl + row_off(kd, D.stride) + jd, tg[i], rn.next());
+      P.st(9 + slot, row_off(kd, D.stride) + jd, tg[i], rn.next());
     else
-      P.st((9 + OPP[i]) * pl + row_off(kb, D.stride) + jb, tg[i], rn.next());
+      P.st(9 + OPP[i], row_off(kb, D.stride) + jb, tg[i], rn.next());
   }
 }
 
@@ -715,22 +812,20 @@ __host__ __device__ inline void radial_wall(const InstDev& D, const A& P, const 
   const float tB = lo ? t[1] : t[3];
   const float ga = WT1 * (Tb - D.T_s) + (1.0f - om) * (tB - WT1 * B.theta - 5.0f * WT1 * B.T * fs * B.ur);
 
-  const int64_t pl = D.plane;
   const bool up = !(z_bounded(D) && k + 1 == D.nz - 1), dn = !(z_bounded(D) && k - 1 == 0);
   Dither rn(mix32(seed ^ (uint32_t)ob));
   const uint32_t r0 = rn.next(), r1 = rn.next(), r2 = rn.next(), r3 = rn.next();
   if (ODD) {
-    // slot i of the destination node jB (rows k, k + 1, k - 1)
-    P.st((lo ? 1 : 3) * pl + row0 + jB, fa, r0);
-    if (up) P.st((lo ? 5 : 6) * pl + rowp + jB, fu, r1);
-    if (dn) P.st((lo ? 8 : 7) * pl + rowm + jB, fd, r2);
-    P.st((lo ? 10 : 12) * pl + row0 + jB, ga, r3);
+    // slot i of the destination node jB (rows k, k + 1, k - 1); the D2Q9 and
+    // D2Q5 populations along r share a word (slots 1, 10 or 3, 12)
+    P.st_pair(lo ? 0 : 2, row0 + jB, fa, ga, r0, r3);
+    if (up) P.st(lo ? 5 : 6, rowp + jB, fu, r1);
+    if (dn) P.st(lo ? 8 : 7, rowm + jB, fd, r2);
   } else {
-    // slot opposite(i) of the wall node itself
-    P.st((lo ? 3 : 1) * pl + ob, fa, r0);
-    if (up) P.st((lo ? 7 : 8) * pl + ob, fu, r1);
-    if (dn) P.st((lo ? 6 : 5) * pl + ob, fd, r2);
-    P.st((lo ? 12 : 10) * pl + ob, ga, r3);
+    // slot opposite(i) of the wall node itself (slots 3, 12 or 1, 10)
+    P.st_pair(lo ? 2 : 0, ob, fa, ga, r0, r3);
+    if (up) P.st(lo ? 7 : 8, ob, fu, r1);
+    if (dn) P.st(lo ? 6 : 5, ob, fd, r2);
   }
 }
 
@@ -742,7 +837,6 @@ template <typename S, bool ODD, bool BUF = false>
 __host__ __device__ inline void node_load(const InstDev& D, const RowC& R, int j, int k, float s[9],
                                           float t[5], float& phi_raw) {
   const PopAcc<S, BUF> P(D);
-  const int64_t pl = D.plane;
   const int st = D.stride;
   int km = k - 1, kp = k + 1;
   if (D.side_z == SIDE_PERIODIC) {
@@ -751,44 +845,67 @@ __host__ __device__ inline void node_load(const InstDev& D, const RowC& R, int j
   }
   const int64_t rowm = row_off(km, st), row0 = row_off(k, st), rowp = row_off(kp, st);
   const int64_t o = row0 + j;
-  if (!ODD) {
+  if constexpr (sizeof(S) == 4) {
+    if (!ODD) {
 #pragma unroll
-    for (int q = 0; q < 9; ++q) s[q] = P.ld(q * pl + o);
-    t[0] = D.g0[o];
+      for (int q = 0; q < 9; ++q) s[q] = P.ld(q, o);
+      t[0] = D.g0[o];
 #pragma unroll
-    for (int q = 1; q < 5; ++q) t[q] = P.ld((9 + q) * pl + o);
+      for (int q = 1; q < 5; ++q) t[q] = P.ld(9 + q, o);
+    } else {
+      const int64_t cm = R.cm, cp = R.cp;
+      s[0] = P.ld(0, o);
+      s[1] = P.ld(R.mir ? 1 : 3, row0 + cm);
+      s[2] = P.ld(4, rowm + j);
+      s[3] = P.ld(1, row0 + cp);
+      s[4] = P.ld(2, rowp + j);
+      s[5] = P.ld(R.mir ? 8 : 7, rowm + cm);
+      s[6] = P.ld(8, rowm + cp);
+      s[7] = P.ld(5, rowp + cp);
+      s[8] = P.ld(R.mir ? 5 : 6, rowp + cm);
+      t[0] = D.g0[o];
+      t[1] = P.ld(R.mir ? 10 : 12, row0 + cm);
+      t[2] = P.ld(13, rowm + j);
+      t[3] = P.ld(10, row0 + cp);
+      t[4] = P.ld(11, rowp + j);
+    }
   } else {
-    const int64_t cm = R.cm, cp = R.cp;
-    s[0] = P.ld(o);
-    s[1] = P.ld((R.mir ? 1 : 3) * pl + row0 + cm);
-    s[2] = P.ld(4 * pl + rowm + j);
-    s[3] = P.ld(1 * pl + row0 + cp);
-    s[4] = P.ld(2 * pl + rowp + j);
-    s[5] = P.ld((R.mir ? 8 : 7) * pl + rowm + cm);
-    s[6] = P.ld(8 * pl + rowm + cp);
-    s[7] = P.ld(5 * pl + rowp + cp);
-    s[8] = P.ld((R.mir ? 5 : 6) * pl + rowp + cm);
-    t[0] = D.g0[o];
-    t[1] = P.ld((R.mir ? 10 : 12) * pl + row0 + cm);
-    t[2] = P.ld(13 * pl + rowm + j);
-    t[3] = P.ld(10 * pl + row0 + cp);
-    t[4] = P.ld(11 * pl + rowp + j);
+    // 16-bit storage: f_i and g_i of the axial directions come in pairs
+    if (!ODD) {
+      s[0] = P.ld(0, o);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) P.ld_pair(a, o, s[a + 1], t[a + 1]);
+#pragma unroll
+      for (int q = 5; q < 9; ++q) s[q] = P.ld(q, o);
+      t[0] = D.g0[o];
+    } else {
+      const int64_t cm = R.cm, cp = R.cp;
+      s[0] = P.ld(0, o);
+      P.ld_pair(R.mir ? 0 : 2, row0 + cm, s[1], t[1]);
+      P.ld_pair(3, rowm + j, s[2], t[2]);
+      P.ld_pair(0, row0 + cp, s[3], t[3]);
+      P.ld_pair(1, rowp + j, s[4], t[4]);
+      s[5] = P.ld(R.mir ? 8 : 7, rowm + cm);
+      s[6] = P.ld(8, rowm + cp);
+      s[7] = P.ld(5, rowp + cp);
+      s[8] = P.ld(R.mir ? 5 : 6, rowp + cm);
+      t[0] = D.g0[o];
+    }
   }
   phi_raw = D.phi_mode == 0 ? 0.0f : D.phi[o];
 }
 
 // Slots of the populations arriving at fluid node (j, k) in the AA layout of
-// the step's parity, as node_load reads them: a[0..8] hold f_0..f_8,
-// a[9..12] g_1..g_4 (indices into the 14-plane array); o is the node's own
-// offset (g_0 plane, porosity).  The step writes its post-collision f_i into
-// the slot it read f_opposite(i) from, so these are also the slots it
+// the step's parity, as node_load reads them: value v (0..8: f_0..f_8,
+// 9..12: g_1..g_4) sits in slot q[v] of node offset off[v]; o is the node's
+// own offset (g_0 plane, porosity).  The step writes its post-collision f_i
+// into the slot it read f_opposite(i) from, so these are also the slots it
 // writes.  Used by the streaming-ceiling probe, whose identity update (every
 // value stored back where node_load found it) leaves the state unchanged only
 // if this map is node_load's.
 template <bool ODD>
-__host__ __device__ inline void node_slots(const InstDev& D, const RowC& R, int j, int k,
-                                           int64_t a[13], int64_t& o) {
-  const int64_t pl = D.plane;
+__host__ __device__ inline void node_slots(const InstDev& D, const RowC& R, int j, int k, int q[13],
+                                           int64_t off[13], int64_t& o) {
   const int st = D.stride;
   int km = k - 1, kp = k + 1;
   if (D.side_z == SIDE_PERIODIC) {
@@ -799,47 +916,62 @@ __host__ __device__ inline void node_slots(const InstDev& D, const RowC& R, int 
   o = row0 + j;
   if (!ODD) {
 #pragma unroll
-    for (int q = 0; q < 9; ++q) a[q] = q * pl + o;
+    for (int v = 0; v < 9; ++v) q[v] = v, off[v] = o;
 #pragma unroll
-    for (int q = 1; q < 5; ++q) a[8 + q] = (9 + q) * pl + o;
+    for (int v = 9; v < 13; ++v) q[v] = v + 1, off[v] = o;
   } else {
     const int64_t cm = R.cm, cp = R.cp;
-    a[0] = o;
-    a[1] = (R.mir ? 1 : 3) * pl + row0 + cm;
-    a[2] = 4 * pl + rowm + j;
-    a[3] = 1 * pl + row0 + cp;
-    a[4] = 2 * pl + rowp + j;
-    a[5] = (R.mir ? 8 : 7) * pl + rowm + cm;
-    a[6] = 8 * pl + rowm + cp;
-    a[7] = 5 * pl + rowp + cp;
-    a[8] = (R.mir ? 5 : 6) * pl + rowp + cm;
-    a[9] = (R.mir ? 10 : 12) * pl + row0 + cm;
-    a[10] = 13 * pl + rowm + j;
-    a[11] = 10 * pl + row0 + cp;
-    a[12] = 11 * pl + rowp + j;
+    q[0] = 0, off[0] = o;
+    q[1] = R.mir ? 1 : 3, off[1] = row0 + cm;
+    q[2] = 4, off[2] = rowm + j;
+    q[3] = 1, off[3] = row0 + cp;
+    q[4] = 2, off[4] = rowp + j;
+    q[5] = R.mir ? 8 : 7, off[5] = rowm + cm;
+    q[6] = 8, off[6] = rowm + cp;
+    q[7] = 5, off[7] = rowp + cp;
+    q[8] = R.mir ? 5 : 6, off[8] = rowp + cm;
+    q[9] = R.mir ? 10 : 12, off[9] = row0 + cm;
+    q[10] = 13, off[10] = rowm + j;
+    q[11] = 10, off[11] = row0 + cp;
+    q[12] = 11, off[12] = rowp + j;
   }
 }
 
 // Streaming-ceiling probe: the stores of fluid node (j, k) with the step's
 // memory traffic and no arithmetic.  After the step's loads (node_load) each
 // value goes back, as the step orders its stores (f_i^+ into the slot of
-// f_opposite(i), then g), into the slot it came from, its bits XORed with
-// key: key = 0 leaves the state as it was, and the compiler cannot drop the
-// stores.  The porosity value is folded into the g_0 store the same way.
+// f_opposite(i), then g; in 16-bit storage the axial f and g of a slot pair
+// in one word), into the slot it came from, its bits XORed with key: key = 0
+// leaves the state as it was, and the compiler cannot drop the stores.  The
+// porosity value is folded into the g_0 store the same way.
 template <typename S, bool ODD, bool BUF>
 __device__ inline void pattern_store(const InstDev& D, const RowC& R, int j, int k, const float s[9],
                                      const float t[5], float ph, uint32_t key) {
   constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
   const PopAcc<S, BUF> P(D);
-  int64_t a[13], o;
-  node_slots<ODD>(D, R, j, k, a, o);
+  int q[13];
+  int64_t off[13], o;
+  node_slots<ODD>(D, R, j, k, q, off, o);
+  auto x = [key](float v) { return __uint_as_float(__float_as_uint(v) ^ key); };
+  if constexpr (sizeof(S) == 4) {
 #pragma unroll
-  for (int i = 0; i < 9; ++i) P.st(a[OPP[i]], __uint_as_float(__float_as_uint(s[OPP[i]]) ^ key), 0u);
-  D.g0[o] = __uint_as_float(__float_as_uint(t[0]) ^ (key & __float_as_uint(ph)));
+    for (int i = 0; i < 9; ++i) P.st(q[OPP[i]], off[OPP[i]], x(s[OPP[i]]), 0u);
+    D.g0[o] = __uint_as_float(__float_as_uint(t[0]) ^ (key & __float_as_uint(ph)));
 #pragma unroll
-  for (int i = 1; i < 5; ++i) {
-    const int q = i <= 2 ? i + 2 : i - 2;  // opposite of i in D2Q5
-    P.st(a[8 + q], __uint_as_float(__float_as_uint(t[q]) ^ key), 0u);
+    for (int i = 1; i < 5; ++i) {
+      const int b = i <= 2 ? i + 2 : i - 2;  // opposite of i in D2Q5
+      P.st(q[8 + b], off[8 + b], x(t[b]), 0u);
+    }
+  } else {
+    P.st(q[0], off[0], x(s[0]), 0u);
+#pragma unroll
+    for (int i = 1; i < 5; ++i) {
+      const int b = OPP[i];  // f_b and g_b share the word of slot pair q[b] - 1
+      P.st_pair(q[b] - 1, off[b], x(s[b]), x(t[b]), 0u, 0u);
+    }
+#pragma unroll
+    for (int i = 5; i < 9; ++i) P.st(q[OPP[i]], off[OPP[i]], x(s[OPP[i]]), 0u);
+    D.g0[o] = __uint_as_float(__float_as_uint(t[0]) ^ (key & __float_as_uint(ph)));
   }
 }
 
@@ -983,37 +1115,68 @@ __host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC&
     for (int q = 0; q < 5; ++q) B.t[q] = t[q];
 
     // ---- stream and store --------------------------------------------------
-    if (!ODD) {
-      P.st(0 * pl + o, d[0], rn.next());
-      P.st(3 * pl + o, d[1], rn.next());
-      P.st(4 * pl + o, d[2], rn.next());
-      P.st(1 * pl + o, d[3], rn.next());
-      P.st(2 * pl + o, d[4], rn.next());
-      P.st(7 * pl + o, d[5], rn.next());
-      P.st(8 * pl + o, d[6], rn.next());
-      P.st(5 * pl + o, d[7], rn.next());
-      P.st(6 * pl + o, d[8], rn.next());
-      D.g0[o] = tg[0];
-      P.st(12 * pl + o, tg[1], rn.next());
-      P.st(13 * pl + o, tg[2], rn.next());
-      P.st(10 * pl + o, tg[3], rn.next());
-      P.st(11 * pl + o, tg[4], rn.next());
+    if constexpr (sizeof(S) == 4) {
+      if (!ODD) {
+        P.st(0, o, d[0], rn.next());
+        P.st(3, o, d[1], rn.next());
+        P.st(4, o, d[2], rn.next());
+        P.st(1, o, d[3], rn.next());
+        P.st(2, o, d[4], rn.next());
+        P.st(7, o, d[5], rn.next());
+        P.st(8, o, d[6], rn.next());
+        P.st(5, o, d[7], rn.next());
+        P.st(6, o, d[8], rn.next());
+        D.g0[o] = tg[0];
+        P.st(12, o, tg[1], rn.next());
+        P.st(13, o, tg[2], rn.next());
+        P.st(10, o, tg[3], rn.next());
+        P.st(11, o, tg[4], rn.next());
+      } else {
+        const int64_t cm = R.cm, cp = R.cp;
+        P.st(0, o, d[0], rn.next());
+        P.st(1, row0 + cp, d[1], rn.next());
+        P.st(2, rowp + j, d[2], rn.next());
+        P.st(R.mir ? 1 : 3, row0 + cm, d[3], rn.next());
+        P.st(4, rowm + j, d[4], rn.next());
+        P.st(5, rowp + cp, d[5], rn.next());
+        P.st(R.mir ? 5 : 6, rowp + cm, d[6], rn.next());
+        P.st(R.mir ? 8 : 7, rowm + cm, d[7], rn.next());
+        P.st(8, rowm + cp, d[8], rn.next());
+        D.g0[o] = tg[0];
+        P.st(10, row0 + cp, tg[1], rn.next());
+        P.st(11, rowp + j, tg[2], rn.next());
+        P.st(R.mir ? 10 : 12, row0 + cm, tg[3], rn.next());
+        P.st(13, rowm + j, tg[4], rn.next());
+      }
     } else {
-      const int64_t cm = R.cm, cp = R.cp;
-      P.st(o, d[0], rn.next());
-      P.st(1 * pl + row0 + cp, d[1], rn.next());
-      P.st(2 * pl + rowp + j, d[2], rn.next());
-      P.st((R.mir ? 1 : 3) * pl + row0 + cm, d[3], rn.next());
-      P.st(4 * pl + rowm + j, d[4], rn.next());
-      P.st(5 * pl + rowp + cp, d[5], rn.next());
-      P.st((R.mir ? 5 : 6) * pl + rowp + cm, d[6], rn.next());
-      P.st((R.mir ? 8 : 7) * pl + rowm + cm, d[7], rn.next());
-      P.st(8 * pl + rowm + cp, d[8], rn.next());
+      // 16-bit storage: f_i^+ and g_i^+ of each axial direction land in the
+      // two halves of one word (slots q and q + 9 of one node)
+      uint32_t r[13];
+#pragma unroll
+      for (int i = 0; i < 13; ++i) r[i] = rn.next();
+      if (!ODD) {
+        P.st(0, o, d[0], r[0]);
+        P.st_pair(2, o, d[1], tg[1], r[1], r[9]);   // slots 3, 12
+        P.st_pair(3, o, d[2], tg[2], r[2], r[10]);  // slots 4, 13
+        P.st_pair(0, o, d[3], tg[3], r[3], r[11]);  // slots 1, 10
+        P.st_pair(1, o, d[4], tg[4], r[4], r[12]);  // slots 2, 11
+        P.st(7, o, d[5], r[5]);
+        P.st(8, o, d[6], r[6]);
+        P.st(5, o, d[7], r[7]);
+        P.st(6, o, d[8], r[8]);
+      } else {
+        const int64_t cm = R.cm, cp = R.cp;
+        P.st(0, o, d[0], r[0]);
+        P.st_pair(0, row0 + cp, d[1], tg[1], r[1], r[9]);
+        P.st_pair(1, rowp + j, d[2], tg[2], r[2], r[10]);
+        P.st_pair(R.mir ? 0 : 2, row0 + cm, d[3], tg[3], r[3], r[11]);
+        P.st_pair(3, rowm + j, d[4], tg[4], r[4], r[12]);
+        P.st(5, rowp + cp, d[5], r[5]);
+        P.st(R.mir ? 5 : 6, rowp + cm, d[6], r[6]);
+        P.st(R.mir ? 8 : 7, rowm + cm, d[7], r[7]);
+        P.st(8, rowm + cp, d[8], r[8]);
+      }
       D.g0[o] = tg[0];
-      P.st(10 * pl + row0 + cp, tg[1], rn.next());
-      P.st(11 * pl + rowp + j, tg[2], rn.next());
-      P.st((R.mir ? 10 : 12) * pl + row0 + cm, tg[3], rn.next());
-      P.st(13 * pl + rowm + j, tg[4], rn.next());
     }
   } else {
     for (int q = 0; q < 5; ++q) B.t[q] = t[q];
@@ -1039,7 +1202,15 @@ __host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC&
   // Each (dr, dz) below is a separate inlined copy with constant offsets: on
   // annuli, where corner owners take three wall nodes, these specialised
   // passes run faster than one generic pass walked per lane.
-  if ((rad_m && own_rm) || (rad_p && own_rp) || own_zm || own_zp) {
+  // Where LBM_OWNER_WALLS_UNLIKELY is defined (the file of the 16-bit
+  // kernels) the branch is marked unlikely, which keeps the compiler from
+  // hoisting parts of the wall-node work into every fluid node's update.
+  const bool owns = (rad_m && own_rm) || (rad_p && own_rp) || own_zm || own_zp;
+#if defined(LBM_OWNER_WALLS_UNLIKELY)
+  if (__builtin_expect(owns, 0)) {
+#else
+  if (owns) {
+#endif
     for (int dr = -1; dr <= 1; ++dr) {
       if ((dr == -1 && !own_rm) || (dr == 1 && !own_rp)) continue;
       for (int dz = -1; dz <= 1; ++dz) {
@@ -1112,13 +1283,13 @@ __host__ __device__ inline void init_node(const InstDev& D, int j, int k, float 
     float v = d[i];
     if (inside && EXr[i] != 0)
       v = (float)(((double)d[i] - (double)w[i] * (rs - r + EXr[i]) / r) * (r / rs));
-    Store<S>::st(P, i * D.plane + o, v, D.st_scale);
+    Store<S>::st(P, slot_elem<S>(i, o, D.plane), v, D.st_scale);
   }
   const float eu[5] = {0.0f, ur, uz, -ur, -uz};
   const float wt[5] = {WT0, WT1, WT1, WT1, WT1};
   D.g0[o] = wt[0] * (T - D.T_s);
   for (int i = 1; i < 5; ++i)
-    Store<S>::st(P, (9 + i) * D.plane + o, wt[i] * (T * (1.0f + 5.0f * eu[i]) - D.T_s),
+    Store<S>::st(P, slot_elem<S>(9 + i, o, D.plane), wt[i] * (T * (1.0f + 5.0f * eu[i]) - D.T_s),
                  D.st_scale);
 }
 
