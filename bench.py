@@ -123,11 +123,14 @@ def storage_variant(Lattice, cfg, phi, storage, steps, warmup, check, stream):
 def pattern_ceiling(lat, reps: int = 20) -> dict:
     """The step's own access pattern without arithmetic on the same handle
     (lbm_axi_pattern_bandwidth): even and odd parity, their pair (harmonic mean:
-    a step pair moves the same bytes in each), and a plain read+write stream."""
+    a step pair moves the same bytes in each), a plain read+write stream, and
+    that stream at 2, 4, 8 and 16 bytes per lane (lbm_axi_lane_bandwidth)."""
     r = lat.pattern_bandwidth(reps=reps)
     pair = 2.0 / (1.0 / r["even_gbs"] + 1.0 / r["odd_gbs"])
+    lanes = lat.lane_bandwidth(reps=max(reps // 2, 1))  # in-place stream, bytes per lane
     return {"even": round(r["even_gbs"], 1), "odd": round(r["odd_gbs"], 1), "pair": round(pair, 1),
-            "stream_rw": round(r["stream_gbs"], 1), "reps": reps}
+            "stream_rw": round(r["stream_gbs"], 1), "reps": reps,
+            "lane_stream_gbs": {f"{w}B": round(v, 1) for w, v in lanes.items()}}
 
 
 def sweep_batch(Lattice, n_inst, steps, stream):
@@ -172,29 +175,38 @@ def sweep_batch(Lattice, n_inst, steps, stream):
                               (("running", 0), ("converged", 1), ("diverged", 2), ("stalled", 3))}}
 
 
-def sweep_to_steady(n_inst, cap, chunk=10_000, floor=3e-7):
+def sweep_to_steady(n_inst, cap, chunk=10_000, floor=3e-7, subset=(0, 1), start="conduction"):
     """The batched sweep run toward res <= 1e-8 with autotuned launches, step
     graphs and finished instances dropped from the launch after every chunk,
     up to `cap` steps.  It starts in FP16 storage, whose rounding noise keeps
     the residual near 1e-7 at a check interval of 1000, and converts the
     whole batch to FP32 in place (precision handoff) once half of the running
-    instances are within 3x of that floor.  Counts of converged / stalled /
-    diverged instances, steps of the converged ones, node updates per second."""
+    instances are within 3x of that floor.  subset = (i, n) runs instances
+    i, i + n, ... of the sweep in one handle (a whole sweep in n calls);
+    start = "conduction" starts every instance at rest with its radial
+    conduction profile of T, "cold" at rest at T_init.  Counts of converged /
+    stalled / diverged instances, steps of the converged ones, node updates
+    per second, and every instance's index, final state and own step count."""
     import numpy as np
     import torch
 
     import lbm_inputs as li
     from paper_1409_5929_amd import Lattice
+    from paper_1409_5929_amd import warmstart as ws
 
-    cfgs = li.sweep(n_inst=n_inst, seed=1409)
+    every = li.sweep(n_inst=n_inst, seed=1409)
+    index = list(range(subset[0], n_inst, subset[1]))
+    cfgs = [every[i] for i in index]
+    n_run = len(cfgs)
+    init = [ws.conduction_start(c) for c in cfgs] if start == "conduction" else None
     sizes = np.array([c["nr"] * c["nz"] for c in cfgs], dtype=np.float64)
-    lat = Lattice(cfgs, storage="fp16", check_interval=1000, tol=1e-8, max_steps=cap)
+    lat = Lattice(cfgs, init=init, storage="fp16", check_interval=1000, tol=1e-8, max_steps=cap)
     lat.autotune(trial_steps=10)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     t = lat.info()["t"]
     updates = 0.0
-    running = n_inst
+    running = n_run
     t_handoff = None
     while t < cap + 1000 and running > 0:
         r = lat.residual()
@@ -211,19 +223,22 @@ def sweep_to_steady(n_inst, cap, chunk=10_000, floor=3e-7):
         t += chunk
         updates += alive * chunk  # upper bound within the chunk: instances that stop mid-chunk
         running = lat.compact()
-        log(f"sweep to steady: t={t}, {running} of {n_inst} running, {time.perf_counter() - t0:.0f} s")
+        log(f"sweep to steady: t={t}, {running} of {n_run} running, {time.perf_counter() - t0:.0f} s")
     lat.sync()
     wall = time.perf_counter() - t0
     r = lat.residual()
-    steps = np.array([lat.info(i)["t"] for i in range(n_inst)])
+    steps = np.array([lat.info(i)["t"] for i in range(n_run)])
     lat.close()
     st = r["status"]
     conv = st == 1
-    return {"instances": n_inst, "cap": cap, "wall_s": round(wall, 1),
+    return {"instances": n_run, "of": n_inst, "subset": list(subset), "start": start, "cap": cap,
+            "wall_s": round(wall, 1),
             "converged": int(conv.sum()), "stalled": int((st == 3).sum()), "diverged": int((st == 2).sum()),
             "running": int((st == 0).sum()), "handoff_step": t_handoff,
             "steps_converged_median": float(np.median(steps[conv])) if conv.any() else None,
-            "node_updates_per_s_upper": round(updates / wall / 1e6, 1)}
+            "node_updates_per_s_upper": round(updates / wall / 1e6, 1),
+            "index": index, "status": [int(v) for v in st], "steps": [int(v) for v in steps],
+            "res": [float(v) for v in r["res"]]}
 
 
 def time_to_steady(n_problems, cap):
@@ -375,6 +390,10 @@ def main():
     ap.add_argument("--steady-max-steps", type=int, default=600_000)
     ap.add_argument("--sweep-to-steady", type=int, default=0, metavar="CAP",
                     help="only run the 1024-instance sweep toward res <= 1e-8 for up to CAP steps")
+    ap.add_argument("--sweep-subset", default="0/1", metavar="I/N",
+                    help="with --sweep-to-steady: run instances I, I+N, ... only")
+    ap.add_argument("--sweep-start", default="conduction", choices=["conduction", "cold"],
+                    help="with --sweep-to-steady: start of every instance")
     ap.add_argument("--sweep-only", action="store_true",
                     help="only run the batched sweep (the --sweep-instances / --sweep-steps line)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -400,7 +419,11 @@ def main():
               flush=True)
         return
     if args.sweep_to_steady > 0:
-        print(json.dumps({"sweep_to_steady": sweep_to_steady(args.sweep_instances, args.sweep_to_steady)}),
+        i, n = (int(v) for v in args.sweep_subset.split("/"))
+        if not 0 <= i < n:
+            sys.exit("--sweep-subset I/N needs 0 <= I < N")
+        print(json.dumps({"sweep_to_steady": sweep_to_steady(args.sweep_instances, args.sweep_to_steady,
+                                                             subset=(i, n), start=args.sweep_start)}),
               flush=True)
         return
     n = args.size

@@ -308,6 +308,17 @@ int lbm_axi_derived(const lbm_axi_params* p, double* out);
 int lbm_axi_pattern_bandwidth(lbm_axi* h, int32_t reps, double* out);
 
 /*
+ * Lane-width probe (no part of the method): an in-place read+write stream
+ * over every instance's population array (bits XORed with 0, so the state
+ * is unchanged) with lanes of 2, 4, 8 and 16 bytes, reps timed passes each
+ * after an untimed one.  out[0..3] = GB/s (bytes read plus written per
+ * second) for the four widths.  The same bytes at narrower lanes take more
+ * memory instructions; the 16-bit storage layout pairs slots in 4-byte words
+ * for this reason.  Waits for the stream; 1 <= reps <= 100000.
+ */
+int lbm_axi_lane_bandwidth(lbm_axi* h, int32_t reps, double* out);
+
+/*
  * Kernel timing: with on = 1 every later step-kernel launch is bracketed by
  * HIP events on the handle's stream; lbm_axi_kernel_time returns the summed
  * milliseconds and the number of launches since timing was switched on

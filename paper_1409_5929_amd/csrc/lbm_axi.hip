@@ -158,6 +158,18 @@ __global__ __launch_bounds__(RB) void k_stream_rw(uint4* __restrict__ p, int64_t
   }
 }
 
+// The same with lanes of sizeof(T) bytes (2, 4, 8 or 16): the lane width
+// probe.
+__device__ inline uint16_t lane_xor(uint16_t v, uint32_t k) { return (uint16_t)(v ^ k); }
+__device__ inline uint32_t lane_xor(uint32_t v, uint32_t k) { return v ^ k; }
+__device__ inline uint2 lane_xor(uint2 v, uint32_t k) { return make_uint2(v.x ^ k, v.y ^ k); }
+__device__ inline uint4 lane_xor(uint4 v, uint32_t k) { return make_uint4(v.x ^ k, v.y ^ k, v.z ^ k, v.w ^ k); }
+template <typename T>
+__global__ __launch_bounds__(RB) void k_stream_lane(T* __restrict__ p, int64_t n, uint32_t key) {
+  const int64_t stride = (int64_t)gridDim.x * RB;
+  for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += stride) p[i] = lane_xor(p[i], key);
+}
+
 // Sets the device clock read by captured step graphs.
 __global__ void k_setclock(long long* clk, long long t) {
   if (threadIdx.x == 0) *clk = t;
@@ -1584,6 +1596,51 @@ int lbm_axi_pattern_bandwidth(lbm_axi* h, int32_t reps, double* out) {
     out[2] = 2.0 * arr / (ms[2] * 1e-3) / 1e9;
     out[3] = bytes;
     return LBM_AXI_OK;
+  });
+}
+
+int lbm_axi_lane_bandwidth(lbm_axi* h, int32_t reps, double* out) {
+  return guarded([&]() -> int {
+    if (!h || !out || reps < 1 || reps > 100000)
+      return fail(LBM_AXI_EINVAL, "bad handle, output or reps out of [1, 100000]");
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const int64_t esz = h->storage == LBM_STORE_FP32 ? 4 : 2;
+    double arr = 0.0;
+    for (const InstDev& D : h->hdesc) arr += 14.0 * D.plane * esz;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    // every instance's population array (14 planes of a multiple-of-64 row
+    // stride: a whole number of 16-byte words), read and written in place
+    auto pass = [&](int w) {
+      for (const InstDev& D : h->hdesc) {
+        const int64_t n = 14 * D.plane * esz / w;
+        const unsigned nb = (unsigned)std::min<int64_t>((n + RB - 1) / RB, 8192);
+        if (w == 2) k_stream_lane<uint16_t><<<nb, RB, 0, h->stream>>>((uint16_t*)D.pop, n, 0u);
+        if (w == 4) k_stream_lane<uint32_t><<<nb, RB, 0, h->stream>>>((uint32_t*)D.pop, n, 0u);
+        if (w == 8) k_stream_lane<uint2><<<nb, RB, 0, h->stream>>>((uint2*)D.pop, n, 0u);
+        if (w == 16) k_stream_lane<uint4><<<nb, RB, 0, h->stream>>>((uint4*)D.pop, n, 0u);
+      }
+    };
+    int rc = LBM_AXI_OK;
+    const int widths[4] = {2, 4, 8, 16};
+    for (int q = 0; q < 4 && rc == LBM_AXI_OK; ++q) {
+      rc = [&]() -> int {
+        pass(widths[q]);  // untimed first pass
+        HIPCHK(hipEventRecord(e0, h->stream));
+        for (int r = 0; r < reps; ++r) pass(widths[q]);
+        HIPCHK(hipEventRecord(e1, h->stream));
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipEventSynchronize(e1));
+        float f = 0.0f;
+        HIPCHK(hipEventElapsedTime(&f, e0, e1));
+        out[q] = 2.0 * arr / (f / reps * 1e-3) / 1e9;
+        return LBM_AXI_OK;
+      }();
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
   });
 }
 

@@ -155,96 +155,75 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, const bf16_t* 
 // col[kidx][p] for kidx = (c, ky, kx), p = (b, oy, ox): the input value under
 // tap (ky, kx) of output (oy, ox), zero outside; with up, the input is the
 // 2x nearest-neighbour upsampling of x.  x is [b][c][y][x] (nchw) or
-// [c][b][y][x].
+// [c][b][y][x].  Grid: y = kidx, x over pairs of p; each thread writes two
+// outputs as one 4-byte word when P is even (2-byte stores would bind the
+// kernel on store instructions).  P = batch Ho Wo < 2^31 (create checks it),
+// so the index arithmetic is 32-bit.
 template <bool NCHW>
 __global__ __launch_bounds__(EW) void k_im2col(const float* __restrict__ x, int C, int Bt, int H,
                                                int W, int up, int k, int s, int pad, int Ho,
                                                int Wo, bf16_t* __restrict__ col) {
-  const int64_t P = (int64_t)Bt * Ho * Wo;
-  const int64_t p = (int64_t)blockIdx.x * EW + threadIdx.x;
-  if (p >= P) return;
+  const int P = Bt * Ho * Wo;
+  const int p0 = 2 * (int)(blockIdx.x * EW + threadIdx.x);
+  if (p0 >= P) return;
   const int kidx = blockIdx.y;
-  const int c = kidx / (k * k), t = kidx % (k * k), ky = t / k, kx = t % k;
-  const int ox = (int)(p % Wo);
-  const int64_t q = p / Wo;
-  const int oy = (int)(q % Ho);
-  const int b = (int)(q / Ho);
+  const int c = kidx / (k * k), t = kidx - c * k * k, ky = t / k, kx = t - ky * k;
   const int He = up ? 2 * H : H, We = up ? 2 * W : W;
-  const int iy = oy * s + ky - pad, ix = ox * s + kx - pad;
-  float v = 0.0f;
-  if (iy >= 0 && iy < He && ix >= 0 && ix < We) {
+  auto value = [&](int p) -> float {
+    const int q = p / Wo, ox = p - q * Wo;
+    const int b = q / Ho, oy = q - b * Ho;
+    const int iy = oy * s + ky - pad, ix = ox * s + kx - pad;
+    if (iy < 0 || iy >= He || ix < 0 || ix >= We) return 0.0f;
     const int sy = up ? iy >> 1 : iy, sx = up ? ix >> 1 : ix;
     const int64_t i = NCHW ? (((int64_t)b * C + c) * H + sy) * W + sx
                            : (((int64_t)c * Bt + b) * H + sy) * W + sx;
-    v = x[i];
+    return x[i];
+  };
+  bf16_t* dst = col + (int64_t)kidx * P + p0;
+  if ((P & 1) == 0) {
+    const uint32_t w = (uint32_t)to_bf16(value(p0)) | ((uint32_t)to_bf16(value(p0 + 1)) << 16);
+    *(uint32_t*)dst = w;
+  } else {
+    dst[0] = to_bf16(value(p0));
+    if (p0 + 1 < P) dst[1] = to_bf16(value(p0 + 1));
   }
-  col[(int64_t)kidx * P + p] = to_bf16(v);
 }
 
 // Adjoint of k_im2col (channel-major x): dx[c][b][y][x] (+)= sum of the dcol
-// entries that read x[c][b][y][x], gathered (no atomics).
+// entries that read x[c][b][y][x], gathered (no atomics), taps in a fixed
+// order.  Grid: y = c, z = b, x over the H W pixels (32-bit index
+// arithmetic); strides 1 or 2.
 __global__ __launch_bounds__(EW) void k_col2im(const float* __restrict__ dcol, int C, int Bt, int H,
                                                int W, int up, int k, int s, int pad, int Ho,
                                                int Wo, float* __restrict__ dx, int accumulate) {
-  const int64_t n = (int64_t)C * Bt * H * W;
-  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
-  if (i >= n) return;
-  const int sx = (int)(i % W);
-  int64_t q = i / W;
-  const int sy = (int)(q % H);
-  q /= H;
-  const int b = (int)(q % Bt);
-  const int c = (int)(q / Bt);
+  const int pix = (int)(blockIdx.x * EW + threadIdx.x);
+  if (pix >= H * W) return;
+  const int c = blockIdx.y, b = blockIdx.z;
+  const int sy = pix / W, sx = pix - sy * W;
   const int64_t P = (int64_t)Bt * Ho * Wo;
+  const int sh = s == 2 ? 1 : 0;
   const int nu = up ? 2 : 1;
+  const float* base = dcol + (int64_t)b * Ho * Wo;
   float acc = 0.0f;
   for (int uy = 0; uy < nu; ++uy)
     for (int ux = 0; ux < nu; ++ux) {
       const int iy = up ? 2 * sy + uy : sy, ix = up ? 2 * sx + ux : sx;
       for (int ky = 0; ky < k; ++ky) {
         const int ty = iy + pad - ky;
-        if (ty < 0 || ty % s) continue;
-        const int oy = ty / s;
+        if (ty < 0 || (ty & (s - 1))) continue;
+        const int oy = ty >> sh;
         if (oy >= Ho) continue;
         for (int kx = 0; kx < k; ++kx) {
           const int tx = ix + pad - kx;
-          if (tx < 0 || tx % s) continue;
-          const int ox = tx / s;
+          if (tx < 0 || (tx & (s - 1))) continue;
+          const int ox = tx >> sh;
           if (ox >= Wo) continue;
-          acc += dcol[(int64_t)((c * k + ky) * k + kx) * P + ((int64_t)b * Ho + oy) * Wo + ox];
+          acc += base[(int64_t)((c * k + ky) * k + kx) * P + oy * Wo + ox];
         }
       }
     }
+  const int64_t i = (((int64_t)c * Bt + b) * H + sy) * W + sx;
   dx[i] = accumulate ? dx[i] + acc : acc;
-}
-
-// a = relu(z) (or z) + skip
-__global__ __launch_bounds__(EW) void k_act(const float* __restrict__ z, const float* __restrict__ skip,
-                                            float* __restrict__ a, int64_t n, int relu) {
-  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
-  if (i >= n) return;
-  float v = z[i];
-  if (relu) v = fmaxf(v, 0.0f);
-  a[i] = skip ? v + skip[i] : v;
-}
-
-// dz = da where z > 0 (relu) or da; written over z, and as bfloat16 (the
-// GEMM operand) into dz16
-__global__ __launch_bounds__(EW) void k_act_bwd(const float* __restrict__ da, float* __restrict__ z,
-                                                bf16_t* __restrict__ dz16, int64_t n, int relu) {
-  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
-  if (i >= n) return;
-  const float v = (!relu || z[i] > 0.0f) ? da[i] : 0.0f;
-  z[i] = v;
-  dz16[i] = to_bf16(v);
-}
-
-// dst (+)= src
-__global__ __launch_bounds__(EW) void k_copy_add(float* __restrict__ dst, const float* __restrict__ src,
-                                                 int64_t n, int accumulate) {
-  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
-  if (i >= n) return;
-  dst[i] = accumulate ? dst[i] + src[i] : src[i];
 }
 
 __device__ inline float block_sum(float v, float* sh) {
@@ -258,13 +237,62 @@ __device__ inline float block_sum(float v, float* sh) {
   return t;
 }
 
-// db[o] = sum_p dz[o][p]: one block per channel, fixed order.
-__global__ __launch_bounds__(EW) void k_bias_grad(const float* __restrict__ dz, int64_t P,
+// a = relu(z) (or z) + skip
+__global__ __launch_bounds__(EW) void k_act(const float* __restrict__ z, const float* __restrict__ skip,
+                                            float* __restrict__ a, int64_t n, int relu) {
+  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
+  if (i >= n) return;
+  float v = z[i];
+  if (relu) v = fmaxf(v, 0.0f);
+  a[i] = skip ? v + skip[i] : v;
+}
+
+// dz = da where z > 0 (relu) or da; written over z, and as bfloat16 (the
+// GEMM operand) into dz16; and the bias gradient's partial sums: block
+// (x, o) covers ACT_CHUNK entries of channel o's row (dz is [cout][P]) and
+// writes their sum, in a fixed order, to bpart[o][x].
+constexpr int ACT_PER = 4;                 // entries per thread
+constexpr int ACT_CHUNK = EW * ACT_PER;   // entries per block
+__global__ __launch_bounds__(EW) void k_act_bwd(const float* __restrict__ da, float* __restrict__ z,
+                                                bf16_t* __restrict__ dz16, int64_t P, int relu,
+                                                float* __restrict__ bpart) {
+  __shared__ float sh[EW / 64];
+  const int o = blockIdx.y;
+  const int64_t row = (int64_t)o * P;
+  const int64_t p0 = (int64_t)blockIdx.x * ACT_CHUNK + threadIdx.x;
+  float sum = 0.0f;
+#pragma unroll
+  for (int r = 0; r < ACT_PER; ++r) {
+    const int64_t p = p0 + (int64_t)r * EW;
+    if (p < P) {
+      const int64_t i = row + p;
+      const float v = (!relu || z[i] > 0.0f) ? da[i] : 0.0f;
+      z[i] = v;
+      dz16[i] = to_bf16(v);
+      sum += v;
+    }
+  }
+  sum = block_sum(sum, sh);
+  if (threadIdx.x == 0) bpart[(int64_t)o * gridDim.x + blockIdx.x] = sum;
+}
+
+// dst (+)= src
+__global__ __launch_bounds__(EW) void k_copy_add(float* __restrict__ dst, const float* __restrict__ src,
+                                                 int64_t n, int accumulate) {
+  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
+  if (i >= n) return;
+  dst[i] = accumulate ? dst[i] + src[i] : src[i];
+}
+
+
+// db[o] = sum_p dz[o][p] from k_act_bwd's nchunk partial sums of channel o:
+// one block per channel, fixed order.
+__global__ __launch_bounds__(EW) void k_bias_grad(const float* __restrict__ bpart, int nchunk,
                                                   float* __restrict__ db) {
   __shared__ float sh[EW / 64];
-  const float* row = dz + (int64_t)blockIdx.x * P;
+  const float* row = bpart + (int64_t)blockIdx.x * nchunk;
   float v = 0.0f;
-  for (int64_t p = threadIdx.x; p < P; p += EW) v += row[p];
+  for (int q = threadIdx.x; q < nchunk; q += EW) v += row[q];
   v = block_sum(v, sh);
   if (threadIdx.x == 0) db[blockIdx.x] = v;
 }
@@ -385,6 +413,7 @@ struct lbm_no {
   int64_t split_n = 0;
   double* lpart = nullptr;
   double* dloss = nullptr;
+  float* bpart = nullptr;  // bias-gradient partial sums, [cout][chunks of P]
   long long adam_t = 0;
 };
 
@@ -441,7 +470,7 @@ int gemm(lbm_no* h, int M, int N, int K, const bf16_t* A, int64_t lda, const bf1
 int im2col(lbm_no* h, const Layer& l, const float* src, bool nchw, int Bt) {
   const int64_t P = (int64_t)Bt * l.Ho * l.Wo;
   const int K = l.cin * l.k * l.k;
-  const dim3 grid(grid1(P), (unsigned)K);
+  const dim3 grid(grid1((P + 1) / 2), (unsigned)K);
   if (nchw)
     k_im2col<true><<<grid, EW, 0, h->stream>>>(src, l.cin, Bt, l.Hs, l.Ws, l.up, l.k, l.s, (l.k - 1) / 2, l.Ho, l.Wo, h->col);
   else
@@ -540,7 +569,7 @@ int lbm_no_create(const int32_t* widths, int32_t height, int32_t width, int32_t 
     h->v = (float*)nalloc(h, np * 4);
     h->parb = (bf16_t*)nalloc(h, np * 2);
     if (!h->par || !h->grad || !h->m || !h->v || !h->parb) return bail(fail(LBM_NO_ENOMEM, "parameters"));
-    int64_t colmax = 0, splitmax = 0, actmax = 0;
+    int64_t colmax = 0, splitmax = 0, actmax = 0, bpmax = 0;
     for (const Layer& l : h->L) {
       const int64_t P = (int64_t)max_batch * l.Ho * l.Wo;
       const size_t n = (size_t)l.cout * P * 4;
@@ -556,6 +585,7 @@ int lbm_no_create(const int32_t* widths, int32_t height, int32_t width, int32_t 
       colmax = std::max(colmax, K * P);
       const int64_t S = (P + KCHUNK - 1) / KCHUNK;
       splitmax = std::max(splitmax, S * l.cout * K);
+      bpmax = std::max(bpmax, (int64_t)l.cout * ((P + ACT_CHUNK - 1) / ACT_CHUNK));
     }
     h->col = (bf16_t*)nalloc(h, (size_t)colmax * 2);
     h->dcol = (float*)nalloc(h, (size_t)colmax * 4);
@@ -565,7 +595,8 @@ int lbm_no_create(const int32_t* widths, int32_t height, int32_t width, int32_t 
     const int64_t lb = (3 * (int64_t)max_batch * height * width + EW - 1) / EW;
     h->lpart = (double*)nalloc(h, (size_t)lb * 8);
     h->dloss = (double*)nalloc(h, 8);
-    if (!h->col || !h->dcol || !h->dz16 || !h->split || !h->lpart || !h->dloss)
+    h->bpart = (float*)nalloc(h, (size_t)bpmax * 4);
+    if (!h->col || !h->dcol || !h->dz16 || !h->split || !h->lpart || !h->dloss || !h->bpart)
       return bail(fail(LBM_NO_ENOMEM, "work space"));
     const int rc = lbm_no_set_params(h, params);
     if (rc) return bail(rc);
@@ -626,8 +657,10 @@ int lbm_no_gradients(lbm_no* h, const float* x, const float* target, int32_t bat
       const int64_t P = (int64_t)batch * l.Ho * l.Wo;
       const int K = l.cin * l.k * l.k;
       const int64_t n = (int64_t)l.cout * P;
-      // dz over z; the skip passes da on unchanged
-      k_act_bwd<<<grid1(n), EW, 0, h->stream>>>(h->da[li], h->z[li], h->dz16, n, l.relu);
+      // dz over z (and the bias gradient's partial sums); the skip passes da on unchanged
+      const unsigned nchunk = (unsigned)((P + ACT_CHUNK - 1) / ACT_CHUNK);
+      k_act_bwd<<<dim3(nchunk, (unsigned)l.cout), EW, 0, h->stream>>>(h->da[li], h->z[li], h->dz16, P, l.relu,
+                                                                       h->bpart);
       NOCHK(hipGetLastError());
       if (l.skip >= 0) {
         k_copy_add<<<grid1(n), EW, 0, h->stream>>>(h->da[l.skip], h->da[li], n, have[l.skip]);
@@ -645,7 +678,7 @@ int lbm_no_gradients(lbm_no* h, const float* x, const float* target, int32_t bat
       if (rc) return rc;
       k_sum_splits<<<grid1(mn), EW, 0, h->stream>>>(h->split, S, mn, h->grad + l.woff);
       NOCHK(hipGetLastError());
-      k_bias_grad<<<(unsigned)l.cout, EW, 0, h->stream>>>(h->z[li], P, h->grad + l.boff);
+      k_bias_grad<<<(unsigned)l.cout, EW, 0, h->stream>>>(h->bpart, (int)nchunk, h->grad + l.boff);
       NOCHK(hipGetLastError());
       if (li == 0) break;  // no gradient with respect to the input
       // input gradient: dcol = W^T dz, then the col2im gather into da[li - 1]
@@ -653,9 +686,9 @@ int lbm_no_gradients(lbm_no* h, const float* x, const float* target, int32_t bat
       rc = gemm<false, false>(h, K, (int)P, l.cout, h->parb + l.woff, K, h->dz16, P, h->dcol, P, 0, 1,
                               l.cout + (l.cout & 1), nullptr);  // one split covering all of cout
       if (rc) return rc;
-      const int64_t ns = (int64_t)l.cin * batch * l.Hs * l.Ws;
-      k_col2im<<<grid1(ns), EW, 0, h->stream>>>(h->dcol, l.cin, batch, l.Hs, l.Ws, l.up, l.k, l.s, (l.k - 1) / 2,
-                                                l.Ho, l.Wo, h->da[li - 1], have[li - 1]);
+      const dim3 g2(grid1((int64_t)l.Hs * l.Ws), (unsigned)l.cin, (unsigned)batch);
+      k_col2im<<<g2, EW, 0, h->stream>>>(h->dcol, l.cin, batch, l.Hs, l.Ws, l.up, l.k, l.s, (l.k - 1) / 2,
+                                         l.Ho, l.Wo, h->da[li - 1], have[li - 1]);
       NOCHK(hipGetLastError());
       have[li - 1] = 1;
     }

@@ -146,6 +146,8 @@ def _load():
     lib.lbm_axi_kernel_time.restype = ctypes.c_int
     lib.lbm_axi_set_tiles.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]
     lib.lbm_axi_set_tiles.restype = ctypes.c_int
+    lib.lbm_axi_lane_bandwidth.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+    lib.lbm_axi_lane_bandwidth.restype = ctypes.c_int
     lib.lbm_axi_set_wall_lanes.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.lbm_axi_set_wall_lanes.restype = ctypes.c_int
     lib.lbm_axi_set_storage.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]
@@ -400,6 +402,13 @@ class Lattice:
         out = (ctypes.c_double * 4)()
         _check(self._lib.lbm_axi_pattern_bandwidth(self._h, int(reps), out))
         return dict(even_gbs=out[0], odd_gbs=out[1], stream_gbs=out[2], bytes_per_launch=out[3])
+
+    def lane_bandwidth(self, reps: int = 20) -> dict:
+        """GB/s of an in-place stream over this handle's population arrays with
+        lanes of 2, 4, 8 and 16 bytes (the state is left unchanged)."""
+        out = (ctypes.c_double * 4)()
+        _check(self._lib.lbm_axi_lane_bandwidth(self._h, int(reps), out))
+        return {2: out[0], 4: out[1], 8: out[2], 16: out[3]}
 
     def set_timing(self, on: bool):
         _check(self._lib.lbm_axi_set_timing(self._h, 1 if on else 0))

@@ -91,6 +91,7 @@ def test_null_handles_are_refused():
     assert lib.lbm_axi_set_storage(None, 1, 0) == -1
     assert lib.lbm_axi_set_tiles(None, 4, 0) == -1
     assert lib.lbm_axi_set_wall_lanes(None, 1, None) == -1
+    assert lib.lbm_axi_lane_bandwidth(None, 1, None) == -1
     assert lib.lbm_axi_set_graph(None, 32) == -1
     assert lib.lbm_axi_compact(None, None) == -1
     assert lib.lbm_axi_autotune(None, 1, None, None, None) == -1

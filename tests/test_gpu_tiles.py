@@ -83,7 +83,9 @@ def test_pattern_probe_leaves_the_state_unchanged(L, storage, case):
     """The streaming-ceiling probe makes the step's loads and stores and puts
     every value back where node_load read it; afterwards the run continues
     bit for bit as if the probe had not run, at either parity.  This also shows
-    that the probe's slot map (node_slots) is node_load's, slot for slot."""
+    that the probe's slot map (node_slots) is node_load's, slot for slot.  The
+    lane-width probe (an in-place stream at 2 to 16 bytes per lane) is run in
+    the same way."""
     if case == "annulus field":
         cfg = li.annulus(nr=150, nz=70, Ra=1e5, Da=1e-3)
         phi = li.porosity_grf(70, 150, seed=2, sigma=3.0)
@@ -103,6 +105,8 @@ def test_pattern_probe_leaves_the_state_unchanged(L, storage, case):
         lat.step(4)
         if probe:
             lat.pattern_bandwidth(reps=2)
+            w = lat.lane_bandwidth(reps=2)  # lane-width probe: also an identity
+            assert all(np.isfinite(v) and v > 0 for v in w.values()), w
         lat.step(3)
         got.append(lat.fields())
         lat.close()
