@@ -120,15 +120,10 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, const bf16_t* 
       const int kq = kk + 4 * (lane >> 4);
       v4s a[4], b[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const bf16_t* p = &As[wm + i * 16 + (lane & 15)][kq];
-        a[i] = v4s{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
-      }
+      for (int i = 0; i < 4; ++i)  // one 8-byte LDS read (rows of 80 B, kq a multiple of 4)
+        a[i] = *(const v4s*)&As[wm + i * 16 + (lane & 15)][kq];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const bf16_t* p = &Bs[wn + j * 16 + (lane & 15)][kq];
-        b[j] = v4s{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
-      }
+      for (int j = 0; j < 4; ++j) b[j] = *(const v4s*)&Bs[wn + j * 16 + (lane & 15)][kq];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -155,10 +150,11 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, const bf16_t* 
 // col[kidx][p] for kidx = (c, ky, kx), p = (b, oy, ox): the input value under
 // tap (ky, kx) of output (oy, ox), zero outside; with up, the input is the
 // 2x nearest-neighbour upsampling of x.  x is [b][c][y][x] (nchw) or
-// [c][b][y][x].  Grid: y = kidx, x over pairs of p; each thread writes two
-// outputs as one 4-byte word when P is even (2-byte stores would bind the
-// kernel on store instructions).  P = batch Ho Wo < 2^31 (create checks it),
-// so the index arithmetic is 32-bit.
+// [c][b][y][x].  Grid: y = input channel c, x over pairs of p; each thread
+// writes the k^2 rows of its channel for two outputs, each as one 4-byte word
+// when P is even (2-byte stores would bind the kernel on store instructions),
+// so the input of a channel is read once per pass, not once per tap.  P =
+// batch Ho Wo < 2^31 (create checks it): 32-bit index arithmetic.
 template <bool NCHW>
 __global__ __launch_bounds__(EW) void k_im2col(const float* __restrict__ x, int C, int Bt, int H,
                                                int W, int up, int k, int s, int pad, int Ho,
@@ -166,27 +162,36 @@ __global__ __launch_bounds__(EW) void k_im2col(const float* __restrict__ x, int 
   const int P = Bt * Ho * Wo;
   const int p0 = 2 * (int)(blockIdx.x * EW + threadIdx.x);
   if (p0 >= P) return;
-  const int kidx = blockIdx.y;
-  const int c = kidx / (k * k), t = kidx - c * k * k, ky = t / k, kx = t - ky * k;
+  const int c = blockIdx.y;
   const int He = up ? 2 * H : H, We = up ? 2 * W : W;
-  auto value = [&](int p) -> float {
-    const int q = p / Wo, ox = p - q * Wo;
-    const int b = q / Ho, oy = q - b * Ho;
-    const int iy = oy * s + ky - pad, ix = ox * s + kx - pad;
+  const bool two = p0 + 1 < P;
+  int oy[2], ox[2], b[2];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int p = two ? p0 + e : p0;
+    const int q = p / Wo;
+    ox[e] = p - q * Wo;
+    b[e] = q / Ho;
+    oy[e] = q - b[e] * Ho;
+  }
+  auto value = [&](int e, int ky, int kx) -> float {
+    const int iy = oy[e] * s + ky - pad, ix = ox[e] * s + kx - pad;
     if (iy < 0 || iy >= He || ix < 0 || ix >= We) return 0.0f;
     const int sy = up ? iy >> 1 : iy, sx = up ? ix >> 1 : ix;
-    const int64_t i = NCHW ? (((int64_t)b * C + c) * H + sy) * W + sx
-                           : (((int64_t)c * Bt + b) * H + sy) * W + sx;
+    const int64_t i = NCHW ? (((int64_t)b[e] * C + c) * H + sy) * W + sx
+                           : (((int64_t)c * Bt + b[e]) * H + sy) * W + sx;
     return x[i];
   };
-  bf16_t* dst = col + (int64_t)kidx * P + p0;
-  if ((P & 1) == 0) {
-    const uint32_t w = (uint32_t)to_bf16(value(p0)) | ((uint32_t)to_bf16(value(p0 + 1)) << 16);
-    *(uint32_t*)dst = w;
-  } else {
-    dst[0] = to_bf16(value(p0));
-    if (p0 + 1 < P) dst[1] = to_bf16(value(p0 + 1));
-  }
+  for (int ky = 0; ky < k; ++ky)
+    for (int kx = 0; kx < k; ++kx) {
+      bf16_t* dst = col + (int64_t)((c * k + ky) * k + kx) * P + p0;
+      if ((P & 1) == 0) {
+        *(uint32_t*)dst = (uint32_t)to_bf16(value(0, ky, kx)) | ((uint32_t)to_bf16(value(1, ky, kx)) << 16);
+      } else {
+        dst[0] = to_bf16(value(0, ky, kx));
+        if (two) dst[1] = to_bf16(value(1, ky, kx));
+      }
+    }
 }
 
 // Adjoint of k_im2col (channel-major x): dx[c][b][y][x] (+)= sum of the dcol
@@ -419,7 +424,19 @@ struct lbm_no {
 
 namespace {
 
-constexpr int KCHUNK = 8192;  // reduction length of one weight-gradient split
+// Weight-gradient GEMMs reduce over p = (batch, y, x), hundreds of thousands
+// long, into outputs of at most a few hundred x a few thousand: the
+// reduction is split so that every layer launches about SPLIT_BLOCKS blocks
+// (256 compute units), each split a multiple of BK long; the partial sums are
+// added in split order.
+constexpr int SPLIT_BLOCKS = 512;
+void wgrad_split(int64_t M, int64_t N, int64_t P, int& S, int64_t& kchunk) {
+  const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  int64_t s = std::max<int64_t>(1, (SPLIT_BLOCKS + tiles - 1) / tiles);
+  s = std::min<int64_t>(s, (P + BK - 1) / BK);
+  kchunk = ((P + s - 1) / s + BK - 1) / BK * BK;
+  S = (int)((P + kchunk - 1) / kchunk);
+}
 
 void* nalloc(lbm_no* h, size_t bytes) {
   void* p = nullptr;
@@ -469,8 +486,7 @@ int gemm(lbm_no* h, int M, int N, int K, const bf16_t* A, int64_t lda, const bf1
 
 int im2col(lbm_no* h, const Layer& l, const float* src, bool nchw, int Bt) {
   const int64_t P = (int64_t)Bt * l.Ho * l.Wo;
-  const int K = l.cin * l.k * l.k;
-  const dim3 grid(grid1((P + 1) / 2), (unsigned)K);
+  const dim3 grid(grid1((P + 1) / 2), (unsigned)l.cin);
   if (nchw)
     k_im2col<true><<<grid, EW, 0, h->stream>>>(src, l.cin, Bt, l.Hs, l.Ws, l.up, l.k, l.s, (l.k - 1) / 2, l.Ho, l.Wo, h->col);
   else
@@ -583,8 +599,10 @@ int lbm_no_create(const int32_t* widths, int32_t height, int32_t width, int32_t 
       h->da.push_back(dl);
       const int64_t K = (int64_t)l.cin * l.k * l.k;
       colmax = std::max(colmax, K * P);
-      const int64_t S = (P + KCHUNK - 1) / KCHUNK;
-      splitmax = std::max(splitmax, S * l.cout * K);
+      int S;
+      int64_t kchunk;
+      wgrad_split(l.cout, K, P, S, kchunk);
+      splitmax = std::max(splitmax, (int64_t)S * l.cout * K);
       bpmax = std::max(bpmax, (int64_t)l.cout * ((P + ACT_CHUNK - 1) / ACT_CHUNK));
     }
     h->col = (bf16_t*)nalloc(h, (size_t)colmax * 2);
@@ -670,11 +688,13 @@ int lbm_no_gradients(lbm_no* h, const float* x, const float* target, int32_t bat
       rc = im2col(h, l, li == 0 ? x : h->a[li - 1], li == 0, batch);
       if (rc) return rc;
       // weight gradient, split over p, partials summed in order
-      const int S = (int)((P + KCHUNK - 1) / KCHUNK);
+      int S;
+      int64_t kchunk;
+      wgrad_split(l.cout, K, P, S, kchunk);
       const int64_t mn = (int64_t)l.cout * K;
       if ((int64_t)S * mn > h->split_n) return fail(LBM_NO_EINVAL, "split work space too small");
       // dW[o][k] = dz[o][p] col[k][p]: A k(=p)-contiguous, B k(=p)-contiguous
-      rc = gemm<true, true>(h, l.cout, K, (int)P, h->dz16, P, h->col, P, h->split, K, mn, S, KCHUNK, nullptr);
+      rc = gemm<true, true>(h, l.cout, K, (int)P, h->dz16, P, h->col, P, h->split, K, mn, S, (int)kchunk, nullptr);
       if (rc) return rc;
       k_sum_splits<<<grid1(mn), EW, 0, h->stream>>>(h->split, S, mn, h->grad + l.woff);
       NOCHK(hipGetLastError());
