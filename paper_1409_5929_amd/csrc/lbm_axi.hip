@@ -620,8 +620,18 @@ int build_tiles(lbm_axi* h, int kz, int kz_odd) {
     for (int i = 0; i < h->n_inst; ++i) {
       if (!(h->active.empty() || h->active[i])) continue;
       const lbm_axi_params& q = h->prm[i];
-      for (int k0 = 0; k0 < q.nz; k0 += BY * kzp)
-        for (int j0 = 0; j0 < q.nr; j0 += BX) live.push_back(make_int4(i, j0, k0, 0));
+      // A row's last column tile, when at most half a wave wide, is packed:
+      // one tile (w = 1) takes two consecutive z strips, one per half wave.
+      // Half-empty waves cost nearly a full wave at 2-byte lanes (measured:
+      // the 1024-instance sweep, 5.7 % of its waves).
+      for (int k0 = 0, s = 0; k0 < q.nz; k0 += BY * kzp, ++s)
+        for (int j0 = 0; j0 < q.nr; j0 += BX) {
+          if (q.nr - j0 <= BX / 2) {
+            if (s % 2 == 0) live.push_back(make_int4(i, j0, k0, 1));
+          } else {
+            live.push_back(make_int4(i, j0, k0, 0));
+          }
+        }
     }
     const int T = (int)live.size();
     const int per = T > 0 ? (T + 7) / 8 : 1;

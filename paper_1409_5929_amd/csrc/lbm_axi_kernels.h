@@ -31,7 +31,10 @@ __global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(sizeof(S
   if (tl.x < 0) return;
   if (MODE != MODE_FIELDS && status[tl.x] != RUN) return;
   const InstDev D = descs[tl.x];
-  const int jt = tl.y + (int)threadIdx.x;
+  // A packed tile (tl.w = 1) covers 32 columns: lanes 32..63 take the z strip
+  // after lanes 0..31's (a row's last, at most half-wide column tile).
+  const int half = tl.w ? (int)(threadIdx.x >> 5) : 0;
+  const int jt = tl.y + (tl.w ? (int)(threadIdx.x & 31) : (int)threadIdx.x);
   if (jt >= D.nr) return;
   // With wall lanes (WL) a radial wall lane (column 0 or nr - 1 of a no-slip
   // side) works on its owner's column j and writes its own wall node
@@ -48,7 +51,7 @@ __global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(sizeof(S
   const RowC R = make_row(D, j);
   const bool zwall = z_bounded(D);
   // Fluid nodes of this thread's strip: k = kbeg, kbeg + BY, ... < kend.
-  const int k0 = tl.z + (int)threadIdx.y;
+  const int k0 = tl.z + (int)threadIdx.y + half * BY * kz;
   int kbeg = k0, kend = min(k0 + BY * kz, D.nz);
   if (zwall) {
     if (kbeg == 0) kbeg += BY;
@@ -92,11 +95,12 @@ __global__ __launch_bounds__(BX* BY) void k_pattern(const InstDev* __restrict__ 
   const int4 tl = tiles[blockIdx.x];
   if (tl.x < 0 || status[tl.x] != RUN) return;
   const InstDev D = descs[tl.x];
-  const int j = tl.y + (int)threadIdx.x;
+  const int half = tl.w ? (int)(threadIdx.x >> 5) : 0;  // packed tile: see k_step
+  const int j = tl.y + (tl.w ? (int)(threadIdx.x & 31) : (int)threadIdx.x);
   if (j >= D.nr) return;
   if ((D.side_rmin == SIDE_WALL && j == 0) || (D.side_rmax == SIDE_WALL && j == D.nr - 1)) return;
   const RowC R = make_row(D, j);
-  const int k0 = tl.z + (int)threadIdx.y;
+  const int k0 = tl.z + (int)threadIdx.y + half * BY * kz;
   int kbeg = k0, kend = min(k0 + BY * kz, D.nz);
   if (z_bounded(D)) {
     if (kbeg == 0) kbeg += BY;
