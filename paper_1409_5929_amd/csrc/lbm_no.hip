@@ -37,7 +37,6 @@ int fail(int code, const std::string& msg) {
     if (e_ != hipSuccess) return fail(LBM_NO_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef uint16_t bf16_t;  // bfloat16 bit pattern
 
@@ -47,104 +46,160 @@ __host__ __device__ inline bf16_t to_bf16(float v) {  // round to nearest even (
   return (bf16_t)(u >> 16);
 }
 
-constexpr int BM = 128, BN = 128, BK = 32, NT = 256;
-constexpr int LDK = BK + 8;  // padded LDS rows (bf16 elements)
+constexpr int NT = 256;      // threads of a GEMM block (four waves)
+constexpr int GBK = 64;      // k per LDS stage of the GEMM
+constexpr int GLD = GBK + 8; // padded LDS row (bf16): 144 B, rows stay 16-byte aligned
 constexpr int EW = 256;      // threads of the elementwise kernels
 
-// C[m][n] = sum_k A(m, k) B(k, n) (+ bias[m] in split 0) on bfloat16 operands.
-// AK: A is k-contiguous, A(m, k) = A[m lda + k]; otherwise A(m, k) = A[k lda + m].
-// BKC: B is k-contiguous, B(k, n) = B[n ldb + k]; otherwise B(k, n) = B[k ldb + n].
-// Split z covers k in [z kchunk, (z + 1) kchunk) and writes C + z cz.
-// Block: 128 x 128 outputs, four waves of 64 x 64, each as 4 x 4 MFMA
-// 16 x 16 x 16 tiles.  Operands move as pairs of bf16 (4-byte loads: every
-// leading dimension, K and the contiguous extent are even), staged in LDS
-// with k contiguous (B transposed), zero outside the matrices.
-template <bool AK, bool BKC>
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// 8 bfloat16 of a row, row[k .. k + 7], zero at and beyond kend; one 16-byte
+// load when vec (row and k 16-byte aligned) and the 8 lie before kend.
+__device__ inline uint4 load8(const bf16_t* __restrict__ row, int k, int kend, bool vec) {
+  if (vec && k + 8 <= kend) return *(const uint4*)(row + k);
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+    if (k + i < kend) w[i >> 1] |= (uint32_t)row[k + i] << (16 * (i & 1));
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// Halves h of the four words a, b (a in the low half): for the register
+// transpose of the n-contiguous B operand.
+__device__ inline uint32_t pick(uint32_t a, uint32_t b, int h) {
+  return h ? (a >> 16) | (b & 0xFFFF0000u) : (a & 0xFFFFu) | (b << 16);
+}
+__device__ inline uint32_t word(const uint4& v, int d) { return d == 0 ? v.x : d == 1 ? v.y : d == 2 ? v.z : v.w; }
+
+// C[m][n] = sum_k A[m][k] B(k, n) (+ bias[m] in split 0) on bfloat16 operands
+// with FP32 accumulation, on v_mfma_f32_16x16x32_bf16.
+// A is k-contiguous (row m at A + m lda).  BKC: B(k, n) = B[n ldb + k];
+// otherwise B(k, n) = B[k ldb + n].  Split z covers k in [z kchunk,
+// (z + 1) kchunk) and writes C + z cz.
+// Block: WM x (4 / WM) waves, each 64 x 64 outputs as 4 x 4 MFMA tiles of
+// 16 x 16; k staged through LDS 64 at a time with k contiguous (B
+// transposed on the way when n-contiguous: each thread turns a 4 (k) x 8 (n)
+// block around in registers and writes eight 8-byte rows).  The next stage's
+// operands are loaded into registers while the current one is multiplied.
+// accumulate: C += instead of C =.
+// vecA / vecB: rows 16-byte aligned (leading dimension a multiple of 8,
+// aligned base, kchunk a multiple of 8), so whole 8-element chunks move as
+// one 16-byte load; otherwise element by element.  Zero outside the
+// matrices.
+template <bool BKC, int WM>
 __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, const bf16_t* __restrict__ A,
-                                             int64_t lda, const bf16_t* __restrict__ B, int64_t ldb,
-                                             float* __restrict__ C, int64_t ldc, int64_t cz, int kchunk,
-                                             const float* __restrict__ bias) {
-  __shared__ bf16_t As[BM][LDK];
-  __shared__ bf16_t Bs[BN][LDK];
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+                                             int64_t lda, int vecA, const bf16_t* __restrict__ B,
+                                             int64_t ldb, int vecB, float* __restrict__ C, int64_t ldc,
+                                             int64_t cz, int kchunk, const float* __restrict__ bias,
+                                             int accumulate) {
+  constexpr int WN = 4 / WM, TBM = 64 * WM, TBN = 64 * WN;
+  constexpr int NA = TBM * GBK / 8 / NT;   // 16-byte A chunks per thread and stage
+  constexpr int NB = TBN * GBK / 8 / NT;   // 16-byte B chunks per thread and stage
+  __shared__ __attribute__((aligned(16))) bf16_t As[TBM * GLD];
+  __shared__ __attribute__((aligned(16))) bf16_t Bs[TBN * GLD];
+  const int m0 = blockIdx.y * TBM, n0 = blockIdx.x * TBN;
   const int kb = blockIdx.z * kchunk;
   const int ke = min(K, kb + kchunk);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int wm = (wave / WN) * 64, wn = (wave % WN) * 64;
   v4f acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int k0 = kb; k0 < ke; k0 += BK) {
-    // A tile: 128 x 32 = 2048 pairs, 8 per thread
+  uint4 ra[NA], rb[NB];
+  auto load = [&](int k0) {
 #pragma unroll
-    for (int it = 0; it < BM * BK / 2 / NT; ++it) {
-      const int e = tid + it * NT;
-      if (AK) {  // pairs along k
-        const int r = e / (BK / 2), c = 2 * (e % (BK / 2));
-        const int gm = m0 + r, gk = k0 + c;
-        uint32_t v = 0;
-        if (gm < M && gk < ke) v = *(const uint32_t*)(A + (int64_t)gm * lda + gk);
-        *(uint32_t*)&As[r][c] = v;
-      } else {  // pairs along m
-        const int c = e / (BM / 2), r = 2 * (e % (BM / 2));
-        const int gm = m0 + r, gk = k0 + c;
-        uint32_t v = 0;
-        if (gm < M && gk < ke) v = *(const uint32_t*)(A + (int64_t)gk * lda + gm);
-        As[r][c] = (bf16_t)(v & 0xFFFFu);
-        As[r + 1][c] = (bf16_t)(v >> 16);
+    for (int it = 0; it < NA; ++it) {
+      const int e = tid + it * NT, r = e >> 3, c = (e & 7) << 3;
+      ra[it] = m0 + r < M ? load8(A + (int64_t)(m0 + r) * lda, k0 + c, ke, vecA) : make_uint4(0u, 0u, 0u, 0u);
+    }
+    if constexpr (BKC) {
+#pragma unroll
+      for (int it = 0; it < NB; ++it) {
+        const int e = tid + it * NT, r = e >> 3, c = (e & 7) << 3;
+        rb[it] = n0 + r < N ? load8(B + (int64_t)(n0 + r) * ldb, k0 + c, ke, vecB) : make_uint4(0u, 0u, 0u, 0u);
+      }
+    } else {  // blocks of 4 k x 8 n: k = 4 (e % 16) + q, n = 8 (e / 16) + 0..7
+#pragma unroll
+      for (int it = 0; it < NB / 4; ++it) {
+        const int e = tid + it * NT, kq = (e & 15) << 2, n8 = (e >> 4) << 3;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int gk = k0 + kq + q;
+          rb[4 * it + q] = gk < ke ? load8(B + (int64_t)gk * ldb, n0 + n8, N, vecB) : make_uint4(0u, 0u, 0u, 0u);
+        }
       }
     }
+  };
+  auto stash = [&]() {
 #pragma unroll
-    for (int it = 0; it < BN * BK / 2 / NT; ++it) {
-      const int e = tid + it * NT;
-      if (BKC) {  // pairs along k
-        const int n = e / (BK / 2), c = 2 * (e % (BK / 2));
-        const int gn = n0 + n, gk = k0 + c;
-        uint32_t v = 0;
-        if (gn < N && gk < ke) v = *(const uint32_t*)(B + (int64_t)gn * ldb + gk);
-        *(uint32_t*)&Bs[n][c] = v;
-      } else {  // pairs along n
-        const int c = e / (BN / 2), n = 2 * (e % (BN / 2));
-        const int gn = n0 + n, gk = k0 + c;
-        uint32_t v = 0;
-        if (gn < N && gk < ke) v = *(const uint32_t*)(B + (int64_t)gk * ldb + gn);
-        Bs[n][c] = (bf16_t)(v & 0xFFFFu);
-        Bs[n + 1][c] = (bf16_t)(v >> 16);
+    for (int it = 0; it < NA; ++it) {
+      const int e = tid + it * NT, r = e >> 3, c = (e & 7) << 3;
+      *(uint4*)&As[r * GLD + c] = ra[it];
+    }
+    if constexpr (BKC) {
+#pragma unroll
+      for (int it = 0; it < NB; ++it) {
+        const int e = tid + it * NT, r = e >> 3, c = (e & 7) << 3;
+        *(uint4*)&Bs[r * GLD + c] = rb[it];
+      }
+    } else {
+#pragma unroll
+      for (int it = 0; it < NB / 4; ++it) {
+        const int e = tid + it * NT, kq = (e & 15) << 2, n8 = (e >> 4) << 3;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int d = i >> 1, h = i & 1;
+          uint2 v;
+          v.x = pick(word(rb[4 * it + 0], d), word(rb[4 * it + 1], d), h);
+          v.y = pick(word(rb[4 * it + 2], d), word(rb[4 * it + 3], d), h);
+          *(uint2*)&Bs[(n8 + i) * GLD + kq] = v;
+        }
       }
     }
+  };
+  if (kb < ke) load(kb);
+  for (int k0 = kb; k0 < ke; k0 += GBK) {
+    __syncthreads();  // the previous stage's fragments are read
+    stash();
     __syncthreads();
+    if (k0 + GBK < ke) load(k0 + GBK);
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 16) {
-      const int kq = kk + 4 * (lane >> 4);
-      v4s a[4], b[4];
+    for (int kk = 0; kk < GBK; kk += 32) {
+      const int kq = kk + 8 * (lane >> 4);
+      v8bf a[4], b[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)  // one 8-byte LDS read (rows of 80 B, kq a multiple of 4)
-        a[i] = *(const v4s*)&As[wm + i * 16 + (lane & 15)][kq];
+      for (int i = 0; i < 4; ++i)
+        a[i] = __builtin_bit_cast(v8bf, *(const uint4*)&As[(wm + i * 16 + (lane & 15)) * GLD + kq]);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = *(const v4s*)&Bs[wn + j * 16 + (lane & 15)][kq];
+      for (int j = 0; j < 4; ++j)
+        b[j] = __builtin_bit_cast(v8bf, *(const uint4*)&Bs[(wn + j * 16 + (lane & 15)) * GLD + kq]);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    __syncthreads();
   }
   float* Cz = C + (int64_t)blockIdx.z * cz;
   // result layout of a 16 x 16 tile: lane holds column lane % 16, rows 4 (lane / 16) + q
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int q = 0; q < 4; ++q) {
+      const int gm = m0 + wm + i * 16 + 4 * (lane >> 4) + q;
+      if (gm >= M) continue;
+      const float bv = (bias && blockIdx.z == 0) ? bias[gm] : 0.0f;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int gm = m0 + wm + i * 16 + 4 * (lane >> 4) + q;
+      for (int j = 0; j < 4; ++j) {
         const int gn = n0 + wn + j * 16 + (lane & 15);
-        if (gm < M && gn < N)
-          Cz[(int64_t)gm * ldc + gn] = acc[i][j][q] + ((bias && blockIdx.z == 0) ? bias[gm] : 0.0f);
+        if (gn < N) {
+          float* c = Cz + (int64_t)gm * ldc + gn;
+          *c = (accumulate ? *c : 0.0f) + (acc[i][j][q] + bv);
+        }
       }
+    }
 }
 
 // col[kidx][p] for kidx = (c, ky, kx), p = (b, oy, ox): the input value under
@@ -302,14 +357,82 @@ __global__ __launch_bounds__(EW) void k_bias_grad(const float* __restrict__ bpar
   if (threadIdx.x == 0) db[blockIdx.x] = v;
 }
 
-// out[i] = sum_s part[s][i]
-__global__ __launch_bounds__(EW) void k_sum_splits(const float* __restrict__ part, int S, int64_t n,
-                                                   float* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
-  if (i >= n) return;
+// out[j(i)] = sum_s part[s][i] in a fixed order: wave w of a block adds
+// splits w, w + SW, ... of 64 outputs, then the SW wave sums are added in
+// wave order.  j(i) = i, or with taps > 0 the canonical weight index of the
+// tap-major weight-gradient rows: i = (t cout + o) cin + c -> (o cin + c)
+// taps + t.
+constexpr int SW = 8;
+__global__ __launch_bounds__(64 * SW) void k_sum_splits(const float* __restrict__ part, int S, int64_t n,
+                                                        float* __restrict__ out, int taps, int cout,
+                                                        int cin) {
+  __shared__ float sh[SW][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
   float v = 0.0f;
-  for (int s = 0; s < S; ++s) v += part[(int64_t)s * n + i];
-  out[i] = v;
+  if (i < n)
+    for (int s = w; s < S; s += SW) v += part[(int64_t)s * n + i];
+  sh[w][lane] = v;
+  __syncthreads();
+  if (w != 0 || i >= n) return;
+  float t = 0.0f;
+#pragma unroll
+  for (int k = 0; k < SW; ++k) t += sh[k][lane];
+  int64_t j = i;
+  if (taps > 0) {
+    const int64_t oc = (int64_t)cout * cin;
+    const int64_t tap = i / oc, r = i - tap * oc;
+    j = r * taps + tap;  // r = o cin + c
+  }
+  out[j] = t;
+}
+
+// Backward of a 3 x 3, padding 1 convolution of a 2x nearest-neighbour
+// upsampled source (Hs x Ws -> Ho x Wo = 2Hs x 2Ws): the output (Y, X) reads
+// source row (Y + ky - 1) / 2, so source row sy receives, through tap ky, the
+// output rows 2sy + 1 - ky and 2sy + 2 - ky (those inside [0, Ho)), and
+// likewise for columns.  Hence, with the box sums
+//   D[t][o][b][sy][sx] = sum of dz[o][b][Y][X] over those 2 x 2 outputs,
+//   t = 3 ky + kx,
+// the input gradient is dsrc[c][s] = sum_{t, o} W[o][c][t] D[t][o][s] and the
+// weight gradient dW[o][c][t] = sum_s D[t][o][s] src[c][s] (s = (b, sy, sx)):
+// two GEMMs over the source grid, with no im2col or col2im pass and 4/9 of
+// the products of the upsampled grid.  One thread per (o, b, sy, sx) sums
+// the 4 x 4 outputs around it into all nine taps; D is bfloat16,
+// [9 cout][P4], P4 = batch Hs Ws.
+__global__ __launch_bounds__(EW) void k_dmap(const float* __restrict__ dz, int cout, int Bt, int Hs,
+                                             int Ws, bf16_t* __restrict__ D) {
+  const int pix = (int)(blockIdx.x * EW + threadIdx.x);
+  if (pix >= Hs * Ws) return;
+  const int o = blockIdx.y, b = blockIdx.z;
+  const int sy = pix / Ws, sx = pix - sy * Ws;
+  const int Ho = 2 * Hs, Wo = 2 * Ws;
+  const float* base = dz + ((int64_t)o * Bt + b) * Ho * Wo;
+  float v[4][4];  // rows 2sy - 1 .. 2sy + 2, columns 2sx - 1 .. 2sx + 2
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int Y = 2 * sy - 1 + i, X = 2 * sx - 1 + j;
+      v[i][j] = (Y >= 0 && Y < Ho && X >= 0 && X < Wo) ? base[Y * Wo + X] : 0.0f;
+    }
+  const int64_t P4 = (int64_t)Bt * Hs * Ws;
+  const int64_t s = (int64_t)b * Hs * Ws + pix;
+#pragma unroll
+  for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+    for (int kx = 0; kx < 3; ++kx) {
+      // tap ky takes rows i = 2 - ky, 3 - ky of the 4 x 4 block
+      const float d = (v[2 - ky][2 - kx] + v[2 - ky][3 - kx]) + (v[3 - ky][2 - kx] + v[3 - ky][3 - kx]);
+      D[((int64_t)(3 * ky + kx) * cout + o) * P4 + s] = to_bf16(d);
+    }
+}
+
+// pb[i] = bfloat16(p[i])
+__global__ __launch_bounds__(EW) void k_to_bf16(const float* __restrict__ p, int64_t n,
+                                                bf16_t* __restrict__ pb) {
+  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
+  if (i < n) pb[i] = to_bf16(p[i]);
 }
 
 // y is [3][b][hw] (channel-major), t is [b][3][hw]: dy = 2 (y - t) / n and
@@ -366,12 +489,11 @@ __global__ __launch_bounds__(EW) void k_to_nchw(const float* __restrict__ y, int
   out[i] = y[(c * Bt + b) * HW + hw];
 }
 
-// Adam with bias correction c1 = 1 - beta1^t, c2 = 1 - beta2^t; refreshes
-// the bfloat16 copy of the weights.
+// Adam with bias correction c1 = 1 - beta1^t, c2 = 1 - beta2^t (the
+// bfloat16 GEMM copies of the weights are refreshed by k_prep after it).
 __global__ __launch_bounds__(EW) void k_adam(float* __restrict__ p, const float* __restrict__ g,
                                              float* __restrict__ m, float* __restrict__ v, int64_t n,
-                                             float lr, float b1, float b2, float eps, float c1, float c2,
-                                             bf16_t* __restrict__ pb) {
+                                             float lr, float b1, float b2, float eps, float c1, float c2) {
   const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
   if (i >= n) return;
   const float gi = g[i];
@@ -379,15 +501,7 @@ __global__ __launch_bounds__(EW) void k_adam(float* __restrict__ p, const float*
   const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
   m[i] = mi;
   v[i] = vi;
-  const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-  p[i] = pi;
-  pb[i] = to_bf16(pi);
-}
-
-__global__ __launch_bounds__(EW) void k_to_bf16(const float* __restrict__ p, int64_t n,
-                                                bf16_t* __restrict__ pb) {
-  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
-  if (i < n) pb[i] = to_bf16(p[i]);
+  p[i] = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
 struct Layer {
@@ -395,7 +509,42 @@ struct Layer {
   int Hs, Ws;    // source size (before upsampling)
   int Ho, Wo;    // output size
   int64_t woff, boff;
+  // bfloat16 GEMM copies of the weights, rows padded to multiples of 8
+  // elements (16 bytes): wf[cout][Kp] (forward) and wt[K][coutp] (input
+  // gradient), at these element offsets of lbm_no::wf / lbm_no::wt
+  int Kp, coutp;
+  int64_t wf, wt;
+  // upsampling layers: wu[c][Kup] with wu[c][t cout + o] = W[o][c][t] (the
+  // input gradient's A operand over the tap-major box sums of k_dmap)
+  int Kup;
+  int64_t wu;
 };
+
+// Weight copies of the layers for the GEMMs (see Layer::wf, Layer::wt).
+constexpr int MAXL = 8;
+struct PrepT {
+  int64_t woff[MAXL], wf[MAXL], wt[MAXL], wu[MAXL];
+  int cout[MAXL], K[MAXL], Kp[MAXL], coutp[MAXL], Kup[MAXL], taps[MAXL];
+};
+
+// Block (x, layer y): weight i of the layer, rounded to bfloat16, into its
+// copies (their padding stays zero from create).
+__global__ __launch_bounds__(EW) void k_prep(const float* __restrict__ par, PrepT t,
+                                             bf16_t* __restrict__ wf, bf16_t* __restrict__ wt,
+                                             bf16_t* __restrict__ wu) {
+  const int l = blockIdx.y;
+  const int K = t.K[l];
+  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
+  if (i >= (int64_t)t.cout[l] * K) return;
+  const int o = (int)(i / K), k = (int)(i - (int64_t)o * K);
+  const bf16_t v = to_bf16(par[t.woff[l] + i]);
+  wf[t.wf[l] + (int64_t)o * t.Kp[l] + k] = v;
+  wt[t.wt[l] + (int64_t)k * t.coutp[l] + o] = v;
+  if (t.wu[l] >= 0) {  // k = c taps + tap
+    const int c = k / t.taps[l], tap = k - c * t.taps[l];
+    wu[t.wu[l] + (int64_t)c * t.Kup[l] + tap * t.cout[l] + o] = v;
+  }
+}
 
 unsigned grid1(int64_t n) { return (unsigned)((n + EW - 1) / EW); }
 
@@ -409,7 +558,8 @@ struct lbm_no {
   hipStream_t stream = nullptr;
   std::vector<void*> allocs;
   float *par = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
-  bf16_t* parb = nullptr;
+  bf16_t *wf = nullptr, *wt = nullptr, *wu = nullptr;  // bfloat16 GEMM copies of the weights (Layer)
+  int64_t wf_n = 0, wt_n = 0, wu_n = 0, wmax = 0;      // their sizes; the largest layer's weight count
   std::vector<float*> z, a, da;  // per layer, [cout][B][Ho][Wo]
   bf16_t* col = nullptr;
   bf16_t* dz16 = nullptr;  // bfloat16 copy of the current layer's dz
@@ -427,14 +577,17 @@ namespace {
 // Weight-gradient GEMMs reduce over p = (batch, y, x), hundreds of thousands
 // long, into outputs of at most a few hundred x a few thousand: the
 // reduction is split so that every layer launches about SPLIT_BLOCKS blocks
-// (256 compute units), each split a multiple of BK long; the partial sums are
-// added in split order.
+// (256 compute units), each split a multiple of GBK long; the partial sums
+// are added in split order.
 constexpr int SPLIT_BLOCKS = 512;
+// GEMM block shape: 64 x 256 outputs for M <= 64 (wm = 1), else 128 x 128.
+int gemm_wm(int64_t M) { return M <= 64 ? 1 : 2; }
 void wgrad_split(int64_t M, int64_t N, int64_t P, int& S, int64_t& kchunk) {
-  const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  const int64_t bm = 64 * gemm_wm(M), bn = 256 / gemm_wm(M);
+  const int64_t tiles = ((M + bm - 1) / bm) * ((N + bn - 1) / bn);
   int64_t s = std::max<int64_t>(1, (SPLIT_BLOCKS + tiles - 1) / tiles);
-  s = std::min<int64_t>(s, (P + BK - 1) / BK);
-  kchunk = ((P + s - 1) / s + BK - 1) / BK * BK;
+  s = std::min<int64_t>(s, (P + GBK - 1) / GBK);
+  kchunk = ((P + s - 1) / s + GBK - 1) / GBK * GBK;
   S = (int)((P + kchunk - 1) / kchunk);
 }
 
@@ -454,7 +607,7 @@ void specs(const int* w, int H, int W, std::vector<Layer>& L, int64_t& npar) {
   npar = 0;
   int h = H, ww = W;
   for (auto& d : def) {
-    Layer l{d[0], d[1], d[2], d[3], d[4], d[5], d[6], h, ww, 0, 0, 0, 0};
+    Layer l{d[0], d[1], d[2], d[3], d[4], d[5], d[6], h, ww, 0, 0, 0, 0, 0, 0, 0, 0, 0, -1};
     const int he = l.up ? 2 * h : h, we = l.up ? 2 * ww : ww;
     const int pad = (l.k - 1) / 2;
     l.Ho = (he + 2 * pad - l.k) / l.s + 1;
@@ -469,17 +622,45 @@ void specs(const int* w, int H, int W, std::vector<Layer>& L, int64_t& npar) {
   }
 }
 
-template <bool AK, bool BKC>
+// C = A B (see k_gemm); A k-contiguous with leading dimension lda >= K.
+template <bool BKC>
 int gemm(lbm_no* h, int M, int N, int K, const bf16_t* A, int64_t lda, const bf16_t* B, int64_t ldb,
-         float* C, int64_t ldc, int64_t cz, int splits, int kchunk, const float* bias) {
+         float* C, int64_t ldc, int64_t cz, int splits, int kchunk, const float* bias, int accumulate = 0) {
   if (M <= 0 || N <= 0 || K <= 0) return LBM_NO_OK;
-  // operands move as bf16 pairs along their contiguous index: that extent,
-  // the leading dimensions and the split length must be even
-  const bool odd = ((lda | ldb | kchunk) & 1) || ((AK || BKC) && (K & 1)) || (!AK && (M & 1)) ||
-                   (!BKC && (N & 1));
-  if (odd) return fail(LBM_NO_EINVAL, "GEMM extents along paired indices must be even");
-  const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)splits);
-  k_gemm<AK, BKC><<<grid, NT, 0, h->stream>>>(M, N, K, A, lda, B, ldb, C, ldc, cz, kchunk, bias);
+  if (lda < K || (BKC ? ldb < K : ldb < N) || kchunk < 1 || (splits > 1 && kchunk % GBK))
+    return fail(LBM_NO_EINVAL, "GEMM operand shapes");
+  auto aligned = [](const void* p, int64_t ld) { return ((uintptr_t)p & 15) == 0 && ld % 8 == 0; };
+  const int vecA = aligned(A, lda) && kchunk % 8 == 0, vecB = aligned(B, ldb) && (!BKC || kchunk % 8 == 0);
+  const int wm = gemm_wm(M), bm = 64 * wm, bn = 256 / wm;
+  const dim3 grid((unsigned)((N + bn - 1) / bn), (unsigned)((M + bm - 1) / bm), (unsigned)splits);
+  if (wm == 1)
+    k_gemm<BKC, 1><<<grid, NT, 0, h->stream>>>(M, N, K, A, lda, vecA, B, ldb, vecB, C, ldc, cz, kchunk, bias,
+                                               accumulate);
+  else
+    k_gemm<BKC, 2><<<grid, NT, 0, h->stream>>>(M, N, K, A, lda, vecA, B, ldb, vecB, C, ldc, cz, kchunk, bias,
+                                               accumulate);
+  NOCHK(hipGetLastError());
+  return LBM_NO_OK;
+}
+
+// Both bfloat16 GEMM copies of every layer's weights from the FP32 master.
+int prep_weights(lbm_no* h) {
+  PrepT t{};
+  const int nl = (int)h->L.size();
+  for (int l = 0; l < nl; ++l) {
+    const Layer& y = h->L[l];
+    t.woff[l] = y.woff;
+    t.wf[l] = y.wf;
+    t.wt[l] = y.wt;
+    t.cout[l] = y.cout;
+    t.K[l] = y.cin * y.k * y.k;
+    t.Kp[l] = y.Kp;
+    t.coutp[l] = y.coutp;
+    t.wu[l] = y.wu;
+    t.Kup[l] = y.Kup;
+    t.taps[l] = y.k * y.k;
+  }
+  k_prep<<<dim3(grid1(h->wmax), (unsigned)nl), EW, 0, h->stream>>>(h->par, t, h->wf, h->wt, h->wu);
   NOCHK(hipGetLastError());
   return LBM_NO_OK;
 }
@@ -503,8 +684,8 @@ int forward_internal(lbm_no* h, const float* x, int Bt) {
     int rc = im2col(h, l, li == 0 ? x : h->a[li - 1], li == 0, Bt);
     if (rc) return rc;
     // z[o][p] = W[o][k] col[k][p]: A k-contiguous, B n-contiguous
-    rc = gemm<true, false>(h, l.cout, (int)P, K, h->parb + l.woff, K, h->col, P, h->z[li], P, 0, 1,
-                           K, h->par + l.boff);
+    rc = gemm<false>(h, l.cout, (int)P, K, h->wf + l.wf, l.Kp, h->col, P, h->z[li], P, 0, 1, K,
+                     h->par + l.boff);
     if (rc) return rc;
     const int64_t n = (int64_t)l.cout * P;
     k_act<<<grid1(n), EW, 0, h->stream>>>(h->z[li], l.skip >= 0 ? h->a[l.skip] : nullptr, h->a[li], n, l.relu);
@@ -583,10 +764,32 @@ int lbm_no_create(const int32_t* widths, int32_t height, int32_t width, int32_t 
     h->grad = (float*)nalloc(h, np * 4);
     h->m = (float*)nalloc(h, np * 4);
     h->v = (float*)nalloc(h, np * 4);
-    h->parb = (bf16_t*)nalloc(h, np * 2);
-    if (!h->par || !h->grad || !h->m || !h->v || !h->parb) return bail(fail(LBM_NO_ENOMEM, "parameters"));
-    int64_t colmax = 0, splitmax = 0, actmax = 0, bpmax = 0;
-    for (const Layer& l : h->L) {
+    for (Layer& l : h->L) {
+      const int K = l.cin * l.k * l.k;
+      l.Kp = (K + 7) / 8 * 8;
+      l.coutp = (l.cout + 7) / 8 * 8;
+      l.wf = h->wf_n;
+      l.wt = h->wt_n;
+      h->wf_n += (int64_t)l.cout * l.Kp;
+      h->wt_n += (int64_t)K * l.coutp;
+      h->wmax = std::max(h->wmax, (int64_t)l.cout * K);
+      if (l.up) {
+        l.Kup = (l.k * l.k * l.cout + 7) / 8 * 8;
+        l.wu = h->wu_n;
+        h->wu_n += (int64_t)l.cin * l.Kup;
+      }
+    }
+    h->wf = (bf16_t*)nalloc(h, (size_t)h->wf_n * 2);
+    h->wt = (bf16_t*)nalloc(h, (size_t)h->wt_n * 2);
+    h->wu = (bf16_t*)nalloc(h, (size_t)h->wu_n * 2);
+    if (!h->par || !h->grad || !h->m || !h->v || !h->wf || !h->wt || !h->wu)
+      return bail(fail(LBM_NO_ENOMEM, "parameters"));
+    NOCHK(hipMemsetAsync(h->wf, 0, (size_t)h->wf_n * 2, h->stream));  // row padding stays zero
+    NOCHK(hipMemsetAsync(h->wt, 0, (size_t)h->wt_n * 2, h->stream));
+    NOCHK(hipMemsetAsync(h->wu, 0, (size_t)h->wu_n * 2, h->stream));
+    int64_t colmax = 0, dcolmax = 0, splitmax = 0, actmax = 0, bpmax = 0;
+    for (size_t li = 0; li < h->L.size(); ++li) {
+      const Layer& l = h->L[li];
       const int64_t P = (int64_t)max_batch * l.Ho * l.Wo;
       const size_t n = (size_t)l.cout * P * 4;
       actmax = std::max(actmax, (int64_t)l.cout * P);
@@ -599,14 +802,21 @@ int lbm_no_create(const int32_t* widths, int32_t height, int32_t width, int32_t 
       h->da.push_back(dl);
       const int64_t K = (int64_t)l.cin * l.k * l.k;
       colmax = std::max(colmax, K * P);
+      if (li > 0 && !l.up && !(l.k == 1 && l.s == 1)) dcolmax = std::max(dcolmax, K * P);  // col2im layers
       int S;
       int64_t kchunk;
       wgrad_split(l.cout, K, P, S, kchunk);
       splitmax = std::max(splitmax, (int64_t)S * l.cout * K);
+      if (l.up) {  // box sums in col, split partials of the tap-major weight gradient
+        const int64_t P4 = (int64_t)max_batch * l.Hs * l.Ws;
+        colmax = std::max(colmax, 9 * l.cout * P4);
+        wgrad_split(9 * l.cout, l.cin, P4, S, kchunk);
+        splitmax = std::max(splitmax, (int64_t)S * 9 * l.cout * l.cin);
+      }
       bpmax = std::max(bpmax, (int64_t)l.cout * ((P + ACT_CHUNK - 1) / ACT_CHUNK));
     }
     h->col = (bf16_t*)nalloc(h, (size_t)colmax * 2);
-    h->dcol = (float*)nalloc(h, (size_t)colmax * 4);
+    h->dcol = (float*)nalloc(h, (size_t)dcolmax * 4);
     h->dz16 = (bf16_t*)nalloc(h, (size_t)actmax * 2);
     h->split = (float*)nalloc(h, (size_t)splitmax * 4);
     h->split_n = splitmax;
@@ -631,8 +841,8 @@ int lbm_no_set_params(lbm_no* h, const float* params) {
     NOCHK(hipMemsetAsync(h->m, 0, np * 4, h->stream));
     NOCHK(hipMemsetAsync(h->v, 0, np * 4, h->stream));
     NOCHK(hipMemsetAsync(h->grad, 0, np * 4, h->stream));
-    k_to_bf16<<<grid1(h->npar), EW, 0, h->stream>>>(h->par, h->npar, h->parb);
-    NOCHK(hipGetLastError());
+    const int rc = prep_weights(h);
+    if (rc) return rc;
     NOCHK(hipStreamSynchronize(h->stream));
     h->adam_t = 0;
     return LBM_NO_OK;
@@ -685,26 +895,64 @@ int lbm_no_gradients(lbm_no* h, const float* x, const float* target, int32_t bat
         NOCHK(hipGetLastError());
         have[l.skip] = 1;
       }
+      int S;
+      int64_t kchunk;
+      if (l.up) {
+        // 3 x 3 convolution of an upsampled source (li > 0): both gradients
+        // over the source grid from the box sums D = k_dmap(dz) (in col)
+        const int64_t P4 = (int64_t)batch * l.Hs * l.Ws;
+        const int M9 = 9 * l.cout;
+        k_dmap<<<dim3(grid1((int64_t)l.Hs * l.Ws), (unsigned)l.cout, (unsigned)batch), EW, 0, h->stream>>>(
+            h->z[li], l.cout, batch, l.Hs, l.Ws, h->col);
+        NOCHK(hipGetLastError());
+        // the source in bfloat16 (over dz16, which this path does not read)
+        k_to_bf16<<<grid1(l.cin * P4), EW, 0, h->stream>>>(h->a[li - 1], l.cin * P4, h->dz16);
+        NOCHK(hipGetLastError());
+        // dW[o][c][t] = sum_s D[t cout + o][s] src[c][s]: A = D, B k(=s)-contiguous
+        wgrad_split(M9, l.cin, P4, S, kchunk);
+        const int64_t mn = (int64_t)M9 * l.cin;
+        if ((int64_t)S * mn > h->split_n) return fail(LBM_NO_EINVAL, "split work space too small");
+        rc = gemm<true>(h, M9, l.cin, (int)P4, h->col, P4, h->dz16, P4, h->split, l.cin, mn, S, (int)kchunk,
+                        nullptr);
+        if (rc) return rc;
+        k_sum_splits<<<(unsigned)((mn + 63) / 64), 64 * SW, 0, h->stream>>>(h->split, S, mn, h->grad + l.woff, 9,
+                                                                         l.cout, l.cin);
+        NOCHK(hipGetLastError());
+        k_bias_grad<<<(unsigned)l.cout, EW, 0, h->stream>>>(h->bpart, (int)nchunk, h->grad + l.boff);
+        NOCHK(hipGetLastError());
+        // da[li - 1][c][s] (+)= sum_{t, o} W[o][c][t] D[t cout + o][s]: A = wu, B = D n(=s)-contiguous
+        rc = gemm<false>(h, l.cin, (int)P4, M9, h->wu + l.wu, l.Kup, h->col, P4, h->da[li - 1], P4, 0, 1, M9,
+                         nullptr, have[li - 1]);
+        if (rc) return rc;
+        have[li - 1] = 1;
+        continue;
+      }
       rc = im2col(h, l, li == 0 ? x : h->a[li - 1], li == 0, batch);
       if (rc) return rc;
       // weight gradient, split over p, partials summed in order
-      int S;
-      int64_t kchunk;
       wgrad_split(l.cout, K, P, S, kchunk);
       const int64_t mn = (int64_t)l.cout * K;
       if ((int64_t)S * mn > h->split_n) return fail(LBM_NO_EINVAL, "split work space too small");
       // dW[o][k] = dz[o][p] col[k][p]: A k(=p)-contiguous, B k(=p)-contiguous
-      rc = gemm<true, true>(h, l.cout, K, (int)P, h->dz16, P, h->col, P, h->split, K, mn, S, (int)kchunk, nullptr);
+      rc = gemm<true>(h, l.cout, K, (int)P, h->dz16, P, h->col, P, h->split, K, mn, S, (int)kchunk, nullptr);
       if (rc) return rc;
-      k_sum_splits<<<grid1(mn), EW, 0, h->stream>>>(h->split, S, mn, h->grad + l.woff);
+      k_sum_splits<<<(unsigned)((mn + 63) / 64), 64 * SW, 0, h->stream>>>(h->split, S, mn, h->grad + l.woff, 0, 0,
+                                                                       0);
       NOCHK(hipGetLastError());
       k_bias_grad<<<(unsigned)l.cout, EW, 0, h->stream>>>(h->bpart, (int)nchunk, h->grad + l.boff);
       NOCHK(hipGetLastError());
       if (li == 0) break;  // no gradient with respect to the input
+      if (l.k == 1 && l.s == 1) {  // 1 x 1: the input gradient is the GEMM itself
+        rc = gemm<false>(h, K, (int)P, l.cout, h->wt + l.wt, l.coutp, h->dz16, P, h->da[li - 1], P, 0, 1, l.cout,
+                         nullptr, have[li - 1]);
+        if (rc) return rc;
+        have[li - 1] = 1;
+        continue;
+      }
       // input gradient: dcol = W^T dz, then the col2im gather into da[li - 1]
-      // dcol[k][p] = W[o][k] dz[o][p]: A m(=k)-contiguous, B n(=p)-contiguous
-      rc = gemm<false, false>(h, K, (int)P, l.cout, h->parb + l.woff, K, h->dz16, P, h->dcol, P, 0, 1,
-                              l.cout + (l.cout & 1), nullptr);  // one split covering all of cout
+      // dcol[k][p] = W[o][k] dz[o][p]: A = the transposed weight copy wt[k][o], B n(=p)-contiguous
+      rc = gemm<false>(h, K, (int)P, l.cout, h->wt + l.wt, l.coutp, h->dz16, P, h->dcol, P, 0, 1, l.cout,
+                       nullptr);
       if (rc) return rc;
       const dim3 g2(grid1((int64_t)l.Hs * l.Ws), (unsigned)l.cin, (unsigned)batch);
       k_col2im<<<g2, EW, 0, h->stream>>>(h->dcol, l.cin, batch, l.Hs, l.Ws, l.up, l.k, l.s, (l.k - 1) / 2,
@@ -728,9 +976,9 @@ int lbm_no_adam(lbm_no* h, float lr, float beta1, float beta2, float eps) {
     const float c1 = (float)(1.0 - std::pow((double)beta1, (double)h->adam_t));
     const float c2 = (float)(1.0 - std::pow((double)beta2, (double)h->adam_t));
     k_adam<<<grid1(h->npar), EW, 0, h->stream>>>(h->par, h->grad, h->m, h->v, h->npar, lr, beta1, beta2, eps, c1,
-                                                 c2, h->parb);
+                                                 c2);
     NOCHK(hipGetLastError());
-    return LBM_NO_OK;
+    return prep_weights(h);
   });
 }
 
