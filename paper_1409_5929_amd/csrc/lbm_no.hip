@@ -1,15 +1,22 @@
 // Warm-start network of the lattice Boltzmann solver: forward pass, loss,
 // backward pass and Adam on gfx950 (layer definitions in include/lbm_no.h).
 //
-// Every convolution is an im2col gather followed by one GEMM on MFMA
-// (v_mfma_f32_16x16x16_bf16: bfloat16 operands, FP32 accumulation):
-//   forward          z[o][p]   = sum_k W[o][k] col[k][p] + b[o]
-//   input gradient   dcol[k][p] = sum_o W[o][k] dz[o][p], then a col2im gather
-//   weight gradient  dW[o][k]  = sum_p dz[o][p] col[k][p] (split over p)
-// with k = (cin, ky, kx) and p = (batch, y, x).  Activations are kept
-// channel-major, [C][batch][H][W], so each GEMM output is the next layer's
-// input without a transpose.  Reductions (bias gradients, split partials,
-// loss) run in a fixed order, so results do not depend on scheduling.
+// Every convolution runs as GEMMs on MFMA (v_mfma_f32_16x16x32_bf16:
+// bfloat16 operands, FP32 accumulation), with k = (cin, ky, kx) and p =
+// (batch, y, x):
+//   forward          z[o][p]  = sum_k W[o][k] col[k][p] + b[o] (im2col),
+//                    for upsampling layers four phase GEMMs over the source
+//                    grid (forward_up)
+//   weight gradient  dW[o][k] = sum_p dz[o][p] col[k][p] (split over p),
+//                    for upsampling layers over 2 x 2 box sums of dz (k_dmap)
+//   input gradient   upsampling layers: a GEMM over the same box sums;
+//                    stride-2 layers: four phase GEMMs over a shifted stack
+//                    of dz (k_emap); 1 x 1 layers: one GEMM
+// so no gradient is scattered back through an im2col (no col2im pass).
+// Activations are kept channel-major, [C][batch][H][W], so each GEMM output
+// is the next layer's input without a transpose.  Reductions (bias
+// gradients, split partials, loss) run in a fixed order, so results do not
+// depend on scheduling.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -82,24 +89,37 @@ __device__ inline uint32_t word(const uint4& v, int d) { return d == 0 ? v.x : d
 // block around in registers and writes eight 8-byte rows).  The next stage's
 // operands are loaded into registers while the current one is multiplied.
 // accumulate: C += instead of C =.
+// PH: four phase GEMMs of a stride-2 grid relation (grid z = phase q, py =
+// q / 2, px = q % 2, no split): A + ph.aoff[q], reduction length ph.K[q], B
+// row k taken from row ph.base[q] + k (+ ph.gap[q] once k >= ph.run[q]), and
+// column n = (b, y, x) of an Hn x Wn grid written to (b, 2y + py, 2x + px) of
+// the 2Hn x 2Wn grid (row m of C at C + m ldc); bias in every phase.
 // vecA / vecB: rows 16-byte aligned (leading dimension a multiple of 8,
 // aligned base, kchunk a multiple of 8), so whole 8-element chunks move as
 // one 16-byte load; otherwise element by element.  Zero outside the
 // matrices.
-template <bool BKC, int WM>
+struct PhaseT {
+  int64_t aoff[4];
+  int K[4], base[4], run[4], gap[4];
+  int Hn, Wn;
+};
+template <bool BKC, int WM, bool PH>
 __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, const bf16_t* __restrict__ A,
                                              int64_t lda, int vecA, const bf16_t* __restrict__ B,
                                              int64_t ldb, int vecB, float* __restrict__ C, int64_t ldc,
                                              int64_t cz, int kchunk, const float* __restrict__ bias,
-                                             int accumulate) {
+                                             int accumulate, PhaseT ph) {
+  static_assert(!(PH && BKC), "phase GEMMs take an n-contiguous B");
   constexpr int WN = 4 / WM, TBM = 64 * WM, TBN = 64 * WN;
   constexpr int NA = TBM * GBK / 8 / NT;   // 16-byte A chunks per thread and stage
   constexpr int NB = TBN * GBK / 8 / NT;   // 16-byte B chunks per thread and stage
   __shared__ __attribute__((aligned(16))) bf16_t As[TBM * GLD];
   __shared__ __attribute__((aligned(16))) bf16_t Bs[TBN * GLD];
   const int m0 = blockIdx.y * TBM, n0 = blockIdx.x * TBN;
-  const int kb = blockIdx.z * kchunk;
-  const int ke = min(K, kb + kchunk);
+  const int q = PH ? (int)blockIdx.z : 0;
+  const int kb = PH ? 0 : (int)blockIdx.z * kchunk;
+  const int ke = PH ? ph.K[q] : min(K, kb + kchunk);
+  if (PH) A += ph.aoff[q];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / WN) * 64, wn = (wave % WN) * 64;
   v4f acc[4][4];
@@ -125,9 +145,10 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, const bf16_t* 
       for (int it = 0; it < NB / 4; ++it) {
         const int e = tid + it * NT, kq = (e & 15) << 2, n8 = (e >> 4) << 3;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int gk = k0 + kq + q;
-          rb[4 * it + q] = gk < ke ? load8(B + (int64_t)gk * ldb, n0 + n8, N, vecB) : make_uint4(0u, 0u, 0u, 0u);
+        for (int r = 0; r < 4; ++r) {
+          const int gk = k0 + kq + r;
+          const int gr = PH ? ph.base[q] + gk + (gk >= ph.run[q] ? ph.gap[q] : 0) : gk;
+          rb[4 * it + r] = gk < ke ? load8(B + (int64_t)gr * ldb, n0 + n8, N, vecB) : make_uint4(0u, 0u, 0u, 0u);
         }
       }
     }
@@ -182,35 +203,47 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, const bf16_t* 
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
   }
-  float* Cz = C + (int64_t)blockIdx.z * cz;
-  // result layout of a 16 x 16 tile: lane holds column lane % 16, rows 4 (lane / 16) + q
+  float* Cz = C + (PH ? 0 : (int64_t)blockIdx.z * cz);
+  int64_t cof[4];  // column offsets in a row of C
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int gn = n0 + wn + j * 16 + (lane & 15);
+    cof[j] = gn;
+    if (PH && gn < N) {
+      const int hw = ph.Hn * ph.Wn;
+      const int b = gn / hw, r = gn - b * hw, y = r / ph.Wn, x = r - y * ph.Wn;
+      cof[j] = ((int64_t)b * 2 * ph.Hn + 2 * y + (q >> 1)) * (2 * ph.Wn) + 2 * x + (q & 1);
+    }
+  }
+  // result layout of a 16 x 16 tile: lane holds column lane % 16, rows 4 (lane / 16) + r
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int gm = m0 + wm + i * 16 + 4 * (lane >> 4) + q;
+    for (int r = 0; r < 4; ++r) {
+      const int gm = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
       if (gm >= M) continue;
-      const float bv = (bias && blockIdx.z == 0) ? bias[gm] : 0.0f;
+      const float bv = (bias && (PH || blockIdx.z == 0)) ? bias[gm] : 0.0f;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int gn = n0 + wn + j * 16 + (lane & 15);
         if (gn < N) {
-          float* c = Cz + (int64_t)gm * ldc + gn;
-          *c = (accumulate ? *c : 0.0f) + (acc[i][j][q] + bv);
+          float* c = Cz + (int64_t)gm * ldc + cof[j];
+          *c = (accumulate ? *c : 0.0f) + (acc[i][j][r] + bv);
         }
       }
     }
 }
 
-// col[kidx][p] for kidx = (c, ky, kx), p = (b, oy, ox): the input value under
-// tap (ky, kx) of output (oy, ox), zero outside; with up, the input is the
+// col[kidx][p] for kidx = (c, ky, kx) (TM: kidx = (ky, kx, c), tap-major), p
+// = (b, oy, ox): the input value under tap (ky, kx) of output (oy, ox), zero
+// outside; with up, the input is the
 // 2x nearest-neighbour upsampling of x.  x is [b][c][y][x] (nchw) or
 // [c][b][y][x].  Grid: y = input channel c, x over pairs of p; each thread
 // writes the k^2 rows of its channel for two outputs, each as one 4-byte word
 // when P is even (2-byte stores would bind the kernel on store instructions),
 // so the input of a channel is read once per pass, not once per tap.  P =
 // batch Ho Wo < 2^31 (create checks it): 32-bit index arithmetic.
-template <bool NCHW>
+template <bool NCHW, bool TM>
 __global__ __launch_bounds__(EW) void k_im2col(const float* __restrict__ x, int C, int Bt, int H,
                                                int W, int up, int k, int s, int pad, int Ho,
                                                int Wo, bf16_t* __restrict__ col) {
@@ -239,7 +272,8 @@ __global__ __launch_bounds__(EW) void k_im2col(const float* __restrict__ x, int 
   };
   for (int ky = 0; ky < k; ++ky)
     for (int kx = 0; kx < k; ++kx) {
-      bf16_t* dst = col + (int64_t)((c * k + ky) * k + kx) * P + p0;
+      const int row = TM ? (ky * k + kx) * C + c : (c * k + ky) * k + kx;
+      bf16_t* dst = col + (int64_t)row * P + p0;
       if ((P & 1) == 0) {
         *(uint32_t*)dst = (uint32_t)to_bf16(value(0, ky, kx)) | ((uint32_t)to_bf16(value(1, ky, kx)) << 16);
       } else {
@@ -247,43 +281,6 @@ __global__ __launch_bounds__(EW) void k_im2col(const float* __restrict__ x, int 
         if (two) dst[1] = to_bf16(value(1, ky, kx));
       }
     }
-}
-
-// Adjoint of k_im2col (channel-major x): dx[c][b][y][x] (+)= sum of the dcol
-// entries that read x[c][b][y][x], gathered (no atomics), taps in a fixed
-// order.  Grid: y = c, z = b, x over the H W pixels (32-bit index
-// arithmetic); strides 1 or 2.
-__global__ __launch_bounds__(EW) void k_col2im(const float* __restrict__ dcol, int C, int Bt, int H,
-                                               int W, int up, int k, int s, int pad, int Ho,
-                                               int Wo, float* __restrict__ dx, int accumulate) {
-  const int pix = (int)(blockIdx.x * EW + threadIdx.x);
-  if (pix >= H * W) return;
-  const int c = blockIdx.y, b = blockIdx.z;
-  const int sy = pix / W, sx = pix - sy * W;
-  const int64_t P = (int64_t)Bt * Ho * Wo;
-  const int sh = s == 2 ? 1 : 0;
-  const int nu = up ? 2 : 1;
-  const float* base = dcol + (int64_t)b * Ho * Wo;
-  float acc = 0.0f;
-  for (int uy = 0; uy < nu; ++uy)
-    for (int ux = 0; ux < nu; ++ux) {
-      const int iy = up ? 2 * sy + uy : sy, ix = up ? 2 * sx + ux : sx;
-      for (int ky = 0; ky < k; ++ky) {
-        const int ty = iy + pad - ky;
-        if (ty < 0 || (ty & (s - 1))) continue;
-        const int oy = ty >> sh;
-        if (oy >= Ho) continue;
-        for (int kx = 0; kx < k; ++kx) {
-          const int tx = ix + pad - kx;
-          if (tx < 0 || (tx & (s - 1))) continue;
-          const int ox = tx >> sh;
-          if (ox >= Wo) continue;
-          acc += base[(int64_t)((c * k + ky) * k + kx) * P + oy * Wo + ox];
-        }
-      }
-    }
-  const int64_t i = (((int64_t)c * Bt + b) * H + sy) * W + sx;
-  dx[i] = accumulate ? dx[i] + acc : acc;
 }
 
 __device__ inline float block_sum(float v, float* sh) {
@@ -428,6 +425,28 @@ __global__ __launch_bounds__(EW) void k_dmap(const float* __restrict__ dz, int c
     }
 }
 
+// Input gradient of a 3 x 3, stride-2, padding-1 convolution (input 2Ho x
+// 2Wo, output Ho x Wo): input (2y + a, 2x + b) receives output rows y + ey,
+// ey in {0, 1}, and columns x + ex, so one stack of dz shifted by (ey, ex),
+//   E[(2 ey + ex) cout + o][b][y][x] = dz[o][b][y + ey][x + ex] (0 outside),
+// bfloat16, [4 cout][P], P = batch Ho Wo, serves all four phase GEMMs.
+__global__ __launch_bounds__(EW) void k_emap(const float* __restrict__ dz, int cout, int Bt, int Ho,
+                                             int Wo, bf16_t* __restrict__ E) {
+  const int pix = (int)(blockIdx.x * EW + threadIdx.x);
+  if (pix >= Ho * Wo) return;
+  const int o = blockIdx.y, b = blockIdx.z;
+  const int y = pix / Wo, x = pix - y * Wo;
+  const float* base = dz + ((int64_t)o * Bt + b) * Ho * Wo;
+  const int64_t P = (int64_t)Bt * Ho * Wo, s = (int64_t)b * Ho * Wo + pix;
+#pragma unroll
+  for (int ey = 0; ey < 2; ++ey)
+#pragma unroll
+    for (int ex = 0; ex < 2; ++ex) {
+      const float v = (y + ey < Ho && x + ex < Wo) ? base[(y + ey) * Wo + x + ex] : 0.0f;
+      E[((int64_t)(2 * ey + ex) * cout + o) * P + s] = to_bf16(v);
+    }
+}
+
 // pb[i] = bfloat16(p[i])
 __global__ __launch_bounds__(EW) void k_to_bf16(const float* __restrict__ p, int64_t n,
                                                 bf16_t* __restrict__ pb) {
@@ -518,24 +537,70 @@ struct Layer {
   // input gradient's A operand over the tap-major box sums of k_dmap)
   int Kup;
   int64_t wu;
+  // phase GEMM weights (k_gemm PH), four phases of rows of Kph elements at
+  // wph: upsampling layers' forward (cout rows, k = (u, v, c)) and stride-2
+  // layers' input gradient (cin rows, k = (ey, ex, o)); see k_prep
+  int Kph;
+  int64_t wph;
 };
 
 // Weight copies of the layers for the GEMMs (see Layer::wf, Layer::wt).
 constexpr int MAXL = 8;
 struct PrepT {
-  int64_t woff[MAXL], wf[MAXL], wt[MAXL], wu[MAXL];
-  int cout[MAXL], K[MAXL], Kp[MAXL], coutp[MAXL], Kup[MAXL], taps[MAXL];
+  int64_t woff[MAXL], wf[MAXL], wt[MAXL], wu[MAXL], wph[MAXL];
+  int cout[MAXL], cin[MAXL], K[MAXL], Kp[MAXL], coutp[MAXL], Kup[MAXL], taps[MAXL], Kph[MAXL];
+  int kind[MAXL];  // 0 plain, 1 upsampling, 2 stride 2
 };
 
+// Phase weights of entry j of the four phases q = (a, b) (rows of Kph; the
+// row padding stays zero from create).
+// Upsampling layer: output (2y + a, 2x + b) reads source rows y + dy with dy
+// = floor((a + ky - 1) / 2), i.e. y + a - 1 + u for u in {0, 1}, and likewise
+// for columns, so its weights are the sums Weff[o][(u, v, c)] of the W[o][c]
+// [ky][kx] that land on (u, v).
+// Stride-2 layer, input gradient at (2y + a, 2x + b): the taps with ky = 1
+// (a = 0), or ky = 2 and ky = 0 (a = 1), reach output rows y and y + 1 (ey
+// = 0, 1), likewise for columns: Wd[c][(ey nx + ex) cout + o] = W[o][c][ky]
+// [kx], nx = 1 + b.
+__device__ inline void prep_phase(const float* __restrict__ W, const PrepT& t, int l, int64_t j,
+                                  bf16_t* __restrict__ wph) {
+  const int cin = t.cin[l], cout = t.cout[l], Kph = t.Kph[l];
+  const int64_t per = 4 * (int64_t)cin * cout;
+  const int q = (int)(j / per), a = q >> 1, b = q & 1;
+  const int r = (int)(j - q * per);
+  if (t.kind[l] == 1) {
+    const int o = r / (4 * cin), kk = r - o * 4 * cin;
+    const int u = kk / (2 * cin), v = (kk / cin) & 1, c = kk % cin;
+    float sum = 0.0f;
+    for (int ky = 0; ky < 3; ++ky)
+      for (int kx = 0; kx < 3; ++kx)
+        if (((a + ky + 1) >> 1) - 1 == a - 1 + u && ((b + kx + 1) >> 1) - 1 == b - 1 + v)
+          sum += W[((int64_t)o * cin + c) * 9 + ky * 3 + kx];
+    wph[t.wph[l] + ((int64_t)q * cout + o) * Kph + kk] = to_bf16(sum);
+  } else {
+    const int c = r / (4 * cout), kk = r - c * 4 * cout;
+    const int nx = 1 + b;
+    if (kk >= (1 + a) * nx * cout) return;
+    const int e = kk / cout, o = kk - e * cout, ey = e / nx, ex = e - ey * nx;
+    const int ky = a == 0 ? 1 : (ey == 0 ? 2 : 0), kx = b == 0 ? 1 : (ex == 0 ? 2 : 0);
+    wph[t.wph[l] + ((int64_t)q * cin + c) * Kph + kk] = to_bf16(W[((int64_t)o * cin + c) * 9 + ky * 3 + kx]);
+  }
+}
+
 // Block (x, layer y): weight i of the layer, rounded to bfloat16, into its
-// copies (their padding stays zero from create).
+// copies (their padding stays zero from create), then the layer's phase
+// weights (prep_phase) for i beyond the weight count.
 __global__ __launch_bounds__(EW) void k_prep(const float* __restrict__ par, PrepT t,
                                              bf16_t* __restrict__ wf, bf16_t* __restrict__ wt,
-                                             bf16_t* __restrict__ wu) {
+                                             bf16_t* __restrict__ wu, bf16_t* __restrict__ wph) {
   const int l = blockIdx.y;
   const int K = t.K[l];
   const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
-  if (i >= (int64_t)t.cout[l] * K) return;
+  const int64_t nw = (int64_t)t.cout[l] * K;
+  if (i >= nw) {
+    if (t.kind[l] != 0 && i < nw + 16 * (int64_t)t.cin[l] * t.cout[l]) prep_phase(par + t.woff[l], t, l, i - nw, wph);
+    return;
+  }
   const int o = (int)(i / K), k = (int)(i - (int64_t)o * K);
   const bf16_t v = to_bf16(par[t.woff[l] + i]);
   wf[t.wf[l] + (int64_t)o * t.Kp[l] + k] = v;
@@ -548,6 +613,11 @@ __global__ __launch_bounds__(EW) void k_prep(const float* __restrict__ par, Prep
 
 unsigned grid1(int64_t n) { return (unsigned)((n + EW - 1) / EW); }
 
+// Layers whose convolution runs as phase GEMMs: 1 the forward of a 3 x 3
+// convolution of an upsampled source, 2 the input gradient of a 3 x 3
+// stride-2 convolution.
+int phase_kind(const Layer& l) { return l.k == 3 ? (l.up ? 1 : (l.s == 2 ? 2 : 0)) : 0; }
+
 }  // namespace
 
 struct lbm_no {
@@ -558,12 +628,11 @@ struct lbm_no {
   hipStream_t stream = nullptr;
   std::vector<void*> allocs;
   float *par = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
-  bf16_t *wf = nullptr, *wt = nullptr, *wu = nullptr;  // bfloat16 GEMM copies of the weights (Layer)
-  int64_t wf_n = 0, wt_n = 0, wu_n = 0, wmax = 0;      // their sizes; the largest layer's weight count
+  bf16_t *wf = nullptr, *wt = nullptr, *wu = nullptr, *wph = nullptr;  // bfloat16 GEMM copies of the weights (Layer)
+  int64_t wf_n = 0, wt_n = 0, wu_n = 0, wph_n = 0, wmax = 0;  // their sizes; k_prep's largest index space
   std::vector<float*> z, a, da;  // per layer, [cout][B][Ho][Wo]
   bf16_t* col = nullptr;
   bf16_t* dz16 = nullptr;  // bfloat16 copy of the current layer's dz
-  float* dcol = nullptr;
   float* split = nullptr;
   int64_t split_n = 0;
   double* lpart = nullptr;
@@ -607,7 +676,7 @@ void specs(const int* w, int H, int W, std::vector<Layer>& L, int64_t& npar) {
   npar = 0;
   int h = H, ww = W;
   for (auto& d : def) {
-    Layer l{d[0], d[1], d[2], d[3], d[4], d[5], d[6], h, ww, 0, 0, 0, 0, 0, 0, 0, 0, 0, -1};
+    Layer l{d[0], d[1], d[2], d[3], d[4], d[5], d[6], h, ww, 0, 0, 0, 0, 0, 0, 0, 0, 0, -1, 0, -1};
     const int he = l.up ? 2 * h : h, we = l.up ? 2 * ww : ww;
     const int pad = (l.k - 1) / 2;
     l.Ho = (he + 2 * pad - l.k) / l.s + 1;
@@ -633,12 +702,36 @@ int gemm(lbm_no* h, int M, int N, int K, const bf16_t* A, int64_t lda, const bf1
   const int vecA = aligned(A, lda) && kchunk % 8 == 0, vecB = aligned(B, ldb) && (!BKC || kchunk % 8 == 0);
   const int wm = gemm_wm(M), bm = 64 * wm, bn = 256 / wm;
   const dim3 grid((unsigned)((N + bn - 1) / bn), (unsigned)((M + bm - 1) / bm), (unsigned)splits);
+  const PhaseT ph{};
   if (wm == 1)
-    k_gemm<BKC, 1><<<grid, NT, 0, h->stream>>>(M, N, K, A, lda, vecA, B, ldb, vecB, C, ldc, cz, kchunk, bias,
-                                               accumulate);
+    k_gemm<BKC, 1, false><<<grid, NT, 0, h->stream>>>(M, N, K, A, lda, vecA, B, ldb, vecB, C, ldc, cz, kchunk,
+                                                      bias, accumulate, ph);
   else
-    k_gemm<BKC, 2><<<grid, NT, 0, h->stream>>>(M, N, K, A, lda, vecA, B, ldb, vecB, C, ldc, cz, kchunk, bias,
-                                               accumulate);
+    k_gemm<BKC, 2, false><<<grid, NT, 0, h->stream>>>(M, N, K, A, lda, vecA, B, ldb, vecB, C, ldc, cz, kchunk,
+                                                      bias, accumulate, ph);
+  NOCHK(hipGetLastError());
+  return LBM_NO_OK;
+}
+
+// The four phase GEMMs of k_gemm PH: M rows, N = batch Hn Wn columns, A =
+// four blocks of M rows of lda at A + q M lda, B n-contiguous with ldb, C
+// rows of ldc over the 2Hn x 2Wn grid.
+int gemm_phases(lbm_no* h, int M, int N, const bf16_t* A, int64_t lda, const bf16_t* B, int64_t ldb,
+                float* C, int64_t ldc, const PhaseT& ph, const float* bias, int accumulate) {
+  if (M <= 0 || N <= 0) return LBM_NO_OK;
+  for (int q = 0; q < 4; ++q)
+    if (ph.K[q] < 1 || ph.K[q] > lda || ph.aoff[q] != (int64_t)q * M * lda)
+      return fail(LBM_NO_EINVAL, "phase GEMM operand shapes");
+  auto aligned = [](const void* p, int64_t ld) { return ((uintptr_t)p & 15) == 0 && ld % 8 == 0; };
+  const int vecA = aligned(A, lda), vecB = aligned(B, ldb);
+  const int wm = gemm_wm(M), bm = 64 * wm, bn = 256 / wm;
+  const dim3 grid((unsigned)((N + bn - 1) / bn), (unsigned)((M + bm - 1) / bm), 4u);
+  if (wm == 1)
+    k_gemm<false, 1, true><<<grid, NT, 0, h->stream>>>(M, N, 0, A, lda, vecA, B, ldb, vecB, C, ldc, 0, 0, bias,
+                                                       accumulate, ph);
+  else
+    k_gemm<false, 2, true><<<grid, NT, 0, h->stream>>>(M, N, 0, A, lda, vecA, B, ldb, vecB, C, ldc, 0, 0, bias,
+                                                       accumulate, ph);
   NOCHK(hipGetLastError());
   return LBM_NO_OK;
 }
@@ -659,8 +752,12 @@ int prep_weights(lbm_no* h) {
     t.wu[l] = y.wu;
     t.Kup[l] = y.Kup;
     t.taps[l] = y.k * y.k;
+    t.cin[l] = y.cin;
+    t.wph[l] = y.wph;
+    t.Kph[l] = y.Kph;
+    t.kind[l] = phase_kind(y);
   }
-  k_prep<<<dim3(grid1(h->wmax), (unsigned)nl), EW, 0, h->stream>>>(h->par, t, h->wf, h->wt, h->wu);
+  k_prep<<<dim3(grid1(h->wmax), (unsigned)nl), EW, 0, h->stream>>>(h->par, t, h->wf, h->wt, h->wu, h->wph);
   NOCHK(hipGetLastError());
   return LBM_NO_OK;
 }
@@ -669,11 +766,60 @@ int im2col(lbm_no* h, const Layer& l, const float* src, bool nchw, int Bt) {
   const int64_t P = (int64_t)Bt * l.Ho * l.Wo;
   const dim3 grid(grid1((P + 1) / 2), (unsigned)l.cin);
   if (nchw)
-    k_im2col<true><<<grid, EW, 0, h->stream>>>(src, l.cin, Bt, l.Hs, l.Ws, l.up, l.k, l.s, (l.k - 1) / 2, l.Ho, l.Wo, h->col);
+    k_im2col<true, false><<<grid, EW, 0, h->stream>>>(src, l.cin, Bt, l.Hs, l.Ws, l.up, l.k, l.s, (l.k - 1) / 2, l.Ho, l.Wo, h->col);
   else
-    k_im2col<false><<<grid, EW, 0, h->stream>>>(src, l.cin, Bt, l.Hs, l.Ws, l.up, l.k, l.s, (l.k - 1) / 2, l.Ho, l.Wo, h->col);
+    k_im2col<false, false><<<grid, EW, 0, h->stream>>>(src, l.cin, Bt, l.Hs, l.Ws, l.up, l.k, l.s, (l.k - 1) / 2, l.Ho, l.Wo, h->col);
   NOCHK(hipGetLastError());
   return LBM_NO_OK;
+}
+
+// Forward of an upsampling layer: the tap-major 3 x 3 im2col of the source
+// (rows (3 (dy + 1) + dx + 1) cin + c over the source grid), then the four
+// phase GEMMs: phase (a, b) reads the taps dy in {a - 1, a}, dx in {b - 1,
+// b}, i.e. rows (3a + b) cin + [0, 2 cin) and, 3 cin further on, another
+// 2 cin rows.
+int forward_up(lbm_no* h, const Layer& l, const float* src, int Bt, float* z) {
+  const int64_t P4 = (int64_t)Bt * l.Hs * l.Ws;
+  const dim3 grid(grid1((P4 + 1) / 2), (unsigned)l.cin);
+  k_im2col<false, true><<<grid, EW, 0, h->stream>>>(src, l.cin, Bt, l.Hs, l.Ws, 0, 3, 1, 1, l.Hs, l.Ws, h->col);
+  NOCHK(hipGetLastError());
+  PhaseT ph{};
+  for (int q = 0; q < 4; ++q) {
+    ph.aoff[q] = (int64_t)q * l.cout * l.Kph;
+    ph.K[q] = 4 * l.cin;
+    ph.base[q] = (3 * (q >> 1) + (q & 1)) * l.cin;
+    ph.run[q] = 2 * l.cin;
+    ph.gap[q] = l.cin;
+  }
+  ph.Hn = l.Hs;
+  ph.Wn = l.Ws;
+  return gemm_phases(h, l.cout, (int)P4, h->wph + l.wph, l.Kph, h->col, P4, z, (int64_t)Bt * l.Ho * l.Wo, ph,
+                     h->par + l.boff, 0);
+}
+
+// Input gradient of a stride-2 layer: E = k_emap(dz), then the four phase
+// GEMMs into dx (accumulating when it already holds a gradient): phase
+// (a, b) takes (1 + a)(1 + b) blocks of cout rows of E, (ey, ex) with ey <=
+// a, ex <= b, i.e. rows [0, (1 + b) cout) and, for a = 1, the rows of ey = 1
+// from 2 cout on.
+int input_grad_s2(lbm_no* h, const Layer& l, const float* dz, int Bt, float* dx, int accumulate) {
+  const int64_t P = (int64_t)Bt * l.Ho * l.Wo;
+  k_emap<<<dim3(grid1((int64_t)l.Ho * l.Wo), (unsigned)l.cout, (unsigned)Bt), EW, 0, h->stream>>>(
+      dz, l.cout, Bt, l.Ho, l.Wo, h->col);
+  NOCHK(hipGetLastError());
+  PhaseT ph{};
+  for (int q = 0; q < 4; ++q) {
+    const int a = q >> 1, b = q & 1;
+    ph.aoff[q] = (int64_t)q * l.cin * l.Kph;
+    ph.K[q] = (1 + a) * (1 + b) * l.cout;
+    ph.base[q] = 0;
+    ph.run[q] = (1 + b) * l.cout;
+    ph.gap[q] = (1 - b) * l.cout;  // a = 1, b = 0: ey = 1 starts at 2 cout
+  }
+  ph.Hn = l.Ho;
+  ph.Wn = l.Wo;
+  return gemm_phases(h, l.cin, (int)P, h->wph + l.wph, l.Kph, h->col, P, dx, (int64_t)Bt * l.Hs * l.Ws, ph,
+                     nullptr, accumulate);
 }
 
 int forward_internal(lbm_no* h, const float* x, int Bt) {
@@ -681,11 +827,16 @@ int forward_internal(lbm_no* h, const float* x, int Bt) {
     const Layer& l = h->L[li];
     const int64_t P = (int64_t)Bt * l.Ho * l.Wo;
     const int K = l.cin * l.k * l.k;
-    int rc = im2col(h, l, li == 0 ? x : h->a[li - 1], li == 0, Bt);
-    if (rc) return rc;
-    // z[o][p] = W[o][k] col[k][p]: A k-contiguous, B n-contiguous
-    rc = gemm<false>(h, l.cout, (int)P, K, h->wf + l.wf, l.Kp, h->col, P, h->z[li], P, 0, 1, K,
-                     h->par + l.boff);
+    int rc;
+    if (phase_kind(l) == 1) {
+      rc = forward_up(h, l, h->a[li - 1], Bt, h->z[li]);
+    } else {
+      rc = im2col(h, l, li == 0 ? x : h->a[li - 1], li == 0, Bt);
+      if (rc) return rc;
+      // z[o][p] = W[o][k] col[k][p]: A k-contiguous, B n-contiguous
+      rc = gemm<false>(h, l.cout, (int)P, K, h->wf + l.wf, l.Kp, h->col, P, h->z[li], P, 0, 1, K,
+                       h->par + l.boff);
+    }
     if (rc) return rc;
     const int64_t n = (int64_t)l.cout * P;
     k_act<<<grid1(n), EW, 0, h->stream>>>(h->z[li], l.skip >= 0 ? h->a[l.skip] : nullptr, h->a[li], n, l.relu);
@@ -772,22 +923,31 @@ int lbm_no_create(const int32_t* widths, int32_t height, int32_t width, int32_t 
       l.wt = h->wt_n;
       h->wf_n += (int64_t)l.cout * l.Kp;
       h->wt_n += (int64_t)K * l.coutp;
-      h->wmax = std::max(h->wmax, (int64_t)l.cout * K);
+      int64_t nprep = (int64_t)l.cout * K;
       if (l.up) {
         l.Kup = (l.k * l.k * l.cout + 7) / 8 * 8;
         l.wu = h->wu_n;
         h->wu_n += (int64_t)l.cin * l.Kup;
       }
+      if (phase_kind(l)) {
+        l.Kph = (4 * (l.up ? l.cin : l.cout) + 7) / 8 * 8;
+        l.wph = h->wph_n;
+        h->wph_n += 4 * (int64_t)(l.up ? l.cout : l.cin) * l.Kph;
+        nprep += 16 * (int64_t)l.cin * l.cout;
+      }
+      h->wmax = std::max(h->wmax, nprep);
     }
     h->wf = (bf16_t*)nalloc(h, (size_t)h->wf_n * 2);
     h->wt = (bf16_t*)nalloc(h, (size_t)h->wt_n * 2);
     h->wu = (bf16_t*)nalloc(h, (size_t)h->wu_n * 2);
-    if (!h->par || !h->grad || !h->m || !h->v || !h->wf || !h->wt || !h->wu)
+    h->wph = (bf16_t*)nalloc(h, (size_t)h->wph_n * 2);
+    if (!h->par || !h->grad || !h->m || !h->v || !h->wf || !h->wt || !h->wu || !h->wph)
       return bail(fail(LBM_NO_ENOMEM, "parameters"));
     NOCHK(hipMemsetAsync(h->wf, 0, (size_t)h->wf_n * 2, h->stream));  // row padding stays zero
     NOCHK(hipMemsetAsync(h->wt, 0, (size_t)h->wt_n * 2, h->stream));
     NOCHK(hipMemsetAsync(h->wu, 0, (size_t)h->wu_n * 2, h->stream));
-    int64_t colmax = 0, dcolmax = 0, splitmax = 0, actmax = 0, bpmax = 0;
+    NOCHK(hipMemsetAsync(h->wph, 0, (size_t)h->wph_n * 2, h->stream));
+    int64_t colmax = 0, splitmax = 0, actmax = 0, bpmax = 0;
     for (size_t li = 0; li < h->L.size(); ++li) {
       const Layer& l = h->L[li];
       const int64_t P = (int64_t)max_batch * l.Ho * l.Wo;
@@ -802,7 +962,7 @@ int lbm_no_create(const int32_t* widths, int32_t height, int32_t width, int32_t 
       h->da.push_back(dl);
       const int64_t K = (int64_t)l.cin * l.k * l.k;
       colmax = std::max(colmax, K * P);
-      if (li > 0 && !l.up && !(l.k == 1 && l.s == 1)) dcolmax = std::max(dcolmax, K * P);  // col2im layers
+      if (phase_kind(l) == 2) colmax = std::max(colmax, 4 * l.cout * P);  // k_emap's stack
       int S;
       int64_t kchunk;
       wgrad_split(l.cout, K, P, S, kchunk);
@@ -816,7 +976,6 @@ int lbm_no_create(const int32_t* widths, int32_t height, int32_t width, int32_t 
       bpmax = std::max(bpmax, (int64_t)l.cout * ((P + ACT_CHUNK - 1) / ACT_CHUNK));
     }
     h->col = (bf16_t*)nalloc(h, (size_t)colmax * 2);
-    h->dcol = (float*)nalloc(h, (size_t)dcolmax * 4);
     h->dz16 = (bf16_t*)nalloc(h, (size_t)actmax * 2);
     h->split = (float*)nalloc(h, (size_t)splitmax * 4);
     h->split_n = splitmax;
@@ -824,7 +983,7 @@ int lbm_no_create(const int32_t* widths, int32_t height, int32_t width, int32_t 
     h->lpart = (double*)nalloc(h, (size_t)lb * 8);
     h->dloss = (double*)nalloc(h, 8);
     h->bpart = (float*)nalloc(h, (size_t)bpmax * 4);
-    if (!h->col || !h->dcol || !h->dz16 || !h->split || !h->lpart || !h->dloss || !h->bpart)
+    if (!h->col || !h->dz16 || !h->split || !h->lpart || !h->dloss || !h->bpart)
       return bail(fail(LBM_NO_ENOMEM, "work space"));
     const int rc = lbm_no_set_params(h, params);
     if (rc) return bail(rc);
@@ -949,16 +1108,14 @@ int lbm_no_gradients(lbm_no* h, const float* x, const float* target, int32_t bat
         have[li - 1] = 1;
         continue;
       }
-      // input gradient: dcol = W^T dz, then the col2im gather into da[li - 1]
-      // dcol[k][p] = W[o][k] dz[o][p]: A = the transposed weight copy wt[k][o], B n(=p)-contiguous
-      rc = gemm<false>(h, K, (int)P, l.cout, h->wt + l.wt, l.coutp, h->dz16, P, h->dcol, P, 0, 1, l.cout,
-                       nullptr);
-      if (rc) return rc;
-      const dim3 g2(grid1((int64_t)l.Hs * l.Ws), (unsigned)l.cin, (unsigned)batch);
-      k_col2im<<<g2, EW, 0, h->stream>>>(h->dcol, l.cin, batch, l.Hs, l.Ws, l.up, l.k, l.s, (l.k - 1) / 2,
-                                         l.Ho, l.Wo, h->da[li - 1], have[li - 1]);
-      NOCHK(hipGetLastError());
-      have[li - 1] = 1;
+      if (phase_kind(l) == 2) {
+        rc = input_grad_s2(h, l, h->z[li], batch, h->da[li - 1], have[li - 1]);
+        if (rc) return rc;
+        have[li - 1] = 1;
+        continue;
+      }
+      // every layer with an input gradient is upsampling, stride 2 or 1 x 1 (specs)
+      return fail(LBM_NO_EINVAL, "no input-gradient path for this layer");
     }
     if (loss) {
       NOCHK(hipMemcpyAsync(loss, h->dloss, 8, hipMemcpyDeviceToHost, h->stream));
