@@ -89,11 +89,12 @@ __device__ inline uint32_t word(const uint4& v, int d) { return d == 0 ? v.x : d
 // block around in registers and writes eight 8-byte rows).  The next stage's
 // operands are loaded into registers while the current one is multiplied.
 // accumulate: C += instead of C =.
-// PH: four phase GEMMs of a stride-2 grid relation (grid z = phase q, py =
-// q / 2, px = q % 2, no split): A + ph.aoff[q], reduction length ph.K[q], B
-// row k taken from row ph.base[q] + k (+ ph.gap[q] once k >= ph.run[q]), and
-// column n = (b, y, x) of an Hn x Wn grid written to (b, 2y + py, 2x + px) of
-// the 2Hn x 2Wn grid (row m of C at C + m ldc); bias in every phase.
+// PH: four phase GEMMs of a stride-2 grid relation, phase q = (py, px) = (q
+// / 2, q % 2), no split: A + ph.aoff[q], reduction length ph.K[q], B row k
+// taken from row ph.base[q] + k (+ ph.gap[q] once k >= ph.run[q]), and column
+// n = (b, y, x) of an Hn x Wn grid written to (b, 2y + py, 2x + px) of the
+// 2Hn x 2Wn grid (row m of C at C + m ldc); bias in every phase.  Block z
+// = py runs both px (C and its rows 8-byte aligned).
 // vecA / vecB: rows 16-byte aligned (leading dimension a multiple of 8,
 // aligned base, kchunk a multiple of 8), so whole 8-element chunks move as
 // one 16-byte load; otherwise element by element.  Zero outside the
@@ -116,122 +117,150 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, const bf16_t* 
   __shared__ __attribute__((aligned(16))) bf16_t As[TBM * GLD];
   __shared__ __attribute__((aligned(16))) bf16_t Bs[TBN * GLD];
   const int m0 = blockIdx.y * TBM, n0 = blockIdx.x * TBN;
-  const int q = PH ? (int)blockIdx.z : 0;
-  const int kb = PH ? 0 : (int)blockIdx.z * kchunk;
-  const int ke = PH ? ph.K[q] : min(K, kb + kchunk);
-  if (PH) A += ph.aoff[q];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / WN) * 64, wn = (wave % WN) * 64;
-  v4f acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
   uint4 ra[NA], rb[NB];
-  auto load = [&](int k0) {
+  // acc += A B over k in [kb, ke) (phase q: A + ph.aoff[q], B rows mapped)
+  auto mainloop = [&](const int q, const int kb, const int ke, v4f (&acc)[4][4]) {
+    const bf16_t* __restrict__ Aq = PH ? A + ph.aoff[q] : A;
+    auto load = [&](int k0) {
 #pragma unroll
-    for (int it = 0; it < NA; ++it) {
-      const int e = tid + it * NT, r = e >> 3, c = (e & 7) << 3;
-      ra[it] = m0 + r < M ? load8(A + (int64_t)(m0 + r) * lda, k0 + c, ke, vecA) : make_uint4(0u, 0u, 0u, 0u);
-    }
-    if constexpr (BKC) {
-#pragma unroll
-      for (int it = 0; it < NB; ++it) {
+      for (int it = 0; it < NA; ++it) {
         const int e = tid + it * NT, r = e >> 3, c = (e & 7) << 3;
-        rb[it] = n0 + r < N ? load8(B + (int64_t)(n0 + r) * ldb, k0 + c, ke, vecB) : make_uint4(0u, 0u, 0u, 0u);
+        ra[it] = m0 + r < M ? load8(Aq + (int64_t)(m0 + r) * lda, k0 + c, ke, vecA) : make_uint4(0u, 0u, 0u, 0u);
       }
-    } else {  // blocks of 4 k x 8 n: k = 4 (e % 16) + q, n = 8 (e / 16) + 0..7
+      if constexpr (BKC) {
 #pragma unroll
-      for (int it = 0; it < NB / 4; ++it) {
-        const int e = tid + it * NT, kq = (e & 15) << 2, n8 = (e >> 4) << 3;
+        for (int it = 0; it < NB; ++it) {
+          const int e = tid + it * NT, r = e >> 3, c = (e & 7) << 3;
+          rb[it] = n0 + r < N ? load8(B + (int64_t)(n0 + r) * ldb, k0 + c, ke, vecB) : make_uint4(0u, 0u, 0u, 0u);
+        }
+      } else {  // blocks of 4 k x 8 n: k = 4 (e % 16) + r, n = 8 (e / 16) + 0..7
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int gk = k0 + kq + r;
-          const int gr = PH ? ph.base[q] + gk + (gk >= ph.run[q] ? ph.gap[q] : 0) : gk;
-          rb[4 * it + r] = gk < ke ? load8(B + (int64_t)gr * ldb, n0 + n8, N, vecB) : make_uint4(0u, 0u, 0u, 0u);
+        for (int it = 0; it < NB / 4; ++it) {
+          const int e = tid + it * NT, kq = (e & 15) << 2, n8 = (e >> 4) << 3;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int gk = k0 + kq + r;
+            const int gr = PH ? ph.base[q] + gk + (gk >= ph.run[q] ? ph.gap[q] : 0) : gk;
+            rb[4 * it + r] = gk < ke ? load8(B + (int64_t)gr * ldb, n0 + n8, N, vecB) : make_uint4(0u, 0u, 0u, 0u);
+          }
         }
       }
-    }
-  };
-  auto stash = [&]() {
+    };
+    auto stash = [&]() {
 #pragma unroll
-    for (int it = 0; it < NA; ++it) {
-      const int e = tid + it * NT, r = e >> 3, c = (e & 7) << 3;
-      *(uint4*)&As[r * GLD + c] = ra[it];
-    }
-    if constexpr (BKC) {
-#pragma unroll
-      for (int it = 0; it < NB; ++it) {
+      for (int it = 0; it < NA; ++it) {
         const int e = tid + it * NT, r = e >> 3, c = (e & 7) << 3;
-        *(uint4*)&Bs[r * GLD + c] = rb[it];
+        *(uint4*)&As[r * GLD + c] = ra[it];
       }
-    } else {
+      if constexpr (BKC) {
 #pragma unroll
-      for (int it = 0; it < NB / 4; ++it) {
-        const int e = tid + it * NT, kq = (e & 15) << 2, n8 = (e >> 4) << 3;
+        for (int it = 0; it < NB; ++it) {
+          const int e = tid + it * NT, r = e >> 3, c = (e & 7) << 3;
+          *(uint4*)&Bs[r * GLD + c] = rb[it];
+        }
+      } else {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int d = i >> 1, h = i & 1;
-          uint2 v;
-          v.x = pick(word(rb[4 * it + 0], d), word(rb[4 * it + 1], d), h);
-          v.y = pick(word(rb[4 * it + 2], d), word(rb[4 * it + 3], d), h);
-          *(uint2*)&Bs[(n8 + i) * GLD + kq] = v;
+        for (int it = 0; it < NB / 4; ++it) {
+          const int e = tid + it * NT, kq = (e & 15) << 2, n8 = (e >> 4) << 3;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const int d = i >> 1, h = i & 1;
+            uint2 v;
+            v.x = pick(word(rb[4 * it + 0], d), word(rb[4 * it + 1], d), h);
+            v.y = pick(word(rb[4 * it + 2], d), word(rb[4 * it + 3], d), h);
+            *(uint2*)&Bs[(n8 + i) * GLD + kq] = v;
+          }
         }
       }
-    }
-  };
-  if (kb < ke) load(kb);
-  for (int k0 = kb; k0 < ke; k0 += GBK) {
-    __syncthreads();  // the previous stage's fragments are read
-    stash();
-    __syncthreads();
-    if (k0 + GBK < ke) load(k0 + GBK);
+    };
 #pragma unroll
-    for (int kk = 0; kk < GBK; kk += 32) {
-      const int kq = kk + 8 * (lane >> 4);
-      v8bf a[4], b[4];
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        a[i] = __builtin_bit_cast(v8bf, *(const uint4*)&As[(wm + i * 16 + (lane & 15)) * GLD + kq]);
+      for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    if (kb < ke) load(kb);
+    for (int k0 = kb; k0 < ke; k0 += GBK) {
+      __syncthreads();  // the previous stage's fragments are read
+      stash();
+      __syncthreads();
+      if (k0 + GBK < ke) load(k0 + GBK);
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        b[j] = __builtin_bit_cast(v8bf, *(const uint4*)&Bs[(wn + j * 16 + (lane & 15)) * GLD + kq]);
+      for (int kk = 0; kk < GBK; kk += 32) {
+        const int kq = kk + 8 * (lane >> 4);
+        v8bf a[4], b[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i)
+          a[i] = __builtin_bit_cast(v8bf, *(const uint4*)&As[(wm + i * 16 + (lane & 15)) * GLD + kq]);
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
-  }
-  float* Cz = C + (PH ? 0 : (int64_t)blockIdx.z * cz);
-  int64_t cof[4];  // column offsets in a row of C
+          b[j] = __builtin_bit_cast(v8bf, *(const uint4*)&Bs[(wn + j * 16 + (lane & 15)) * GLD + kq]);
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int gn = n0 + wn + j * 16 + (lane & 15);
-    cof[j] = gn;
-    if (PH && gn < N) {
-      const int hw = ph.Hn * ph.Wn;
-      const int b = gn / hw, r = gn - b * hw, y = r / ph.Wn, x = r - y * ph.Wn;
-      cof[j] = ((int64_t)b * 2 * ph.Hn + 2 * y + (q >> 1)) * (2 * ph.Wn) + 2 * x + (q & 1);
-    }
-  }
-  // result layout of a 16 x 16 tile: lane holds column lane % 16, rows 4 (lane / 16) + r
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int gm = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
-      if (gm >= M) continue;
-      const float bv = (bias && (PH || blockIdx.z == 0)) ? bias[gm] : 0.0f;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int gn = n0 + wn + j * 16 + (lane & 15);
-        if (gn < N) {
-          float* c = Cz + (int64_t)gm * ldc + cof[j];
-          *c = (accumulate ? *c : 0.0f) + (acc[i][j][r] + bv);
-        }
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
       }
     }
+  };
+  // result layout of a 16 x 16 tile: lane holds column lane % 16, rows 4 (lane / 16) + r
+  if constexpr (!PH) {
+    const int kb = (int)blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+    v4f acc[4][4];
+    mainloop(0, kb, ke, acc);
+    float* Cz = C + (int64_t)blockIdx.z * cz;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        if (gm >= M) continue;
+        const float bv = (bias && blockIdx.z == 0) ? bias[gm] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int gn = n0 + wn + j * 16 + (lane & 15);
+          if (gn < N) {
+            float* c = Cz + (int64_t)gm * ldc + gn;
+            *c = (accumulate ? *c : 0.0f) + (acc[i][j][r] + bv);
+          }
+        }
+      }
+  } else {
+    // block z = py: both column phases px = 0, 1 of the row phase, so each
+    // output (b, 2y + py, 2x .. 2x + 1) is one 8-byte store
+    const int py = (int)blockIdx.z;
+    v4f acc0[4][4], acc1[4][4];
+    mainloop(2 * py, 0, ph.K[2 * py], acc0);
+    __syncthreads();  // LDS reused by the second phase
+    mainloop(2 * py + 1, 0, ph.K[2 * py + 1], acc1);
+    int64_t cof[4];  // offset of (b, 2y + py, 2x) in a row of C
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gn = n0 + wn + j * 16 + (lane & 15);
+      const int hw = ph.Hn * ph.Wn;
+      const int b = gn / hw, r = gn - b * hw, y = r / ph.Wn, x = r - y * ph.Wn;
+      cof[j] = ((int64_t)b * 2 * ph.Hn + 2 * y + py) * (2 * ph.Wn) + 2 * x;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        if (gm >= M) continue;
+        const float bv = bias ? bias[gm] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int gn = n0 + wn + j * 16 + (lane & 15);
+          if (gn < N) {
+            float2* c = (float2*)(C + (int64_t)gm * ldc + cof[j]);
+            float2 v = accumulate ? *c : make_float2(0.0f, 0.0f);
+            v.x += acc0[i][j][r] + bv;
+            v.y += acc1[i][j][r] + bv;
+            *c = v;
+          }
+        }
+      }
+  }
 }
 
 // col[kidx][p] for kidx = (c, ky, kx) (TM: kidx = (ky, kx, c), tap-major), p
@@ -305,14 +334,16 @@ __global__ __launch_bounds__(EW) void k_act(const float* __restrict__ z, const f
 }
 
 // dz = da where z > 0 (relu) or da; written over z, and as bfloat16 (the
-// GEMM operand) into dz16; and the bias gradient's partial sums: block
-// (x, o) covers ACT_CHUNK entries of channel o's row (dz is [cout][P]) and
-// writes their sum, in a fixed order, to bpart[o][x].
+// GEMM operand) into dz16; the bias gradient's partial sums: block (x, o)
+// covers ACT_CHUNK entries of channel o's row (dz is [cout][P]) and writes
+// their sum, in a fixed order, to bpart[o][x]; and with a skip input (a =
+// act(z) + skip), its gradient: skip_da (+)= da.
 constexpr int ACT_PER = 4;                 // entries per thread
 constexpr int ACT_CHUNK = EW * ACT_PER;   // entries per block
 __global__ __launch_bounds__(EW) void k_act_bwd(const float* __restrict__ da, float* __restrict__ z,
                                                 bf16_t* __restrict__ dz16, int64_t P, int relu,
-                                                float* __restrict__ bpart) {
+                                                float* __restrict__ bpart, float* __restrict__ skip_da,
+                                                int skip_acc) {
   __shared__ float sh[EW / 64];
   const int o = blockIdx.y;
   const int64_t row = (int64_t)o * P;
@@ -323,7 +354,9 @@ __global__ __launch_bounds__(EW) void k_act_bwd(const float* __restrict__ da, fl
     const int64_t p = p0 + (int64_t)r * EW;
     if (p < P) {
       const int64_t i = row + p;
-      const float v = (!relu || z[i] > 0.0f) ? da[i] : 0.0f;
+      const float d = da[i];
+      if (skip_da) skip_da[i] = skip_acc ? skip_da[i] + d : d;
+      const float v = (!relu || z[i] > 0.0f) ? d : 0.0f;
       z[i] = v;
       dz16[i] = to_bf16(v);
       sum += v;
@@ -333,13 +366,6 @@ __global__ __launch_bounds__(EW) void k_act_bwd(const float* __restrict__ da, fl
   if (threadIdx.x == 0) bpart[(int64_t)o * gridDim.x + blockIdx.x] = sum;
 }
 
-// dst (+)= src
-__global__ __launch_bounds__(EW) void k_copy_add(float* __restrict__ dst, const float* __restrict__ src,
-                                                 int64_t n, int accumulate) {
-  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
-  if (i >= n) return;
-  dst[i] = accumulate ? dst[i] + src[i] : src[i];
-}
 
 
 // db[o] = sum_p dz[o][p] from k_act_bwd's nchunk partial sums of channel o:
@@ -725,7 +751,8 @@ int gemm_phases(lbm_no* h, int M, int N, const bf16_t* A, int64_t lda, const bf1
   auto aligned = [](const void* p, int64_t ld) { return ((uintptr_t)p & 15) == 0 && ld % 8 == 0; };
   const int vecA = aligned(A, lda), vecB = aligned(B, ldb);
   const int wm = gemm_wm(M), bm = 64 * wm, bn = 256 / wm;
-  const dim3 grid((unsigned)((N + bn - 1) / bn), (unsigned)((M + bm - 1) / bm), 4u);
+  if (((uintptr_t)C & 7) || (ldc & 1)) return fail(LBM_NO_EINVAL, "phase GEMM output alignment");
+  const dim3 grid((unsigned)((N + bn - 1) / bn), (unsigned)((M + bm - 1) / bm), 2u);
   if (wm == 1)
     k_gemm<false, 1, true><<<grid, NT, 0, h->stream>>>(M, N, 0, A, lda, vecA, B, ldb, vecB, C, ldc, 0, 0, bias,
                                                        accumulate, ph);
@@ -1043,17 +1070,14 @@ int lbm_no_gradients(lbm_no* h, const float* x, const float* target, int32_t bat
       const Layer& l = h->L[li];
       const int64_t P = (int64_t)batch * l.Ho * l.Wo;
       const int K = l.cin * l.k * l.k;
-      const int64_t n = (int64_t)l.cout * P;
       // dz over z (and the bias gradient's partial sums); the skip passes da on unchanged
       const unsigned nchunk = (unsigned)((P + ACT_CHUNK - 1) / ACT_CHUNK);
+      float* skip_da = l.skip >= 0 ? h->da[l.skip] : nullptr;
       k_act_bwd<<<dim3(nchunk, (unsigned)l.cout), EW, 0, h->stream>>>(h->da[li], h->z[li], h->dz16, P, l.relu,
-                                                                       h->bpart);
+                                                                       h->bpart, skip_da,
+                                                                       l.skip >= 0 ? have[l.skip] : 0);
       NOCHK(hipGetLastError());
-      if (l.skip >= 0) {
-        k_copy_add<<<grid1(n), EW, 0, h->stream>>>(h->da[l.skip], h->da[li], n, have[l.skip]);
-        NOCHK(hipGetLastError());
-        have[l.skip] = 1;
-      }
+      if (l.skip >= 0) have[l.skip] = 1;
       int S;
       int64_t kchunk;
       if (l.up) {
