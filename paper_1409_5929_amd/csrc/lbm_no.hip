@@ -88,13 +88,15 @@ __device__ inline uint32_t word(const uint4& v, int d) { return d == 0 ? v.x : d
 // transposed on the way when n-contiguous: each thread turns a 4 (k) x 8 (n)
 // block around in registers and writes eight 8-byte rows).  The next stage's
 // operands are loaded into registers while the current one is multiplied.
-// accumulate: C += instead of C =.
+// accumulate: C += instead of C =.  act (single split): also act[i] =
+// relu(C[i]) (or C[i]) + skip[i] (skip may be null), the layer activation.
 // PH: four phase GEMMs of a stride-2 grid relation, phase q = (py, px) = (q
 // / 2, q % 2), no split: A + ph.aoff[q], reduction length ph.K[q], B row k
 // taken from row ph.base[q] + k (+ ph.gap[q] once k >= ph.run[q]), and column
 // n = (b, y, x) of an Hn x Wn grid written to (b, 2y + py, 2x + px) of the
-// 2Hn x 2Wn grid (row m of C at C + m ldc); bias in every phase.  Block z
-// = py runs both px (C and its rows 8-byte aligned).
+// 2Hn x 2Wn grid (row m of C at C + m ldc); bias in every phase.  PAIR:
+// block z = py runs both px, each output pair one 8-byte store (C and its
+// rows 8-byte aligned); otherwise block z = q runs one phase.
 // vecA / vecB: rows 16-byte aligned (leading dimension a multiple of 8,
 // aligned base, kchunk a multiple of 8), so whole 8-element chunks move as
 // one 16-byte load; otherwise element by element.  Zero outside the
@@ -104,13 +106,16 @@ struct PhaseT {
   int K[4], base[4], run[4], gap[4];
   int Hn, Wn;
 };
-template <bool BKC, int WM, bool PH>
+template <bool BKC, int WM, bool PH, bool PAIR>
 __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, const bf16_t* __restrict__ A,
                                              int64_t lda, int vecA, const bf16_t* __restrict__ B,
                                              int64_t ldb, int vecB, float* __restrict__ C, int64_t ldc,
                                              int64_t cz, int kchunk, const float* __restrict__ bias,
-                                             int accumulate, PhaseT ph) {
-  static_assert(!(PH && BKC), "phase GEMMs take an n-contiguous B");
+                                             int accumulate, PhaseT ph, float* __restrict__ act,
+                                             const float* __restrict__ skip, int relu) {
+  static_assert(!(PH && BKC) && (PH || !PAIR), "phase GEMMs take an n-contiguous B");
+  // the layer activation of an output value v (same layout as C)
+  auto activate = [&](float v, int64_t i) { return (relu ? fmaxf(v, 0.0f) : v) + (skip ? skip[i] : 0.0f); };
   constexpr int WN = 4 / WM, TBM = 64 * WM, TBN = 64 * WN;
   constexpr int NA = TBM * GBK / 8 / NT;   // 16-byte A chunks per thread and stage
   constexpr int NB = TBN * GBK / 8 / NT;   // 16-byte B chunks per thread and stage
@@ -204,24 +209,39 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, const bf16_t* 
     }
   };
   // result layout of a 16 x 16 tile: lane holds column lane % 16, rows 4 (lane / 16) + r
-  if constexpr (!PH) {
-    const int kb = (int)blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+  if constexpr (!PAIR) {
+    const int q = PH ? (int)blockIdx.z : 0;
+    const int kb = PH ? 0 : (int)blockIdx.z * kchunk, ke = PH ? ph.K[q] : min(K, kb + kchunk);
     v4f acc[4][4];
-    mainloop(0, kb, ke, acc);
-    float* Cz = C + (int64_t)blockIdx.z * cz;
+    mainloop(q, kb, ke, acc);
+    float* Cz = C + (PH ? 0 : (int64_t)blockIdx.z * cz);
+    int64_t cof[4];  // column offsets in a row of C
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gn = n0 + wn + j * 16 + (lane & 15);
+      cof[j] = gn;
+      if (PH) {
+        const int hw = ph.Hn * ph.Wn;
+        const int b = gn / hw, r = gn - b * hw, y = r / ph.Wn, x = r - y * ph.Wn;
+        cof[j] = ((int64_t)b * 2 * ph.Hn + 2 * y + (q >> 1)) * (2 * ph.Wn) + 2 * x + (q & 1);
+      }
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gm = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
         if (gm >= M) continue;
-        const float bv = (bias && blockIdx.z == 0) ? bias[gm] : 0.0f;
+        const float bv = (bias && (PH || blockIdx.z == 0)) ? bias[gm] : 0.0f;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int gn = n0 + wn + j * 16 + (lane & 15);
           if (gn < N) {
-            float* c = Cz + (int64_t)gm * ldc + gn;
-            *c = (accumulate ? *c : 0.0f) + (acc[i][j][r] + bv);
+            const int64_t idx = (int64_t)gm * ldc + cof[j];
+            float* c = Cz + idx;
+            const float v = (accumulate ? *c : 0.0f) + (acc[i][j][r] + bv);
+            *c = v;
+            if (act) act[idx] = activate(v, idx);
           }
         }
       }
@@ -252,11 +272,13 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, const bf16_t* 
         for (int j = 0; j < 4; ++j) {
           const int gn = n0 + wn + j * 16 + (lane & 15);
           if (gn < N) {
-            float2* c = (float2*)(C + (int64_t)gm * ldc + cof[j]);
+            const int64_t idx = (int64_t)gm * ldc + cof[j];
+            float2* c = (float2*)(C + idx);
             float2 v = accumulate ? *c : make_float2(0.0f, 0.0f);
             v.x += acc0[i][j][r] + bv;
             v.y += acc1[i][j][r] + bv;
             *c = v;
+            if (act) *(float2*)(act + idx) = make_float2(activate(v.x, idx), activate(v.y, idx + 1));
           }
         }
       }
@@ -321,16 +343,6 @@ __device__ inline float block_sum(float v, float* sh) {
   if (threadIdx.x == 0)
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
   return t;
-}
-
-// a = relu(z) (or z) + skip
-__global__ __launch_bounds__(EW) void k_act(const float* __restrict__ z, const float* __restrict__ skip,
-                                            float* __restrict__ a, int64_t n, int relu) {
-  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
-  if (i >= n) return;
-  float v = z[i];
-  if (relu) v = fmaxf(v, 0.0f);
-  a[i] = skip ? v + skip[i] : v;
 }
 
 // dz = da where z > 0 (relu) or da; written over z, and as bfloat16 (the
@@ -471,13 +483,6 @@ __global__ __launch_bounds__(EW) void k_emap(const float* __restrict__ dz, int c
       const float v = (y + ey < Ho && x + ex < Wo) ? base[(y + ey) * Wo + x + ex] : 0.0f;
       E[((int64_t)(2 * ey + ex) * cout + o) * P + s] = to_bf16(v);
     }
-}
-
-// pb[i] = bfloat16(p[i])
-__global__ __launch_bounds__(EW) void k_to_bf16(const float* __restrict__ p, int64_t n,
-                                                bf16_t* __restrict__ pb) {
-  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
-  if (i < n) pb[i] = to_bf16(p[i]);
 }
 
 // y is [3][b][hw] (channel-major), t is [b][3][hw]: dy = 2 (y - t) / n and
@@ -657,7 +662,8 @@ struct lbm_no {
   bf16_t *wf = nullptr, *wt = nullptr, *wu = nullptr, *wph = nullptr;  // bfloat16 GEMM copies of the weights (Layer)
   int64_t wf_n = 0, wt_n = 0, wu_n = 0, wph_n = 0, wmax = 0;  // their sizes; k_prep's largest index space
   std::vector<float*> z, a, da;  // per layer, [cout][B][Ho][Wo]
-  bf16_t* col = nullptr;
+  std::vector<bf16_t*> colL;  // per layer: the forward's im2col, kept for the weight gradient
+  bf16_t* col = nullptr;       // work: the backward's box sums (k_dmap) and shifted stacks (k_emap)
   bf16_t* dz16 = nullptr;  // bfloat16 copy of the current layer's dz
   float* split = nullptr;
   int64_t split_n = 0;
@@ -718,11 +724,19 @@ void specs(const int* w, int H, int W, std::vector<Layer>& L, int64_t& npar) {
 }
 
 // C = A B (see k_gemm); A k-contiguous with leading dimension lda >= K.
+// Layer activation written by a GEMM epilogue (k_gemm act).
+struct Epi {
+  float* act = nullptr;
+  const float* skip = nullptr;
+  int relu = 0;
+};
+
 template <bool BKC>
 int gemm(lbm_no* h, int M, int N, int K, const bf16_t* A, int64_t lda, const bf16_t* B, int64_t ldb,
-         float* C, int64_t ldc, int64_t cz, int splits, int kchunk, const float* bias, int accumulate = 0) {
+         float* C, int64_t ldc, int64_t cz, int splits, int kchunk, const float* bias, int accumulate = 0,
+         const Epi& epi = Epi()) {
   if (M <= 0 || N <= 0 || K <= 0) return LBM_NO_OK;
-  if (lda < K || (BKC ? ldb < K : ldb < N) || kchunk < 1 || (splits > 1 && kchunk % GBK))
+  if (lda < K || (BKC ? ldb < K : ldb < N) || kchunk < 1 || (splits > 1 && (kchunk % GBK || epi.act)))
     return fail(LBM_NO_EINVAL, "GEMM operand shapes");
   auto aligned = [](const void* p, int64_t ld) { return ((uintptr_t)p & 15) == 0 && ld % 8 == 0; };
   const int vecA = aligned(A, lda) && kchunk % 8 == 0, vecB = aligned(B, ldb) && (!BKC || kchunk % 8 == 0);
@@ -730,11 +744,13 @@ int gemm(lbm_no* h, int M, int N, int K, const bf16_t* A, int64_t lda, const bf1
   const dim3 grid((unsigned)((N + bn - 1) / bn), (unsigned)((M + bm - 1) / bm), (unsigned)splits);
   const PhaseT ph{};
   if (wm == 1)
-    k_gemm<BKC, 1, false><<<grid, NT, 0, h->stream>>>(M, N, K, A, lda, vecA, B, ldb, vecB, C, ldc, cz, kchunk,
-                                                      bias, accumulate, ph);
+    k_gemm<BKC, 1, false, false><<<grid, NT, 0, h->stream>>>(M, N, K, A, lda, vecA, B, ldb, vecB, C, ldc, cz,
+                                                             kchunk, bias, accumulate, ph, epi.act, epi.skip,
+                                                             epi.relu);
   else
-    k_gemm<BKC, 2, false><<<grid, NT, 0, h->stream>>>(M, N, K, A, lda, vecA, B, ldb, vecB, C, ldc, cz, kchunk,
-                                                      bias, accumulate, ph);
+    k_gemm<BKC, 2, false, false><<<grid, NT, 0, h->stream>>>(M, N, K, A, lda, vecA, B, ldb, vecB, C, ldc, cz,
+                                                             kchunk, bias, accumulate, ph, epi.act, epi.skip,
+                                                             epi.relu);
   NOCHK(hipGetLastError());
   return LBM_NO_OK;
 }
@@ -743,7 +759,8 @@ int gemm(lbm_no* h, int M, int N, int K, const bf16_t* A, int64_t lda, const bf1
 // four blocks of M rows of lda at A + q M lda, B n-contiguous with ldb, C
 // rows of ldc over the 2Hn x 2Wn grid.
 int gemm_phases(lbm_no* h, int M, int N, const bf16_t* A, int64_t lda, const bf16_t* B, int64_t ldb,
-                float* C, int64_t ldc, const PhaseT& ph, const float* bias, int accumulate) {
+                float* C, int64_t ldc, const PhaseT& ph, const float* bias, int accumulate,
+                const Epi& epi = Epi()) {
   if (M <= 0 || N <= 0) return LBM_NO_OK;
   for (int q = 0; q < 4; ++q)
     if (ph.K[q] < 1 || ph.K[q] > lda || ph.aoff[q] != (int64_t)q * M * lda)
@@ -751,14 +768,21 @@ int gemm_phases(lbm_no* h, int M, int N, const bf16_t* A, int64_t lda, const bf1
   auto aligned = [](const void* p, int64_t ld) { return ((uintptr_t)p & 15) == 0 && ld % 8 == 0; };
   const int vecA = aligned(A, lda), vecB = aligned(B, ldb);
   const int wm = gemm_wm(M), bm = 64 * wm, bn = 256 / wm;
-  if (((uintptr_t)C & 7) || (ldc & 1)) return fail(LBM_NO_EINVAL, "phase GEMM output alignment");
-  const dim3 grid((unsigned)((N + bn - 1) / bn), (unsigned)((M + bm - 1) / bm), 2u);
-  if (wm == 1)
-    k_gemm<false, 1, true><<<grid, NT, 0, h->stream>>>(M, N, 0, A, lda, vecA, B, ldb, vecB, C, ldc, 0, 0, bias,
-                                                       accumulate, ph);
-  else
-    k_gemm<false, 2, true><<<grid, NT, 0, h->stream>>>(M, N, 0, A, lda, vecA, B, ldb, vecB, C, ldc, 0, 0, bias,
-                                                       accumulate, ph);
+  const unsigned tiles = (unsigned)(((N + bn - 1) / bn) * ((M + bm - 1) / bm));
+  // both column phases per block (contiguous output pairs) when that still
+  // gives at least two blocks per compute unit
+  const bool pair = 2 * tiles >= 512 && ((uintptr_t)C & 7) == 0 && (ldc & 1) == 0 &&
+                    ((uintptr_t)epi.act & 7) == 0;
+  const dim3 grid((unsigned)((N + bn - 1) / bn), (unsigned)((M + bm - 1) / bm), pair ? 2u : 4u);
+#define LBM_NO_PH(WMV, PAIRV)                                                                                  \
+  k_gemm<false, WMV, true, PAIRV><<<grid, NT, 0, h->stream>>>(M, N, 0, A, lda, vecA, B, ldb, vecB, C, ldc, 0, 0, \
+                                                              bias, accumulate, ph, epi.act, epi.skip, epi.relu)
+  if (wm == 1) {
+    if (pair) LBM_NO_PH(1, true); else LBM_NO_PH(1, false);
+  } else {
+    if (pair) LBM_NO_PH(2, true); else LBM_NO_PH(2, false);
+  }
+#undef LBM_NO_PH
   NOCHK(hipGetLastError());
   return LBM_NO_OK;
 }
@@ -789,13 +813,13 @@ int prep_weights(lbm_no* h) {
   return LBM_NO_OK;
 }
 
-int im2col(lbm_no* h, const Layer& l, const float* src, bool nchw, int Bt) {
+int im2col(lbm_no* h, const Layer& l, const float* src, bool nchw, int Bt, bf16_t* col) {
   const int64_t P = (int64_t)Bt * l.Ho * l.Wo;
   const dim3 grid(grid1((P + 1) / 2), (unsigned)l.cin);
   if (nchw)
-    k_im2col<true, false><<<grid, EW, 0, h->stream>>>(src, l.cin, Bt, l.Hs, l.Ws, l.up, l.k, l.s, (l.k - 1) / 2, l.Ho, l.Wo, h->col);
+    k_im2col<true, false><<<grid, EW, 0, h->stream>>>(src, l.cin, Bt, l.Hs, l.Ws, l.up, l.k, l.s, (l.k - 1) / 2, l.Ho, l.Wo, col);
   else
-    k_im2col<false, false><<<grid, EW, 0, h->stream>>>(src, l.cin, Bt, l.Hs, l.Ws, l.up, l.k, l.s, (l.k - 1) / 2, l.Ho, l.Wo, h->col);
+    k_im2col<false, false><<<grid, EW, 0, h->stream>>>(src, l.cin, Bt, l.Hs, l.Ws, l.up, l.k, l.s, (l.k - 1) / 2, l.Ho, l.Wo, col);
   NOCHK(hipGetLastError());
   return LBM_NO_OK;
 }
@@ -805,10 +829,10 @@ int im2col(lbm_no* h, const Layer& l, const float* src, bool nchw, int Bt) {
 // phase GEMMs: phase (a, b) reads the taps dy in {a - 1, a}, dx in {b - 1,
 // b}, i.e. rows (3a + b) cin + [0, 2 cin) and, 3 cin further on, another
 // 2 cin rows.
-int forward_up(lbm_no* h, const Layer& l, const float* src, int Bt, float* z) {
+int forward_up(lbm_no* h, const Layer& l, const float* src, int Bt, bf16_t* col, float* z, const Epi& epi) {
   const int64_t P4 = (int64_t)Bt * l.Hs * l.Ws;
   const dim3 grid(grid1((P4 + 1) / 2), (unsigned)l.cin);
-  k_im2col<false, true><<<grid, EW, 0, h->stream>>>(src, l.cin, Bt, l.Hs, l.Ws, 0, 3, 1, 1, l.Hs, l.Ws, h->col);
+  k_im2col<false, true><<<grid, EW, 0, h->stream>>>(src, l.cin, Bt, l.Hs, l.Ws, 0, 3, 1, 1, l.Hs, l.Ws, col);
   NOCHK(hipGetLastError());
   PhaseT ph{};
   for (int q = 0; q < 4; ++q) {
@@ -820,8 +844,8 @@ int forward_up(lbm_no* h, const Layer& l, const float* src, int Bt, float* z) {
   }
   ph.Hn = l.Hs;
   ph.Wn = l.Ws;
-  return gemm_phases(h, l.cout, (int)P4, h->wph + l.wph, l.Kph, h->col, P4, z, (int64_t)Bt * l.Ho * l.Wo, ph,
-                     h->par + l.boff, 0);
+  return gemm_phases(h, l.cout, (int)P4, h->wph + l.wph, l.Kph, col, P4, z, (int64_t)Bt * l.Ho * l.Wo, ph,
+                     h->par + l.boff, 0, epi);
 }
 
 // Input gradient of a stride-2 layer: E = k_emap(dz), then the four phase
@@ -854,20 +878,22 @@ int forward_internal(lbm_no* h, const float* x, int Bt) {
     const Layer& l = h->L[li];
     const int64_t P = (int64_t)Bt * l.Ho * l.Wo;
     const int K = l.cin * l.k * l.k;
+    // z and, in the GEMM epilogue, a = relu(z) (or z) + skip
+    Epi epi;
+    epi.act = h->a[li];
+    epi.skip = l.skip >= 0 ? h->a[l.skip] : nullptr;
+    epi.relu = l.relu;
     int rc;
     if (phase_kind(l) == 1) {
-      rc = forward_up(h, l, h->a[li - 1], Bt, h->z[li]);
+      rc = forward_up(h, l, h->a[li - 1], Bt, h->colL[li], h->z[li], epi);
     } else {
-      rc = im2col(h, l, li == 0 ? x : h->a[li - 1], li == 0, Bt);
+      rc = im2col(h, l, li == 0 ? x : h->a[li - 1], li == 0, Bt, h->colL[li]);
       if (rc) return rc;
       // z[o][p] = W[o][k] col[k][p]: A k-contiguous, B n-contiguous
-      rc = gemm<false>(h, l.cout, (int)P, K, h->wf + l.wf, l.Kp, h->col, P, h->z[li], P, 0, 1, K,
-                       h->par + l.boff);
+      rc = gemm<false>(h, l.cout, (int)P, K, h->wf + l.wf, l.Kp, h->colL[li], P, h->z[li], P, 0, 1, K,
+                       h->par + l.boff, 0, epi);
     }
     if (rc) return rc;
-    const int64_t n = (int64_t)l.cout * P;
-    k_act<<<grid1(n), EW, 0, h->stream>>>(h->z[li], l.skip >= 0 ? h->a[l.skip] : nullptr, h->a[li], n, l.relu);
-    NOCHK(hipGetLastError());
   }
   return LBM_NO_OK;
 }
@@ -988,7 +1014,11 @@ int lbm_no_create(const int32_t* widths, int32_t height, int32_t width, int32_t 
       h->a.push_back(al);
       h->da.push_back(dl);
       const int64_t K = (int64_t)l.cin * l.k * l.k;
-      colmax = std::max(colmax, K * P);
+      // the forward's im2col, kept: over the source grid for upsampling layers
+      const int64_t ncol = l.up ? 9 * l.cin * (int64_t)max_batch * l.Hs * l.Ws : K * P;
+      bf16_t* cl = (bf16_t*)nalloc(h, (size_t)ncol * 2);
+      if (!cl) return bail(fail(LBM_NO_ENOMEM, "im2col buffers"));
+      h->colL.push_back(cl);
       if (phase_kind(l) == 2) colmax = std::max(colmax, 4 * l.cout * P);  // k_emap's stack
       int S;
       int64_t kchunk;
@@ -1088,15 +1118,13 @@ int lbm_no_gradients(lbm_no* h, const float* x, const float* target, int32_t bat
         k_dmap<<<dim3(grid1((int64_t)l.Hs * l.Ws), (unsigned)l.cout, (unsigned)batch), EW, 0, h->stream>>>(
             h->z[li], l.cout, batch, l.Hs, l.Ws, h->col);
         NOCHK(hipGetLastError());
-        // the source in bfloat16 (over dz16, which this path does not read)
-        k_to_bf16<<<grid1(l.cin * P4), EW, 0, h->stream>>>(h->a[li - 1], l.cin * P4, h->dz16);
-        NOCHK(hipGetLastError());
-        // dW[o][c][t] = sum_s D[t cout + o][s] src[c][s]: A = D, B k(=s)-contiguous
+        // dW[o][c][t] = sum_s D[t cout + o][s] src[c][s]: A = D, B k(=s)-contiguous, the
+        // source in bfloat16 being the centre tap (rows 4 cin ..) of the forward's im2col
         wgrad_split(M9, l.cin, P4, S, kchunk);
         const int64_t mn = (int64_t)M9 * l.cin;
         if ((int64_t)S * mn > h->split_n) return fail(LBM_NO_EINVAL, "split work space too small");
-        rc = gemm<true>(h, M9, l.cin, (int)P4, h->col, P4, h->dz16, P4, h->split, l.cin, mn, S, (int)kchunk,
-                        nullptr);
+        rc = gemm<true>(h, M9, l.cin, (int)P4, h->col, P4, h->colL[li] + 4 * l.cin * P4, P4, h->split, l.cin, mn,
+                        S, (int)kchunk, nullptr);
         if (rc) return rc;
         k_sum_splits<<<(unsigned)((mn + 63) / 64), 64 * SW, 0, h->stream>>>(h->split, S, mn, h->grad + l.woff, 9,
                                                                          l.cout, l.cin);
@@ -1110,14 +1138,12 @@ int lbm_no_gradients(lbm_no* h, const float* x, const float* target, int32_t bat
         have[li - 1] = 1;
         continue;
       }
-      rc = im2col(h, l, li == 0 ? x : h->a[li - 1], li == 0, batch);
-      if (rc) return rc;
-      // weight gradient, split over p, partials summed in order
+      // weight gradient over the forward's im2col, split over p, partials summed in order
       wgrad_split(l.cout, K, P, S, kchunk);
       const int64_t mn = (int64_t)l.cout * K;
       if ((int64_t)S * mn > h->split_n) return fail(LBM_NO_EINVAL, "split work space too small");
       // dW[o][k] = dz[o][p] col[k][p]: A k(=p)-contiguous, B k(=p)-contiguous
-      rc = gemm<true>(h, l.cout, K, (int)P, h->dz16, P, h->col, P, h->split, K, mn, S, (int)kchunk, nullptr);
+      rc = gemm<true>(h, l.cout, K, (int)P, h->dz16, P, h->colL[li], P, h->split, K, mn, S, (int)kchunk, nullptr);
       if (rc) return rc;
       k_sum_splits<<<(unsigned)((mn + 63) / 64), 64 * SW, 0, h->stream>>>(h->split, S, mn, h->grad + l.woff, 0, 0,
                                                                        0);
