@@ -88,8 +88,8 @@ __device__ inline uint32_t word(const uint4& v, int d) { return d == 0 ? v.x : d
 // transposed on the way when n-contiguous: each thread turns a 4 (k) x 8 (n)
 // block around in registers and writes eight 8-byte rows).  The next stage's
 // operands are loaded into registers while the current one is multiplied.
-// accumulate: C += instead of C =.  act (single split): also act[i] =
-// relu(C[i]) (or C[i]) + skip[i] (skip may be null), the layer activation.
+// accumulate: C += instead of C =.  relu (single split): C = max(C, 0) as
+// stored, the activation of a layer without a skip input.
 // PH: four phase GEMMs of a stride-2 grid relation, phase q = (py, px) = (q
 // / 2, q % 2), no split: A + ph.aoff[q], reduction length ph.K[q], B row k
 // taken from row ph.base[q] + k (+ ph.gap[q] once k >= ph.run[q]), and column
@@ -111,11 +111,8 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, const bf16_t* 
                                              int64_t lda, int vecA, const bf16_t* __restrict__ B,
                                              int64_t ldb, int vecB, float* __restrict__ C, int64_t ldc,
                                              int64_t cz, int kchunk, const float* __restrict__ bias,
-                                             int accumulate, PhaseT ph, float* __restrict__ act,
-                                             const float* __restrict__ skip, int relu) {
+                                             int accumulate, PhaseT ph, int relu) {
   static_assert(!(PH && BKC) && (PH || !PAIR), "phase GEMMs take an n-contiguous B");
-  // the layer activation of an output value v (same layout as C)
-  auto activate = [&](float v, int64_t i) { return (relu ? fmaxf(v, 0.0f) : v) + (skip ? skip[i] : 0.0f); };
   constexpr int WN = 4 / WM, TBM = 64 * WM, TBN = 64 * WN;
   constexpr int NA = TBM * GBK / 8 / NT;   // 16-byte A chunks per thread and stage
   constexpr int NB = TBN * GBK / 8 / NT;   // 16-byte B chunks per thread and stage
@@ -237,11 +234,9 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, const bf16_t* 
         for (int j = 0; j < 4; ++j) {
           const int gn = n0 + wn + j * 16 + (lane & 15);
           if (gn < N) {
-            const int64_t idx = (int64_t)gm * ldc + cof[j];
-            float* c = Cz + idx;
+            float* c = Cz + (int64_t)gm * ldc + cof[j];
             const float v = (accumulate ? *c : 0.0f) + (acc[i][j][r] + bv);
-            *c = v;
-            if (act) act[idx] = activate(v, idx);
+            *c = relu ? fmaxf(v, 0.0f) : v;
           }
         }
       }
@@ -272,13 +267,12 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, const bf16_t* 
         for (int j = 0; j < 4; ++j) {
           const int gn = n0 + wn + j * 16 + (lane & 15);
           if (gn < N) {
-            const int64_t idx = (int64_t)gm * ldc + cof[j];
-            float2* c = (float2*)(C + idx);
+            float2* c = (float2*)(C + (int64_t)gm * ldc + cof[j]);
             float2 v = accumulate ? *c : make_float2(0.0f, 0.0f);
             v.x += acc0[i][j][r] + bv;
             v.y += acc1[i][j][r] + bv;
+            if (relu) v = make_float2(fmaxf(v.x, 0.0f), fmaxf(v.y, 0.0f));
             *c = v;
-            if (act) *(float2*)(act + idx) = make_float2(activate(v.x, idx), activate(v.y, idx + 1));
           }
         }
       }
@@ -345,16 +339,26 @@ __device__ inline float block_sum(float v, float* sh) {
   return t;
 }
 
-// dz = da where z > 0 (relu) or da; written over z, and as bfloat16 (the
-// GEMM operand) into dz16; the bias gradient's partial sums: block (x, o)
+// a = relu(z) (or z) + skip
+__global__ __launch_bounds__(EW) void k_act(const float* __restrict__ z, const float* __restrict__ skip,
+                                            float* __restrict__ a, int64_t n, int relu) {
+  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
+  if (i >= n) return;
+  float v = z[i];
+  if (relu) v = fmaxf(v, 0.0f);
+  a[i] = skip ? v + skip[i] : v;
+}
+
+// dz = da where mask > 0 (relu; the mask is z, or a = relu(z)) or da;
+// written to dz, and as bfloat16 (the GEMM operand) into dz16; the bias gradient's partial sums: block (x, o)
 // covers ACT_CHUNK entries of channel o's row (dz is [cout][P]) and writes
 // their sum, in a fixed order, to bpart[o][x]; and with a skip input (a =
 // act(z) + skip), its gradient: skip_da (+)= da.
 constexpr int ACT_PER = 4;                 // entries per thread
 constexpr int ACT_CHUNK = EW * ACT_PER;   // entries per block
-__global__ __launch_bounds__(EW) void k_act_bwd(const float* __restrict__ da, float* __restrict__ z,
-                                                bf16_t* __restrict__ dz16, int64_t P, int relu,
-                                                float* __restrict__ bpart, float* __restrict__ skip_da,
+__global__ __launch_bounds__(EW) void k_act_bwd(const float* __restrict__ da, const float* __restrict__ mask,
+                                                float* __restrict__ dz, bf16_t* __restrict__ dz16, int64_t P,
+                                                int relu, float* __restrict__ bpart, float* __restrict__ skip_da,
                                                 int skip_acc) {
   __shared__ float sh[EW / 64];
   const int o = blockIdx.y;
@@ -368,8 +372,8 @@ __global__ __launch_bounds__(EW) void k_act_bwd(const float* __restrict__ da, fl
       const int64_t i = row + p;
       const float d = da[i];
       if (skip_da) skip_da[i] = skip_acc ? skip_da[i] + d : d;
-      const float v = (!relu || z[i] > 0.0f) ? d : 0.0f;
-      z[i] = v;
+      const float v = (!relu || mask[i] > 0.0f) ? d : 0.0f;
+      dz[i] = v;
       dz16[i] = to_bf16(v);
       sum += v;
     }
@@ -724,19 +728,12 @@ void specs(const int* w, int H, int W, std::vector<Layer>& L, int64_t& npar) {
 }
 
 // C = A B (see k_gemm); A k-contiguous with leading dimension lda >= K.
-// Layer activation written by a GEMM epilogue (k_gemm act).
-struct Epi {
-  float* act = nullptr;
-  const float* skip = nullptr;
-  int relu = 0;
-};
-
 template <bool BKC>
 int gemm(lbm_no* h, int M, int N, int K, const bf16_t* A, int64_t lda, const bf16_t* B, int64_t ldb,
          float* C, int64_t ldc, int64_t cz, int splits, int kchunk, const float* bias, int accumulate = 0,
-         const Epi& epi = Epi()) {
+         int relu = 0) {
   if (M <= 0 || N <= 0 || K <= 0) return LBM_NO_OK;
-  if (lda < K || (BKC ? ldb < K : ldb < N) || kchunk < 1 || (splits > 1 && (kchunk % GBK || epi.act)))
+  if (lda < K || (BKC ? ldb < K : ldb < N) || kchunk < 1 || (splits > 1 && (kchunk % GBK || relu)))
     return fail(LBM_NO_EINVAL, "GEMM operand shapes");
   auto aligned = [](const void* p, int64_t ld) { return ((uintptr_t)p & 15) == 0 && ld % 8 == 0; };
   const int vecA = aligned(A, lda) && kchunk % 8 == 0, vecB = aligned(B, ldb) && (!BKC || kchunk % 8 == 0);
@@ -745,12 +742,10 @@ int gemm(lbm_no* h, int M, int N, int K, const bf16_t* A, int64_t lda, const bf1
   const PhaseT ph{};
   if (wm == 1)
     k_gemm<BKC, 1, false, false><<<grid, NT, 0, h->stream>>>(M, N, K, A, lda, vecA, B, ldb, vecB, C, ldc, cz,
-                                                             kchunk, bias, accumulate, ph, epi.act, epi.skip,
-                                                             epi.relu);
+                                                             kchunk, bias, accumulate, ph, relu);
   else
     k_gemm<BKC, 2, false, false><<<grid, NT, 0, h->stream>>>(M, N, K, A, lda, vecA, B, ldb, vecB, C, ldc, cz,
-                                                             kchunk, bias, accumulate, ph, epi.act, epi.skip,
-                                                             epi.relu);
+                                                             kchunk, bias, accumulate, ph, relu);
   NOCHK(hipGetLastError());
   return LBM_NO_OK;
 }
@@ -759,8 +754,7 @@ int gemm(lbm_no* h, int M, int N, int K, const bf16_t* A, int64_t lda, const bf1
 // four blocks of M rows of lda at A + q M lda, B n-contiguous with ldb, C
 // rows of ldc over the 2Hn x 2Wn grid.
 int gemm_phases(lbm_no* h, int M, int N, const bf16_t* A, int64_t lda, const bf16_t* B, int64_t ldb,
-                float* C, int64_t ldc, const PhaseT& ph, const float* bias, int accumulate,
-                const Epi& epi = Epi()) {
+                float* C, int64_t ldc, const PhaseT& ph, const float* bias, int accumulate, int relu = 0) {
   if (M <= 0 || N <= 0) return LBM_NO_OK;
   for (int q = 0; q < 4; ++q)
     if (ph.K[q] < 1 || ph.K[q] > lda || ph.aoff[q] != (int64_t)q * M * lda)
@@ -771,12 +765,11 @@ int gemm_phases(lbm_no* h, int M, int N, const bf16_t* A, int64_t lda, const bf1
   const unsigned tiles = (unsigned)(((N + bn - 1) / bn) * ((M + bm - 1) / bm));
   // both column phases per block (contiguous output pairs) when that still
   // gives at least two blocks per compute unit
-  const bool pair = 2 * tiles >= 512 && ((uintptr_t)C & 7) == 0 && (ldc & 1) == 0 &&
-                    ((uintptr_t)epi.act & 7) == 0;
+  const bool pair = 2 * tiles >= 512 && ((uintptr_t)C & 7) == 0 && (ldc & 1) == 0;
   const dim3 grid((unsigned)((N + bn - 1) / bn), (unsigned)((M + bm - 1) / bm), pair ? 2u : 4u);
 #define LBM_NO_PH(WMV, PAIRV)                                                                                  \
   k_gemm<false, WMV, true, PAIRV><<<grid, NT, 0, h->stream>>>(M, N, 0, A, lda, vecA, B, ldb, vecB, C, ldc, 0, 0, \
-                                                              bias, accumulate, ph, epi.act, epi.skip, epi.relu)
+                                                              bias, accumulate, ph, relu)
   if (wm == 1) {
     if (pair) LBM_NO_PH(1, true); else LBM_NO_PH(1, false);
   } else {
@@ -829,7 +822,7 @@ int im2col(lbm_no* h, const Layer& l, const float* src, bool nchw, int Bt, bf16_
 // phase GEMMs: phase (a, b) reads the taps dy in {a - 1, a}, dx in {b - 1,
 // b}, i.e. rows (3a + b) cin + [0, 2 cin) and, 3 cin further on, another
 // 2 cin rows.
-int forward_up(lbm_no* h, const Layer& l, const float* src, int Bt, bf16_t* col, float* z, const Epi& epi) {
+int forward_up(lbm_no* h, const Layer& l, const float* src, int Bt, bf16_t* col, float* z) {
   const int64_t P4 = (int64_t)Bt * l.Hs * l.Ws;
   const dim3 grid(grid1((P4 + 1) / 2), (unsigned)l.cin);
   k_im2col<false, true><<<grid, EW, 0, h->stream>>>(src, l.cin, Bt, l.Hs, l.Ws, 0, 3, 1, 1, l.Hs, l.Ws, col);
@@ -845,7 +838,7 @@ int forward_up(lbm_no* h, const Layer& l, const float* src, int Bt, bf16_t* col,
   ph.Hn = l.Hs;
   ph.Wn = l.Ws;
   return gemm_phases(h, l.cout, (int)P4, h->wph + l.wph, l.Kph, col, P4, z, (int64_t)Bt * l.Ho * l.Wo, ph,
-                     h->par + l.boff, 0, epi);
+                     h->par + l.boff, 0);
 }
 
 // Input gradient of a stride-2 layer: E = k_emap(dz), then the four phase
@@ -878,22 +871,28 @@ int forward_internal(lbm_no* h, const float* x, int Bt) {
     const Layer& l = h->L[li];
     const int64_t P = (int64_t)Bt * l.Ho * l.Wo;
     const int K = l.cin * l.k * l.k;
-    // z and, in the GEMM epilogue, a = relu(z) (or z) + skip
-    Epi epi;
-    epi.act = h->a[li];
-    epi.skip = l.skip >= 0 ? h->a[l.skip] : nullptr;
-    epi.relu = l.relu;
+    // a layer with a skip input keeps z (the relu mask of its backward) and
+    // adds the skip in k_act; any other layer's GEMM writes a = relu(z) (or
+    // z) itself, and its backward takes the mask from a (a > 0 exactly where
+    // z > 0)
     int rc;
     if (phase_kind(l) == 1) {
-      rc = forward_up(h, l, h->a[li - 1], Bt, h->colL[li], h->z[li], epi);
+      if (l.skip < 0) return fail(LBM_NO_EINVAL, "upsampling layer without a skip input");
+      rc = forward_up(h, l, h->a[li - 1], Bt, h->colL[li], h->z[li]);
     } else {
       rc = im2col(h, l, li == 0 ? x : h->a[li - 1], li == 0, Bt, h->colL[li]);
       if (rc) return rc;
       // z[o][p] = W[o][k] col[k][p]: A k-contiguous, B n-contiguous
-      rc = gemm<false>(h, l.cout, (int)P, K, h->wf + l.wf, l.Kp, h->colL[li], P, h->z[li], P, 0, 1, K,
-                       h->par + l.boff, 0, epi);
+      float* out = l.skip >= 0 ? h->z[li] : h->a[li];
+      rc = gemm<false>(h, l.cout, (int)P, K, h->wf + l.wf, l.Kp, h->colL[li], P, out, P, 0, 1, K,
+                       h->par + l.boff, 0, l.skip >= 0 ? 0 : l.relu);
     }
     if (rc) return rc;
+    if (l.skip >= 0) {
+      const int64_t n = (int64_t)l.cout * P;
+      k_act<<<grid1(n), EW, 0, h->stream>>>(h->z[li], h->a[l.skip], h->a[li], n, l.relu);
+      NOCHK(hipGetLastError());
+    }
   }
   return LBM_NO_OK;
 }
@@ -1103,7 +1102,9 @@ int lbm_no_gradients(lbm_no* h, const float* x, const float* target, int32_t bat
       // dz over z (and the bias gradient's partial sums); the skip passes da on unchanged
       const unsigned nchunk = (unsigned)((P + ACT_CHUNK - 1) / ACT_CHUNK);
       float* skip_da = l.skip >= 0 ? h->da[l.skip] : nullptr;
-      k_act_bwd<<<dim3(nchunk, (unsigned)l.cout), EW, 0, h->stream>>>(h->da[li], h->z[li], h->dz16, P, l.relu,
+      // the relu mask: z where the layer has a skip input, else a (= relu(z)); dz over z
+      const float* mask = l.skip >= 0 ? h->z[li] : h->a[li];
+      k_act_bwd<<<dim3(nchunk, (unsigned)l.cout), EW, 0, h->stream>>>(h->da[li], mask, h->z[li], h->dz16, P, l.relu,
                                                                        h->bpart, skip_da,
                                                                        l.skip >= 0 ? have[l.skip] : 0);
       NOCHK(hipGetLastError());
