@@ -114,6 +114,38 @@ def test_full_widths_match_oracle(torch):
             o += n
 
 
+def test_paired_phase_gemms_match_oracle(torch):
+    """128 x 128, batch 16: the phase GEMMs of the first stride-2 layer's input
+    gradient and of the last upsampling layer's forward have 256 tiles of
+    64 x 256 outputs, so each block runs both column phases and stores output
+    pairs (the form the training runs take); the smaller phase GEMMs of the
+    same step run one phase per block."""
+    from paper_1409_5929_amd.no import WarmStartNet
+
+    rng = np.random.default_rng(22)
+    params = li.no_init_params(WIDTHS, seed=22)
+    params = params + (0.05 * rng.standard_normal(params.size)).astype(np.float32)
+    x = rng.standard_normal((16, 6, 128, 128)).astype(np.float32)
+    t = rng.standard_normal((16, 3, 128, 128)).astype(np.float32)
+    net = WarmStartNet(WIDTHS, 128, 128, 16, params)
+    y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
+    loss = net.gradients(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
+    g = net.grads()
+    net.close()
+    p64 = params.astype(np.float64)
+    ref, _ = N.forward(p64, WIDTHS, x.astype(np.float64))
+    lref, gref = N.loss_and_grads(p64, WIDTHS, x.astype(np.float64), t.astype(np.float64))
+    ey, eg = rel(y, ref), rel(g, gref)
+    print(f"paired phases: forward rel L2 {ey:.2e}, loss {loss:.6f} (oracle {lref:.6f}), gradient rel L2 {eg:.2e}",
+          flush=True)
+    assert ey <= TOL and eg <= TOL and abs(loss - lref) <= TOL * lref
+    o = 0
+    for ci, co, k, *_ in N.layer_specs(WIDTHS):
+        for n in (co * ci * k * k, co):
+            assert rel(g[o:o + n], gref[o:o + n]) <= 2 * TOL, (o, n)
+            o += n
+
+
 def test_adam_step_matches_oracle(torch):
     from paper_1409_5929_amd.no import WarmStartNet
 
