@@ -350,7 +350,8 @@ __global__ __launch_bounds__(EW) void k_act(const float* __restrict__ z, const f
 }
 
 // dz = da where mask > 0 (relu; the mask is z, or a = relu(z)) or da;
-// written to dz, and as bfloat16 (the GEMM operand) into dz16; the bias gradient's partial sums: block (x, o)
+// written to dz and (the GEMM operand) as bfloat16 into dz16 (either may be
+// null); the bias gradient's partial sums: block (x, o)
 // covers ACT_CHUNK entries of channel o's row (dz is [cout][P]) and writes
 // their sum, in a fixed order, to bpart[o][x]; and with a skip input (a =
 // act(z) + skip), its gradient: skip_da (+)= da.
@@ -373,8 +374,8 @@ __global__ __launch_bounds__(EW) void k_act_bwd(const float* __restrict__ da, co
       const float d = da[i];
       if (skip_da) skip_da[i] = skip_acc ? skip_da[i] + d : d;
       const float v = (!relu || mask[i] > 0.0f) ? d : 0.0f;
-      dz[i] = v;
-      dz16[i] = to_bf16(v);
+      if (dz) dz[i] = v;
+      if (dz16) dz16[i] = to_bf16(v);
       sum += v;
     }
   }
@@ -384,16 +385,26 @@ __global__ __launch_bounds__(EW) void k_act_bwd(const float* __restrict__ da, co
 
 
 
-// db[o] = sum_p dz[o][p] from k_act_bwd's nchunk partial sums of channel o:
-// one block per channel, fixed order.
-__global__ __launch_bounds__(EW) void k_bias_grad(const float* __restrict__ bpart, int nchunk,
-                                                  float* __restrict__ db) {
+// db[o] = sum_p dz[o][p] of every layer from k_act_bwd's partial sums:
+// block b is channel b - first[l] of layer l, adding the layer's nchunk
+// partial sums of that channel in a fixed order into grad[boff[l] + o].
+constexpr int MAXLB = 8;
+struct BiasT {
+  int64_t bpoff[MAXLB], boff[MAXLB];
+  int nchunk[MAXLB], first[MAXLB + 1];
+  int nl;
+};
+__global__ __launch_bounds__(EW) void k_bias_grad(const float* __restrict__ bpart, BiasT t,
+                                                  float* __restrict__ grad) {
   __shared__ float sh[EW / 64];
-  const float* row = bpart + (int64_t)blockIdx.x * nchunk;
+  int l = 0;
+  while ((int)blockIdx.x >= t.first[l + 1]) ++l;
+  const int o = (int)blockIdx.x - t.first[l];
+  const float* row = bpart + t.bpoff[l] + (int64_t)o * t.nchunk[l];
   float v = 0.0f;
-  for (int q = threadIdx.x; q < nchunk; q += EW) v += row[q];
+  for (int q = threadIdx.x; q < t.nchunk[l]; q += EW) v += row[q];
   v = block_sum(v, sh);
-  if (threadIdx.x == 0) db[blockIdx.x] = v;
+  if (threadIdx.x == 0) grad[t.boff[l] + o] = v;
 }
 
 // out[j(i)] = sum_s part[s][i] in a fixed order: wave w of a block adds
@@ -471,22 +482,22 @@ __global__ __launch_bounds__(EW) void k_dmap(const float* __restrict__ dz, int c
 // 2Wo, output Ho x Wo): input (2y + a, 2x + b) receives output rows y + ey,
 // ey in {0, 1}, and columns x + ex, so one stack of dz shifted by (ey, ex),
 //   E[(2 ey + ex) cout + o][b][y][x] = dz[o][b][y + ey][x + ex] (0 outside),
-// bfloat16, [4 cout][P], P = batch Ho Wo, serves all four phase GEMMs.
-__global__ __launch_bounds__(EW) void k_emap(const float* __restrict__ dz, int cout, int Bt, int Ho,
+// bfloat16, [4 cout][P], P = batch Ho Wo, serves all four phase GEMMs
+// (copied from dz in bfloat16).
+__global__ __launch_bounds__(EW) void k_emap(const bf16_t* __restrict__ dz, int cout, int Bt, int Ho,
                                              int Wo, bf16_t* __restrict__ E) {
   const int pix = (int)(blockIdx.x * EW + threadIdx.x);
   if (pix >= Ho * Wo) return;
   const int o = blockIdx.y, b = blockIdx.z;
   const int y = pix / Wo, x = pix - y * Wo;
-  const float* base = dz + ((int64_t)o * Bt + b) * Ho * Wo;
+  const bf16_t* base = dz + ((int64_t)o * Bt + b) * Ho * Wo;
   const int64_t P = (int64_t)Bt * Ho * Wo, s = (int64_t)b * Ho * Wo + pix;
 #pragma unroll
   for (int ey = 0; ey < 2; ++ey)
 #pragma unroll
-    for (int ex = 0; ex < 2; ++ex) {
-      const float v = (y + ey < Ho && x + ex < Wo) ? base[(y + ey) * Wo + x + ex] : 0.0f;
-      E[((int64_t)(2 * ey + ex) * cout + o) * P + s] = to_bf16(v);
-    }
+    for (int ex = 0; ex < 2; ++ex)
+      E[((int64_t)(2 * ey + ex) * cout + o) * P + s] =
+          (y + ey < Ho && x + ex < Wo) ? base[(y + ey) * Wo + x + ex] : (bf16_t)0;
 }
 
 // y is [3][b][hw] (channel-major), t is [b][3][hw]: dy = 2 (y - t) / n and
@@ -577,6 +588,7 @@ struct Layer {
   // layers' input gradient (cin rows, k = (ey, ex, o)); see k_prep
   int Kph;
   int64_t wph;
+  int64_t bpoff;  // the layer's bias-gradient partial sums in lbm_no::bpart
 };
 
 // Weight copies of the layers for the GEMMs (see Layer::wf, Layer::wt).
@@ -585,6 +597,8 @@ struct PrepT {
   int64_t woff[MAXL], wf[MAXL], wt[MAXL], wu[MAXL], wph[MAXL];
   int cout[MAXL], cin[MAXL], K[MAXL], Kp[MAXL], coutp[MAXL], Kup[MAXL], taps[MAXL], Kph[MAXL];
   int kind[MAXL];  // 0 plain, 1 upsampling, 2 stride 2
+  int64_t first[MAXL + 1];  // k_prep's flat index: layer l covers [first[l], first[l + 1])
+  int nl;
 };
 
 // Phase weights of entry j of the four phases q = (a, b) (rows of Kph; the
@@ -622,15 +636,18 @@ __device__ inline void prep_phase(const float* __restrict__ W, const PrepT& t, i
   }
 }
 
-// Block (x, layer y): weight i of the layer, rounded to bfloat16, into its
-// copies (their padding stays zero from create), then the layer's phase
-// weights (prep_phase) for i beyond the weight count.
+// One flat index over the layers: in layer l, weight i, rounded to
+// bfloat16, into its copies (their padding stays zero from create), then the
+// layer's phase weights (prep_phase) for i beyond the weight count.
 __global__ __launch_bounds__(EW) void k_prep(const float* __restrict__ par, PrepT t,
                                              bf16_t* __restrict__ wf, bf16_t* __restrict__ wt,
                                              bf16_t* __restrict__ wu, bf16_t* __restrict__ wph) {
-  const int l = blockIdx.y;
+  const int64_t g = (int64_t)blockIdx.x * EW + threadIdx.x;
+  if (g >= t.first[t.nl]) return;
+  int l = 0;
+  while (g >= t.first[l + 1]) ++l;
   const int K = t.K[l];
-  const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
+  const int64_t i = g - t.first[l];
   const int64_t nw = (int64_t)t.cout[l] * K;
   if (i >= nw) {
     if (t.kind[l] != 0 && i < nw + 16 * (int64_t)t.cin[l] * t.cout[l]) prep_phase(par + t.woff[l], t, l, i - nw, wph);
@@ -712,7 +729,7 @@ void specs(const int* w, int H, int W, std::vector<Layer>& L, int64_t& npar) {
   npar = 0;
   int h = H, ww = W;
   for (auto& d : def) {
-    Layer l{d[0], d[1], d[2], d[3], d[4], d[5], d[6], h, ww, 0, 0, 0, 0, 0, 0, 0, 0, 0, -1, 0, -1};
+    Layer l{d[0], d[1], d[2], d[3], d[4], d[5], d[6], h, ww, 0, 0, 0, 0, 0, 0, 0, 0, 0, -1, 0, -1, 0};
     const int he = l.up ? 2 * h : h, we = l.up ? 2 * ww : ww;
     const int pad = (l.k - 1) / 2;
     l.Ho = (he + 2 * pad - l.k) / l.s + 1;
@@ -784,6 +801,7 @@ int gemm_phases(lbm_no* h, int M, int N, const bf16_t* A, int64_t lda, const bf1
 int prep_weights(lbm_no* h) {
   PrepT t{};
   const int nl = (int)h->L.size();
+  t.first[0] = 0;
   for (int l = 0; l < nl; ++l) {
     const Layer& y = h->L[l];
     t.woff[l] = y.woff;
@@ -800,8 +818,10 @@ int prep_weights(lbm_no* h) {
     t.wph[l] = y.wph;
     t.Kph[l] = y.Kph;
     t.kind[l] = phase_kind(y);
+    t.first[l + 1] = t.first[l] + (int64_t)y.cout * t.K[l] + (t.kind[l] ? 16 * (int64_t)y.cin * y.cout : 0);
   }
-  k_prep<<<dim3(grid1(h->wmax), (unsigned)nl), EW, 0, h->stream>>>(h->par, t, h->wf, h->wt, h->wu, h->wph);
+  t.nl = nl;
+  k_prep<<<grid1(t.first[nl]), EW, 0, h->stream>>>(h->par, t, h->wf, h->wt, h->wu, h->wph);
   NOCHK(hipGetLastError());
   return LBM_NO_OK;
 }
@@ -841,12 +861,12 @@ int forward_up(lbm_no* h, const Layer& l, const float* src, int Bt, bf16_t* col,
                      h->par + l.boff, 0);
 }
 
-// Input gradient of a stride-2 layer: E = k_emap(dz), then the four phase
+// Input gradient of a stride-2 layer: E = k_emap(dz, bfloat16), then the four phase
 // GEMMs into dx (accumulating when it already holds a gradient): phase
 // (a, b) takes (1 + a)(1 + b) blocks of cout rows of E, (ey, ex) with ey <=
 // a, ex <= b, i.e. rows [0, (1 + b) cout) and, for a = 1, the rows of ey = 1
 // from 2 cout on.
-int input_grad_s2(lbm_no* h, const Layer& l, const float* dz, int Bt, float* dx, int accumulate) {
+int input_grad_s2(lbm_no* h, const Layer& l, const bf16_t* dz, int Bt, float* dx, int accumulate) {
   const int64_t P = (int64_t)Bt * l.Ho * l.Wo;
   k_emap<<<dim3(grid1((int64_t)l.Ho * l.Wo), (unsigned)l.cout, (unsigned)Bt), EW, 0, h->stream>>>(
       dz, l.cout, Bt, l.Ho, l.Wo, h->col);
@@ -1029,7 +1049,8 @@ int lbm_no_create(const int32_t* widths, int32_t height, int32_t width, int32_t 
         wgrad_split(9 * l.cout, l.cin, P4, S, kchunk);
         splitmax = std::max(splitmax, (int64_t)S * 9 * l.cout * l.cin);
       }
-      bpmax = std::max(bpmax, (int64_t)l.cout * ((P + ACT_CHUNK - 1) / ACT_CHUNK));
+      h->L[li].bpoff = bpmax;  // the layers' partial sums side by side
+      bpmax += (int64_t)l.cout * ((P + ACT_CHUNK - 1) / ACT_CHUNK);
     }
     h->col = (bf16_t*)nalloc(h, (size_t)colmax * 2);
     h->dz16 = (bf16_t*)nalloc(h, (size_t)actmax * 2);
@@ -1104,8 +1125,10 @@ int lbm_no_gradients(lbm_no* h, const float* x, const float* target, int32_t bat
       float* skip_da = l.skip >= 0 ? h->da[l.skip] : nullptr;
       // the relu mask: z where the layer has a skip input, else a (= relu(z)); dz over z
       const float* mask = l.skip >= 0 ? h->z[li] : h->a[li];
-      k_act_bwd<<<dim3(nchunk, (unsigned)l.cout), EW, 0, h->stream>>>(h->da[li], mask, h->z[li], h->dz16, P, l.relu,
-                                                                       h->bpart, skip_da,
+      // FP32 dz for the box sums of an upsampling layer, else bfloat16 dz for the GEMMs
+      k_act_bwd<<<dim3(nchunk, (unsigned)l.cout), EW, 0, h->stream>>>(h->da[li], mask, l.up ? h->z[li] : nullptr,
+                                                                       l.up ? nullptr : h->dz16, P, l.relu,
+                                                                       h->bpart + l.bpoff, skip_da,
                                                                        l.skip >= 0 ? have[l.skip] : 0);
       NOCHK(hipGetLastError());
       if (l.skip >= 0) have[l.skip] = 1;
@@ -1130,8 +1153,6 @@ int lbm_no_gradients(lbm_no* h, const float* x, const float* target, int32_t bat
         k_sum_splits<<<(unsigned)((mn + 63) / 64), 64 * SW, 0, h->stream>>>(h->split, S, mn, h->grad + l.woff, 9,
                                                                          l.cout, l.cin);
         NOCHK(hipGetLastError());
-        k_bias_grad<<<(unsigned)l.cout, EW, 0, h->stream>>>(h->bpart, (int)nchunk, h->grad + l.boff);
-        NOCHK(hipGetLastError());
         // da[li - 1][c][s] (+)= sum_{t, o} W[o][c][t] D[t cout + o][s]: A = wu, B = D n(=s)-contiguous
         rc = gemm<false>(h, l.cin, (int)P4, M9, h->wu + l.wu, l.Kup, h->col, P4, h->da[li - 1], P4, 0, 1, M9,
                          nullptr, have[li - 1]);
@@ -1149,8 +1170,6 @@ int lbm_no_gradients(lbm_no* h, const float* x, const float* target, int32_t bat
       k_sum_splits<<<(unsigned)((mn + 63) / 64), 64 * SW, 0, h->stream>>>(h->split, S, mn, h->grad + l.woff, 0, 0,
                                                                        0);
       NOCHK(hipGetLastError());
-      k_bias_grad<<<(unsigned)l.cout, EW, 0, h->stream>>>(h->bpart, (int)nchunk, h->grad + l.boff);
-      NOCHK(hipGetLastError());
       if (li == 0) break;  // no gradient with respect to the input
       if (l.k == 1 && l.s == 1) {  // 1 x 1: the input gradient is the GEMM itself
         rc = gemm<false>(h, K, (int)P, l.cout, h->wt + l.wt, l.coutp, h->dz16, P, h->da[li - 1], P, 0, 1, l.cout,
@@ -1160,7 +1179,7 @@ int lbm_no_gradients(lbm_no* h, const float* x, const float* target, int32_t bat
         continue;
       }
       if (phase_kind(l) == 2) {
-        rc = input_grad_s2(h, l, h->z[li], batch, h->da[li - 1], have[li - 1]);
+        rc = input_grad_s2(h, l, h->dz16, batch, h->da[li - 1], have[li - 1]);
         if (rc) return rc;
         have[li - 1] = 1;
         continue;
@@ -1168,6 +1187,20 @@ int lbm_no_gradients(lbm_no* h, const float* x, const float* target, int32_t bat
       // every layer with an input gradient is upsampling, stride 2 or 1 x 1 (specs)
       return fail(LBM_NO_EINVAL, "no input-gradient path for this layer");
     }
+    // every layer's bias gradient from its partial sums, one launch
+    BiasT bt{};
+    bt.first[0] = 0;
+    for (int li = 0; li < nl; ++li) {
+      const Layer& l = h->L[li];
+      const int64_t P = (int64_t)batch * l.Ho * l.Wo;
+      bt.bpoff[li] = l.bpoff;
+      bt.boff[li] = l.boff;
+      bt.nchunk[li] = (int)((P + ACT_CHUNK - 1) / ACT_CHUNK);
+      bt.first[li + 1] = bt.first[li] + l.cout;
+    }
+    bt.nl = nl;
+    k_bias_grad<<<(unsigned)bt.first[nl], EW, 0, h->stream>>>(h->bpart, bt, h->grad);
+    NOCHK(hipGetLastError());
     if (loss) {
       NOCHK(hipMemcpyAsync(loss, h->dloss, 8, hipMemcpyDeviceToHost, h->stream));
       NOCHK(hipStreamSynchronize(h->stream));
