@@ -442,8 +442,8 @@ __host__ __device__ inline bool is_boundary(const InstDev& D, int j, int k) {
 }
 
 // Radial wall nodes beside fluid rows can be computed in the step by their
-// own lanes (radial_wall, step kernels with wall lanes), which load their
-// owner's populations.  That is safe only in the owner's wave, where the
+// own lanes (wall_lane_inputs, step kernels with wall lanes), which load
+// their owner's populations.  That is safe only in the owner's wave, where the
 // loads precede the owner's in-place stores: always at r_min (columns 0 and
 // 1), at r_max unless column nr - 1 starts a new wave; otherwise the owner
 // computes the wall node (wall_node).
@@ -753,82 +753,6 @@ __host__ __device__ inline void wall_node(const InstDev& D, const A& P, const No
   }
 }
 
-// Radial wall node b = (jB - sg, k) beside fluid row k, computed by its own
-// lane from the state B of its owner (jB, k) (non-equilibrium extrapolation,
-// Sec. 4; no-slip, so u_b = 0): sg = +1 for the wall at r_min (owner j = 1),
-// -1 for the wall at r_max (owner j = nr - 2).  It is wall_node's no-slip
-// case for (dr, dz) = (-sg, 0), reduced to what streams into fluid nodes: the
-// three populations with e_r = sg (towards jB at rows k, k + 1, k - 1) and
-// the D2Q5 one with e_r = sg.  The lane loads its owner's populations and
-// forms B with the same instructions as its wave's fluid lanes, so a wave
-// with a wall lane runs this short tail once instead of the owner running a
-// full wall_node after its own update.
-template <typename S, bool ODD, int MODE, typename A>
-__host__ __device__ inline void radial_wall(const InstDev& D, const A& P, const NodeState& B,
-                                            const float t[5], float rB, int jB, int k, int sg,
-                                            int64_t rowm, int64_t row0, int64_t rowp,
-                                            int mac_slot, uint32_t seed) {
-  const bool lo = sg > 0;
-  const float fs = (float)sg;
-  const int jb = jB - sg;
-  const float rb = rB - fs;
-  const float inv_rb = frcp(rb);
-  const int64_t ob = row0 + jb;
-  const float phib = D.phi_mode == 0 ? D.phiu : D.phi[ob];
-  float Tb = B.T;
-  const int th = lo ? D.therm_rmin : D.therm_rmax;
-  if (th == THERM_FIXED) Tb = lo ? D.T_rmin : D.T_rmax;
-  else if (th == THERM_FLUX && k >= D.qk_lo && k <= D.qk_hi) Tb = B.T + (lo ? D.q_rmin : D.q_rmax);
-
-  if (MODE == MODE_STEP_MACRO) {
-    float* mac = mac_slot ? D.mac[1] : D.mac[0];
-    mac[ob] = 0.0f;
-    mac[D.plane + ob] = 0.0f;
-    mac[2 * D.plane + ob] = Tb;
-  }
-  // m+(b) = m^eq(rho_B, 0) + (I - L)(r_B / r_b) n(B) + (I - L/2) S(b), all / r_b,
-  // as deviations from the quiescent post-collision moments; only the rows of
-  // M^{-1} for the three outgoing directions are applied (back_transform).
-  const float drho = B.drho, rhob = 1.0f + drho;
-  const float q = rB * inv_rb;
-  const float hb = 0.5f * CS2 * inv_rb;
-  const float Gz = D.gbeta * (Tb - D.T_ref) + D.accel_z;
-  const float S3 = rhob * (phib * D.accel_r + CS2 * inv_rb), S5 = rhob * phib * Gz;
-  const float a1 = ((1.0f - D.s_e) * q * B.n1) * (float)(1.0 / 36.0);
-  const float a2 = ((1.0f - D.s_eps) * q * B.n2) * (float)(1.0 / 36.0);
-  const float a3 = ((1.0f - D.s_j) * q * B.n3 + (1.0f - 0.5f * D.s_j) * S3 - hb) * (float)(1.0 / 6.0);
-  const float a4 = ((1.0f - D.s_q) * q * B.n4 - (1.0f - 0.5f * D.s_q) * S3 + hb) * (float)(1.0 / 12.0);
-  const float a5 = ((1.0f - D.s_j) * q * B.n5 + (1.0f - 0.5f * D.s_j) * S5) * (float)(1.0 / 6.0);
-  const float a6 = ((1.0f - D.s_q) * q * B.n6 - (1.0f - 0.5f * D.s_q) * S5) * (float)(1.0 / 12.0);
-  const float a7 = ((1.0f - D.s_nu) * q * B.n7) * 0.25f;
-  const float a8 = ((1.0f - D.s_nu) * q * B.n8) * 0.25f;
-  const float e = -a1 - 2.0f * a2, c = 2.0f * a1 + a2;
-  const float pr = fs * (a3 + a4), pz = a5 + a6, s8 = fs * a8;
-  const float fa = W1 * drho + (e + fs * a3 - 2.0f * fs * a4 + a7);  // e_z = 0
-  const float fu = W5 * drho + (c + pr + pz + s8);                    // e_z = +1
-  const float fd = W5 * drho + (c + pr - pz - s8);                    // e_z = -1
-  // g+(b) = wt (T_b - T_s) + (1 - omega(r_b)) g^neq(B) along e_r = sg, u_b = 0
-  const float om = D.omc * (1.0f + fs * D.tau_T * inv_rb);
-  const float tB = lo ? t[1] : t[3];
-  const float ga = WT1 * (Tb - D.T_s) + (1.0f - om) * (tB - WT1 * B.theta - 5.0f * WT1 * B.T * fs * B.ur);
-
-  const bool up = !(z_bounded(D) && k + 1 == D.nz - 1), dn = !(z_bounded(D) && k - 1 == 0);
-  Dither rn(mix32(seed ^ (uint32_t)ob));
-  const uint32_t r0 = rn.next(), r1 = rn.next(), r2 = rn.next(), r3 = rn.next();
-  if (ODD) {
-    // slot i of the destination node jB (rows k, k + 1, k - 1); the D2Q9 and
-    // D2Q5 populations along r share a word (slots 1, 10 or 3, 12)
-    P.st_pair(lo ? 0 : 2, row0 + jB, fa, ga, r0, r3);
-    if (up) P.st(lo ? 5 : 6, rowp + jB, fu, r1);
-    if (dn) P.st(lo ? 8 : 7, rowm + jB, fd, r2);
-  } else {
-    // slot opposite(i) of the wall node itself (slots 3, 12 or 1, 10)
-    P.st_pair(lo ? 2 : 0, ob, fa, ga, r0, r3);
-    if (up) P.st(lo ? 7 : 8, ob, fu, r1);
-    if (dn) P.st(lo ? 6 : 5, ob, fd, r2);
-  }
-}
-
 // The populations arriving at fluid node (j, k) (as stored, unscaled to
 // FP32) and its porosity value.  Each slot is read and written by one node
 // only in a step, so these loads may be issued before earlier nodes of the
@@ -975,6 +899,66 @@ __device__ inline void pattern_store(const InstDev& D, const RowC& R, int j, int
   }
 }
 
+// Inputs of a radial wall lane's collision (step kernels with wall lanes).
+// The lane holds its owner B (column j, radius r_B) and turns the fluid
+// collision into the no-slip wall node b = j - wl at r_b = r_B - wl (Sec. 4,
+// non-equilibrium extrapolation): its post-collision state is
+//   m+(b) = m^eq(rho_B, 0) + (I - L)(r_B / r_b) n(B) + (I - L/2) S(b),
+// all / r_b, as deviations from the quiescent post-collision moments.  So
+// the pre-collision d becomes the rest equilibrium w_i (rho_B - 1) and the
+// moment increments X of the back-transform become (1 - s_i)(r_B / r_b) n_i
+// plus the wall's source, with the quiescent parts -+ c_s^2 / (2 r_b) of the
+// radial moments; the thermal population along e_r = wl becomes
+//   g+(b) = wt (T_b - T_s) + (1 - omega(r_b)) g^neq(B).
+// The node's stores then write the wall node's outgoing populations (e_r =
+// wl: directions 1, 5, 8 or 3, 6, 7, and the D2Q5 one) to the slots its
+// fluid neighbours read; its other populations go to the wall column's own
+// slots, which no fluid node reads (node_update_loaded).
+__host__ __device__ inline void wall_lane_inputs(const InstDev& D, const NodeState& B, const float t[5],
+                                                 float rB, int wl, int k, int64_t ob, float d[9],
+                                                 float X[8], float& ga, float& Tb) {
+  const bool lo = wl > 0;
+  const float fs = (float)wl;
+  const float inv_rb = frcp(rB - fs);
+  const float phib = D.phi_mode == 0 ? D.phiu : D.phi[ob];
+  Tb = B.T;
+  const int th = lo ? D.therm_rmin : D.therm_rmax;
+  if (th == THERM_FIXED) Tb = lo ? D.T_rmin : D.T_rmax;
+  else if (th == THERM_FLUX && k >= D.qk_lo && k <= D.qk_hi) Tb = B.T + (lo ? D.q_rmin : D.q_rmax);
+  const float drho = B.drho, rhob = 1.0f + drho;
+  const float q = rB * inv_rb;
+  const float hb = 0.5f * CS2 * inv_rb;
+  const float Gz = D.gbeta * (Tb - D.T_ref) + D.accel_z;
+  const float S3 = rhob * (phib * D.accel_r + CS2 * inv_rb), S5 = rhob * phib * Gz;
+  X[0] = (1.0f - D.s_e) * q * B.n1;
+  X[1] = (1.0f - D.s_eps) * q * B.n2;
+  X[2] = (1.0f - D.s_j) * q * B.n3 + (1.0f - 0.5f * D.s_j) * S3 - hb;
+  X[3] = (1.0f - D.s_q) * q * B.n4 - (1.0f - 0.5f * D.s_q) * S3 + hb;
+  X[4] = (1.0f - D.s_j) * q * B.n5 + (1.0f - 0.5f * D.s_j) * S5;
+  X[5] = (1.0f - D.s_q) * q * B.n6 - (1.0f - 0.5f * D.s_q) * S5;
+  X[6] = (1.0f - D.s_nu) * q * B.n7;
+  X[7] = (1.0f - D.s_nu) * q * B.n8;
+  d[0] = W0 * drho;
+#pragma unroll
+  for (int i = 1; i < 5; ++i) d[i] = W1 * drho;
+#pragma unroll
+  for (int i = 5; i < 9; ++i) d[i] = W5 * drho;
+  const float om = D.omc * (1.0f + fs * D.tau_T * inv_rb);
+  const float tB = lo ? t[1] : t[3];
+  ga = WT1 * (Tb - D.T_s) + (1.0f - om) * (tB - WT1 * B.theta - 5.0f * WT1 * B.T * fs * B.ur);
+}
+
+// Whether the predicate holds on any lane of the wave (on the host, for this
+// node): a branch on it is taken by whole waves, so what follows stays one
+// path for all lanes.
+__host__ __device__ inline bool any_lane(bool p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __any(p);
+#else
+  return p;
+#endif
+}
+
 // One fluid node (j, k) at one time step, from its loaded populations s, t
 // and porosity value.  seed: random bits of this step for stochastic
 // rounding of 16-bit storage.
@@ -993,7 +977,7 @@ __host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC&
   }
   const int64_t rowm = row_off(km, st), row0 = row_off(k, st), rowp = row_off(kp, st);
   const int64_t o = row0 + j;
-  Dither rn(mix32(seed ^ (uint32_t)o));
+  Dither rn(mix32(seed ^ (uint32_t)(o - wl)));  // a wall lane draws its wall node's stream
   float t[5] = {t_in[0], t_in[1], t_in[2], t_in[3], t_in[4]};
   float phi, cD, cF;
   porosity_of(D, phi_raw, phi, cD, cF);
@@ -1069,9 +1053,13 @@ __host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC&
   B.n7 = (d[1] - d[2] + d[3] - d[4]) - rho * (ur * ur - uz * uz) * iphi;
   B.n8 = (d[5] - d[6] + d[7] - d[8]) - rho * ur * uz * iphi;
 
-  // A radial wall lane (WL kernels, wl = +-1, node (j, k) being its owner)
-  // skips the fluid node's collision and stores and takes its wall node below.
-  if (MODE != MODE_FIELDS && (!WL || wl == 0)) {
+  // Where the stores go: the node's own position and neighbour columns, or
+  // for a radial wall lane (WL kernels, wl = +-1, node (j, k) being its
+  // owner) its wall node jb = j - wl, whose missing neighbour column is the
+  // wall column itself (see wall_lane_inputs).
+  int js = j, cms = R.cm, cps = R.cp;
+  int64_t os = o;
+  if (MODE != MODE_FIELDS) {
     // ---- source (Eq. 24) and relaxation (Eq. 21) --------------------------
     float S1, S7, S8;
     source(D.src_printed != 0, rho, ur, uz, iphi, Fr, Fz, ar, S1, S7, S8);
@@ -1085,13 +1073,14 @@ __host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC&
                      (2.0f - D.s_j) * R.hcs2r * B.drho;
     const float X4 = -D.s_q * (m4 + rho * ur) - (1.0f - 0.5f * D.s_q) * S3d -
                      (2.0f - D.s_q) * R.hcs2r * B.drho;
-    // ---- back-transform (Eq. 22) ------------------------------------------
-    back_transform(d, -D.s_e * B.n1 + (1.0f - 0.5f * D.s_e) * S1,
-                   -D.s_eps * B.n2 - (1.0f - 0.5f * D.s_eps) * S1, X3, X4,
-                   -D.s_j * B.n5 + (1.0f - 0.5f * D.s_j) * S5,
-                   -D.s_q * B.n6 - (1.0f - 0.5f * D.s_q) * S5,
-                   -D.s_nu * B.n7 + (1.0f - 0.5f * D.s_nu) * S7,
-                   -D.s_nu * B.n8 + (1.0f - 0.5f * D.s_nu) * S8);
+    float X[8] = {-D.s_e * B.n1 + (1.0f - 0.5f * D.s_e) * S1,
+                  -D.s_eps * B.n2 - (1.0f - 0.5f * D.s_eps) * S1,
+                  X3,
+                  X4,
+                  -D.s_j * B.n5 + (1.0f - 0.5f * D.s_j) * S5,
+                  -D.s_q * B.n6 - (1.0f - 0.5f * D.s_q) * S5,
+                  -D.s_nu * B.n7 + (1.0f - 0.5f * D.s_nu) * S7,
+                  -D.s_nu * B.n8 + (1.0f - 0.5f * D.s_nu) * S8};
 
     // ---- temperature collision (Eqs. 33-37) ------------------------------
     // q_i = g_i - wt_i T is the part of g - g^eq that does not depend on u;
@@ -1114,39 +1103,70 @@ __host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC&
     }
     for (int q = 0; q < 5; ++q) B.t[q] = t[q];
 
+    if constexpr (WL) {
+      // A wave with a wall lane forms the wall node's inputs on every lane and
+      // the wall lane selects them (per-lane selects, not a divergent branch,
+      // so the back-transform and the stores below stay one path).
+      if (any_lane(wl != 0)) {
+        const bool isw = wl != 0;
+        const int jw = j - wl;  // the wall column (the node's own column on fluid lanes)
+        float dw[9], Xw[8], ga, Tb;
+        wall_lane_inputs(D, B, t, R.r, wl, k, row0 + jw, dw, Xw, ga, Tb);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) d[i] = isw ? dw[i] : d[i];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) X[i] = isw ? Xw[i] : X[i];
+        tg[1] = wl > 0 ? ga : tg[1];
+        tg[3] = wl < 0 ? ga : tg[3];
+        js = jw;
+        os = row0 + jw;
+        cms = wl > 0 ? jw : (wl < 0 ? jw - 1 : cms);  // the missing neighbour column is the wall column itself
+        cps = wl < 0 ? jw : (wl > 0 ? jw + 1 : cps);
+        if (MODE == MODE_STEP_MACRO && isw) {
+          float* mac = mac_slot ? D.mac[1] : D.mac[0];
+          mac[os] = 0.0f;
+          mac[pl + os] = 0.0f;
+          mac[2 * pl + os] = Tb;
+        }
+      }
+    }
+
+    // ---- back-transform (Eq. 22) ------------------------------------------
+    back_transform(d, X[0], X[1], X[2], X[3], X[4], X[5], X[6], X[7]);
+
     // ---- stream and store --------------------------------------------------
     if constexpr (sizeof(S) == 4) {
       if (!ODD) {
-        P.st(0, o, d[0], rn.next());
-        P.st(3, o, d[1], rn.next());
-        P.st(4, o, d[2], rn.next());
-        P.st(1, o, d[3], rn.next());
-        P.st(2, o, d[4], rn.next());
-        P.st(7, o, d[5], rn.next());
-        P.st(8, o, d[6], rn.next());
-        P.st(5, o, d[7], rn.next());
-        P.st(6, o, d[8], rn.next());
-        D.g0[o] = tg[0];
-        P.st(12, o, tg[1], rn.next());
-        P.st(13, o, tg[2], rn.next());
-        P.st(10, o, tg[3], rn.next());
-        P.st(11, o, tg[4], rn.next());
+        P.st(0, os, d[0], rn.next());
+        P.st(3, os, d[1], rn.next());
+        P.st(4, os, d[2], rn.next());
+        P.st(1, os, d[3], rn.next());
+        P.st(2, os, d[4], rn.next());
+        P.st(7, os, d[5], rn.next());
+        P.st(8, os, d[6], rn.next());
+        P.st(5, os, d[7], rn.next());
+        P.st(6, os, d[8], rn.next());
+        D.g0[os] = tg[0];
+        P.st(12, os, tg[1], rn.next());
+        P.st(13, os, tg[2], rn.next());
+        P.st(10, os, tg[3], rn.next());
+        P.st(11, os, tg[4], rn.next());
       } else {
-        const int64_t cm = R.cm, cp = R.cp;
-        P.st(0, o, d[0], rn.next());
+        const int64_t cm = cms, cp = cps;
+        P.st(0, os, d[0], rn.next());
         P.st(1, row0 + cp, d[1], rn.next());
-        P.st(2, rowp + j, d[2], rn.next());
+        P.st(2, rowp + js, d[2], rn.next());
         P.st(R.mir ? 1 : 3, row0 + cm, d[3], rn.next());
-        P.st(4, rowm + j, d[4], rn.next());
+        P.st(4, rowm + js, d[4], rn.next());
         P.st(5, rowp + cp, d[5], rn.next());
         P.st(R.mir ? 5 : 6, rowp + cm, d[6], rn.next());
         P.st(R.mir ? 8 : 7, rowm + cm, d[7], rn.next());
         P.st(8, rowm + cp, d[8], rn.next());
-        D.g0[o] = tg[0];
+        D.g0[os] = tg[0];
         P.st(10, row0 + cp, tg[1], rn.next());
-        P.st(11, rowp + j, tg[2], rn.next());
+        P.st(11, rowp + js, tg[2], rn.next());
         P.st(R.mir ? 10 : 12, row0 + cm, tg[3], rn.next());
-        P.st(13, rowm + j, tg[4], rn.next());
+        P.st(13, rowm + js, tg[4], rn.next());
       }
     } else {
       // 16-bit storage: f_i^+ and g_i^+ of each axial direction land in the
@@ -1155,28 +1175,28 @@ __host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC&
 #pragma unroll
       for (int i = 0; i < 13; ++i) r[i] = rn.next();
       if (!ODD) {
-        P.st(0, o, d[0], r[0]);
-        P.st_pair(2, o, d[1], tg[1], r[1], r[9]);   // slots 3, 12
-        P.st_pair(3, o, d[2], tg[2], r[2], r[10]);  // slots 4, 13
-        P.st_pair(0, o, d[3], tg[3], r[3], r[11]);  // slots 1, 10
-        P.st_pair(1, o, d[4], tg[4], r[4], r[12]);  // slots 2, 11
-        P.st(7, o, d[5], r[5]);
-        P.st(8, o, d[6], r[6]);
-        P.st(5, o, d[7], r[7]);
-        P.st(6, o, d[8], r[8]);
+        P.st(0, os, d[0], r[0]);
+        P.st_pair(2, os, d[1], tg[1], r[1], r[9]);   // slots 3, 12
+        P.st_pair(3, os, d[2], tg[2], r[2], r[10]);  // slots 4, 13
+        P.st_pair(0, os, d[3], tg[3], r[3], r[11]);  // slots 1, 10
+        P.st_pair(1, os, d[4], tg[4], r[4], r[12]);  // slots 2, 11
+        P.st(7, os, d[5], r[5]);
+        P.st(8, os, d[6], r[6]);
+        P.st(5, os, d[7], r[7]);
+        P.st(6, os, d[8], r[8]);
       } else {
-        const int64_t cm = R.cm, cp = R.cp;
-        P.st(0, o, d[0], r[0]);
+        const int64_t cm = cms, cp = cps;
+        P.st(0, os, d[0], r[0]);
         P.st_pair(0, row0 + cp, d[1], tg[1], r[1], r[9]);
-        P.st_pair(1, rowp + j, d[2], tg[2], r[2], r[10]);
+        P.st_pair(1, rowp + js, d[2], tg[2], r[2], r[10]);
         P.st_pair(R.mir ? 0 : 2, row0 + cm, d[3], tg[3], r[3], r[11]);
-        P.st_pair(3, rowm + j, d[4], tg[4], r[4], r[12]);
+        P.st_pair(3, rowm + js, d[4], tg[4], r[4], r[12]);
         P.st(5, rowp + cp, d[5], r[5]);
         P.st(R.mir ? 5 : 6, rowp + cm, d[6], r[6]);
         P.st(R.mir ? 8 : 7, rowm + cm, d[7], r[7]);
         P.st(8, rowm + cp, d[8], r[8]);
       }
-      D.g0[o] = tg[0];
+      D.g0[os] = tg[0];
     }
   } else {
     for (int q = 0; q < 5; ++q) B.t[q] = t[q];
@@ -1185,17 +1205,14 @@ __host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC&
   // ---- wall nodes owned by this node ---------------------------------------
   // (after the fluid node's stores: only B stays live across them)
   if constexpr (WL && MODE != MODE_FIELDS) {
-    if (wl != 0) {
-      radial_wall<S, ODD, MODE>(D, P, B, B.t, R.r, j, k, wl, rowm, row0, rowp, mac_slot, seed);
-      return;
-    }
+    if (wl != 0) return;  // a wall lane's wall node is stored above
   }
   const bool own_rm = D.side_rmin == SIDE_WALL && j == 1;
   const bool own_rp = D.side_rmax == SIDE_WALL && j == D.nr - 2;
   const bool own_zm = z_bounded(D) && k == 1;
   const bool own_zp = z_bounded(D) && k == D.nz - 2;
   // In the step kernels with wall lanes the radial wall nodes beside fluid
-  // rows are their own lanes' (radial_wall, where wall_lane_rmax allows);
+  // rows are their own lanes' (wall_lane_inputs, where wall_lane_rmax allows);
   // owners keep the rest: the z-wall nodes and the corners.
   const bool rad_m = MODE == MODE_FIELDS || !WL;
   const bool rad_p = MODE == MODE_FIELDS || !WL || !wall_lane_rmax(D);

@@ -38,7 +38,7 @@ __global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(sizeof(S
   if (jt >= D.nr) return;
   // With wall lanes (WL) a radial wall lane (column 0 or nr - 1 of a no-slip
   // side) works on its owner's column j and writes its own wall node
-  // (radial_wall) when it shares the owner's wave; otherwise, and without
+  // (wall_lane_inputs) when it shares the owner's wave; otherwise, and without
   // wall lanes, the owner computes the wall node and the wall lane idles.
   int wl = 0;
   if constexpr (WL && MODE != MODE_FIELDS) {
