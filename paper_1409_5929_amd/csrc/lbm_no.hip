@@ -339,14 +339,18 @@ __device__ inline float block_sum(float v, float* sh) {
   return t;
 }
 
-// a = relu(z) (or z) + skip
+// a = relu(z) (or z) + skip; and a in bfloat16 into a16 (may be null): the
+// im2col of a following 1 x 1 layer, whose rows are a's channels.
 __global__ __launch_bounds__(EW) void k_act(const float* __restrict__ z, const float* __restrict__ skip,
-                                            float* __restrict__ a, int64_t n, int relu) {
+                                            float* __restrict__ a, int64_t n, int relu,
+                                            bf16_t* __restrict__ a16) {
   const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
   if (i >= n) return;
   float v = z[i];
   if (relu) v = fmaxf(v, 0.0f);
-  a[i] = skip ? v + skip[i] : v;
+  v = skip ? v + skip[i] : v;
+  a[i] = v;
+  if (a16) a16[i] = to_bf16(v);
 }
 
 // dz = da where mask > 0 (relu; the mask is z, or a = relu(z)) or da;
@@ -886,7 +890,11 @@ int input_grad_s2(lbm_no* h, const Layer& l, const bf16_t* dz, int Bt, float* dx
                      nullptr, accumulate);
 }
 
+// A 1 x 1, stride-1 layer: its im2col is its input in bfloat16.
+bool pointwise(const Layer& l) { return l.k == 1 && l.s == 1 && !l.up; }
+
 int forward_internal(lbm_no* h, const float* x, int Bt) {
+  bool col_ready = false;  // the layer's im2col was written with the previous layer's activation
   for (size_t li = 0; li < h->L.size(); ++li) {
     const Layer& l = h->L[li];
     const int64_t P = (int64_t)Bt * l.Ho * l.Wo;
@@ -895,12 +903,12 @@ int forward_internal(lbm_no* h, const float* x, int Bt) {
     // adds the skip in k_act; any other layer's GEMM writes a = relu(z) (or
     // z) itself, and its backward takes the mask from a (a > 0 exactly where
     // z > 0)
-    int rc;
+    int rc = LBM_NO_OK;
     if (phase_kind(l) == 1) {
       if (l.skip < 0) return fail(LBM_NO_EINVAL, "upsampling layer without a skip input");
       rc = forward_up(h, l, h->a[li - 1], Bt, h->colL[li], h->z[li]);
     } else {
-      rc = im2col(h, l, li == 0 ? x : h->a[li - 1], li == 0, Bt, h->colL[li]);
+      if (!col_ready) rc = im2col(h, l, li == 0 ? x : h->a[li - 1], li == 0, Bt, h->colL[li]);
       if (rc) return rc;
       // z[o][p] = W[o][k] col[k][p]: A k-contiguous, B n-contiguous
       float* out = l.skip >= 0 ? h->z[li] : h->a[li];
@@ -908,10 +916,14 @@ int forward_internal(lbm_no* h, const float* x, int Bt) {
                        h->par + l.boff, 0, l.skip >= 0 ? 0 : l.relu);
     }
     if (rc) return rc;
+    const bool next_pw = li + 1 < h->L.size() && pointwise(h->L[li + 1]);
+    col_ready = false;
     if (l.skip >= 0) {
       const int64_t n = (int64_t)l.cout * P;
-      k_act<<<grid1(n), EW, 0, h->stream>>>(h->z[li], h->a[l.skip], h->a[li], n, l.relu);
+      k_act<<<grid1(n), EW, 0, h->stream>>>(h->z[li], h->a[l.skip], h->a[li], n, l.relu,
+                                            next_pw ? h->colL[li + 1] : nullptr);
       NOCHK(hipGetLastError());
+      col_ready = next_pw;
     }
   }
   return LBM_NO_OK;
