@@ -23,8 +23,11 @@
  * Optimiser: Adam with bias correction.
  *
  * Arithmetic: the convolutions run as GEMMs on MFMA with bfloat16 operands
- * (weights and activations rounded to nearest even) and FP32 accumulation;
- * master weights, Adam moments, biases, activations and gradients are FP32.
+ * (rounded to nearest even) and FP32 accumulation: weights, activations and
+ * activation gradients, or, where a layer runs in an equivalent form, the
+ * sums those forms take first (the taps of an upsampling layer that meet one
+ * source pixel, the 2 x 2 sums of its output gradient).  Master weights, Adam
+ * moments, biases, activations and gradients are FP32.
  *
  * Parameters are packed layer by layer: W[cout][cin][k][k] then b[cout]
  * (FP32).  Tensors passed in or out are device arrays in

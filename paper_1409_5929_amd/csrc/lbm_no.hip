@@ -450,7 +450,7 @@ __global__ __launch_bounds__(64 * SW) void k_sum_splits(const float* __restrict_
 //   t = 3 ky + kx,
 // the input gradient is dsrc[c][s] = sum_{t, o} W[o][c][t] D[t][o][s] and the
 // weight gradient dW[o][c][t] = sum_s D[t][o][s] src[c][s] (s = (b, sy, sx)):
-// two GEMMs over the source grid, with no im2col or col2im pass and 4/9 of
+// two GEMMs over the source grid, with no im2col or col2im pass and 1/4 of
 // the products of the upsampled grid.  One thread per (o, b, sy, sx) sums
 // the 4 x 4 outputs around it into all nine taps; D is bfloat16,
 // [9 cout][P4], P4 = batch Hs Ws.
