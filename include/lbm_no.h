@@ -50,15 +50,17 @@ enum { LBM_NO_OK = 0, LBM_NO_EINVAL = -1, LBM_NO_ENOMEM = -2, LBM_NO_EDEVICE = -
 
 typedef struct lbm_no lbm_no;
 
-/* Number of packed parameters for widths[4] = {c1, c2, c3, c4}. */
+/* Number of packed parameters for widths[4] = {c1, c2, c3, c4}, each in
+ * [1, 1024]. */
 int lbm_no_param_count(const int32_t* widths, int64_t* count);
 
 /*
  * Network for height x width inputs and batches of at most max_batch.
  * params: host array of lbm_no_param_count floats (copied).  hip_stream:
  * the hipStream_t all work is ordered on; NULL is the null (default) stream.
- * Widths in [1, 1024]; height and width multiples of 8 in [8, 2048];
- * max_batch >= 1.
+ * Widths even, in [2, 1024]; height and width multiples of 8 in [8, 2048];
+ * max_batch >= 1 with max_batch * height * width <= 2^25.  Other values:
+ * LBM_NO_EINVAL.
  */
 int lbm_no_create(const int32_t* widths, int32_t height, int32_t width, int32_t max_batch,
                   const float* params, void* hip_stream, lbm_no** out);

@@ -121,6 +121,15 @@ def test_network_library_exports_and_counts_parameters():
     bad = (ctypes.c_int32 * 4)(0, 1, 1, 1)
     n = ctypes.c_int64()
     assert lib.lbm_no_param_count(bad, ctypes.byref(n)) == -1
+    # create checks its arguments before any device call: the limits of lbm_no.h
+    par = (ctypes.c_float * 1)()
+    for widths, hh, ww, mb in [((8, 16, 24, 33), 64, 64, 1), ((0, 16, 24, 32), 64, 64, 1),
+                               ((8, 16, 24, 1026), 64, 64, 1), ((8, 16, 24, 32), 60, 64, 1),
+                               ((8, 16, 24, 32), 64, 2056, 1), ((8, 16, 24, 32), 64, 64, 0),
+                               ((8, 16, 24, 32), 2048, 2048, 9)]:
+        handle = ctypes.c_void_p(1)
+        rc = lib.lbm_no_create((ctypes.c_int32 * 4)(*widths), hh, ww, mb, par, None, ctypes.byref(handle))
+        assert rc == -1 and handle.value is None, (widths, hh, ww, mb, rc)
     assert lib.lbm_no_forward(None, None, 1, None) == -1
     assert lib.lbm_no_adam(None, 1e-3, 0.9, 0.999, 1e-8) == -1
     lib.lbm_no_destroy(None)
