@@ -36,6 +36,7 @@ def build_host_lib(force: bool = False) -> str:
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(f) for f in DEPS):
         hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
         subprocess.check_call([hipcc, "--offload-arch=gfx950", "-O2", "-std=c++17", "-shared", "-fPIC",
+                               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                                "-I", os.path.join(ROOT, "include"), "-o", LIB + ".tmp", SRC])
         os.replace(LIB + ".tmp", LIB)
     return LIB
