@@ -112,9 +112,6 @@
 /* Eq. (14): D2Q9 velocities in (r, z) order. */
 static const int EX9[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 static const int EZ9[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-/* Weights listed after Eq. (32). */
-static const double W9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
-                             1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 /* Eq. (34): D2Q5 velocities; Eq. (36) weights with omega_0 = 3/5. */
 static const int EX5[5] = {0, 1, 0, -1, 0};
 static const int EZ5[5] = {0, 0, 1, 0, -1};
