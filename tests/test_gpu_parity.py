@@ -5,8 +5,6 @@ runs the same number of steps in both implementations and compares the
 macroscopic fields node by node (u = (u_z, u_r) as one vector, p, T:
 relative L2 <= 1e-5 for FP32; node classes bit-exact).
 """
-import math
-
 import numpy as np
 import pytest
 
@@ -223,7 +221,7 @@ def _window(cfg, phi, j0, k0, w):
     walls where it touches them and walls (contaminating only a margin)
     elsewhere."""
     c = dict(cfg)
-    nr, nz = cfg["nr"], cfg["nz"]
+    nr = cfg["nr"]
     c.update(nr=w, nz=w, r0=cfg["r0"] + j0)
     if j0 > 0:
         c.update(side_rmin="wall", therm_rmin="adiabatic")

@@ -97,7 +97,7 @@ def test_a_planted_sign_error_is_caught(oracle_mod, monkeypatch):
     """The comparison has teeth: flipping the sign of the axisymmetric term a_r
     of Eq. (25) in the literal oracle makes the two disagree far beyond
     rounding."""
-    name, cfg, field = _cases()[0]
+    _, cfg, _ = _cases()[0]
     cfg = dict(cfg, nr=4, nz=6)
     rng = np.random.default_rng(3)
     phi = rng.uniform(0.4, 0.8, (6, 4))

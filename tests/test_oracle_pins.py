@@ -203,9 +203,9 @@ def test_mass_conserved_on_periodic_lattice(oracle_mod):
                side_z="periodic", phi=0.6, Da=1e-2, F_phi=-1.0, tau_nu=1.0, Pr=1.0,
                accel_z=1e-5, T_rmin=1.0, T_rmax=0.0, T_ref=0.5)
     o = oracle_mod.Oracle(cfg, init=init)
-    f0, g0 = o.populations()
+    f0, _ = o.populations()
     o.step(300)
-    f1, g1 = o.populations()
+    f1, _ = o.populations()
     assert np.isfinite(f1).all()
     assert abs(f1.sum() - f0.sum()) <= 1e-13 * abs(f0.sum())
 
@@ -273,8 +273,8 @@ def test_printed_source_form_misses_porous_pipe(oracle_mod):
     """Eq. (24) as printed scales the axisymmetric correction a_r by 1/phi; at
     phi = 1 both forms agree up to rounding, at phi = 0.6 the printed form makes
     Hagen-Poiseuille flow 1.5 times too fast."""
-    e0, o0 = _pipe_error(oracle_mod, 16, phi=1.0, Da=1e8, printed=0)
-    e1, o1 = _pipe_error(oracle_mod, 16, phi=1.0, Da=1e8, printed=1)
+    _, o0 = _pipe_error(oracle_mod, 16, phi=1.0, Da=1e8, printed=0)
+    _, o1 = _pipe_error(oracle_mod, 16, phi=1.0, Da=1e8, printed=1)
     np.testing.assert_allclose(o0.macros()["uz"], o1.macros()["uz"], rtol=1e-12, atol=0)
     nr = 32
     cfg = li.pipe(nr=nr, nz=2, phi=0.6, Da=1e8, Re=10.0, tau_nu=0.8, F_phi=0.0)
