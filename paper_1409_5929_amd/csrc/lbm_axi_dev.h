@@ -1111,7 +1111,17 @@ __host__ __device__ inline void node_update_loaded(const InstDev& D, const RowC&
         const bool isw = wl != 0;
         const int jw = j - wl;  // the wall column (the node's own column on fluid lanes)
         float dw[9], Xw[8], ga, Tb;
-        wall_lane_inputs(D, B, t, R.r, wl, k, row0 + jw, dw, Xw, ga, Tb);
+        // In the 16-bit kernels (four waves per SIMD, so 128 VGPRs) the wall
+        // lane's radius and side pass through an empty asm statement: the
+        // compiler then forms the wall inputs' per-lane products in every
+        // node update of a wave with a wall lane, instead of hoisting them out
+        // of the node loop and spilling them to scratch. Same operations.
+        float rw = R.r;
+        int wlw = wl;
+#if defined(__HIP_DEVICE_COMPILE__)
+        if constexpr (sizeof(S) == 2) asm volatile("" : "+v"(rw), "+v"(wlw));
+#endif
+        wall_lane_inputs(D, B, t, rw, wlw, k, row0 + jw, dw, Xw, ga, Tb);
 #pragma unroll
         for (int i = 0; i < 9; ++i) d[i] = isw ? dw[i] : d[i];
 #pragma unroll
