@@ -1,5 +1,7 @@
-"""bench.py's command line on the host: more than one GPU is refused with a
-message, before anything touches a device."""
+"""bench.py on the host: more than one GPU is refused with a message, before
+anything touches a device; every function's globals are defined; the counter
+traffic on the bench line is tied to the kernel source it was measured on."""
+import json
 import os
 import subprocess
 import sys
@@ -57,3 +59,30 @@ def test_no_function_reads_an_undefined_global(rel):
     """A function that calls a name nothing defines fails only when that line
     runs, which for bench.py is on the GPU after minutes of work."""
     assert _undefined_globals(os.path.join(ROOT, rel)) == []
+
+
+def test_traffic_is_reported_only_for_the_kernel_source_it_was_taken_on(tmp_path, monkeypatch):
+    """The counter traffic on the bench line belongs to the kernel source it
+    was measured on: the same bytes while the hash of the kernel sources
+    matches the file's, none once a source differs."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    srcs = []
+    for i, p in enumerate(bench.KERNEL_SOURCES):
+        q = tmp_path / f"src{i}"
+        q.write_bytes(open(p, "rb").read())
+        srcs.append(str(q))
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", srcs)
+    record = {"source_sha": bench.kernel_source_sha(), "note": "test",
+              "fp32": {"bytes_per_launch": 123}, "fp16": {"bytes_per_launch": 45}}
+    f = tmp_path / "traffic.json"
+    f.write_text(json.dumps(record))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.measured_traffic("fp32") == 123 and bench.measured_traffic("fp16") == 45
+    assert bench.measured_traffic("bf16") is None
+    with open(srcs[-1], "ab") as g:
+        g.write(b"\n// changed\n")
+    assert bench.measured_traffic("fp32") is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.json"))
+    assert bench.measured_traffic("fp32") is None
