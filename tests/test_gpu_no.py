@@ -220,3 +220,23 @@ def test_network_on_another_stream_is_ordered(torch):
     np.testing.assert_array_equal(ya, yb)
     assert la == lb
     np.testing.assert_array_equal(ga, gb)
+
+
+@pytest.mark.parametrize("H, W", [(8, 8), (8, 24), (16, 8)])
+def test_smallest_grids_match_oracle(torch, H, W):
+    """Down to the smallest grid the library accepts (8 x 8): the deepest
+    layer is 1 x 1 and its upsampling layer reads a single source pixel per
+    image; forward, loss and gradients against the oracle."""
+    from paper_1409_5929_amd.no import WarmStartNet
+
+    params, x, t = problem(seed=13, B=2, H=H, W=W)
+    net = WarmStartNet(WIDTHS, H, W, 2, params)
+    y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
+    loss = net.gradients(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
+    g = net.grads()
+    net.close()
+    ref, _ = N.forward(params.astype(np.float64), WIDTHS, x.astype(np.float64))
+    lref, gref = N.loss_and_grads(params.astype(np.float64), WIDTHS, x.astype(np.float64), t.astype(np.float64))
+    e = (rel(y, ref), abs(loss - lref) / lref, rel(g, gref))
+    print(f"{H}x{W}: forward {e[0]:.2e} loss {e[1]:.2e} gradient {e[2]:.2e}", flush=True)
+    assert max(e) <= TOL
