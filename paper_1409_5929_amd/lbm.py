@@ -326,6 +326,17 @@ class Lattice:
         allocation: psi a float32 [nz, nr] device tensor (or None), psi_absmax a
         float64 device tensor of one element (or None); written on the
         handle's stream."""
+        import torch
+
+        nz, nr = self.shapes[int(inst)]
+        # the library writes nz nr floats and one double through these pointers
+        for t, dtype, n, what in ((psi, torch.float32, nz * nr, "psi"), (psi_absmax, torch.float64, 1, "psi_absmax")):
+            if t is None:
+                continue
+            if t.dtype != dtype or t.numel() != n or not t.is_contiguous():
+                raise ValueError(f"{what}: expected a contiguous {dtype} tensor of {n} elements")
+            if not t.is_cuda:
+                raise ValueError(f"{what}: expected device memory")
         _check(self._lib.lbm_axi_stream_function_static(
             self._h, int(inst), None if psi is None else psi.data_ptr(),
             None if psi_absmax is None else psi_absmax.data_ptr()))

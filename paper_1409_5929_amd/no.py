@@ -151,6 +151,8 @@ class WarmStartNet:
 
     def set_params(self, params):
         p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != param_count(self.widths):  # the library copies that many floats
+            raise NoError("parameter vector has the wrong length")
         _check(self._lib.lbm_no_set_params(self._h, _fptr(p)))
 
     def sync(self):

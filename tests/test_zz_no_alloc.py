@@ -66,3 +66,25 @@ def test_static_stream_function_refuses_more_columns_than_its_scratch(lbm):
     assert _static(lib, lat, None, mx) == -1  # LBM_AXI_EINVAL
     assert "scratch" in lib.lbm_axi_last_error().decode()
     lat.close()
+
+
+def test_binding_method_checks_the_tensors_and_makes_the_same_call(lbm):
+    """Lattice.stream_function_static: caller device tensors of the right size
+    give the allocating entry point's values; a tensor too small for the
+    instance is refused before the library writes through it."""
+    import torch
+
+    lat = lbm.Lattice(li.pipe(nr=41, nz=30), check_interval=0)
+    lat.step(200)
+    psi_ref, mx_ref = lat.stream_function()
+    nz, nr = lat.shapes[0]
+    psi = torch.full((nz, nr), float("nan"), dtype=torch.float32, device="cuda")
+    mx = torch.full((1,), float("nan"), dtype=torch.float64, device="cuda")
+    lat.stream_function_static(0, psi, mx)
+    lat.sync()
+    got, got_mx = psi.cpu().numpy(), mx.item()
+    with pytest.raises(ValueError):
+        lat.stream_function_static(0, torch.zeros((nz, nr - 1), dtype=torch.float32, device="cuda"), None)
+    lat.close()
+    np.testing.assert_array_equal(got, psi_ref)
+    assert got_mx == mx_ref
